@@ -1,0 +1,78 @@
+"""Brute-force dependency check of a tiled schedule (version stamps).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Section 4.2 states the condition a tiling must satisfy: a block of a later loop
+may only contain iterations whose inputs were already computed by the blocks
+executed before it, and a later loop's write must not be seen by an earlier
+loop's read that, in program order, came first.  Equivalently: every read in
+the tiled schedule sees exactly the writer (loop index) it sees in program
+order.  This module simulates both orders on tiny grids with per-point write
+stamps and compares every read.
+"""
+from __future__ import annotations
+
+import itertools
+from typing import Callable, Dict, Iterable, List, Sequence, Tuple
+
+from .skewed import Loop
+
+
+def _points(lo: Sequence[int], hi: Sequence[int]):
+    return itertools.product(*[range(a, b) for a, b in zip(lo, hi)])
+
+
+def _run(loops: List[Loop], schedule: Iterable[Tuple[int, Sequence[int], Sequence[int]]]):
+    stamp: Dict[Tuple[int, Tuple[int, ...]], int] = {}
+    seen: Dict[Tuple, int] = {}
+    writes: Dict[int, List[Tuple[int, ...]]] = {}
+    done = set()
+    for l, lo, hi in schedule:
+        lp = loops[l]
+        for x in _points(lo, hi):
+            if (l, x) in done:
+                raise AssertionError(f"loop {l} point {x} executed twice")
+            done.add((l, x))
+            for ai, a in enumerate(lp.args):
+                if a.reads():
+                    for qi, q in enumerate(a.stencil):
+                        y = tuple(xi + qi_ for xi, qi_ in zip(x, q))
+                        key = (l, x, ai, qi)
+                        seen[key] = stamp.get((a.dat, y), -1)
+            for a in lp.args:
+                if a.writes():
+                    stamp[(a.dat, x)] = l
+                    writes.setdefault(l, []).append(x)
+    return seen, stamp, done
+
+
+def program_order(loops: List[Loop]):
+    return [(l, lp.start, lp.end) for l, lp in enumerate(loops)]
+
+
+def check_schedule(loops: List[Loop], schedule) -> None:
+    """Raise AssertionError if the schedule's reads or final state differ from
+    program order, or if a loop's points are not each executed exactly once."""
+    ref_seen, ref_stamp, ref_done = _run(loops, program_order(loops))
+    got_seen, got_stamp, got_done = _run(loops, schedule)
+    if ref_done != got_done:
+        raise AssertionError("executed points differ from the loops' ranges")
+    if ref_seen.keys() != got_seen.keys():
+        missing = set(ref_seen) - set(got_seen)
+        extra = set(got_seen) - set(ref_seen)
+        raise AssertionError(f"coverage differs: missing {sorted(missing)[:5]} extra {sorted(extra)[:5]}")
+    for k, v in ref_seen.items():
+        if got_seen[k] != v:
+            raise AssertionError(f"read {k} saw writer {got_seen[k]}, program order saw {v}")
+    if ref_stamp != got_stamp:
+        raise AssertionError("final writers differ")
+
+
+def tiled_schedule(plan, n_loops: int):
+    out = []
+    for t in plan.tiles():
+        for l in range(n_loops):
+            lo, hi = plan.box(t, l)
+            if all(h > o for o, h in zip(lo, hi)):
+                out.append((l, lo, hi))
+    return out
