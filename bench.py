@@ -1,0 +1,208 @@
+"""Benchmark: run-time tiled execution of a synthetic 2D loop chain on one MI355X.
+
+Workload (one step = one flush of the whole chain over the grid, inputs
+resident in HBM): 4096^2 FP64 cells, 12 datasets with halo 2, a chain of 40
+weighted-sum loops each reading 2-4 datasets through 5-point or 9-point
+stencils (seeded, synthgen.chain_2d).
+
+Every execution mode runs the same chain; the JSON line reports the best
+tiled mode as `value` (cell-updates/s) next to the untiled run, the effective
+bandwidth under the per-loop byte model, a roofline entry for the dominant
+kernel (timed with HIP events inside the run) and the oracle timed on the
+host's cores on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes none,skewed,fused]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tiled vs untiled cell-updates/s & HBM GB/s; batched solves/s + p99 latency"
+HBM_PEAK_GBS = 8000.0
+MODE_NAMES = {"none": 0, "skewed": 1, "fused": 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1704_00693_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(src, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(mode_name: str):
+    """HBM traffic per launch of the dominant kernel from the committed rocprofv3
+    counter summary, or None if absent or taken on different kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+    except ValueError:
+        return None
+    ent = t.get(mode_name)
+    if not ent or ent.get("source_sha") != kernel_source_sha():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def time_mode(tc, ctx, runner, mode, tile, steps, warmup, cells_per_step):
+    import torch
+    ctx.tc_set_tiling(mode, tile)
+    for _ in range(warmup):
+        runner.record()
+        ctx.tc_flush()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        runner.record()
+        ctx.tc_flush()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ctx.tc_get_stats()
+    # one more flush with per-launch HIP-event timing (separate from the timed loop)
+    ctx.tc_set_profiling(True)
+    runner.record()
+    ctx.tc_flush()
+    prof = ctx.tc_get_stats()
+    ctx.tc_set_profiling(False)
+    ms = dt / steps * 1e3
+    res = {
+        "ms_per_step": ms,
+        "cell_updates_per_s": cells_per_step * steps / dt,
+        "effective_GBps": st["modelled_bytes"] * steps / dt / 1e9,
+        "launches_per_step": st["last_launches"],
+        "tiles": st["last_tiles"],
+        "groups": st["last_groups"],
+        "max_skew": st["max_skew"],
+        "plan_seconds": st["plan_seconds"],
+        "modelled_bytes": st["modelled_bytes"],
+        "kernel_seconds": prof["prof_kernel_seconds"],
+        "kernel_launches": prof["prof_launches"],
+    }
+    return res
+
+
+def cpu_baseline(ch_full, n_sample: int):
+    """The oracle (single-threaded C, FP64) on the same chain over an
+    n_sample^2 grid (a bounded sample of the workload)."""
+    import oracle
+    from synthgen import make_chain, chain_data
+    ch = make_chain(2, n_sample, ch_full.ndat, len(ch_full.loops), ch_full.seed)
+    data = chain_data(ch)
+    t0 = time.perf_counter()
+    oracle.run_chain(ch, data)
+    dt = time.perf_counter() - t0
+    return {"value": ch.cell_updates() / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"same 40-loop chain on a {n_sample}^2 grid ({ch.cell_updates()} cell-updates, {dt:.1f} s)",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--modes", default="none,skewed,fused")
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="grid edge of the oracle's timed sample (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1704_00693_amd as tc
+    from paper_1704_00693_amd.apps import ChainRunner
+    from synthgen import chain_2d, chain_data
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ch = chain_2d(n=args.n)
+    log(f"generating inputs: {ch.ndat} x {ch.n + 4}^2 FP64")
+    data = chain_data(ch)
+    cells = ch.cell_updates()
+    results = {}
+    with tc.Context(0) as ctx:
+        runner = ChainRunner(ctx, ch, data)
+        del data
+        torch.cuda.synchronize()
+        for name in args.modes.split(","):
+            mode = MODE_NAMES[name]
+            log(f"mode {name}: warmup {args.warmup}, steps {args.steps}")
+            try:
+                results[name] = time_mode(tc, ctx, runner, mode, (0, 0, 0), args.steps, args.warmup, cells)
+            except tc.TcError as e:
+                if e.status != tc.TC_ERR_UNSUPPORTED:
+                    raise
+                log(f"mode {name} unsupported: {e}")
+                continue
+            log(f"  {results[name]['ms_per_step']:.3f} ms/step, "
+                f"{results[name]['cell_updates_per_s'] / 1e9:.2f} Gcell/s, "
+                f"{results[name]['effective_GBps']:.0f} GB/s effective")
+    tiled = {k: v for k, v in results.items() if k != "none"}
+    best_name = max(tiled, key=lambda k: tiled[k]["cell_updates_per_s"]) if tiled else "none"
+    best = results[best_name]
+    # dominant kernel of the reported mode: the per-loop / fused kernel
+    avg = best["kernel_seconds"] / max(best["kernel_launches"], 1)
+    bytes_per_launch = best["modelled_bytes"] / max(best["kernel_launches"], 1)
+    achieved = bytes_per_launch / avg / 1e9 if avg > 0 else 0.0
+    traffic = load_traffic(best_name)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "fused_group_kernel" if best_name == "fused" else "loop_kernel<OpWsum<double>>",
+                "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch}
+    cpu = cpu_baseline(ch, args.cpu_sample) if args.cpu_sample > 0 else None
+    untiled = results.get("none")
+    line = {
+        "metric": METRIC,
+        "value": best["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": best["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D synthetic loop chain {ch.n}^2 FP64, 12 datasets (halo 2), 40 weighted-sum "
+                               f"loops with 5/9-point stencils, seed {ch.seed}",
+                   "tiling": best_name},
+        "effective_GBps": best["effective_GBps"],
+        "untiled": None if untiled is None else {
+            "cell_updates_per_s": untiled["cell_updates_per_s"], "ms_per_step": untiled["ms_per_step"],
+            "effective_GBps": untiled["effective_GBps"]},
+        "speedup_vs_untiled": None if untiled is None else best["cell_updates_per_s"] / untiled["cell_updates_per_s"],
+        "modes": results,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

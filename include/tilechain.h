@@ -1,0 +1,264 @@
+/*
+ * tilechain -- run-time tiling of chains of stencil loops on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * C ABI of the library.  It follows the problem statement of Reguly, Mudalige
+ * and Giles, "Loop Tiling in Large-Scale Stencil Codes at Run-time with OPS":
+ *
+ *   - Section 3: a computation is a sequence of parallel loops over an
+ *     iteration range of a block; each loop applies a point kernel and names
+ *     its datasets, each with a stencil and an access mode (read, write,
+ *     read-write, increment).  Point order within a loop is irrelevant.
+ *   - Section 4.1: loops are not executed when they are issued; they are
+ *     recorded, and the recorded chain runs when the user needs data back
+ *     (a reduction result, or a dataset).
+ *   - Section 4.2: at that point the chain is analysed and executed tile by
+ *     tile (skewed tiling, Algorithms 1 and 2); the plan is cached and reused
+ *     when the same sequence of loops recurs.
+ *   - Section 4.4: overlapped tiling (tiles recompute the points they need
+ *     from their neighbours and run concurrently, read dependencies only).
+ *
+ * Conventions
+ *   - Every call returns tc_status: TC_OK (0) or a negative error code.  No
+ *     call aborts or throws across the ABI.  tc_last_error() gives the text
+ *     of the last error of a context.
+ *   - After a device (HIP) failure the context is poisoned: every later call
+ *     on it returns TC_ERR_DEVICE until tc_finalize().
+ *   - Handles (blocks, datasets, stencils, reductions) are small integers
+ *     owned by their context; they stay valid until tc_finalize().
+ *   - Coordinates are logical: dataset point (x, y, z) with 0 <= x < size[0]
+ *     is an interior point, negative or >= size coordinates are halo points.
+ *     x is the fastest-varying dimension.  Ranges are half-open [lo, hi).
+ *   - A context is used from one host thread at a time.
+ */
+#ifndef TILECHAIN_H
+#define TILECHAIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tc_status;
+enum {
+    TC_OK = 0,
+    TC_ERR_ARG = -1,         /* invalid argument (bad handle, size, range, access) */
+    TC_ERR_STATE = -2,       /* call not allowed in this state (e.g. host-only context) */
+    TC_ERR_DEVICE = -3,      /* a HIP call failed; the context is poisoned */
+    TC_ERR_NOMEM = -4,       /* device or host allocation failed */
+    TC_ERR_UNSUPPORTED = -5, /* valid request the library does not implement */
+    TC_ERR_RANGE = -6        /* iteration range plus stencil leaves the allocated halo */
+};
+
+typedef struct tc_ctx tc_ctx;
+typedef int32_t tc_block;
+typedef int32_t tc_dat;
+typedef int32_t tc_stencil;
+typedef int32_t tc_red;
+
+typedef enum { TC_F64 = 0, TC_F32 = 1 } tc_dtype;
+typedef enum { TC_READ = 0, TC_WRITE = 1, TC_RW = 2, TC_INC = 3 } tc_access;
+typedef enum { TC_ARG_DAT = 0, TC_ARG_RED = 1 } tc_argkind;
+typedef enum { TC_RED_SUM = 0, TC_RED_MIN = 1, TC_RED_MAX = 2 } tc_redop;
+
+/* Tiling of a flushed chain.
+ *   NONE       : every loop runs over its whole range, one kernel per loop.
+ *   SKEWED     : Algorithm 1 plan; tiles run in order, each (tile, loop) is a
+ *                whole-GPU sweep of the tile's range (Algorithm 2).
+ *   FUSED      : overlapped tiles (Section 4.4 applied per workgroup); each
+ *                workgroup streams its tile through the chain with the
+ *                working set in LDS; one kernel per fusion group.
+ *   AUTO       : the autotuner measures the candidates once per chain
+ *                structure and keeps the fastest. */
+typedef enum { TC_TILING_NONE = 0, TC_TILING_SKEWED = 1, TC_TILING_FUSED = 2, TC_TILING_AUTO = 3 } tc_tiling;
+
+/* Point operations (closed vocabulary).  Argument lists are positional; the
+ * accesses and stencils given at tc_par_loop must match the signature.
+ * Arithmetic is FP64 for F64 datasets and FP32 for F32 datasets; reductions
+ * always accumulate in FP64 (double-double for sums).
+ *
+ *  TC_OP_WSUM        args: out(W), in_1..in_k(R, any stencil)   params: one weight per (input, stencil point)
+ *                    out = sum over inputs, stencil points (listed order) of w * in[x+q], as acc = fma(w, v, acc) from 0
+ *  TC_OP_COPY        args: out(W), in(R centre)                  out = in (also converts F64 <-> F32)
+ *  TC_OP_AXPBY       args: y(RW), x(R centre)          params a,b y = fma(a, x, b*y)
+ *  TC_OP_DOT         args: a(R), b(R), red(SUM)                  red += a*b
+ *  TC_OP_SUM         args: a(R), red(SUM)                        red += a
+ *  TC_OP_HALO_REFLECT args: v(RW, stencil covering the source offsets)  params axis, side, n
+ *                    ghost c (outside [0,n) along axis) takes v at -1-c (side 0) or 2n-1-c (side 1)
+ *  Heat conduction (2D/3D, K_d = face coefficient on the cell's low face along d):
+ *  TC_OP_TEA_INIT    args: rho(R), e(R), u0(W), u(W)             u0 = u = e*rho
+ *  TC_OP_TEA_K       args: rho(R: centre, -x, -y[, -z]), Kx(W), Ky(W)[, Kz(W)]   params r
+ *                    K_d = (2r) / (rho(c - e_d) + rho(c))
+ *  TC_OP_TEA_RESID   args: Kx, Ky[, Kz](R: centre, +e_d), x(R star), b(R), r(W)   r = b - A x
+ *  TC_OP_TEA_MATVEC_DOT args: K..(R), p(R star), w(W), red(SUM)  w = A p; red += p*w
+ *  TC_OP_TEA_P1      args: K..(R), sd(R star), rt(RW), z(RW)      rt = rt - A sd; z = z + sd
+ *  TC_OP_TEA_P2      args: sd(RW), rt(R)              params alpha, beta   sd = fma(alpha, sd, beta*rt)
+ *  TC_OP_TEA_PRECON_INIT args: r(R), rt(W), sd(W), z(W) params theta   rt = r; sd = r/theta; z = 0
+ *  TC_OP_TEA_CG_UPDATE args: x(RW), r(RW), p(R), w(R) params alpha   x = fma(alpha,p,x); r = fma(-alpha,w,r)
+ *  TC_OP_TEA_CG_P    args: p(RW), z(R)                params beta    p = fma(beta, p, z)
+ *  TC_OP_TEA_GERSH   args: K..(R: centre, +e_d), red(MAX)         red = max(red, fma(2, sum of face K, 1))
+ *  where (A v) = diag*v - K_E v_E - K_W v_W - K_N v_N - K_S v_S [- K_T v_T - K_B v_B],
+ *  diag = 1 + K_E + K_W + K_N + K_S [+ K_T + K_B] summed left to right, the
+ *  off-diagonal terms applied with fma in the order E, W, N, S[, T, B].
+ */
+typedef enum {
+    TC_OP_WSUM = 0,
+    TC_OP_COPY = 1,
+    TC_OP_AXPBY = 2,
+    TC_OP_DOT = 3,
+    TC_OP_SUM = 4,
+    TC_OP_HALO_REFLECT = 5,
+    TC_OP_TEA_INIT = 10,
+    TC_OP_TEA_K = 11,
+    TC_OP_TEA_RESID = 12,
+    TC_OP_TEA_MATVEC_DOT = 13,
+    TC_OP_TEA_P1 = 14,
+    TC_OP_TEA_P2 = 15,
+    TC_OP_TEA_PRECON_INIT = 16,
+    TC_OP_TEA_CG_UPDATE = 17,
+    TC_OP_TEA_CG_P = 18,
+    TC_OP_TEA_GERSH = 19
+} tc_op;
+
+/* One loop argument: a dataset through a stencil with an access mode, or a
+ * reduction handle (kind TC_ARG_RED; stencil and access are ignored). */
+typedef struct {
+    int32_t kind;    /* tc_argkind */
+    int32_t handle;  /* tc_dat or tc_red */
+    int32_t stencil; /* tc_stencil (datasets) */
+    int32_t access;  /* tc_access (datasets) */
+} tc_arg;
+
+/* Device memory callbacks.  alloc returns device memory of at least `bytes`
+ * bytes (256-byte aligned) or NULL; free releases it.  NULL callbacks mean
+ * hipMalloc / hipFree. */
+typedef void *(*tc_alloc_fn)(size_t bytes, void *user);
+typedef void (*tc_free_fn)(void *ptr, void *user);
+
+enum { TC_INIT_HOST_ONLY = 1 }; /* record and analyse only; no device, flush fails */
+
+typedef struct {
+    int32_t device;   /* HIP device ordinal */
+    int32_t flags;    /* TC_INIT_* */
+    void *stream;     /* hipStream_t to run on (borrowed); NULL = the library creates one */
+    tc_alloc_fn alloc;
+    tc_free_fn free;
+    void *alloc_user;
+} tc_init_opts;
+
+/* Create a context.  opts may be NULL (device 0, own stream, hipMalloc). */
+tc_status tc_init(const tc_init_opts *opts, tc_ctx **out);
+
+/* Flush the pending chain, release all device memory the library owns, free
+ * the context.  Safe on a poisoned context.  ctx may be NULL. */
+tc_status tc_finalize(tc_ctx *ctx);
+
+/* Declare a structured block of dimension 1..3 (Section 3: blocks). */
+tc_status tc_decl_block(tc_ctx *ctx, int ndim, const char *name, tc_block *out);
+
+/* Declare a dataset on a block (Section 3: datasets, Section 3: ownership of
+ * data is handed to the library).  size[d] interior points, halo_neg[d] /
+ * halo_pos[d] halo depths per side (0..16).  host_init: NULL (zero fill) or
+ * the initial values of the whole padded array INCLUDING halos, packed with x
+ * fastest: dims (size[d] + halo_neg[d] + halo_pos[d]).  The buffer is copied
+ * before the call returns and is not retained.  Device storage is allocated
+ * here (plus, lazily, a second buffer used by fused execution). */
+tc_status tc_decl_dat(tc_ctx *ctx, tc_block blk, tc_dtype dtype, const int32_t *size,
+                      const int32_t *halo_neg, const int32_t *halo_pos, const void *host_init,
+                      const char *name, tc_dat *out);
+
+/* Declare a stencil: npoints offsets of ndim ints each (x first). */
+tc_status tc_decl_stencil(tc_ctx *ctx, int ndim, int npoints, const int32_t *offsets,
+                          const char *name, tc_stencil *out);
+
+/* Declare a global reduction (Section 4.1: fetching its result flushes). */
+tc_status tc_decl_reduction(tc_ctx *ctx, tc_redop op, const char *name, tc_red *out);
+
+/* Record a parallel loop (Section 3; delayed, Section 4.1).  range has 2*ndim
+ * ints: lo[0], hi[0], lo[1], hi[1], ...  The call validates, deep-copies the
+ * arguments and parameters and returns; nothing runs.  On error the chain is
+ * unchanged.  Rejected: block or dimension mismatch; range plus stencil
+ * outside a dataset's allocated halo (TC_ERR_RANGE); a write with a stencil
+ * other than the centre; a dataset read at an offset and written in the same
+ * loop (except TC_OP_HALO_REFLECT, whose reads and writes are disjoint);
+ * arguments or parameter count not matching the op's signature. */
+tc_status tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_block blk, const int32_t *range,
+                      const tc_arg *args, int nargs, const double *params, int nparams);
+
+/* Flush the chain (Section 4.1), then return the reduction's value (as
+ * double) and reset it to its identity.  A reduction accumulates over every
+ * loop that used it since its previous fetch. */
+tc_status tc_reduction_result(tc_ctx *ctx, tc_red red, double *out);
+
+/* Execute the pending chain now. */
+tc_status tc_flush(tc_ctx *ctx);
+
+/* Flush, then copy a dataset to / from host memory.  The host layout is the
+ * padded array with halos, packed, x fastest (as in tc_decl_dat). */
+tc_status tc_dat_read(tc_ctx *ctx, tc_dat dat, void *host);
+tc_status tc_dat_write(tc_ctx *ctx, tc_dat dat, const void *host);
+
+/* Flush, then return the device address of logical point (0,0,0) of the
+ * dataset's current buffer and its element strides (x stride is 1).  Valid
+ * until the next flush. */
+tc_status tc_dat_device_view(tc_ctx *ctx, tc_dat dat, void **origin, int64_t strides[3]);
+
+/* Choose how the following flushes are tiled (Section 4.3: manual tile sizes
+ * or automatic choice).  tile[d] <= 0 means "choose automatically" for that
+ * dimension (skewed: the whole extent along x, a cache-sized height along the
+ * slowest dimension).  For TC_TILING_FUSED, tile[0] is the workgroup's owned
+ * width in x, tile[1] the streamed height, tile[2] the LDS budget in KiB. */
+tc_status tc_set_tiling(tc_ctx *ctx, tc_tiling mode, const int32_t *tile);
+
+typedef struct {
+    int64_t loops_recorded;
+    int64_t flushes;
+    int64_t plan_hits;
+    int64_t plan_misses;
+    double plan_seconds;        /* total host time spent building plans */
+    int32_t max_skew[3];        /* largest tile-boundary skew of the last plan (Section 6 skew report) */
+    int32_t last_tiles;         /* tiles (skewed) or workgroups (fused) of the last flush */
+    int32_t last_groups;        /* fusion groups of the last flush */
+    int32_t last_launches;      /* kernel launches of the last flush */
+    int32_t last_mode;          /* tc_tiling actually used by the last flush */
+    int64_t modelled_bytes;     /* bytes of the last flush under the per-loop model:
+                                   range points x element size x (1 for R or W, 2 for RW/INC) */
+    int64_t cell_updates;       /* sum of loop range sizes of the last flush */
+    double last_flush_seconds;  /* host wall time of the last flush, including the final sync */
+    /* kernel timing of the last flush (only with tc_set_profiling on): sum of
+       the device durations of its kernels, measured with HIP events recorded
+       on the library's stream around every launch, and the number of launches
+       timed; the main kernels only (reduction finalisation excluded) */
+    double prof_kernel_seconds;
+    int64_t prof_launches;
+} tc_stats;
+
+tc_status tc_get_stats(tc_ctx *ctx, tc_stats *out);
+
+/* Turn per-launch kernel timing on (1) or off (0).  Timing records two HIP
+ * events around every kernel launch and synchronises at the end of each
+ * flush, so it is for measurement runs, not production. */
+tc_status tc_set_profiling(tc_ctx *ctx, int on);
+
+/* Analyse the pending chain without running it (works on host-only
+ * contexts).  Skewed mode: writes num_tiles[3] and, into ranges, for every
+ * tile index t_d of every dimension d and every loop l, the pair (start, end):
+ * ranges[((d * max_tiles + t_d) * nloops + l) * 2 + {0,1}] with max_tiles the
+ * largest num_tiles[d]; cap is the number of int32 slots available.  Returns
+ * TC_ERR_ARG if cap is too small (num_tiles is still written). */
+tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_t *num_tiles,
+                        int32_t *ranges, int64_t cap);
+
+/* Number of loops currently recorded and not yet executed. */
+tc_status tc_pending(tc_ctx *ctx, int32_t *nloops);
+
+const char *tc_status_string(tc_status s);
+const char *tc_last_error(tc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TILECHAIN_H */

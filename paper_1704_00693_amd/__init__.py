@@ -1,0 +1,311 @@
+"""Python binding of the tilechain C ABI (``include/tilechain.h``).
+
+Argument marshalling only: every loop runs in the HIP kernels of
+``libtilechain.so``.  The functions keep the C names (``tc_init``,
+``tc_par_loop``, ...).  Device memory comes from PyTorch's caching allocator
+through the allocator callbacks of ``tc_init`` and work runs on PyTorch's
+current HIP stream, so the library interleaves with torch work.
+
+The shared library must have been built (``python -m paper_1704_00693_amd.build``
+or ``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtilechain.so")
+
+# ---- enums (mirror include/tilechain.h) -----------------------------------
+TC_OK, TC_ERR_ARG, TC_ERR_STATE, TC_ERR_DEVICE, TC_ERR_NOMEM, TC_ERR_UNSUPPORTED, TC_ERR_RANGE = 0, -1, -2, -3, -4, -5, -6
+TC_F64, TC_F32 = 0, 1
+TC_READ, TC_WRITE, TC_RW, TC_INC = 0, 1, 2, 3
+TC_ARG_DAT, TC_ARG_RED = 0, 1
+TC_RED_SUM, TC_RED_MIN, TC_RED_MAX = 0, 1, 2
+TC_TILING_NONE, TC_TILING_SKEWED, TC_TILING_FUSED, TC_TILING_AUTO = 0, 1, 2, 3
+TC_INIT_HOST_ONLY = 1
+OPS = {
+    "WSUM": 0, "COPY": 1, "AXPBY": 2, "DOT": 3, "SUM": 4, "HALO_REFLECT": 5,
+    "TEA_INIT": 10, "TEA_K": 11, "TEA_RESID": 12, "TEA_MATVEC_DOT": 13, "TEA_P1": 14, "TEA_P2": 15,
+    "TEA_PRECON_INIT": 16, "TEA_CG_UPDATE": 17, "TEA_CG_P": 18, "TEA_GERSH": 19,
+}
+ACCESS = {"R": TC_READ, "W": TC_WRITE, "RW": TC_RW, "INC": TC_INC}
+EXPORTS = ["tc_init", "tc_finalize", "tc_decl_block", "tc_decl_dat", "tc_decl_stencil", "tc_decl_reduction",
+           "tc_par_loop", "tc_reduction_result", "tc_flush", "tc_dat_read", "tc_dat_write", "tc_dat_device_view",
+           "tc_set_tiling", "tc_set_profiling", "tc_get_stats", "tc_chain_plan", "tc_pending", "tc_status_string", "tc_last_error"]
+
+
+class TcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class InitOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("flags", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", ctypes.c_void_p)]
+
+
+class Arg(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("handle", ctypes.c_int32), ("stencil", ctypes.c_int32),
+                ("access", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("loops_recorded", ctypes.c_int64), ("flushes", ctypes.c_int64), ("plan_hits", ctypes.c_int64),
+                ("plan_misses", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
+                ("max_skew", ctypes.c_int32 * 3), ("last_tiles", ctypes.c_int32), ("last_groups", ctypes.c_int32),
+                ("last_launches", ctypes.c_int32), ("last_mode", ctypes.c_int32),
+                ("modelled_bytes", ctypes.c_int64), ("cell_updates", ctypes.c_int64),
+                ("last_flush_seconds", ctypes.c_double), ("prof_kernel_seconds", ctypes.c_double),
+                ("prof_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if name == "max_skew" else v
+        return out
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libtilechain.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1704_00693_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "tc_init": [ctypes.POINTER(InitOpts), ctypes.POINTER(P)],
+        "tc_finalize": [P],
+        "tc_decl_block": [P, ctypes.c_int, ctypes.c_char_p, i32p],
+        "tc_decl_dat": [P, i32, i32, i32p, i32p, i32p, P, ctypes.c_char_p, i32p],
+        "tc_decl_stencil": [P, ctypes.c_int, ctypes.c_int, i32p, ctypes.c_char_p, i32p],
+        "tc_decl_reduction": [P, i32, ctypes.c_char_p, i32p],
+        "tc_par_loop": [P, ctypes.c_char_p, i32, i32, i32p, ctypes.POINTER(Arg), ctypes.c_int,
+                        ctypes.POINTER(ctypes.c_double), ctypes.c_int],
+        "tc_reduction_result": [P, i32, ctypes.POINTER(ctypes.c_double)],
+        "tc_flush": [P],
+        "tc_dat_read": [P, i32, P],
+        "tc_dat_write": [P, i32, P],
+        "tc_dat_device_view": [P, i32, ctypes.POINTER(P), ctypes.POINTER(i64)],
+        "tc_set_tiling": [P, i32, i32p],
+        "tc_get_stats": [P, ctypes.POINTER(Stats)],
+        "tc_set_profiling": [P, ctypes.c_int],
+        "tc_chain_plan": [P, i32, i32p, i32p, i32p, i64],
+        "tc_pending": [P, i32p],
+        "tc_status_string": [i32],
+        "tc_last_error": [P],
+    }
+    for name, argtypes in sig.items():
+        f = getattr(L, name)
+        f.argtypes = argtypes
+        f.restype = ctypes.c_char_p if name in ("tc_status_string", "tc_last_error") else ctypes.c_int32
+    _lib = L
+    return L
+
+
+def _i32(vals):
+    vals = [int(v) for v in vals]
+    return (ctypes.c_int32 * max(len(vals), 1))(*vals)
+
+
+class Context:
+    """One tilechain context (``tc_ctx*``) plus the Python objects that must
+    outlive it (allocator callbacks and the tensors they handed out)."""
+
+    def __init__(self, device: int = 0, host_only: bool = False, torch_memory: bool = True,
+                 stream: Optional[int] = None):
+        L = lib()
+        self._tensors: Dict[int, object] = {}
+        opts = InitOpts()
+        opts.device = device
+        opts.flags = TC_INIT_HOST_ONLY if host_only else 0
+        self._alloc_cb = ALLOC_FN(0)
+        self._free_cb = FREE_FN(0)
+        if not host_only:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("tilechain needs a HIP device (torch.cuda.is_available() is False)")
+            torch.cuda.set_device(device)
+            if stream is None:
+                stream = torch.cuda.current_stream(device).cuda_stream
+            opts.stream = stream
+            if torch_memory:
+                dev = torch.device("cuda", device)
+
+                def _alloc(nbytes, _user):
+                    try:
+                        t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+                    except RuntimeError:
+                        return None
+                    p = t.data_ptr()
+                    self._tensors[p] = t
+                    return p
+
+                def _free(ptr, _user):
+                    self._tensors.pop(ptr, None)
+
+                self._alloc_cb = ALLOC_FN(_alloc)
+                self._free_cb = FREE_FN(_free)
+                opts.alloc = self._alloc_cb
+                opts.free = self._free_cb
+        self.ptr = ctypes.c_void_p()
+        st = L.tc_init(ctypes.byref(opts), ctypes.byref(self.ptr))
+        if st != TC_OK:
+            raise TcError(st, "tc_init failed")
+        self.host_only = host_only
+        self.dat_shapes: Dict[int, tuple] = {}
+        self.dat_dtypes: Dict[int, int] = {}
+
+    # error helper
+    def _ck(self, st: int, what: str):
+        if st != TC_OK:
+            msg = lib().tc_last_error(self.ptr).decode()
+            raise TcError(st, f"{what}: {msg}")
+
+    def close(self):
+        if self.ptr:
+            st = lib().tc_finalize(self.ptr)
+            self.ptr = ctypes.c_void_p()
+            self._tensors.clear()
+            if st != TC_OK:
+                raise TcError(st, "tc_finalize failed")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- declarations ----------------------------------------------------
+    def tc_decl_block(self, ndim: int, name: str = "") -> int:
+        out = ctypes.c_int32()
+        self._ck(lib().tc_decl_block(self.ptr, ndim, name.encode(), ctypes.byref(out)), "tc_decl_block")
+        return out.value
+
+    def tc_decl_dat(self, blk: int, size: Sequence[int], halo_neg: Sequence[int], halo_pos: Sequence[int],
+                    init: Optional[np.ndarray] = None, dtype: int = TC_F64, name: str = "") -> int:
+        out = ctypes.c_int32()
+        ptr = None
+        keep = None
+        npdt = np.float64 if dtype == TC_F64 else np.float32
+        shape = tuple(int(s) + int(a) + int(b) for s, a, b in zip(size, halo_neg, halo_pos))[::-1]
+        if init is not None:
+            keep = np.ascontiguousarray(init, dtype=npdt)
+            if keep.shape != shape:
+                raise ValueError(f"init has shape {keep.shape}, expected padded shape {shape}")
+            ptr = keep.ctypes.data
+        self._ck(lib().tc_decl_dat(self.ptr, blk, dtype, _i32(size), _i32(halo_neg), _i32(halo_pos), ptr,
+                                   name.encode(), ctypes.byref(out)), "tc_decl_dat")
+        self.dat_shapes[out.value] = shape
+        self.dat_dtypes[out.value] = dtype
+        return out.value
+
+    def tc_decl_stencil(self, points: Sequence[Sequence[int]], name: str = "") -> int:
+        pts = [tuple(p) for p in points]
+        ndim = len(pts[0])
+        flat = [c for p in pts for c in p]
+        out = ctypes.c_int32()
+        self._ck(lib().tc_decl_stencil(self.ptr, ndim, len(pts), _i32(flat), name.encode(), ctypes.byref(out)),
+                 "tc_decl_stencil")
+        return out.value
+
+    def tc_decl_reduction(self, op: int = TC_RED_SUM, name: str = "") -> int:
+        out = ctypes.c_int32()
+        self._ck(lib().tc_decl_reduction(self.ptr, op, name.encode(), ctypes.byref(out)), "tc_decl_reduction")
+        return out.value
+
+    # ---- loops -------------------------------------------------------------
+    def tc_par_loop(self, op, blk: int, rng: Sequence[int], args, params: Sequence[float] = (), name: str = ""):
+        """args: tuples (dat, stencil, access) for datasets, ("red", handle)
+        for reductions; access as "R"/"W"/"RW"/"INC" or the TC_ constant."""
+        opc = OPS[op] if isinstance(op, str) else int(op)
+        arr = (Arg * max(len(args), 1))()
+        for i, a in enumerate(args):
+            if a[0] == "red":
+                arr[i] = Arg(TC_ARG_RED, int(a[1]), 0, 0)
+            else:
+                acc = ACCESS[a[2]] if isinstance(a[2], str) else int(a[2])
+                arr[i] = Arg(TC_ARG_DAT, int(a[0]), int(a[1]), acc)
+        prm = (ctypes.c_double * max(len(params), 1))(*[float(p) for p in params])
+        self._ck(lib().tc_par_loop(self.ptr, name.encode(), opc, blk, _i32(rng), arr, len(args), prm, len(params)),
+                 f"tc_par_loop({name})")
+
+    def tc_flush(self):
+        self._ck(lib().tc_flush(self.ptr), "tc_flush")
+
+    def tc_reduction_result(self, red: int) -> float:
+        out = ctypes.c_double()
+        self._ck(lib().tc_reduction_result(self.ptr, red, ctypes.byref(out)), "tc_reduction_result")
+        return out.value
+
+    def tc_dat_read(self, dat: int) -> np.ndarray:
+        npdt = np.float64 if self.dat_dtypes[dat] == TC_F64 else np.float32
+        out = np.empty(self.dat_shapes[dat], dtype=npdt)
+        self._ck(lib().tc_dat_read(self.ptr, dat, out.ctypes.data), "tc_dat_read")
+        return out
+
+    def tc_dat_write(self, dat: int, values: np.ndarray):
+        npdt = np.float64 if self.dat_dtypes[dat] == TC_F64 else np.float32
+        a = np.ascontiguousarray(values, dtype=npdt)
+        if a.shape != self.dat_shapes[dat]:
+            raise ValueError("shape mismatch")
+        self._ck(lib().tc_dat_write(self.ptr, dat, a.ctypes.data), "tc_dat_write")
+
+    def tc_dat_device_view(self, dat: int):
+        p = ctypes.c_void_p()
+        st = (ctypes.c_int64 * 3)()
+        self._ck(lib().tc_dat_device_view(self.ptr, dat, ctypes.byref(p), st), "tc_dat_device_view")
+        return p.value, list(st)
+
+    def tc_set_tiling(self, mode: int, tile: Sequence[int] = (0, 0, 0)):
+        t = list(tile) + [0] * (3 - len(tile))
+        self._ck(lib().tc_set_tiling(self.ptr, mode, _i32(t)), "tc_set_tiling")
+
+    def tc_set_profiling(self, on: bool):
+        self._ck(lib().tc_set_profiling(self.ptr, 1 if on else 0), "tc_set_profiling")
+
+    def tc_get_stats(self) -> dict:
+        s = Stats()
+        self._ck(lib().tc_get_stats(self.ptr, ctypes.byref(s)), "tc_get_stats")
+        return s.as_dict()
+
+    def tc_pending(self) -> int:
+        n = ctypes.c_int32()
+        self._ck(lib().tc_pending(self.ptr, ctypes.byref(n)), "tc_pending")
+        return n.value
+
+    def tc_chain_plan(self, tile: Sequence[int], nloops: int, ndim: int):
+        """Skewed plan of the pending chain: (num_tiles, start[d][t][l], end[d][t][l])."""
+        t = list(tile) + [0] * (3 - len(tile))
+        nt = (ctypes.c_int32 * 3)()
+        st = lib().tc_chain_plan(self.ptr, TC_TILING_SKEWED, _i32(t), nt, None, 0)
+        maxt = max(nt)
+        cap = ndim * maxt * nloops * 2
+        buf = (ctypes.c_int32 * max(cap, 1))()
+        self._ck(lib().tc_chain_plan(self.ptr, TC_TILING_SKEWED, _i32(t), nt, buf, cap), "tc_chain_plan")
+        a = np.frombuffer(buf, dtype=np.int32, count=cap).reshape(ndim, maxt, nloops, 2)
+        num = list(nt)[:ndim]
+        start = [[list(a[d, tt, :, 0]) for tt in range(num[d])] for d in range(ndim)]
+        end = [[list(a[d, tt, :, 1]) for tt in range(num[d])] for d in range(ndim)]
+        return num, start, end
+
+
+def tc_status_string(status: int) -> str:
+    return lib().tc_status_string(status).decode()

@@ -1,0 +1,234 @@
+"""Workload drivers written against the tilechain ABI (user code of the library,
+as the paper's applications are user code of OPS): the synthetic
+weighted-sum chains and the heat-conduction PPCG solve.
+
+Nothing here computes on the host beyond the scalar recurrences of the solver
+(CG's alpha and beta, the Chebyshev coefficients); every loop is recorded with
+``tc_par_loop`` and runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import (TC_F32, TC_F64, TC_RED_MAX, TC_RED_SUM, Context)
+
+
+# ---------------------------------------------------------------------------
+# synthetic weighted-sum chains
+# ---------------------------------------------------------------------------
+class ChainRunner:
+    """Declares a chain's datasets and stencils once; ``record()`` enqueues
+    its loops (and the final sum reduction if the chain has one)."""
+
+    def __init__(self, ctx: Context, chain, data: Optional[Sequence[np.ndarray]] = None, dtype: int = TC_F64):
+        self.ctx, self.chain = ctx, chain
+        nd, n, h = chain.ndim, chain.n, chain.halo
+        self.blk = ctx.tc_decl_block(nd, "chain")
+        self.dats = []
+        for d in range(chain.ndat):
+            init = None if data is None else data[d]
+            self.dats.append(ctx.tc_decl_dat(self.blk, [n] * nd, [h] * nd, [h] * nd, init, dtype, f"d{d}"))
+        self.stencils: Dict[Tuple, int] = {}
+        self.centre = self.stencil([tuple([0] * nd)])
+        self.red = ctx.tc_decl_reduction(TC_RED_SUM, "sum") if chain.reduce_last else None
+        self.range = [v for _ in range(nd) for v in (0, n)]
+
+    def stencil(self, pts) -> int:
+        key = tuple(tuple(p) for p in pts)
+        if key not in self.stencils:
+            self.stencils[key] = self.ctx.tc_decl_stencil(list(key))
+        return self.stencils[key]
+
+    def record(self):
+        for i, lp in enumerate(self.chain.loops):
+            args = [(self.dats[lp.out], self.centre, "W")]
+            args += [(self.dats[ci.dat], self.stencil(ci.stencil), "R") for ci in lp.inputs]
+            self.ctx.tc_par_loop("WSUM", self.blk, self.range, args, lp.weights, name=f"loop{i}")
+        if self.red is not None:
+            self.ctx.tc_par_loop("SUM", self.blk, self.range,
+                                 [(self.dats[self.chain.last_written()], self.centre, "R"), ("red", self.red)],
+                                 name="sum")
+
+    def run(self) -> Optional[float]:
+        """Record the chain and execute it (the reduction fetch flushes)."""
+        self.record()
+        if self.red is not None:
+            return self.ctx.tc_reduction_result(self.red)
+        self.ctx.tc_flush()
+        return None
+
+    def read(self, d: int) -> np.ndarray:
+        return self.ctx.tc_dat_read(self.dats[d])
+
+
+# ---------------------------------------------------------------------------
+# heat conduction, PPCG
+# ---------------------------------------------------------------------------
+def chebyshev_coefs(lmin: float, lmax: float, steps: int):
+    """Chebyshev iteration scalars for the spectrum [lmin, lmax]:
+    theta, delta, and (alpha_j, beta_j) for j = 1..steps-1 with rho_0 =
+    1/sigma, rho_j = 1/(2 sigma - rho_{j-1}), alpha_j = rho_j rho_{j-1},
+    beta_j = 2 rho_j / delta."""
+    theta = (lmax + lmin) / 2.0
+    delta = (lmax - lmin) / 2.0
+    sigma = theta / delta
+    r_old = 1.0 / sigma
+    al, be = [], []
+    for _ in range(1, steps):
+        r_new = 1.0 / (2.0 * sigma - r_old)
+        al.append(r_new * r_old)
+        be.append(2.0 * r_new / delta)
+        r_old = r_new
+    return theta, delta, al, be
+
+
+class HeatSolver:
+    """Implicit heat-conduction step solved with PPCG (CG preconditioned by a
+    fixed number of Chebyshev steps), every loop through the tilechain ABI.
+
+    The per-iteration chain between two reduction fetches is what the
+    library tiles: chain A = p update, ghost fill of p, w = A p with p.w;
+    chain B = x, r update, preconditioner (ghost fill of sd, P1, P2 per
+    inner step), r.z and r.r."""
+
+    FIELDS = ("rho", "e", "u0", "u", "kx", "ky", "kz", "r", "p", "w", "z", "rt", "sd")
+
+    def __init__(self, ctx: Context, density: np.ndarray, energy: np.ndarray, dt: float = 0.004, halo: int = 2,
+                 dtype: int = TC_F64):
+        self.ctx = ctx
+        self.D = density.ndim
+        self.n = n = density.shape[0]
+        self.h = halo
+        self.rx = dt * n * n
+        D = self.D
+        self.blk = ctx.tc_decl_block(D, "heat")
+        shape = tuple([n + 2 * halo] * D)
+        inner = tuple([slice(halo, halo + n)] * D)
+        self.f: Dict[str, int] = {}
+        names = [k for k in self.FIELDS if not (k == "kz" and D < 3)]
+        for k in names:
+            init = None
+            if k in ("rho", "e"):
+                init = np.zeros(shape)
+                init[inner] = density if k == "rho" else energy
+            self.f[k] = ctx.tc_decl_dat(self.blk, [n] * D, [halo] * D, [halo] * D, init, dtype, k)
+        z = [0] * D
+
+        def unit(d, s):
+            p = [0] * D
+            p[d] = s
+            return tuple(p)
+
+        self.S_c = ctx.tc_decl_stencil([tuple(z)])
+        self.S_star = ctx.tc_decl_stencil([tuple(z)] + [unit(d, s) for d in range(D) for s in (-1, 1)])
+        self.S_kface = [ctx.tc_decl_stencil([tuple(z), unit(d, 1)]) for d in range(D)]
+        self.S_rho = ctx.tc_decl_stencil([tuple(z)] + [unit(d, -1) for d in range(D)])
+        self.S_reflect = {}
+        for axis in range(D):
+            for side in (0, 1):
+                sgn = 1 if side == 0 else -1
+                self.S_reflect[(axis, side)] = ctx.tc_decl_stencil(
+                    [tuple(z), unit(axis, sgn * 1), unit(axis, sgn * 3)])
+        self.r_sum = [ctx.tc_decl_reduction(TC_RED_SUM, f"s{i}") for i in range(3)]
+        self.r_max = ctx.tc_decl_reduction(TC_RED_MAX, "lmax")
+        self.interior = [v for _ in range(D) for v in (0, n)]
+
+    # -- loop helpers --------------------------------------------------------
+    def K(self):
+        return [(self.f[k], self.S_kface[d], "R") for d, k in enumerate(["kx", "ky", "kz"][: self.D])]
+
+    def halo_fill(self, name: str):
+        n, h, D = self.n, self.h, self.D
+        for axis in range(D):
+            for side in (0, 1):
+                rng = []
+                for d in range(D):
+                    if d == axis:
+                        rng += [-h, 0] if side == 0 else [n, n + h]
+                    elif d < axis:
+                        rng += [-h, n + h]
+                    else:
+                        rng += [0, n]
+                self.ctx.tc_par_loop("HALO_REFLECT", self.blk, rng,
+                                     [(self.f[name], self.S_reflect[(axis, side)], "RW")], [axis, side, n],
+                                     name=f"halo_{name}_{axis}{side}")
+
+    def loop(self, op, args, params=(), rng=None, name=""):
+        self.ctx.tc_par_loop(op, self.blk, rng or self.interior, args, params, name=name or op)
+
+    def F(self, k, acc, st=None):
+        return (self.f[k], self.S_c if st is None else st, acc)
+
+    # -- solver ---------------------------------------------------------------
+    def setup(self) -> float:
+        D = self.D
+        self.halo_fill("rho")
+        self.loop("TEA_INIT", [self.F("rho", "R"), self.F("e", "R"), self.F("u0", "W"), self.F("u", "W")])
+        kout = [self.F(k, "W") for k in ["kx", "ky", "kz"][:D]]
+        self.loop("TEA_K", [self.F("rho", "R", self.S_rho)] + kout, [self.rx],
+                  rng=[v for _ in range(D) for v in (0, self.n + 1)])
+        self.loop("TEA_GERSH", self.K() + [("red", self.r_max)])
+        return self.ctx.tc_reduction_result(self.r_max)
+
+    def dot(self, a, b, red):
+        self.loop("DOT", [self.F(a, "R"), self.F(b, "R"), ("red", red)], name=f"dot_{a}{b}")
+
+    def precondition(self, theta, al, be, steps):
+        self.loop("TEA_PRECON_INIT", [self.F("r", "R"), self.F("rt", "W"), self.F("sd", "W"), self.F("z", "W")],
+                  [theta])
+        for j in range(1, steps + 1):
+            self.halo_fill("sd")
+            self.loop("TEA_P1", self.K() + [self.F("sd", "R", self.S_star), self.F("rt", "RW"), self.F("z", "RW")])
+            if j < steps:
+                self.loop("TEA_P2", [self.F("sd", "RW"), self.F("rt", "R")], [al[j - 1], be[j - 1]])
+
+    def solve(self, outer: int = 50, inner: int = 10, tol: Optional[float] = None, max_iter: int = 10000):
+        """Same sequence of loops and reductions as the FP64 reference PPCG:
+        exactly ``outer`` iterations when tol is None, else stop at
+        sqrt(r.r) <= tol ||b||.  Returns a dict of scalars and histories."""
+        ctx = self.ctx
+        lmax = self.setup()
+        theta, delta, al, be = chebyshev_coefs(1.0, lmax, inner)
+        s0, s1, s2 = self.r_sum
+        self.dot("u0", "u0", s0)
+        bnorm = math.sqrt(ctx.tc_reduction_result(s0))
+        self.halo_fill("u")
+        self.loop("TEA_RESID", self.K() + [self.F("u", "R", self.S_star), self.F("u0", "R"), self.F("r", "W")])
+        self.precondition(theta, al, be, inner)
+        self.loop("COPY", [self.F("p", "W"), self.F("z", "R")])
+        self.dot("r", "z", s0)
+        rz = ctx.tc_reduction_result(s0)
+        hist = {"rr": [], "rz": [], "pw": []}
+        it = 0
+        limit = outer if tol is None else max_iter
+        while it < limit:
+            self.halo_fill("p")
+            self.loop("TEA_MATVEC_DOT", self.K() + [self.F("p", "R", self.S_star), self.F("w", "W"), ("red", s0)])
+            pw = ctx.tc_reduction_result(s0)
+            alpha = rz / pw
+            self.loop("TEA_CG_UPDATE", [self.F("u", "RW"), self.F("r", "RW"), self.F("p", "R"), self.F("w", "R")],
+                      [alpha])
+            self.precondition(theta, al, be, inner)
+            self.dot("r", "z", s1)
+            self.dot("r", "r", s2)
+            rz_new = ctx.tc_reduction_result(s1)
+            rr = ctx.tc_reduction_result(s2)
+            it += 1
+            hist["rr"].append(rr)
+            hist["rz"].append(rz_new)
+            hist["pw"].append(pw)
+            if tol is not None and math.sqrt(rr) <= tol * bnorm:
+                break
+            beta = rz_new / rz
+            rz = rz_new
+            self.loop("TEA_CG_P", [self.F("p", "RW"), self.F("z", "R")], [beta])
+        ctx.tc_flush()
+        return {"iterations": it, "lmax": lmax, "bnorm": bnorm, **hist}
+
+    def field(self, name: str) -> np.ndarray:
+        a = self.ctx.tc_dat_read(self.f[name])
+        h, n = self.h, self.n
+        return a[tuple([slice(h, h + n)] * self.D)]

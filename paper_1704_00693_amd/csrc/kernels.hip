@@ -1,0 +1,463 @@
+// Per-loop HIP kernels for gfx950: one launch runs one loop over one box of
+// its iteration range (the whole range when untiled, a tile's range in the
+// skewed schedule of Algorithm 2).  Each op is a small device functor; the
+// kernel maps workgroups to boxes of 64 x 4 points (x fastest, one FP64 row
+// segment of 512 bytes per wavefront) and orders the workgroup index so that
+// each of the 8 XCDs gets one contiguous band of rows (vertical stencil
+// neighbours then hit in that XCD's own L2).
+//
+// Reductions accumulate in FP64 as double-double (error-free transforms:
+// TwoSum, and fma for the exact product), per thread, then across the
+// workgroup, and each workgroup writes one (hi, lo) partial.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace tc {
+
+// ---------------------------------------------------------------------------
+// double-double helpers
+// ---------------------------------------------------------------------------
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ void dd_add(DD &a, double v) {
+    double s = a.hi + v;
+    double bb = s - a.hi;
+    double e = (a.hi - (s - bb)) + (v - bb);
+    a.hi = s;
+    a.lo += e;
+}
+
+__device__ __forceinline__ void dd_add_prod(DD &a, double x, double y) {
+    double p = x * y;
+    double pe = __builtin_fma(x, y, -p);
+    dd_add(a, p);
+    a.lo += pe;
+}
+
+__device__ __forceinline__ DD dd_merge(DD a, DD b) {
+    double s = a.hi + b.hi;
+    double bb = s - a.hi;
+    double e = (a.hi - (s - bb)) + (b.hi - bb);
+    DD r;
+    r.hi = s;
+    r.lo = (a.lo + b.lo) + e;
+    return r;
+}
+
+__device__ __forceinline__ DD red_combine(int op, DD a, DD b) {
+    if (op == TC_RED_SUM) return dd_merge(a, b);
+    DD r;
+    r.lo = 0.0;
+    if (op == TC_RED_MIN)
+        r.hi = fmin(a.hi, b.hi);
+    else
+        r.hi = fmax(a.hi, b.hi);
+    return r;
+}
+
+__device__ __forceinline__ DD red_identity(int op) {
+    DD r;
+    r.lo = 0.0;
+    r.hi = op == TC_RED_SUM ? 0.0 : (op == TC_RED_MIN ? __builtin_inf() : -__builtin_inf());
+    return r;
+}
+
+// Workgroup-wide combine of one DD value per thread; thread 0 gets the result.
+__device__ DD block_reduce(int op, DD v) {
+    __shared__ double sh_hi[kBlockThreads / 64], sh_lo[kBlockThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        DD w;
+        w.hi = __shfl_xor(v.hi, o);
+        w.lo = __shfl_xor(v.lo, o);
+        v = red_combine(op, v, w);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh_hi[wv] = v.hi;
+        sh_lo[wv] = v.lo;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DD a;
+        a.hi = sh_hi[0];
+        a.lo = sh_lo[0];
+        for (int i = 1; i < kBlockThreads / 64; ++i) {
+            DD b;
+            b.hi = sh_hi[i];
+            b.lo = sh_lo[i];
+            a = red_combine(op, a, b);
+        }
+        v = a;
+    }
+    __syncthreads();
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// point operations
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T *P(const LoopDesc &d, int a) {
+    return (T *)d.arg[a].ptr;
+}
+
+__device__ __forceinline__ int64_t IX(const LoopDesc &d, int a, int x, int y, int z) {
+    return (int64_t)x + (int64_t)y * d.arg[a].sy + (int64_t)z * d.arg[a].sz;
+}
+
+template <typename T>
+__device__ __forceinline__ T fmaT(T a, T b, T c) {
+    return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fmaT<float>(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+}
+
+// Weighted sum: acc = fma(w, in[x+q], acc) over inputs and stencil points in
+// order.  Common stencil sizes are unrolled so the loads issue together; the
+// fma chain keeps its order.
+template <typename T, int NP>
+__device__ __forceinline__ T wsum_input(const LoopDesc &d, const T *p, int q0, T acc) {
+    T v[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) v[k] = p[d.off[q0 + k]];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc = fmaT<T>((T)d.prm[q0 + k], v[k], acc);
+    return acc;
+}
+
+template <typename T>
+struct OpWsum {
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        T acc = (T)0;
+        for (int a = 1; a < d.nargs; ++a) {
+            const T *p = P<T>(d, a) + IX(d, a, x, y, z);
+            const int q0 = d.pt0[a];
+            switch (d.npts[a]) {
+            case 5: acc = wsum_input<T, 5>(d, p, q0, acc); break;
+            case 9: acc = wsum_input<T, 9>(d, p, q0, acc); break;
+            case 7: acc = wsum_input<T, 7>(d, p, q0, acc); break;
+            case 13: acc = wsum_input<T, 13>(d, p, q0, acc); break;
+            default:
+                for (int k = 0; k < d.npts[a]; ++k) acc = fmaT<T>((T)d.prm[q0 + k], p[d.off[q0 + k]], acc);
+            }
+        }
+        P<T>(d, 0)[IX(d, 0, x, y, z)] = acc;
+    }
+};
+
+// COPY with possible conversion: arg0 type TO, arg1 type FROM
+template <typename TO, typename FROM>
+struct OpCopy {
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        P<TO>(d, 0)[IX(d, 0, x, y, z)] = (TO)P<FROM>(d, 1)[IX(d, 1, x, y, z)];
+    }
+};
+
+template <typename T>
+struct OpAxpby {
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        T *yp = P<T>(d, 0) + IX(d, 0, x, y, z);
+        T xv = P<T>(d, 1)[IX(d, 1, x, y, z)];
+        *yp = fmaT<T>((T)d.prm[0], xv, (T)d.prm[1] * *yp);
+    }
+};
+
+template <typename T>
+struct OpDot {
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *r) {
+        double a = (double)P<T>(d, 0)[IX(d, 0, x, y, z)];
+        double b = (double)P<T>(d, 1)[IX(d, 1, x, y, z)];
+        dd_add_prod(r[0], a, b);
+    }
+};
+
+template <typename T>
+struct OpSum {
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *r) {
+        dd_add(r[0], (double)P<T>(d, 0)[IX(d, 0, x, y, z)]);
+    }
+};
+
+template <typename T>
+struct OpHaloReflect {
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        const int axis = (int)d.prm[0], side = (int)d.prm[1], n = (int)d.prm[2];
+        int c[3] = {x, y, z};
+        int s[3] = {x, y, z};
+        s[axis] = side == 0 ? -1 - c[axis] : 2 * n - 1 - c[axis];
+        T *v = P<T>(d, 0);
+        v[IX(d, 0, x, y, z)] = v[IX(d, 0, s[0], s[1], s[2])];
+    }
+};
+
+// ---- heat conduction ------------------------------------------------------
+// K arguments are the first ndim dataset arguments.
+template <typename T>
+__device__ __forceinline__ T tea_apply(const LoopDesc &d, int vi, int x, int y, int z) {
+    const T *kx = P<T>(d, 0), *ky = P<T>(d, 1);
+    const T ke = kx[IX(d, 0, x + 1, y, z)], kw = kx[IX(d, 0, x, y, z)];
+    const T kn = ky[IX(d, 1, x, y + 1, z)], ks = ky[IX(d, 1, x, y, z)];
+    const T *v = P<T>(d, vi);
+    const int64_t c = IX(d, vi, x, y, z);
+    const int64_t sy = d.arg[vi].sy;
+    T diag = (T)1 + ke;
+    diag = diag + kw;
+    diag = diag + kn;
+    diag = diag + ks;
+    T kt = 0, kb = 0;
+    const bool three = d.ndim == 3;
+    if (three) {
+        const T *kz = P<T>(d, 2);
+        kt = kz[IX(d, 2, x, y, z + 1)];
+        kb = kz[IX(d, 2, x, y, z)];
+        diag = diag + kt;
+        diag = diag + kb;
+    }
+    T av = diag * v[c];
+    av = fmaT<T>(-ke, v[c + 1], av);
+    av = fmaT<T>(-kw, v[c - 1], av);
+    av = fmaT<T>(-kn, v[c + sy], av);
+    av = fmaT<T>(-ks, v[c - sy], av);
+    if (three) {
+        const int64_t sz = d.arg[vi].sz;
+        av = fmaT<T>(-kt, v[c + sz], av);
+        av = fmaT<T>(-kb, v[c - sz], av);
+    }
+    return av;
+}
+
+template <typename T>
+struct OpTeaInit {  // rho, e, u0, u
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        T t = P<T>(d, 1)[IX(d, 1, x, y, z)] * P<T>(d, 0)[IX(d, 0, x, y, z)];
+        P<T>(d, 2)[IX(d, 2, x, y, z)] = t;
+        P<T>(d, 3)[IX(d, 3, x, y, z)] = t;
+    }
+};
+
+template <typename T>
+struct OpTeaK {  // rho, Kx, Ky[, Kz]; prm r
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        const T *rho = P<T>(d, 0);
+        const int64_t c = IX(d, 0, x, y, z);
+        const T rc = rho[c];
+        const T two_r = (T)2 * (T)d.prm[0];
+        P<T>(d, 1)[IX(d, 1, x, y, z)] = two_r / (rho[c - 1] + rc);
+        P<T>(d, 2)[IX(d, 2, x, y, z)] = two_r / (rho[c - d.arg[0].sy] + rc);
+        if (d.ndim == 3) P<T>(d, 3)[IX(d, 3, x, y, z)] = two_r / (rho[c - d.arg[0].sz] + rc);
+    }
+};
+
+template <typename T>
+struct OpTeaResid {  // K.., x, b, r
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        const int nd = d.ndim;
+        T av = tea_apply<T>(d, nd, x, y, z);
+        P<T>(d, nd + 2)[IX(d, nd + 2, x, y, z)] = P<T>(d, nd + 1)[IX(d, nd + 1, x, y, z)] - av;
+    }
+};
+
+template <typename T>
+struct OpTeaMatvecDot {  // K.., p, w, red
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *r) {
+        const int nd = d.ndim;
+        T av = tea_apply<T>(d, nd, x, y, z);
+        P<T>(d, nd + 1)[IX(d, nd + 1, x, y, z)] = av;
+        dd_add_prod(r[0], (double)P<T>(d, nd)[IX(d, nd, x, y, z)], (double)av);
+    }
+};
+
+template <typename T>
+struct OpTeaP1 {  // K.., sd, rt, z
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        const int nd = d.ndim;
+        T av = tea_apply<T>(d, nd, x, y, z);
+        T *rt = P<T>(d, nd + 1) + IX(d, nd + 1, x, y, z);
+        *rt = *rt - av;
+        T *zz = P<T>(d, nd + 2) + IX(d, nd + 2, x, y, z);
+        *zz = *zz + P<T>(d, nd)[IX(d, nd, x, y, z)];
+    }
+};
+
+template <typename T>
+struct OpTeaP2 {  // sd, rt; alpha, beta
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        T *sd = P<T>(d, 0) + IX(d, 0, x, y, z);
+        T rt = P<T>(d, 1)[IX(d, 1, x, y, z)];
+        *sd = fmaT<T>((T)d.prm[0], *sd, (T)d.prm[1] * rt);
+    }
+};
+
+template <typename T>
+struct OpTeaPreconInit {  // r, rt, sd, z; theta
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        T v = P<T>(d, 0)[IX(d, 0, x, y, z)];
+        P<T>(d, 1)[IX(d, 1, x, y, z)] = v;
+        P<T>(d, 2)[IX(d, 2, x, y, z)] = v / (T)d.prm[0];
+        P<T>(d, 3)[IX(d, 3, x, y, z)] = (T)0;
+    }
+};
+
+template <typename T>
+struct OpTeaCgUpdate {  // x, r, p, w; alpha
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        const T al = (T)d.prm[0];
+        T *xp = P<T>(d, 0) + IX(d, 0, x, y, z);
+        T *rp = P<T>(d, 1) + IX(d, 1, x, y, z);
+        *xp = fmaT<T>(al, P<T>(d, 2)[IX(d, 2, x, y, z)], *xp);
+        *rp = fmaT<T>(-al, P<T>(d, 3)[IX(d, 3, x, y, z)], *rp);
+    }
+};
+
+template <typename T>
+struct OpTeaCgP {  // p, z; beta
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        T *pp = P<T>(d, 0) + IX(d, 0, x, y, z);
+        *pp = fmaT<T>((T)d.prm[0], *pp, P<T>(d, 1)[IX(d, 1, x, y, z)]);
+    }
+};
+
+template <typename T>
+struct OpTeaGersh {  // K.., red(max)
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *r) {
+        const T *kx = P<T>(d, 0), *ky = P<T>(d, 1);
+        T s = kx[IX(d, 0, x + 1, y, z)] + kx[IX(d, 0, x, y, z)];
+        s = s + ky[IX(d, 1, x, y + 1, z)];
+        s = s + ky[IX(d, 1, x, y, z)];
+        if (d.ndim == 3) {
+            const T *kz = P<T>(d, 2);
+            s = s + kz[IX(d, 2, x, y, z + 1)];
+            s = s + kz[IX(d, 2, x, y, z)];
+        }
+        double g = (double)fmaT<T>((T)2, s, (T)1);
+        r[0].hi = fmax(r[0].hi, g);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// the loop kernel
+// ---------------------------------------------------------------------------
+template <class Op>
+__global__ void __launch_bounds__(kBlockThreads) loop_kernel(LoopDesc d, Box b) {
+    // XCD-aware order: hardware block i runs on XCD i % 8; give XCD k the
+    // contiguous block range [k*q + min(k, r), ...).
+    const int nb = b.nb;
+    const int i = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, xcd = i & 7, k = i >> 3;
+    const int lin = xcd * q + (xcd < r ? xcd : r) + k;
+    const int bx = lin % b.nbx;
+    const int rest = lin / b.nbx;
+    const int by = rest % b.nby;
+    const int bz = rest / b.nby;
+    const int x = b.lo[0] + bx * b.bw + (int)(threadIdx.x % b.bw);
+    const int y = b.lo[1] + by * b.bh + (int)(threadIdx.x / b.bw);
+    const int z = b.lo[2] + bz;
+    DD red[2];
+    red[0] = red_identity(d.red_op[0]);
+    red[1] = red_identity(d.red_op[1]);
+    if (x < b.hi[0] && y < b.hi[1]) Op::run(d, x, y, z, red);
+    for (int j = 0; j < d.nred; ++j) {
+        DD v = block_reduce(d.red_op[j], red[j]);
+        if (threadIdx.x == 0) {
+            d.partials[j][2 * (int64_t)lin] = v.hi;
+            d.partials[j][2 * (int64_t)lin + 1] = v.lo;
+        }
+    }
+}
+
+// One workgroup combines `count` partials in a fixed order.
+__global__ void __launch_bounds__(kBlockThreads) finalize_kernel(const double *part, int64_t count, int op,
+                                                                 double *out) {
+    DD a = red_identity(op);
+    for (int64_t i = threadIdx.x; i < count; i += kBlockThreads) {
+        DD b;
+        b.hi = part[2 * i];
+        b.lo = part[2 * i + 1];
+        a = red_combine(op, a, b);
+    }
+    a = block_reduce(op, a);
+    if (threadIdx.x == 0) {
+        out[0] = a.hi;
+        out[1] = a.lo;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+Box make_box(int ndim, const int lo[3], const int hi[3]) {
+    Box b;
+    for (int k = 0; k < 3; ++k) {
+        b.lo[k] = lo[k];
+        b.hi[k] = hi[k];
+    }
+    int nx = hi[0] - lo[0], ny = hi[1] - lo[1], nz = hi[2] - lo[2];
+    if (ndim == 1 || ny == 1) {
+        b.bw = kBlockThreads;
+        b.bh = 1;
+    } else if (nx <= 4) {
+        b.bw = 4;
+        b.bh = kBlockThreads / 4;
+    } else if (nx <= 16) {
+        b.bw = 16;
+        b.bh = kBlockThreads / 16;
+    } else {
+        b.bw = 64;
+        b.bh = kBlockThreads / 64;
+    }
+    b.nbx = (nx + b.bw - 1) / b.bw;
+    b.nby = (ny + b.bh - 1) / b.bh;
+    b.nb = b.nbx * b.nby * nz;
+    return b;
+}
+
+template <class Op>
+static hipError_t go(const LoopDesc &d, const Box &b, hipStream_t s) {
+    hipLaunchKernelGGL(loop_kernel<Op>, dim3(b.nb), dim3(kBlockThreads), 0, s, d, b);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t dispatch_t(const LoopDesc &d, const Box &b, hipStream_t s) {
+    switch (d.op) {
+    case TC_OP_WSUM: return go<OpWsum<T>>(d, b, s);
+    case TC_OP_AXPBY: return go<OpAxpby<T>>(d, b, s);
+    case TC_OP_DOT: return go<OpDot<T>>(d, b, s);
+    case TC_OP_SUM: return go<OpSum<T>>(d, b, s);
+    case TC_OP_HALO_REFLECT: return go<OpHaloReflect<T>>(d, b, s);
+    case TC_OP_TEA_INIT: return go<OpTeaInit<T>>(d, b, s);
+    case TC_OP_TEA_K: return go<OpTeaK<T>>(d, b, s);
+    case TC_OP_TEA_RESID: return go<OpTeaResid<T>>(d, b, s);
+    case TC_OP_TEA_MATVEC_DOT: return go<OpTeaMatvecDot<T>>(d, b, s);
+    case TC_OP_TEA_P1: return go<OpTeaP1<T>>(d, b, s);
+    case TC_OP_TEA_P2: return go<OpTeaP2<T>>(d, b, s);
+    case TC_OP_TEA_PRECON_INIT: return go<OpTeaPreconInit<T>>(d, b, s);
+    case TC_OP_TEA_CG_UPDATE: return go<OpTeaCgUpdate<T>>(d, b, s);
+    case TC_OP_TEA_CG_P: return go<OpTeaCgP<T>>(d, b, s);
+    case TC_OP_TEA_GERSH: return go<OpTeaGersh<T>>(d, b, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, hipStream_t s) {
+    if (b.nb <= 0) return hipSuccess;
+    if (d.op == TC_OP_COPY) {
+        if (dtype0 == TC_F64 && dtype1 == TC_F64) return go<OpCopy<double, double>>(d, b, s);
+        if (dtype0 == TC_F32 && dtype1 == TC_F32) return go<OpCopy<float, float>>(d, b, s);
+        if (dtype0 == TC_F64 && dtype1 == TC_F32) return go<OpCopy<double, float>>(d, b, s);
+        return go<OpCopy<float, double>>(d, b, s);
+    }
+    return dtype0 == TC_F64 ? dispatch_t<double>(d, b, s) : dispatch_t<float>(d, b, s);
+}
+
+hipError_t launch_finalize(const double *part, int64_t count, int op, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlockThreads), 0, s, part, count, op, out);
+    return hipGetLastError();
+}
+
+}  // namespace tc

@@ -1,0 +1,26 @@
+// Launch interface of the per-loop kernels (kernels.hip).
+#pragma once
+
+#include "tc_internal.hpp"
+
+namespace tc {
+
+constexpr int kBlockThreads = 256;
+
+// A box of points handed to one launch, with its workgroup decomposition.
+struct Box {
+    int lo[3], hi[3];
+    int bw, bh;        // workgroup footprint: bw points in x by bh rows in y
+    int nbx, nby, nb;  // workgroups along x, along y, total (z: nb / (nbx*nby))
+};
+
+Box make_box(int ndim, const int lo[3], const int hi[3]);
+
+// Launch one loop over a box.  dtype0 / dtype1: element types of dataset
+// arguments 0 and 1 (they differ only for a converting TC_OP_COPY).
+hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, hipStream_t s);
+
+// Combine `count` (hi, lo) partials into out[0..1] with one workgroup.
+hipError_t launch_finalize(const double *part, int64_t count, int op, double *out, hipStream_t s);
+
+}  // namespace tc

@@ -1,0 +1,203 @@
+// Internal types of the tilechain library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "tilechain.h"
+
+namespace tc {
+
+constexpr int kMaxArgs = 8;      // dataset + reduction arguments of one loop
+constexpr int kMaxPts = 64;      // stencil points over all dataset arguments of one loop
+constexpr int kMaxParams = 64;   // scalar parameters of one loop
+constexpr int kMaxHalo = 16;
+constexpr int kXAlign = 16;      // x origin and row pitch aligned to 16 elements
+
+struct Block {
+    int ndim;
+    std::string name;
+};
+
+struct Stencil {
+    int ndim;
+    std::vector<int> pts;  // npoints * 3 (x, y, z), unused dims 0
+    int lo[3], hi[3];      // min / max offset per dimension
+    std::string name;
+    int npoints() const { return (int)pts.size() / 3; }
+    bool centre_only() const {
+        for (int v : pts)
+            if (v != 0) return false;
+        return npoints() >= 1;
+    }
+};
+
+struct Dataset {
+    int block;
+    tc_dtype dtype;
+    int ndim;
+    int size[3];
+    int hneg[3], hpos[3];
+    // padded device layout: x origin at column xorg of a row of `pitch`
+    // elements; rows of ny_alloc per plane
+    int64_t pitch, ny_alloc, nz_alloc, xorg;
+    int64_t bytes;
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;               // buffer holding the current values
+    bool twin_synced = false;  // buf[1-cur] equals buf[cur] outside the written hull
+    // hull of every point written by any loop so far (logical coords)
+    int wlo[3], whi[3];
+    bool ever_written = false;
+    std::string name;
+
+    size_t esize() const { return dtype == TC_F64 ? 8 : 4; }
+    int64_t origin_offset() const {  // element offset of logical (0,0,0) in a buffer
+        return (int64_t)hneg[2] * ny_alloc * pitch + (int64_t)hneg[1] * pitch + xorg;
+    }
+    int64_t sy() const { return pitch; }
+    int64_t sz() const { return pitch * ny_alloc; }
+    void *origin(int which) const {
+        return (char *)buf[which] + origin_offset() * (int64_t)esize();
+    }
+};
+
+struct Reduction {
+    tc_redop op;
+    std::string name;
+    // host accumulator (double-double for sums)
+    double hi = 0.0, lo = 0.0;
+    bool touched = false;
+};
+
+struct ArgRec {
+    int kind;
+    int handle;
+    int stencil;
+    int access;
+    bool reads() const { return kind == TC_ARG_DAT && (access == TC_READ || access == TC_RW || access == TC_INC); }
+    bool writes() const { return kind == TC_ARG_DAT && (access == TC_WRITE || access == TC_RW || access == TC_INC); }
+};
+
+struct LoopRec {
+    int op;
+    int block;
+    int ndim;
+    int lo[3], hi[3];  // unused dims: [0,1)
+    std::vector<ArgRec> args;
+    std::vector<double> params;
+    std::string name;
+    int64_t points() const {
+        int64_t n = 1;
+        for (int d = 0; d < 3; ++d) n *= (hi[d] > lo[d]) ? (hi[d] - lo[d]) : 0;
+        return n;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Device-side descriptors (passed by value as kernel arguments)
+// ---------------------------------------------------------------------------
+struct DArg {
+    void *ptr;   // logical (0,0,0) of the buffer to use
+    int64_t sy;  // element stride of y
+    int64_t sz;  // element stride of z
+};
+
+struct LoopDesc {
+    int op;
+    int ndim;
+    int nargs;       // dataset arguments (reductions are not listed here)
+    int npts[kMaxArgs];
+    int pt0[kMaxArgs];  // first stencil point of each argument in off[]
+    DArg arg[kMaxArgs];
+    int64_t off[kMaxPts];  // linear element offset of every stencil point
+    double prm[kMaxParams];  // WSUM: weight of stencil point i at prm[i] (aligned with off[])
+    int nred;            // reduction arguments (0..2)
+    int red_op[2];
+    double *partials[2];  // per-block (hi, lo) partial results, indexed from part_base
+};
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+struct SkewedPlan {
+    int ndim = 0;
+    int num_tiles[3] = {1, 1, 1};
+    // start/end[d][t][l]
+    std::vector<int> start[3], end[3];
+    int nloops = 0;
+    int s(int d, int t, int l) const { return start[d][(size_t)t * nloops + l]; }
+    int e(int d, int t, int l) const { return end[d][(size_t)t * nloops + l]; }
+};
+
+struct FusedGroup;  // defined in fused.hpp
+
+// One kernel launch of a per-loop schedule: loop index, box, and where its
+// workgroups write reduction partials (in units of (hi, lo) pairs).
+struct Launch {
+    int loop;
+    int lo[3], hi[3];
+    int nb;
+    int64_t part_off[2];
+};
+
+struct CachedPlan {
+    tc_tiling mode;
+    SkewedPlan skewed;
+    std::vector<Launch> launches;
+    std::vector<int> red_handles;      // reductions used by the chain, slot order
+    std::vector<int64_t> red_base;     // first partial of each slot
+    std::vector<int64_t> red_count;    // partials of each slot
+    int64_t partials_total = 0;
+    std::vector<std::shared_ptr<FusedGroup>> groups;  // fused mode
+    double build_seconds = 0.0;
+    int max_skew[3] = {0, 0, 0};
+};
+
+struct Ctx {
+    int device = 0;
+    bool host_only = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    tc_alloc_fn alloc = nullptr;
+    tc_free_fn free = nullptr;
+    void *alloc_user = nullptr;
+    bool poisoned = false;
+    std::string last_error;
+
+    std::vector<Block> blocks;
+    std::vector<Dataset> dats;
+    std::vector<Stencil> stencils;
+    std::vector<Reduction> reds;
+    std::vector<LoopRec> chain;
+
+    tc_tiling mode = TC_TILING_NONE;
+    int tile[3] = {0, 0, 0};
+
+    std::unordered_map<uint64_t, std::shared_ptr<CachedPlan>> plans;
+    std::unordered_map<uint64_t, int> tuned;  // AUTO: chain key -> chosen candidate index
+
+    // reduction partials (device) and host staging
+    double *partials = nullptr;
+    int64_t partials_cap = 0;  // in doubles
+    double *red_out = nullptr;  // device: 2 doubles per reduction
+    int64_t red_out_cap = 0;
+    double *red_host = nullptr;  // pinned host mirror
+
+    tc_stats stats{};
+
+    // per-launch kernel timing (tc_set_profiling)
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+};
+
+// plan.cpp
+SkewedPlan build_skewed_plan(const Ctx &c, const std::vector<LoopRec> &chain, const int tile[3]);
+uint64_t chain_key(const Ctx &c, const std::vector<LoopRec> &chain, int mode, const int tile[3]);
+
+}  // namespace tc

@@ -1,0 +1,117 @@
+"""Host-side tests of the library (no GPU): the shared library loads and
+exports every function the header declares; recording, validation and error
+reporting; the library's Algorithm 1 plans equal the oracle's plans exactly."""
+import os
+import random
+import re
+
+import numpy as np
+import pytest
+
+import paper_1704_00693_amd as tc
+from oracle.skewed import skewed_plan
+from randchains import random_op_chain, record_op_chain, to_oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tilechain.h")).read()
+    return sorted(set(re.findall(r"^(?:tc_status|const char \*)\s*(tc_\w+)\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    L = tc.lib()
+    names = header_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(tc.EXPORTS) == names
+
+
+def host_ctx():
+    return tc.Context(host_only=True)
+
+
+def test_status_strings():
+    assert tc.tc_status_string(0) == "ok"
+    assert tc.tc_status_string(-6) == "range outside halo"
+
+
+def test_recording_is_delayed_and_validated():
+    with host_ctx() as c:
+        b = c.tc_decl_block(2)
+        d0 = c.tc_decl_dat(b, [8, 8], [1, 1], [1, 1])
+        d1 = c.tc_decl_dat(b, [8, 8], [1, 1], [1, 1])
+        s1 = c.tc_decl_stencil([(0, 0), (1, 0), (-1, 0)])
+        s2 = c.tc_decl_stencil([(0, 0), (2, 0)])
+        cen = c.tc_decl_stencil([(0, 0)])
+        c.tc_par_loop("WSUM", b, [0, 8, 0, 8], [(d1, cen, "W"), (d0, s1, "R")], [1, 2, 3])
+        assert c.tc_pending() == 1
+        # stencil leaves the halo
+        with pytest.raises(tc.TcError) as e:
+            c.tc_par_loop("WSUM", b, [0, 8, 0, 8], [(d1, cen, "W"), (d0, s2, "R")], [1, 2])
+        assert e.value.status == tc.TC_ERR_RANGE
+        # write through a non-centre stencil
+        with pytest.raises(tc.TcError):
+            c.tc_par_loop("WSUM", b, [0, 8, 0, 8], [(d1, s1, "W"), (d0, cen, "R")], [1])
+        # wrong parameter count
+        with pytest.raises(tc.TcError):
+            c.tc_par_loop("WSUM", b, [0, 8, 0, 8], [(d1, cen, "W"), (d0, s1, "R")], [1, 2])
+        # same dataset written and read at an offset
+        with pytest.raises(tc.TcError):
+            c.tc_par_loop("WSUM", b, [1, 7, 1, 7], [(d0, cen, "W"), (d0, s1, "R")], [1, 2, 3])
+        # wrong access for the op
+        with pytest.raises(tc.TcError):
+            c.tc_par_loop("AXPBY", b, [0, 8, 0, 8], [(d1, cen, "W"), (d0, cen, "R")], [1, 2])
+        # unknown op
+        with pytest.raises(tc.TcError):
+            c.tc_par_loop(77, b, [0, 8, 0, 8], [(d1, cen, "W")], [])
+        assert c.tc_pending() == 1  # rejected calls left no trace
+        # flushing a host-only context is refused
+        with pytest.raises(tc.TcError) as e:
+            c.tc_flush()
+        assert e.value.status == tc.TC_ERR_STATE
+
+
+def test_reflect_validation():
+    with host_ctx() as c:
+        b = c.tc_decl_block(2)
+        d = c.tc_decl_dat(b, [8, 8], [2, 2], [2, 2])
+        ok = c.tc_decl_stencil([(0, 0), (1, 0), (3, 0)])
+        bad = c.tc_decl_stencil([(0, 0), (1, 0)])
+        c.tc_par_loop("HALO_REFLECT", b, [-2, 0, 0, 8], [(d, ok, "RW")], [0, 0, 8])
+        with pytest.raises(tc.TcError):
+            c.tc_par_loop("HALO_REFLECT", b, [-2, 0, 0, 8], [(d, bad, "RW")], [0, 0, 8])
+        with pytest.raises(tc.TcError):  # interior points are not ghosts
+            c.tc_par_loop("HALO_REFLECT", b, [0, 2, 0, 8], [(d, ok, "RW")], [0, 0, 8])
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_plan_equals_oracle_plan(ndim):
+    rng = random.Random(77 + ndim)
+    for it in range(120):
+        ch = random_op_chain(rng, ndim)
+        tile = [rng.randint(1, 6) for _ in range(ndim)]
+        with host_ctx() as c:
+            record_op_chain(c, ch)
+            num, start, end = c.tc_chain_plan(tile, len(ch["loops"]), ndim)
+        ref = skewed_plan(to_oracle(ch), ndim, tile)
+        assert num == ref.num_tiles
+        assert start == ref.start and end == ref.end, (it, tile)
+
+
+def test_paper_example_through_abi():
+    """The paper's 1D example (Section 4.2) through the library's analyser."""
+    with host_ctx() as c:
+        b = c.tc_decl_block(1)
+        d1 = c.tc_decl_dat(b, [8], [1], [1])
+        d2 = c.tc_decl_dat(b, [8], [1], [1])
+        cen = c.tc_decl_stencil([(0,)])
+        s3 = c.tc_decl_stencil([(-1,), (0,), (1,)])
+        c.tc_par_loop("COPY", b, [0, 8], [(d2, cen, "W"), (d1, cen, "R")])
+        c.tc_par_loop("WSUM", b, [0, 8], [(d1, cen, "W"), (d2, s3, "R")], [1, 1, 1])
+        num, start, end = c.tc_chain_plan([4], 2, 1)
+    assert num == [2]
+    assert [[start[0][t][0], end[0][t][0]] for t in range(2)] == [[0, 5], [5, 8]]
+    assert [[start[0][t][1], end[0][t][1]] for t in range(2)] == [[0, 4], [4, 8]]

@@ -1,0 +1,161 @@
+"""GPU parity of loop chains: the HIP path (untiled and skewed-tiled) against
+the oracle's program-order execution, element by element.
+
+Tolerance: 1e-12 relative to the largest magnitude of the reference dataset
+(the FP64 bound the workloads fix).  Both sides evaluate every point with the
+same fma order, so the values are expected to agree exactly; tiled and
+untiled GPU runs must agree bit for bit (tiling only reorders points)."""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from randchains import op_chain_data, random_op_chain, record_op_chain, run_op_chain_oracle
+from synthgen import chain_data, make_chain
+from windows import window_oracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1704_00693_amd as tcm
+    tcm.lib()  # raises if the library was not built
+    return tcm
+
+
+def rel_err(got, ref):
+    scale = max(np.abs(ref).max(), 1e-300)
+    return float(np.abs(got - ref).max() / scale)
+
+
+def run_gpu_op_chain(tc, ch, data, mode, tile=(0, 0, 0)):
+    with tc.Context() as c:
+        c.tc_set_tiling(mode, tile)
+        blk, dats = record_op_chain(c, ch, data)
+        c.tc_flush()
+        out = [c.tc_dat_read(d) for d in dats]
+        st = c.tc_get_stats()
+    return out, st
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_random_op_chains(tc, ndim):
+    rng = random.Random(500 + ndim)
+    for it in range(12):
+        ch = random_op_chain(rng, ndim)
+        data = op_chain_data(ch, seed=it)
+        ref = run_op_chain_oracle(ch, data)
+        say(f"random op chain ndim={ndim} it={it} n={ch['n']} loops={len(ch['loops'])} untiled")
+        got, _ = run_gpu_op_chain(tc, ch, data, tc.TC_TILING_NONE)
+        for g, r in zip(got, ref):
+            assert rel_err(g, r) <= TOL
+        tile = [rng.randint(1, 5) for _ in range(ndim)] + [0] * (3 - ndim)
+        say(f"  skewed tile={tile}")
+        got_t, st = run_gpu_op_chain(tc, ch, data, tc.TC_TILING_SKEWED, tile)
+        for g, gt in zip(got, got_t):
+            assert np.array_equal(g, gt)
+
+
+@pytest.mark.parametrize("ndim,n,ndat,nloops,tiles", [
+    (2, 67, 12, 40, [(0, 16, 0), (24, 7, 0), (67, 67, 0)]),
+    (3, 23, 25, 20, [(0, 0, 5), (9, 6, 4)]),
+])
+def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
+    from paper_1704_00693_amd.apps import ChainRunner
+    ch = make_chain(ndim, n, ndat, nloops, seed=1 + ndim)
+    data = chain_data(ch)
+    ref = oracle.run_chain(ch, data)
+    results = {}
+    for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0))] + [(tc.TC_TILING_SKEWED, t) for t in tiles]:
+        say(f"synthetic chain ndim={ndim} n={n} mode={mode} tile={tile}")
+        with tc.Context() as c:
+            c.tc_set_tiling(mode, tile)
+            r = ChainRunner(c, ch, data)
+            r.run()
+            results[(mode, tile)] = [r.read(d) for d in range(ndat)]
+    base = results[(tc.TC_TILING_NONE, (0, 0, 0))]
+    exact = 0
+    for d in range(ndat):
+        assert rel_err(base[d], ref[d]) <= TOL
+        exact += int(np.array_equal(base[d], ref[d]))
+    say(f"  datasets bit-identical to the oracle: {exact}/{ndat}")
+    for k, v in results.items():
+        for d in range(ndat):
+            assert np.array_equal(v[d], base[d]), k
+
+
+def test_chain_sum_reduction(tc):
+    from paper_1704_00693_amd.apps import ChainRunner
+    ch = make_chain(3, 19, 6, 7, seed=5, reduce_last=True)
+    data = chain_data(ch)
+    ref = oracle.run_chain(ch, data)
+    g = oracle.Grid(3, ch.n, ch.halo)
+    want = oracle.exact_sum(oracle.interior(g, ref[ch.last_written()]))
+    for mode, tile in [(0, (0, 0, 0)), (1, (0, 0, 4)), (1, (5, 7, 3))]:
+        say(f"chain with reduction mode={mode} tile={tile}")
+        with tc.Context() as c:
+            c.tc_set_tiling(mode, tile)
+            r = ChainRunner(c, ch, data)
+            got = r.run()
+        assert abs(got - want) <= 4e-16 * abs(want) + 1e-300
+
+
+def test_reduction_accumulates_until_fetched(tc):
+    with tc.Context() as c:
+        b = c.tc_decl_block(2)
+        a = np.zeros((12, 10))
+        a[1:11, 1:9] = 1.5
+        d = c.tc_decl_dat(b, [8, 10], [1, 1], [1, 1], a)
+        cen = c.tc_decl_stencil([(0, 0)])
+        red = c.tc_decl_reduction(tc.TC_RED_SUM)
+        mx = c.tc_decl_reduction(tc.TC_RED_MAX)
+        c.tc_par_loop("SUM", b, [0, 8, 0, 10], [(d, cen, "R"), ("red", red)])
+        c.tc_flush()
+        c.tc_par_loop("SUM", b, [0, 4, 0, 10], [(d, cen, "R"), ("red", red)])
+        assert c.tc_reduction_result(red) == 1.5 * 120
+        assert c.tc_reduction_result(red) == 0.0
+        c.tc_par_loop("SUM", b, [0, 0, 0, 10], [(d, cen, "R"), ("red", red)])  # empty range
+        assert c.tc_reduction_result(red) == 0.0
+
+
+def test_full_size_2d_chain_sampled(tc):
+    """The 4096^2, 12-dataset, 40-loop chain in the launch configuration the
+    benchmark times (untiled and skewed with the automatic tile), checked on
+    sampled windows (corners, edges, interior) against the oracle."""
+    from paper_1704_00693_amd.apps import ChainRunner
+    from synthgen import chain_2d
+    ch = chain_2d()
+    data = chain_data(ch)
+    n = ch.n
+    centres = [(0, 0), (n - 1, n - 1), (n // 2, 3), (1234, 2987), (4000, 2048)]
+    refs = [window_oracle(ch, data, c, 100) for c in centres]
+    outs = {}
+    for mode in (tc.TC_TILING_NONE, tc.TC_TILING_SKEWED):
+        say(f"full-size 2D chain mode={mode}")
+        with tc.Context() as c:
+            c.tc_set_tiling(mode, (0, 0, 0))
+            r = ChainRunner(c, ch, data)
+            r.run()
+            outs[mode] = [r.read(d) for d in range(ch.ndat)]
+    for mode, out in outs.items():
+        for (arrs, lo, glo, ghi) in refs:
+            for d in range(ch.ndat):
+                ys = slice(glo[1] + 2, ghi[1] + 2)
+                xs = slice(glo[0] + 2, ghi[0] + 2)
+                got = out[d][ys, xs]
+                want = arrs[d][glo[1] - lo[1]:ghi[1] - lo[1], glo[0] - lo[0]:ghi[0] - lo[0]]
+                assert got.size > 0
+                assert rel_err(got, want) <= TOL
+    for d in range(ch.ndat):
+        assert np.array_equal(outs[0][d], outs[1][d])

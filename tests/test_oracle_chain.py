@@ -107,3 +107,17 @@ def test_exact_sum_and_dot():
     lo, hi = g.box([0], [1000])
     L.orc_dot_terms(lo, hi, g.view(a), g.view(b), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     assert oracle.exact_dot_terms(c) == float(exact)
+
+
+def test_window_oracle_equals_full_oracle():
+    """The windowed evaluation used to sample full-size GPU results is exact."""
+    from windows import window_oracle
+    ch = make_chain(2, 150, 6, 20, seed=8)
+    data = chain_data(ch)
+    ref = oracle.run_chain(ch, data)
+    for c in [(0, 0), (149, 149), (75, 2), (60, 100)]:
+        arrs, lo, glo, ghi = window_oracle(ch, data, c, 60)
+        for d in range(ch.ndat):
+            got = ref[d][glo[1] + 2:ghi[1] + 2, glo[0] + 2:ghi[0] + 2]
+            want = arrs[d][glo[1] - lo[1]:ghi[1] - lo[1], glo[0] - lo[0]:ghi[0] - lo[0]]
+            assert got.size > 0 and np.array_equal(got, want)
