@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -204,6 +205,7 @@ void build_desc(const Ctx &c, const LoopRec &lp, LoopDesc &d) {
         d.arg[na].sz = ds.sz();
         d.npts[na] = st.npoints();
         d.pt0[na] = q;
+        for (int k = 0; k < st.npoints(); ++k) d.qarg[q + k] = (unsigned char)na;
         for (int k = 0; k < st.npoints(); ++k, ++q)
             d.off[q] = (int64_t)st.pts[3 * k] + (int64_t)st.pts[3 * k + 1] * ds.sy() +
                        (int64_t)st.pts[3 * k + 2] * ds.sz();
@@ -219,6 +221,34 @@ void build_desc(const Ctx &c, const LoopRec &lp, LoopDesc &d) {
     } else {
         for (size_t i = 0; i < lp.params.size(); ++i) d.prm[i] = lp.params[i];
     }
+}
+
+// Radius of a 2D star stencil listed in the canonical order (centre, -x, +x,
+// [-2x, +2x,] -y, +y, [-2y, +2y]), or -1.
+int canonical_star2(const Stencil &st) {
+    static const int r1[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+    static const int r2[9][2] = {{0, 0}, {-1, 0}, {1, 0}, {-2, 0}, {2, 0}, {0, -1}, {0, 1}, {0, -2}, {0, 2}};
+    if (st.ndim != 2) return -1;
+    const int n = st.npoints();
+    if (n != 5 && n != 9) return -1;
+    for (int p = 0; p < n; ++p) {
+        const int *w = n == 5 ? r1[p] : r2[p];
+        if (st.pts[3 * p] != w[0] || st.pts[3 * p + 1] != w[1]) return -1;
+    }
+    return n == 5 ? 1 : 2;
+}
+
+// Radius mask for the register-window weighted-sum kernel, or -1.
+int wsum_march_mask(const Ctx &c, const LoopRec &lp) {
+    if (lp.op != TC_OP_WSUM || lp.ndim != 2 || lp.args.size() > 5) return -1;
+    if (!c.stencils[lp.args[0].stencil].centre_only() || c.stencils[lp.args[0].stencil].npoints() != 1) return -1;
+    int mask = 0;
+    for (size_t a = 1; a < lp.args.size(); ++a) {
+        const int r = canonical_star2(c.stencils[lp.args[a].stencil]);
+        if (r < 0) return -1;
+        if (r == 2) mask |= 1 << (a - 1);
+    }
+    return mask;
 }
 
 int dat_dtype(const Ctx &c, const LoopRec &lp, int which) {
@@ -345,7 +375,11 @@ tc_status ensure_events(Ctx &c, size_t n) {
 
 tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, const CachedPlan &P) {
     std::vector<LoopDesc> descs(chain.size());
-    for (size_t l = 0; l < chain.size(); ++l) build_desc(c, chain[l], descs[l]);
+    std::vector<int> march(chain.size());
+    for (size_t l = 0; l < chain.size(); ++l) {
+        build_desc(c, chain[l], descs[l]);
+        march[l] = c.march_enabled ? wsum_march_mask(c, chain[l]) : -1;
+    }
     if (c.profiling) {
         tc_status st = ensure_events(c, 2 * P.launches.size());
         if (st != TC_OK) return st;
@@ -356,7 +390,8 @@ tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, const CachedPl
         for (int j = 0; j < d.nred; ++j) d.partials[j] = c.partials + 2 * L.part_off[j];
         Box b = make_box(chain[L.loop].ndim, L.lo, L.hi);
         if (c.profiling) HIPCHK(c, hipEventRecord(c.events[2 * i], c.stream));
-        HIPCHK(c, launch_loop(d, b, dat_dtype(c, chain[L.loop], 0), dat_dtype(c, chain[L.loop], 1), c.stream));
+        HIPCHK(c, launch_loop(d, b, dat_dtype(c, chain[L.loop], 0), dat_dtype(c, chain[L.loop], 1), march[L.loop],
+                              c.stream));
         if (c.profiling) HIPCHK(c, hipEventRecord(c.events[2 * i + 1], c.stream));
         ++i;
     }
@@ -531,6 +566,7 @@ tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
             return TC_ERR_ARG;
         }
     }
+    if (const char *e = getenv("TC_WSUM_MARCH")) c.march_enabled = atoi(e) != 0;
     if (!c.host_only) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || n <= 0 || c.device < 0 || c.device >= n) {

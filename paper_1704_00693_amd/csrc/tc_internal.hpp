@@ -116,6 +116,7 @@ struct LoopDesc {
     int pt0[kMaxArgs];  // first stencil point of each argument in off[]
     DArg arg[kMaxArgs];
     int64_t off[kMaxPts];  // linear element offset of every stencil point
+    unsigned char qarg[kMaxPts];  // dataset argument of every stencil point
     double prm[kMaxParams];  // WSUM: weight of stencil point i at prm[i] (aligned with off[])
     int nred;            // reduction arguments (0..2)
     int red_op[2];
@@ -190,6 +191,10 @@ struct Ctx {
     double *red_host = nullptr;  // pinned host mirror
 
     tc_stats stats{};
+
+    // weighted-sum loops on canonical 2D star stencils use the register-window
+    // kernel (TC_WSUM_MARCH=0 in the environment selects the generic kernel)
+    bool march_enabled = true;
 
     // per-launch kernel timing (tc_set_profiling)
     bool profiling = false;

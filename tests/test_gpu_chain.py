@@ -84,6 +84,16 @@ def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
             r = ChainRunner(c, ch, data)
             r.run()
             results[(mode, tile)] = [r.read(d) for d in range(ndat)]
+    # the generic weighted-sum kernel instead of the register-window one
+    import os
+    os.environ["TC_WSUM_MARCH"] = "0"
+    try:
+        with tc.Context() as c:
+            r = ChainRunner(c, ch, data)
+            r.run()
+            results["generic"] = [r.read(d) for d in range(ndat)]
+    finally:
+        del os.environ["TC_WSUM_MARCH"]
     base = results[(tc.TC_TILING_NONE, (0, 0, 0))]
     exact = 0
     for d in range(ndat):
