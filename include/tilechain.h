@@ -137,12 +137,16 @@ typedef struct {
 typedef void *(*tc_alloc_fn)(size_t bytes, void *user);
 typedef void (*tc_free_fn)(void *ptr, void *user);
 
-enum { TC_INIT_HOST_ONLY = 1 }; /* record and analyse only; no device, flush fails */
+enum {
+    TC_INIT_HOST_ONLY = 1,    /* record and analyse only; no device, flush fails */
+    TC_INIT_BORROW_STREAM = 2 /* run on opts.stream even when it is NULL (the null stream) */
+};
 
 typedef struct {
     int32_t device;   /* HIP device ordinal */
     int32_t flags;    /* TC_INIT_* */
-    void *stream;     /* hipStream_t to run on (borrowed); NULL = the library creates one */
+    void *stream;     /* hipStream_t to run on (borrowed); NULL without TC_INIT_BORROW_STREAM:
+                         the library creates its own stream */
     tc_alloc_fn alloc;
     tc_free_fn free;
     void *alloc_user;

@@ -28,6 +28,7 @@ TC_ARG_DAT, TC_ARG_RED = 0, 1
 TC_RED_SUM, TC_RED_MIN, TC_RED_MAX = 0, 1, 2
 TC_TILING_NONE, TC_TILING_SKEWED, TC_TILING_FUSED, TC_TILING_AUTO = 0, 1, 2, 3
 TC_INIT_HOST_ONLY = 1
+TC_INIT_BORROW_STREAM = 2
 OPS = {
     "WSUM": 0, "COPY": 1, "AXPBY": 2, "DOT": 3, "SUM": 4, "HALO_REFLECT": 5,
     "TEA_INIT": 10, "TEA_K": 11, "TEA_RESID": 12, "TEA_MATVEC_DOT": 13, "TEA_P1": 14, "TEA_P2": 15,
@@ -146,6 +147,7 @@ class Context:
             if stream is None:
                 stream = torch.cuda.current_stream(device).cuda_stream
             opts.stream = stream
+            opts.flags |= TC_INIT_BORROW_STREAM
             if torch_memory:
                 dev = torch.device("cuda", device)
 

@@ -20,7 +20,7 @@ struct tc_ctx {
 
 using namespace tc;
 
-namespace {
+namespace tc {
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -284,6 +284,7 @@ void add_launch(const Ctx &c, const LoopRec &lp, int l, const int lo[3], const i
         L.part_off[j++] = slot;  // temporarily the slot; fixed up below
         slot_used[slot] += b.nb;
     }
+    P->steps.push_back({0, (int)P->launches.size()});
     P->launches.push_back(L);
 }
 
@@ -354,6 +355,19 @@ std::shared_ptr<CachedPlan> build_plan(Ctx &c, const std::vector<LoopRec> &chain
                         }
                         add_launch(c, chain[l], l, lo, hi, P, used);
                     }
+    } else if (mode == TC_TILING_FUSED) {
+        P->groups = fused_split(c, chain, tile);
+        size_t gi = 0;
+        for (int l = 0; l < (int)chain.size();) {
+            if (gi < P->groups.size() && P->groups[gi]->g0 == l) {
+                P->steps.push_back({1, (int)gi});
+                l = P->groups[gi]->g1;
+                ++gi;
+            } else {
+                add_launch(c, chain[l], l, chain[l].lo, chain[l].hi, P, used);
+                ++l;
+            }
+        }
     } else {
         for (int l = 0; l < (int)chain.size(); ++l) add_launch(c, chain[l], l, chain[l].lo, chain[l].hi, P, used);
     }
@@ -375,23 +389,32 @@ tc_status ensure_events(Ctx &c, size_t n) {
 
 tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, const CachedPlan &P) {
     std::vector<LoopDesc> descs(chain.size());
+    std::vector<char> built(chain.size(), 0);
     std::vector<int> march(chain.size());
-    for (size_t l = 0; l < chain.size(); ++l) {
-        build_desc(c, chain[l], descs[l]);
-        march[l] = c.march_enabled ? wsum_march_mask(c, chain[l]) : -1;
-    }
+    for (size_t l = 0; l < chain.size(); ++l) march[l] = c.march_enabled ? wsum_march_mask(c, chain[l]) : -1;
     if (c.profiling) {
-        tc_status st = ensure_events(c, 2 * P.launches.size());
+        tc_status st = ensure_events(c, 2 * P.steps.size());
         if (st != TC_OK) return st;
     }
     size_t i = 0;
-    for (const auto &L : P.launches) {
-        LoopDesc d = descs[L.loop];
-        for (int j = 0; j < d.nred; ++j) d.partials[j] = c.partials + 2 * L.part_off[j];
-        Box b = make_box(chain[L.loop].ndim, L.lo, L.hi);
+    for (const auto &S : P.steps) {
         if (c.profiling) HIPCHK(c, hipEventRecord(c.events[2 * i], c.stream));
-        HIPCHK(c, launch_loop(d, b, dat_dtype(c, chain[L.loop], 0), dat_dtype(c, chain[L.loop], 1), march[L.loop],
-                              c.stream));
+        if (S.kind == 0) {
+            const Launch &L = P.launches[S.index];
+            if (!built[L.loop]) {  // descriptors see the buffers current at this point
+                build_desc(c, chain[L.loop], descs[L.loop]);
+                built[L.loop] = 1;
+            }
+            LoopDesc d = descs[L.loop];
+            for (int j = 0; j < d.nred; ++j) d.partials[j] = c.partials + 2 * L.part_off[j];
+            Box b = make_box(chain[L.loop].ndim, L.lo, L.hi);
+            HIPCHK(c, launch_loop(d, b, dat_dtype(c, chain[L.loop], 0), dat_dtype(c, chain[L.loop], 1),
+                                  march[L.loop], c.march_ty, c.stream));
+        } else {
+            tc_status st = fused_run(c, chain, *P.groups[S.index]);
+            if (st != TC_OK) return st;
+            std::fill(built.begin(), built.end(), 0);  // buffers were swapped
+        }
         if (c.profiling) HIPCHK(c, hipEventRecord(c.events[2 * i + 1], c.stream));
         ++i;
     }
@@ -453,10 +476,7 @@ tc_status flush(Ctx &c) {
     std::vector<int> red_handles;
     std::vector<int64_t> red_base, red_count;
     int launches = 0, tiles = 0, groups = 0;
-    if (mode == TC_TILING_FUSED) {
-        st = fused_flush(c, chain, tile, red_handles, red_base, red_count, launches, tiles, groups);
-        if (st != TC_OK) return st;
-    } else {
+    {
         const uint64_t key = chain_key(c, chain, mode, tile);
         std::shared_ptr<CachedPlan> P;
         auto it = c.plans.find(key);
@@ -478,8 +498,13 @@ tc_status flush(Ctx &c) {
         red_handles = P->red_handles;
         red_base = P->red_base;
         red_count = P->red_count;
-        launches = (int)P->launches.size();
+        launches = (int)P->steps.size();
         tiles = P->skewed.num_tiles[0] * P->skewed.num_tiles[1] * P->skewed.num_tiles[2];
+        groups = (int)P->groups.size();
+        if (mode == TC_TILING_FUSED) {
+            tiles = 0;
+            for (auto &g : P->groups) tiles += g->nblocks;
+        }
         for (int d = 0; d < 3; ++d) c.stats.max_skew[d] = P->max_skew[d];
     }
     note_writes(c, chain);
@@ -541,7 +566,7 @@ tc_status copy_host(Ctx &c, Dataset &ds, void *host, const void *src, int which,
     return TC_OK;
 }
 
-}  // namespace
+}  // namespace tc
 
 // ===========================================================================
 // C ABI
@@ -567,6 +592,8 @@ tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
         }
     }
     if (const char *e = getenv("TC_WSUM_MARCH")) c.march_enabled = atoi(e) != 0;
+    if (const char *e = getenv("TC_MARCH_TY")) c.march_ty = std::max(1, atoi(e));
+    if (const char *e = getenv("TC_STAGGER")) c.stagger_unit = std::max(0ll, atoll(e)) / 256 * 256;
     if (!c.host_only) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || n <= 0 || c.device < 0 || c.device >= n) {
@@ -577,7 +604,7 @@ tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
             delete ctx;
             return TC_ERR_DEVICE;
         }
-        if (!c.stream) {
+        if (!c.stream && !(opts && (opts->flags & TC_INIT_BORROW_STREAM))) {
             if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) {
                 delete ctx;
                 return TC_ERR_DEVICE;
@@ -599,8 +626,8 @@ tc_status tc_finalize(tc_ctx *ctx) {
     }
     if (!c.host_only) {
         for (auto &d : c.dats) {
-            dev_free(c, d.buf[0]);
-            dev_free(c, d.buf[1]);
+            dev_free(c, d.raw[0]);
+            dev_free(c, d.raw[1]);
         }
         fused_release(c);
         for (auto e : c.events) (void)hipEventDestroy(e);
@@ -649,12 +676,14 @@ tc_status tc_decl_dat(tc_ctx *ctx, tc_block blk, tc_dtype dtype, const int32_t *
     ds.ny_alloc = (int64_t)ds.size[1] + ds.hneg[1] + ds.hpos[1];
     ds.nz_alloc = (int64_t)ds.size[2] + ds.hneg[2] + ds.hpos[2];
     ds.bytes = ds.pitch * ds.ny_alloc * ds.nz_alloc * (int64_t)ds.esize();
+    ds.stagger = c.stagger_unit * (int64_t)(c.dats.size() % 16);
     if (!c.host_only) {
-        ds.buf[0] = dev_alloc(c, (size_t)ds.bytes);
-        if (!ds.buf[0]) return fail(c, TC_ERR_NOMEM, "tc_decl_dat: cannot allocate %lld bytes", (long long)ds.bytes);
+        ds.raw[0] = dev_alloc(c, (size_t)(ds.bytes + ds.stagger));
+        if (!ds.raw[0]) return fail(c, TC_ERR_NOMEM, "tc_decl_dat: cannot allocate %lld bytes", (long long)ds.bytes);
+        ds.buf[0] = (char *)ds.raw[0] + ds.stagger;
         hipError_t e = hipMemsetAsync(ds.buf[0], 0, (size_t)ds.bytes, c.stream);
         if (e != hipSuccess) {
-            dev_free(c, ds.buf[0]);
+            dev_free(c, ds.raw[0]);
             return fail(c, TC_ERR_DEVICE, "hipMemsetAsync failed: %s", hipGetErrorString(e));
         }
     }

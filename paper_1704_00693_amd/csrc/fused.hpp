@@ -1,21 +1,113 @@
-// Fused (overlapped, LDS-streamed) execution of a loop chain and the
-// autotuner's choice between execution modes.
+// Fused execution of a loop chain: overlapped tiles (Section 4.4 of the
+// paper, applied to GPU workgroups instead of MPI ranks) streamed through
+// LDS.
+//
+// A fusion group is a run of consecutive 2D weighted-sum loops.  Every
+// workgroup owns a block of W columns by Hseg rows of the group's domain and
+// marches up y two rows per step.  At every step each loop of the group
+// computes one row pair at its own lag, reading its inputs from per-dataset
+// ring buffers in LDS; loaders bring chain-start values of datasets into their
+// rings ahead of their first readers, storers write each dataset's final
+// values for the owned block back to HBM.  A loop recomputes the points its
+// later readers need beyond the owned block (its x and y extents), so blocks
+// run concurrently with no communication; datasets the group writes are
+// written to a second buffer (ping-pong) so that no workgroup overwrites
+// values another one still loads.
 #pragma once
 
 #include "tc_internal.hpp"
 
 namespace tc {
 
-// Execute `chain` in fused mode.  Fills the reductions it used (slot order),
-// their partial ranges, and launch / tile / group counts for the statistics.
-tc_status fused_flush(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3], std::vector<int> &red_handles,
-                      std::vector<int64_t> &red_base, std::vector<int64_t> &red_count, int &launches, int &tiles,
-                      int &groups);
+constexpr int kFMaxLoops = 16;
+constexpr int kFMaxRings = 16;
+constexpr int kFMaxEnt = 384;
+constexpr int kFCols = 128;     // ring width in columns = threads per row
+constexpr int kFRows = 2;       // rows per step
+constexpr int kFThreads = kFCols * kFRows;
+
+struct FLoopD {
+    int out_ring;
+    int ent0, nent;      // stencil-point entries of the inputs, listed order
+    int in0, nin;        // inputs (for per-input slot computation)
+    int lag;
+    int xlo, xhi, ylo, yhi;  // iteration range
+    int hlo, hhi, vlo, vhi;  // columns left/right and rows below/above the owned block it computes
+};
+
+struct FInD {   // one input of a loop: ring and its entries
+    int ring, ent0, nent;
+};
+
+struct FRingD {
+    void *src;    // logical (0,0) of the buffer holding the chain-start values
+    void *dst;    // logical (0,0) of the buffer receiving the final values
+    int64_t sy;   // row pitch (elements)
+    int depth;    // rows
+    int lds_off;  // elements
+    float inv_depth;
+    int load;     // 0: none, 1: every point, 2: points outside the first write's range
+    int load_lag, ld_below, ld_above;
+    int fw_xlo, fw_xhi, fw_ylo, fw_yhi;
+    int store, store_lag;
+    int hull_xlo, hull_xhi, hull_ylo, hull_yhi;  // store region
+    int ext_xlo, ext_xhi, ext_ylo, ext_yhi;      // allocated extent
+};
+
+struct FEnt {
+    short ring;
+    signed char dx, dy;
+};
+
+struct FGroupD {
+    int nloops, nrings, nin;
+    int W, HR, Hseg;
+    int dom_xlo, dom_ylo, nbx, nby;
+    FLoopD loops[kFMaxLoops];
+    FRingD rings[kFMaxRings];
+    FInD ins[kFMaxLoops * 8];
+    FEnt ent[kFMaxEnt];
+    double w[kFMaxEnt];
+};
+
+// Static analysis of one fusion group (cached with the plan).
+struct FusedGroup {
+    int g0, g1;               // loops [g0, g1) of the chain
+    int dtype;
+    std::vector<int> ring_dat;  // dataset of every ring
+    std::vector<int> ring_store;
+    FGroupD tmpl;             // descriptor without pointers, store regions or weights
+    int lds_bytes = 0;
+    int nblocks = 0;
+    // per-group staging: pinned host copy and device copy of the descriptor,
+    // and an event marking the end of the last upload from the host copy
+    FGroupD *host = nullptr;
+    FGroupD *dev = nullptr;
+    hipEvent_t uploaded = nullptr;
+};
+
+// Split a chain into fusion groups; loops outside any group run one kernel
+// each.  Returns the groups in chain order.
+std::vector<std::shared_ptr<FusedGroup>> fused_split(const Ctx &c, const std::vector<LoopRec> &chain,
+                                                     const int tile[3]);
+
+// Run one fusion group on the context's stream (ping-pong buffers are
+// prepared and swapped here).
+tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &g);
+
+// Kernel launch (fused_kernel.hip).
+hipError_t launch_fused(const FGroupD *dev_desc, int dtype, int nblocks, int lds_bytes, hipStream_t s);
 
 // Release device memory held for fused execution.
 void fused_release(Ctx &c);
 
 // AUTO mode: the execution mode (and tile, written back) to use for this chain.
 tc_tiling autotune_choose(Ctx &c, const std::vector<LoopRec> &chain, int tile[3]);
+
+// shared helpers (api.cpp)
+double now_s();
+tc_status fail(Ctx &c, tc_status s, const char *fmt, ...);
+void *dev_alloc(Ctx &c, size_t bytes);
+void dev_free(Ctx &c, void *p);
 
 }  // namespace tc

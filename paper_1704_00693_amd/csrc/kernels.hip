@@ -444,9 +444,10 @@ static hipError_t dispatch_t(const LoopDesc &d, const Box &b, hipStream_t s) {
     }
 }
 
-hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, int march_mask, hipStream_t s) {
+hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, int march_mask, int march_ty,
+                       hipStream_t s) {
     if (b.nb <= 0) return hipSuccess;
-    if (d.op == TC_OP_WSUM) return launch_wsum(d, b, dtype0, march_mask, s);
+    if (d.op == TC_OP_WSUM) return launch_wsum(d, b, dtype0, march_mask, march_ty, s);
     if (d.op == TC_OP_COPY) {
         if (dtype0 == TC_F64 && dtype1 == TC_F64) return go<OpCopy<double, double>>(d, b, s);
         if (dtype0 == TC_F32 && dtype1 == TC_F32) return go<OpCopy<float, float>>(d, b, s);

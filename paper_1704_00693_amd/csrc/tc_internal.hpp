@@ -49,6 +49,8 @@ struct Dataset {
     int64_t pitch, ny_alloc, nz_alloc, xorg;
     int64_t bytes;
     void *buf[2] = {nullptr, nullptr};
+    void *raw[2] = {nullptr, nullptr};  // allocations (buf = raw + stagger)
+    int64_t stagger = 0;                // byte offset of buf in raw
     int cur = 0;               // buffer holding the current values
     bool twin_synced = false;  // buf[1-cur] equals buf[cur] outside the written hull
     // hull of every point written by any loop so far (logical coords)
@@ -147,9 +149,16 @@ struct Launch {
     int64_t part_off[2];
 };
 
+// One step of a schedule: a per-loop launch or a fused group.
+struct Step {
+    int kind;   // 0: launches[index], 1: groups[index]
+    int index;
+};
+
 struct CachedPlan {
     tc_tiling mode;
     SkewedPlan skewed;
+    std::vector<Step> steps;
     std::vector<Launch> launches;
     std::vector<int> red_handles;      // reductions used by the chain, slot order
     std::vector<int64_t> red_base;     // first partial of each slot
@@ -195,6 +204,8 @@ struct Ctx {
     // weighted-sum loops on canonical 2D star stencils use the register-window
     // kernel (TC_WSUM_MARCH=0 in the environment selects the generic kernel)
     bool march_enabled = true;
+    int march_ty = 16;            // rows per workgroup of the register-window kernel
+    int64_t stagger_unit = 0;     // dataset i's base is offset by (i % 16) * stagger_unit bytes
 
     // per-launch kernel timing (tc_set_profiling)
     bool profiling = false;

@@ -5,12 +5,13 @@
 //
 //  * march: 2D, every input read through a radius-1 or radius-2 star stencil
 //    listed in the canonical order (centre, -x, +x, [-2x, +2x,] -y, +y,
-//    [-2y, +2y]).  A workgroup covers 256 consecutive x and marches TY rows
-//    up y; each thread keeps the vertical window of every input in
-//    registers (one new row load per input per output row) and takes its x
-//    neighbours from adjacent lanes with cross-lane shuffles, so global
-//    loads per output point drop from sum(stencil points) to about the
-//    number of inputs.
+//    [-2y, +2y]).  A workgroup covers 240 consecutive x (four wavefronts of
+//    60 output columns plus two halo columns per side) and marches TY rows
+//    up y; each lane keeps the vertical window of every input in registers
+//    (one new row load per input per output row, issued one row ahead) and
+//    takes its x neighbours from adjacent lanes with cross-lane shuffles, so
+//    global loads per output point drop from sum(stencil points) to about
+//    the number of inputs and no load is conditional.
 //  * generic: any stencils and dimensions; all loads of a point are issued
 //    before its fma chain so one memory latency covers the whole point.
 #include <hip/hip_runtime.h>
@@ -21,8 +22,10 @@ namespace tc {
 
 namespace {
 
-constexpr int kMarchTY = 16;  // rows per workgroup in the march kernel
-constexpr int kMarchW = 256;  // columns per workgroup (4 wavefronts)
+constexpr int kMarchW = 256;                 // threads per workgroup (4 wavefronts side by side in x)
+constexpr int kWaveOut = 60;                 // output columns per wavefront
+constexpr int kMarchOut = 4 * kWaveOut;      // output columns per workgroup
+constexpr int kMarchBatch = 4;               // rows computed per batch (loaded one batch ahead)
 
 template <typename T>
 __device__ __forceinline__ T fmaT(T a, T b, T c) {
@@ -51,76 +54,86 @@ __device__ __forceinline__ int xcd_linear(int i, int nb) {
 
 template <typename T, int K, int MASK>
 __global__ void __launch_bounds__(kMarchW) wsum_march_kernel(LoopDesc d, int lo0, int hi0, int lo1, int hi1, int nbx,
-                                                             int nb) {
+                                                             int nb, int ty) {
+    constexpr int TB = kMarchBatch;
     const int lin = xcd_linear(blockIdx.x, nb);
     const int bx = lin % nbx, by = lin / nbx;
-    const int lane = threadIdx.x & 63;
-    const int x = lo0 + bx * kMarchW + (int)threadIdx.x;
-    const bool active = x < hi0;
-    const int xc = active ? x : hi0 - 1;  // inactive lanes load a valid address
-    const int y0 = lo1 + by * kMarchTY;
-    const int y1 = min(y0 + kMarchTY, hi1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // each wavefront produces 60 columns; lanes 0-1 and 62-63 hold the x halo
+    const int xw = lo0 + bx * kMarchOut + wave * kWaveOut;
+    const int x = xw - 2 + lane;
+    const bool active = lane >= 2 && lane < 62 && x < hi0;
+    const int y0 = lo1 + by * ty;
+    const int y1 = min(y0 + ty, hi1);
 
     const T *ptr[K];
     int64_t sy[K];
-    T win[K][5];  // vertical window rows y-2 .. y+2 (radius 1 uses 1..3)
-    T pf[K];      // next row of every input, loaded one step ahead
+    // win[a][j] holds row y - 2 + j of input a for the batch starting at y;
+    // pf[a][t] holds row y + TB + r + t, loaded while batch y is computed
+    T win[K][TB + 4];
+    T pf[K][TB];
 #pragma unroll
     for (int a = 0; a < K; ++a) {
-        ptr[a] = (const T *)d.arg[a + 1].ptr;
-        sy[a] = d.arg[a + 1].sy;
         const int r = (MASK >> a) & 1 ? 2 : 1;
-        const T *col = ptr[a] + xc + (int64_t)y0 * sy[a];
+        // columns outside this input's reach are clamped; no output uses them
+        const int xc = min(max(x, lo0 - r), hi0 - 1 + r);
+        sy[a] = d.arg[a + 1].sy;
+        ptr[a] = (const T *)d.arg[a + 1].ptr + xc;
 #pragma unroll
-        for (int j = -2; j < 2; ++j)
-            if (j >= -r && j < r) win[a][j + 2] = col[(int64_t)j * sy[a]];
-        pf[a] = col[(int64_t)r * sy[a]];
+        for (int j = 0; j < 4; ++j)
+            if (j >= 2 - r && j < 2 + r) win[a][j] = ptr[a][(int64_t)(y0 - 2 + j) * sy[a]];
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+            if (y0 + r + t <= y1 - 1 + r) pf[a][t] = ptr[a][(int64_t)(y0 + r + t) * sy[a]];
     }
-    T *out = (T *)d.arg[0].ptr;
+    T *out = (T *)d.arg[0].ptr + x;
     const int64_t osy = d.arg[0].sy;
-    for (int y = y0; y < y1; ++y) {
-        T acc = (T)0;
-        const bool more = y + 1 < y1;
+    for (int y = y0; y < y1; y += TB) {
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             const int r = (MASK >> a) & 1 ? 2 : 1;
-            win[a][2 + r] = pf[a];
-            if (more) pf[a] = ptr[a][(int64_t)(y + 1 + r) * sy[a] + xc];
-        }
 #pragma unroll
-        for (int a = 0; a < K; ++a) {
-            const int r = (MASK >> a) & 1 ? 2 : 1;
-            const T *row = ptr[a] + (int64_t)y * sy[a];
-            const T c = win[a][2];
-            T xm1 = shfl_up(c, 1), xp1 = shfl_down(c, 1);
-            if (lane < 1) xm1 = row[xc - 1];
-            if (lane > 62 || x + 1 >= hi0) xp1 = row[xc + 1];
-            const int q = d.pt0[a + 1];
-            if (r == 1) {
-                acc = fmaT<T>((T)d.prm[q + 0], c, acc);
-                acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
-                acc = fmaT<T>((T)d.prm[q + 2], xp1, acc);
-                acc = fmaT<T>((T)d.prm[q + 3], win[a][1], acc);
-                acc = fmaT<T>((T)d.prm[q + 4], win[a][3], acc);
-            } else {
-                T xm2 = shfl_up(c, 2), xp2 = shfl_down(c, 2);
-                if (lane < 2) xm2 = row[xc - 2];
-                if (lane > 61 || x + 2 >= hi0) xp2 = row[xc + 2];
-                acc = fmaT<T>((T)d.prm[q + 0], c, acc);
-                acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
-                acc = fmaT<T>((T)d.prm[q + 2], xp1, acc);
-                acc = fmaT<T>((T)d.prm[q + 3], xm2, acc);
-                acc = fmaT<T>((T)d.prm[q + 4], xp2, acc);
-                acc = fmaT<T>((T)d.prm[q + 5], win[a][1], acc);
-                acc = fmaT<T>((T)d.prm[q + 6], win[a][3], acc);
-                acc = fmaT<T>((T)d.prm[q + 7], win[a][0], acc);
-                acc = fmaT<T>((T)d.prm[q + 8], win[a][4], acc);
+            for (int t = 0; t < TB; ++t) win[a][2 + r + t] = pf[a][t];
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const int row = y + TB + r + t;
+                if (row <= y1 - 1 + r) pf[a][t] = ptr[a][(int64_t)row * sy[a]];
             }
-            // shift the window one row up
-#pragma unroll
-            for (int j = 0; j < 4; ++j) win[a][j] = win[a][j + 1];
         }
-        if (active) out[(int64_t)y * osy + x] = acc;
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            T acc = (T)0;
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const int r = (MASK >> a) & 1 ? 2 : 1;
+                const T c = win[a][2 + t];
+                const T xm1 = shfl_up(c, 1), xp1 = shfl_down(c, 1);
+                const int q = d.pt0[a + 1];
+                if (r == 1) {
+                    acc = fmaT<T>((T)d.prm[q + 0], c, acc);
+                    acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 2], xp1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 3], win[a][1 + t], acc);
+                    acc = fmaT<T>((T)d.prm[q + 4], win[a][3 + t], acc);
+                } else {
+                    const T xm2 = shfl_up(c, 2), xp2 = shfl_down(c, 2);
+                    acc = fmaT<T>((T)d.prm[q + 0], c, acc);
+                    acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 2], xp1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 3], xm2, acc);
+                    acc = fmaT<T>((T)d.prm[q + 4], xp2, acc);
+                    acc = fmaT<T>((T)d.prm[q + 5], win[a][1 + t], acc);
+                    acc = fmaT<T>((T)d.prm[q + 6], win[a][3 + t], acc);
+                    acc = fmaT<T>((T)d.prm[q + 7], win[a][t], acc);
+                    acc = fmaT<T>((T)d.prm[q + 8], win[a][4 + t], acc);
+                }
+            }
+            if (active && y + t < y1) out[(int64_t)(y + t) * osy] = acc;
+        }
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) win[a][j] = win[a][j + TB];
     }
 }
 
@@ -165,21 +178,21 @@ __global__ void __launch_bounds__(kBlockThreads) wsum_generic_kernel(LoopDesc d,
 }
 
 template <typename T, int K, int MASK>
-hipError_t go_march(const LoopDesc &d, const int lo[3], const int hi[3], hipStream_t s) {
-    const int nbx = (hi[0] - lo[0] + kMarchW - 1) / kMarchW;
-    const int nby = (hi[1] - lo[1] + kMarchTY - 1) / kMarchTY;
+hipError_t go_march(const LoopDesc &d, const int lo[3], const int hi[3], int ty, hipStream_t s) {
+    const int nbx = (hi[0] - lo[0] + kMarchOut - 1) / kMarchOut;
+    const int nby = (hi[1] - lo[1] + ty - 1) / ty;
     const int nb = nbx * nby;
     hipLaunchKernelGGL((wsum_march_kernel<T, K, MASK>), dim3(nb), dim3(kMarchW), 0, s, d, lo[0], hi[0], lo[1], hi[1],
-                       nbx, nb);
+                       nbx, nb, ty);
     return hipGetLastError();
 }
 
 template <typename T, int K>
-hipError_t march_k(const LoopDesc &d, int mask, const int lo[3], const int hi[3], hipStream_t s) {
+hipError_t march_k(const LoopDesc &d, int mask, const int lo[3], const int hi[3], int ty, hipStream_t s) {
     switch (mask) {
 #define M(m)                                                                     \
     case m:                                                                      \
-        if constexpr ((m >> K) == 0) return go_march<T, K, m>(d, lo, hi, s);      \
+        if constexpr ((m >> K) == 0) return go_march<T, K, m>(d, lo, hi, ty, s);  \
         break;
         M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15)
 #undef M
@@ -188,14 +201,14 @@ hipError_t march_k(const LoopDesc &d, int mask, const int lo[3], const int hi[3]
 }
 
 template <typename T>
-hipError_t wsum_t(const LoopDesc &d, const Box &b, int march_mask, hipStream_t s) {
+hipError_t wsum_t(const LoopDesc &d, const Box &b, int march_mask, int ty, hipStream_t s) {
     const int k = d.nargs - 1;
     if (march_mask >= 0 && d.ndim == 2 && b.hi[2] - b.lo[2] == 1) {
         switch (k) {
-        case 1: return march_k<T, 1>(d, march_mask, b.lo, b.hi, s);
-        case 2: return march_k<T, 2>(d, march_mask, b.lo, b.hi, s);
-        case 3: return march_k<T, 3>(d, march_mask, b.lo, b.hi, s);
-        case 4: return march_k<T, 4>(d, march_mask, b.lo, b.hi, s);
+        case 1: return march_k<T, 1>(d, march_mask, b.lo, b.hi, ty, s);
+        case 2: return march_k<T, 2>(d, march_mask, b.lo, b.hi, ty, s);
+        case 3: return march_k<T, 3>(d, march_mask, b.lo, b.hi, ty, s);
+        case 4: return march_k<T, 4>(d, march_mask, b.lo, b.hi, ty, s);
         default: break;
         }
     }
@@ -205,9 +218,9 @@ hipError_t wsum_t(const LoopDesc &d, const Box &b, int march_mask, hipStream_t s
 
 }  // namespace
 
-hipError_t launch_wsum(const LoopDesc &d, const Box &b, int dtype, int march_mask, hipStream_t s) {
+hipError_t launch_wsum(const LoopDesc &d, const Box &b, int dtype, int march_mask, int ty, hipStream_t s) {
     if (b.nb <= 0) return hipSuccess;
-    return dtype == TC_F64 ? wsum_t<double>(d, b, march_mask, s) : wsum_t<float>(d, b, march_mask, s);
+    return dtype == TC_F64 ? wsum_t<double>(d, b, march_mask, ty, s) : wsum_t<float>(d, b, march_mask, ty, s);
 }
 
 }  // namespace tc

@@ -65,31 +65,44 @@ def test_random_op_chains(tc, ndim):
         got_t, st = run_gpu_op_chain(tc, ch, data, tc.TC_TILING_SKEWED, tile)
         for g, gt in zip(got, got_t):
             assert np.array_equal(g, gt)
+        hseg = rng.choice([0, 3, 5, 16])
+        say(f"  fused rows per block={hseg}")
+        got_f, st = run_gpu_op_chain(tc, ch, data, tc.TC_TILING_FUSED, (0, hseg, 0))
+        for g, gf in zip(got, got_f):
+            assert np.array_equal(g, gf)
 
 
 @pytest.mark.parametrize("ndim,n,ndat,nloops,tiles", [
     (2, 67, 12, 40, [(0, 16, 0), (24, 7, 0), (67, 67, 0)]),
+    (2, 300, 12, 40, [(0, 0, 0)]),
     (3, 23, 25, 20, [(0, 0, 5), (9, 6, 4)]),
 ])
 def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
     from paper_1704_00693_amd.apps import ChainRunner
     ch = make_chain(ndim, n, ndat, nloops, seed=1 + ndim)
     data = chain_data(ch)
-    ref = oracle.run_chain(ch, data)
+    ref = oracle.run_chain(ch, oracle.run_chain(ch, data))
     results = {}
-    for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0))] + [(tc.TC_TILING_SKEWED, t) for t in tiles]:
+    fused = [(tc.TC_TILING_FUSED, t) for t in [(0, 0, 0), (0, 9, 0), (0, 40, 64), (0, 0, 24)]] if ndim == 2 else []
+    for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0))] + [(tc.TC_TILING_SKEWED, t) for t in tiles] + fused:
         say(f"synthetic chain ndim={ndim} n={n} mode={mode} tile={tile}")
         with tc.Context() as c:
             c.tc_set_tiling(mode, tile)
             r = ChainRunner(c, ch, data)
             r.run()
+            r.run()  # a second flush reuses the cached plan (and the ping-pong buffers)
             results[(mode, tile)] = [r.read(d) for d in range(ndat)]
+            st = c.tc_get_stats()
+            if mode == tc.TC_TILING_FUSED:
+                say(f"  fused groups={st['last_groups']} blocks={st['last_tiles']} steps={st['last_launches']}")
+                assert st["last_groups"] >= 1
     # the generic weighted-sum kernel instead of the register-window one
     import os
     os.environ["TC_WSUM_MARCH"] = "0"
     try:
         with tc.Context() as c:
             r = ChainRunner(c, ch, data)
+            r.run()
             r.run()
             results["generic"] = [r.read(d) for d in range(ndat)]
     finally:
@@ -151,7 +164,7 @@ def test_full_size_2d_chain_sampled(tc):
     centres = [(0, 0), (n - 1, n - 1), (n // 2, 3), (1234, 2987), (4000, 2048)]
     refs = [window_oracle(ch, data, c, 100) for c in centres]
     outs = {}
-    for mode in (tc.TC_TILING_NONE, tc.TC_TILING_SKEWED):
+    for mode in (tc.TC_TILING_NONE, tc.TC_TILING_SKEWED, tc.TC_TILING_FUSED):
         say(f"full-size 2D chain mode={mode}")
         with tc.Context() as c:
             c.tc_set_tiling(mode, (0, 0, 0))
@@ -169,3 +182,4 @@ def test_full_size_2d_chain_sampled(tc):
                 assert rel_err(got, want) <= TOL
     for d in range(ch.ndat):
         assert np.array_equal(outs[0][d], outs[1][d])
+        assert np.array_equal(outs[0][d], outs[2][d])
