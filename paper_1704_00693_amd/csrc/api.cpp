@@ -378,6 +378,20 @@ std::shared_ptr<CachedPlan> build_plan(Ctx &c, const std::vector<LoopRec> &chain
 // ---------------------------------------------------------------------------
 // flush
 // ---------------------------------------------------------------------------
+// Extend the hull of points ever written of every dataset the loop writes.
+void note_loop_writes(Ctx &c, const LoopRec &lp) {
+    if (lp.points() == 0) return;
+    for (const auto &a : lp.args) {
+        if (!a.writes()) continue;
+        Dataset &ds = c.dats[a.handle];
+        for (int d = 0; d < 3; ++d) {
+            ds.wlo[d] = ds.ever_written ? std::min(ds.wlo[d], lp.lo[d]) : lp.lo[d];
+            ds.whi[d] = ds.ever_written ? std::max(ds.whi[d], lp.hi[d]) : lp.hi[d];
+        }
+        ds.ever_written = true;
+    }
+}
+
 tc_status ensure_events(Ctx &c, size_t n) {
     while (c.events.size() < n) {
         hipEvent_t e;
@@ -410,9 +424,12 @@ tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, const CachedPl
             Box b = make_box(chain[L.loop].ndim, L.lo, L.hi);
             HIPCHK(c, launch_loop(d, b, dat_dtype(c, chain[L.loop], 0), dat_dtype(c, chain[L.loop], 1),
                                   march[L.loop], c.march_ty, c.stream));
+            note_loop_writes(c, chain[L.loop]);
         } else {
+            const FusedGroup &G = *P.groups[S.index];
             tc_status st = fused_run(c, chain, *P.groups[S.index]);
             if (st != TC_OK) return st;
+            for (int l = G.g0; l < G.g1; ++l) note_loop_writes(c, chain[l]);
             std::fill(built.begin(), built.end(), 0);  // buffers were swapped
         }
         if (c.profiling) HIPCHK(c, hipEventRecord(c.events[2 * i + 1], c.stream));
@@ -430,25 +447,6 @@ tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, const CachedPl
         c.stats.prof_launches = (int64_t)i;
     }
     return TC_OK;
-}
-
-void note_writes(Ctx &c, const std::vector<LoopRec> &chain) {
-    for (const auto &lp : chain)
-        for (const auto &a : lp.args) {
-            if (!a.writes()) continue;
-            Dataset &ds = c.dats[a.handle];
-            if (lp.points() == 0) continue;
-            for (int d = 0; d < 3; ++d) {
-                if (!ds.ever_written) {
-                    ds.wlo[d] = lp.lo[d];
-                    ds.whi[d] = lp.hi[d];
-                } else {
-                    ds.wlo[d] = std::min(ds.wlo[d], lp.lo[d]);
-                    ds.whi[d] = std::max(ds.whi[d], lp.hi[d]);
-                }
-            }
-            ds.ever_written = true;
-        }
 }
 
 tc_status flush(Ctx &c) {
@@ -507,7 +505,6 @@ tc_status flush(Ctx &c) {
         }
         for (int d = 0; d < 3; ++d) c.stats.max_skew[d] = P->max_skew[d];
     }
-    note_writes(c, chain);
 
     if (!red_handles.empty()) {
         st = ensure_partials(c, 0, (int)red_handles.size());

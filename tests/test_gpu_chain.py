@@ -95,7 +95,8 @@ def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
             st = c.tc_get_stats()
             if mode == tc.TC_TILING_FUSED:
                 say(f"  fused groups={st['last_groups']} blocks={st['last_tiles']} steps={st['last_launches']}")
-                assert st["last_groups"] >= 1
+                if tile[2] == 0 or tile[2] >= 64:
+                    assert st["last_groups"] >= 1
     # the generic weighted-sum kernel instead of the register-window one
     import os
     os.environ["TC_WSUM_MARCH"] = "0"
