@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--modes", default="none,skewed,fused")
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--cpu-sample", type=int, default=2048, help="grid edge of the oracle's timed sample (0: skip)")
+    ap.add_argument("--fused-tile", default="0,0,0",
+                    help="fused mode tile: rows per step (2 or 4), rows per workgroup (0 auto), LDS KiB (0 auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -153,7 +155,8 @@ def main():
             mode = MODE_NAMES[name]
             log(f"mode {name}: warmup {args.warmup}, steps {args.steps}")
             try:
-                results[name] = time_mode(tc, ctx, runner, mode, (0, 0, 0), args.steps, args.warmup, cells)
+                tile = tuple(int(v) for v in args.fused_tile.split(",")) if name == "fused" else (0, 0, 0)
+                results[name] = time_mode(tc, ctx, runner, mode, tile, args.steps, args.warmup, cells)
             except tc.TcError as e:
                 if e.status != tc.TC_ERR_UNSUPPORTED:
                     raise

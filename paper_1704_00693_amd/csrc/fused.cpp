@@ -107,7 +107,7 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     if (W < 32) return false;
 
     // forward pass: lags (rows)
-    const int R = kFRows;
+    const int R = G.rows;
     std::vector<int> lag(n, 0);
     std::vector<int> lastw(nr, -1);
     std::vector<std::vector<std::pair<int, int>>> readers(nr);  // (lag, dymin) of every earlier reader
@@ -165,7 +165,7 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
             int l = INT_MAX;
             if (live) l = live_lag[r] - R;
             if (written) l = std::min(l, wmin[r] - R);
-            rd.load_lag = l - R;  // one extra step of prefetch distance
+            rd.load_lag = l;
             top = std::min(top, rd.load_lag);
         }
         if (written) {
@@ -198,6 +198,12 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
         }
     }
     if (lds > lds_budget) return false;
+    D.nload = D.nstore = 0;
+    for (int r = 0; r < nr; ++r) {
+        if (D.rings[r].load) D.load_list[D.nload++] = r;
+        if (D.rings[r].store) D.store_list[D.nstore++] = r;
+    }
+    if (D.nload > kFMaxLoaded) return false;
 
     // loops and their entries
     int e = 0, in = 0;
@@ -222,6 +228,8 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
             I.ring = ring_of[lp.args[a].handle];
             I.ent0 = e;
             I.nent = st.npoints();
+            I.star = canonical_star2(st);
+            if (I.star < 0) I.star = 0;
             for (int p = 0; p < st.npoints(); ++p, ++e) {
                 D.ent[e].ring = (short)I.ring;
                 D.ent[e].dx = (signed char)st.pts[3 * p];
@@ -232,6 +240,7 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
         L.nin = in - L.in0;
     }
     D.nin = in;
+    D.R = R;
     D.HR = HR;
     D.W = W;
     G.g0 = g0;
@@ -269,6 +278,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(const Ctx &c, const std::ve
                                                      const int tile[3]) {
     std::vector<std::shared_ptr<FusedGroup>> out;
     const int budget = (tile[2] > 0 ? tile[2] : 156) * 1024;
+    const int rows = (tile[0] == 2 || tile[0] == 8) ? tile[0] : 4;
     const int L = (int)chain.size();
     int g0 = 0;
     while (g0 < L) {
@@ -276,11 +286,13 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(const Ctx &c, const std::ve
         int g1 = g0;
         for (int cand = g0 + 1; cand <= L; ++cand) {
             FusedGroup G;
+            G.rows = rows;
             if (!analyse(c, chain, g0, cand, tile, budget, G)) break;
             *best = G;
             g1 = cand;
         }
         if (g1 - g0 >= 2) {
+            best->hseg_req = tile[1];
             out.push_back(best);
             g0 = g1;
         } else {
@@ -323,7 +335,7 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
         }
     const int width = dom[1] - dom[0], height = dom[3] - dom[2];
     const int nbx = (width + T.W - 1) / T.W;
-    int Hseg = c.tile[1] > 0 ? c.tile[1] : 0;
+    int Hseg = G.hseg_req;
     if (Hseg <= 0) {
         int nby = std::max(1, (int)std::lround(256.0 / nbx));
         Hseg = std::max(16, (height + nby - 1) / nby);
@@ -383,7 +395,7 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
         return fail(c, TC_ERR_DEVICE, "hipMemcpyAsync (fused descriptor) failed");
     if (hipEventRecord(G.uploaded, c.stream) != hipSuccess) return fail(c, TC_ERR_DEVICE, "hipEventRecord failed");
     G.nblocks = nbx * nby;
-    hipError_t e = launch_fused(G.dev, G.dtype, G.nblocks, G.lds_bytes, c.stream);
+    hipError_t e = launch_fused(G.dev, G.dtype, G.rows, G.nblocks, G.lds_bytes, c.stream);
     if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "fused kernel launch failed: %s", hipGetErrorString(e));
     // the written datasets now live in their second buffers
     for (int r = 0; r < D.nrings; ++r)

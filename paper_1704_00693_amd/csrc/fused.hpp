@@ -21,10 +21,12 @@ namespace tc {
 
 constexpr int kFMaxLoops = 16;
 constexpr int kFMaxRings = 16;
+constexpr int kFMaxLoaded = 12;  // rings with a loader (register buffers per thread)
 constexpr int kFMaxEnt = 384;
 constexpr int kFCols = 128;     // ring width in columns = threads per row
-constexpr int kFRows = 2;       // rows per step
-constexpr int kFThreads = kFCols * kFRows;
+// Workgroup: 128 columns x 2 thread rows (256 threads); every thread computes
+// 1, 2 or 4 consecutive rows per step, so a step covers 2, 4 or 8 rows.
+constexpr int kFThreadRows = 2;
 
 struct FLoopD {
     int out_ring;
@@ -37,6 +39,7 @@ struct FLoopD {
 
 struct FInD {   // one input of a loop: ring and its entries
     int ring, ent0, nent;
+    int star;   // 1 or 2: canonical radius-1/2 star (centre, -x, +x, [-2x, +2x,] -y, +y, [-2y, +2y]); 0: entries
 };
 
 struct FRingD {
@@ -61,6 +64,9 @@ struct FEnt {
 
 struct FGroupD {
     int nloops, nrings, nin;
+    int R;  // rows per step
+    int nload, nstore;
+    int load_list[kFMaxRings], store_list[kFMaxRings];  // rings with a loader / a storer
     int W, HR, Hseg;
     int dom_xlo, dom_ylo, nbx, nby;
     FLoopD loops[kFMaxLoops];
@@ -74,6 +80,8 @@ struct FGroupD {
 struct FusedGroup {
     int g0, g1;               // loops [g0, g1) of the chain
     int dtype;
+    int rows = 2;             // rows per step (2 or 4)
+    int hseg_req = 0;         // requested rows per workgroup (0: automatic)
     std::vector<int> ring_dat;  // dataset of every ring
     std::vector<int> ring_store;
     FGroupD tmpl;             // descriptor without pointers, store regions or weights
@@ -96,7 +104,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(const Ctx &c, const std::ve
 tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &g);
 
 // Kernel launch (fused_kernel.hip).
-hipError_t launch_fused(const FGroupD *dev_desc, int dtype, int nblocks, int lds_bytes, hipStream_t s);
+hipError_t launch_fused(const FGroupD *dev_desc, int dtype, int rows, int nblocks, int lds_bytes, hipStream_t s);
 
 // Release device memory held for fused execution.
 void fused_release(Ctx &c);
@@ -105,6 +113,7 @@ void fused_release(Ctx &c);
 tc_tiling autotune_choose(Ctx &c, const std::vector<LoopRec> &chain, int tile[3]);
 
 // shared helpers (api.cpp)
+int canonical_star2(const Stencil &st);
 double now_s();
 tc_status fail(Ctx &c, tc_status s, const char *fmt, ...);
 void *dev_alloc(Ctx &c, size_t bytes);
