@@ -401,7 +401,95 @@ tc_status ensure_events(Ctx &c, size_t n) {
     return TC_OK;
 }
 
-tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, const CachedPlan &P) {
+uint64_t fnv(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Per-loop schedules (no fused groups): launch directly, or capture the
+// launches into a graph and replay it when the arguments repeat.
+tc_status run_per_loop_graph(Ctx &c, const std::vector<LoopRec> &chain, CachedPlan &P, bool &done) {
+    done = false;
+    std::vector<LoopDesc> descs(chain.size());
+    std::vector<int> march(chain.size());
+    for (size_t l = 0; l < chain.size(); ++l) {
+        build_desc(c, chain[l], descs[l]);
+        march[l] = c.march_enabled ? wsum_march_mask(c, chain[l]) : -1;
+    }
+    struct Item {
+        LoopDesc d;
+        Box b;
+        int t0, t1, mm;
+    };
+    std::vector<Item> items;
+    items.reserve(P.launches.size());
+    uint64_t h = 1469598103934665603ull;
+    for (const auto &L : P.launches) {
+        Item it;
+        it.d = descs[L.loop];
+        for (int j = 0; j < it.d.nred; ++j) it.d.partials[j] = c.partials + 2 * L.part_off[j];
+        it.b = make_box(chain[L.loop].ndim, L.lo, L.hi);
+        it.t0 = dat_dtype(c, chain[L.loop], 0);
+        it.t1 = dat_dtype(c, chain[L.loop], 1);
+        it.mm = march[L.loop];
+        h = fnv(h, &it.d, sizeof(LoopDesc));
+        h = fnv(h, &it.b, sizeof(Box));
+        h = fnv(h, &it.t0, 3 * sizeof(int));
+        items.push_back(it);
+    }
+    h = fnv(h, &c.march_ty, sizeof(int));
+    if (P.gexec && P.ghash == h) {
+        HIPCHK(c, hipGraphLaunch(P.gexec, c.stream));
+        done = true;
+        return TC_OK;
+    }
+    hipStream_t s = c.stream;
+    const bool capture = P.ghash_prev == h;
+    P.ghash_prev = h;
+    if (capture) {
+        if (!c.cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+        s = c.cap_stream;
+    }
+    hipError_t err = hipSuccess;
+    for (const auto &it : items) {
+        err = launch_loop(it.d, it.b, it.t0, it.t1, it.mm, c.march_ty, s);
+        if (err != hipSuccess) break;
+    }
+    if (capture) {
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c.cap_stream, &graph);
+        if (err == hipSuccess) err = e2;
+        if (err == hipSuccess) {
+            if (P.gexec) (void)hipGraphExecDestroy(P.gexec);
+            P.gexec = nullptr;
+            err = hipGraphInstantiate(&P.gexec, graph, nullptr, nullptr, 0);
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        if (err == hipSuccess) {
+            P.ghash = h;
+            err = hipGraphLaunch(P.gexec, c.stream);
+        }
+    }
+    if (err != hipSuccess) return fail(c, TC_ERR_DEVICE, "per-loop launch failed: %s", hipGetErrorString(err));
+    done = true;
+    return TC_OK;
+}
+
+tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, CachedPlan &P) {
+    if (c.use_graphs && !c.profiling && P.groups.empty() && P.launches.size() >= 2) {
+        bool done = false;
+        tc_status st = run_per_loop_graph(c, chain, P, done);
+        if (st != TC_OK) return st;
+        if (done) {
+            for (const auto &L : P.launches) note_loop_writes(c, chain[L.loop]);
+            return TC_OK;
+        }
+    }
     std::vector<LoopDesc> descs(chain.size());
     std::vector<char> built(chain.size(), 0);
     std::vector<int> march(chain.size());
@@ -590,6 +678,7 @@ tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
     }
     if (const char *e = getenv("TC_WSUM_MARCH")) c.march_enabled = atoi(e) != 0;
     if (const char *e = getenv("TC_MARCH_TY")) c.march_ty = std::max(1, atoi(e));
+    if (const char *e = getenv("TC_GRAPHS")) c.use_graphs = atoi(e) != 0;
     if (const char *e = getenv("TC_STAGGER")) c.stagger_unit = std::max(0ll, atoll(e)) / 256 * 256;
     if (!c.host_only) {
         int n = 0;
@@ -627,6 +716,9 @@ tc_status tc_finalize(tc_ctx *ctx) {
             dev_free(c, d.raw[1]);
         }
         fused_release(c);
+        for (auto &kv : c.plans)
+            if (kv.second->gexec) (void)hipGraphExecDestroy(kv.second->gexec);
+        if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
         for (auto e : c.events) (void)hipEventDestroy(e);
         dev_free(c, c.partials);
         dev_free(c, c.red_out);

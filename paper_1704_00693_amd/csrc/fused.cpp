@@ -33,7 +33,7 @@ struct Ext {
 
 bool fusable(const Ctx &c, const LoopRec &lp) {
     if (lp.op != TC_OP_WSUM || lp.ndim != 2) return false;
-    if (lp.args.size() > 9) return false;
+    if (lp.args.size() > 1 + kFMaxIn) return false;
     for (const auto &a : lp.args)
         if (a.kind != TC_ARG_DAT) return false;
     // stencil reach within what a signed byte and the ring width allow
@@ -333,6 +333,9 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
             dom[2] = std::min(dom[2], hull[4 * r + 2]);
             dom[3] = std::max(dom[3], hull[4 * r + 3]);
         }
+    // the first column of every workgroup's ring rows must be even (16-byte
+    // aligned row loads straight into LDS)
+    if (((dom[0] - T.HR) & 1) != 0) dom[0] -= 1;
     const int width = dom[1] - dom[0], height = dom[3] - dom[2];
     const int nbx = (width + T.W - 1) / T.W;
     int Hseg = G.hseg_req;
@@ -390,6 +393,73 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
             rd.hull_ylo = hull[4 * r + 2];
             rd.hull_yhi = hull[4 * r + 3];
         }
+    }
+    // flat records for the kernel's steps
+    for (int i = 0; i < D.nloops; ++i) {
+        const FLoopD &L = D.loops[i];
+        FLoopRec &Q = D.lrec[i];
+        std::memset(&Q, 0, sizeof Q);
+        Q.lag = L.lag;
+        Q.ylo = L.ylo;
+        Q.yhi = L.yhi;
+        Q.vlo = L.vlo;
+        Q.vhi = L.vhi;
+        const FRingD &O = D.rings[L.out_ring];
+        Q.out_off = O.lds_off;
+        Q.out_depth = O.depth;
+        Q.out_inv = O.inv_depth;
+        Q.nin = L.nin;
+        for (int k = 0; k < L.nin; ++k) {
+            const FInD &I = D.ins[L.in0 + k];
+            const FRingD &Rg = D.rings[I.ring];
+            FInRec &J = Q.in[k];
+            J.off = Rg.lds_off;
+            J.depth = Rg.depth;
+            J.inv = Rg.inv_depth;
+            J.star = I.star;
+            J.ent0 = I.ent0;
+            J.nent = I.nent;
+            if (I.star)
+                for (int q = 0; q < I.nent; ++q) Q.w[k][q] = D.w[I.ent0 + q];
+        }
+    }
+    for (int i = 0; i < D.nload; ++i) {
+        const FRingD &Rg = D.rings[D.load_list[i]];
+        FLoadRec &Q = D.ld[i];
+        std::memset(&Q, 0, sizeof Q);
+        Q.src = Rg.src;
+        Q.sy = Rg.sy;
+        Q.off = Rg.lds_off;
+        Q.depth = Rg.depth;
+        Q.inv = Rg.inv_depth;
+        Q.lag = Rg.load_lag;
+        Q.ext_ylo = Rg.ext_ylo;
+        Q.ext_yhi = Rg.ext_yhi;
+        Q.ld_below = Rg.ld_below;
+        Q.ld_above = Rg.ld_above;
+        Q.ext_xlo = Rg.ext_xlo;
+        Q.ext_xhi = Rg.ext_xhi;
+        Q.fw = Rg.load == 2;
+        Q.fw_xlo = Rg.fw_xlo;
+        Q.fw_xhi = Rg.fw_xhi;
+        Q.fw_ylo = Rg.fw_ylo;
+        Q.fw_yhi = Rg.fw_yhi;
+        Q.alloc_xlo = -(int)c.dats[G.ring_dat[D.load_list[i]]].xorg;
+    }
+    for (int i = 0; i < D.nstore; ++i) {
+        const FRingD &Rg = D.rings[D.store_list[i]];
+        FStoreRec &Q = D.st[i];
+        std::memset(&Q, 0, sizeof Q);
+        Q.dst = Rg.dst;
+        Q.sy = Rg.sy;
+        Q.off = Rg.lds_off;
+        Q.depth = Rg.depth;
+        Q.inv = Rg.inv_depth;
+        Q.lag = Rg.store_lag;
+        Q.hxlo = Rg.hull_xlo;
+        Q.hxhi = Rg.hull_xhi;
+        Q.hylo = Rg.hull_ylo;
+        Q.hyhi = Rg.hull_yhi;
     }
     if (hipMemcpyAsync(G.dev, G.host, sizeof(FGroupD), hipMemcpyHostToDevice, c.stream) != hipSuccess)
         return fail(c, TC_ERR_DEVICE, "hipMemcpyAsync (fused descriptor) failed");

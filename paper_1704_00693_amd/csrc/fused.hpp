@@ -62,11 +62,52 @@ struct FEnt {
     signed char dx, dy;
 };
 
+// Flat per-step records read by the kernel (built per flush): one record per
+// loop, per loaded ring and per stored ring, so that a step reads each with a
+// few wide scalar loads and no indirection.
+constexpr int kFMaxIn = 4;  // inputs of a fused loop
+struct FInRec {
+    int off, depth;
+    float inv;
+    int star;  // 1 or 2: canonical star, weights in FLoopRec::w; 0: entries ent0..ent0+nent
+    int ent0, nent;
+};
+struct FLoopRec {
+    int lag, ylo, yhi, vlo, vhi;
+    int out_off, out_depth;
+    float out_inv;
+    int nin, pad[3];
+    FInRec in[kFMaxIn];
+    double w[kFMaxIn][9];
+};
+struct FLoadRec {
+    const void *src;
+    int64_t sy;
+    int off, depth;
+    float inv;
+    int lag;
+    int ext_ylo, ext_yhi, ld_below, ld_above;
+    int ext_xlo, ext_xhi;
+    int fw, fw_xlo, fw_xhi, fw_ylo, fw_yhi;
+    int alloc_xlo;  // first column of the allocated row (aligned to 16 elements)
+};
+struct FStoreRec {
+    void *dst;
+    int64_t sy;
+    int off, depth;
+    float inv;
+    int lag;
+    int hxlo, hxhi, hylo, hyhi;
+};
+
 struct FGroupD {
     int nloops, nrings, nin;
     int R;  // rows per step
     int nload, nstore;
     int load_list[kFMaxRings], store_list[kFMaxRings];  // rings with a loader / a storer
+    FLoopRec lrec[kFMaxLoops];
+    FLoadRec ld[kFMaxLoaded];
+    FStoreRec st[kFMaxRings];
     int W, HR, Hseg;
     int dom_xlo, dom_ylo, nbx, nby;
     FLoopD loops[kFMaxLoops];

@@ -66,50 +66,35 @@ struct Blk {
 };
 
 // Rows handled by a thread at step s: R*s + sub*P + p - lag, p in [0, P).
-template <typename T, int P>
-__device__ __forceinline__ void issue_loads(const FGroupD *__restrict__ g, const Blk &b, int base,
-                                            T (&buf)[kFMaxLoaded][P]) {
-    // every lane loads a clamped, always valid address; write_loads decides
-    // which values enter the ring
-    const int nload = g->nload;
-#pragma unroll
-    for (int i = 0; i < kFMaxLoaded; ++i) {
-        if (i < nload) {
-            const FRingD &Rg = g->rings[g->load_list[i]];
-            const int xc = min(max(b.x, Rg.ext_xlo), Rg.ext_xhi - 1);
-            gconst<T> src = (gconst<T>)Rg.src + xc;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int y = min(max(base + p - Rg.load_lag, Rg.ext_ylo), Rg.ext_yhi - 1);
-                buf[i][p] = src[(int64_t)y * Rg.sy];
-            }
-        }
-    }
-}
-
-template <typename T, int P>
-__device__ __forceinline__ void write_loads(const FGroupD *__restrict__ g, const Blk &b, int base, T *lds,
-                                            const T (&buf)[kFMaxLoaded][P]) {
-    const int nload = g->nload;
-#pragma unroll
-    for (int i = 0; i < kFMaxLoaded; ++i) {
-        if (i < nload) {
-            const int r = g->load_list[i];
-            const FRingD &Rg = g->rings[r];
-            const int ra = max(Rg.ext_ylo, b.Y0 - Rg.ld_below), rb = min(Rg.ext_yhi, b.Y0 + b.Hseg + Rg.ld_above);
-            const bool col = (b.cload >> r) & 1u;
-            const bool fwc = Rg.load == 2 && ((b.cfw >> r) & 1u);
-            const int y0 = base - Rg.load_lag;
-            int sl = slot_of(y0, Rg.depth, Rg.inv_depth);
-            T *ring = lds + Rg.lds_off + b.col;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int y = y0 + p;
-                const bool ok = col && y >= ra && y < rb && !(fwc && y >= Rg.fw_ylo && y < Rg.fw_yhi);
-                if (ok) ring[sl * kFCols] = buf[i][p];
-                sl = wrap(sl + 1, Rg.depth);
-            }
-        }
+// Loaders: the rows a step needs from the chain-start buffers go straight
+// from global memory into their ring slots (global_load_lds, 16 bytes per
+// lane: one wave instruction moves one 128-column FP64 row).  Rows are spread
+// over the wavefronts; a lane loads only if its column pair is needed.  The
+// loads of step s complete before the barrier that ends step s.
+template <typename T, int R>
+__device__ __forceinline__ void issue_row_loads(const FGroupD *__restrict__ g, const Blk &b, int s, T *lds) {
+    constexpr int EPL = 16 / sizeof(T);           // elements per lane
+    constexpr int LANES_PER_ROW = kFCols / EPL;   // 64 (FP64) or 32 (FP32)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwaves = (kFCols * kFThreadRows) >> 6;
+    const int nitems = g->nload * R;
+    const int x0 = b.X0 - b.HR;
+    for (int it = wave; it < nitems; it += nwaves) {  // one row per wavefront
+        const int l = lane;
+        const int i = it / R, p = it % R;
+        const FLoadRec &Q = g->ld[i];
+        const int y = R * s + p - Q.lag;
+        const int ra = max(Q.ext_ylo, b.Y0 - Q.ld_below), rb = min(Q.ext_yhi, b.Y0 + b.Hseg + Q.ld_above);
+        if (y < ra || y >= rb) continue;
+        const int xl = x0 + EPL * l;
+        bool act = l < LANES_PER_ROW && xl + EPL > Q.ext_xlo && xl < Q.ext_xhi;
+        if (Q.fw && y >= Q.fw_ylo && y < Q.fw_yhi) act = act && !(xl >= Q.fw_xlo && xl + EPL <= Q.fw_xhi);
+        if (!act) continue;
+        const T __attribute__((address_space(1))) *src =
+            (const T __attribute__((address_space(1))) *)Q.src + (int64_t)y * Q.sy + xl;
+        T *dst = lds + Q.off + slot_of(y, Q.depth, Q.inv) * kFCols;  // wave-uniform row base
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
+                                         (void __attribute__((address_space(3))) *)dst, 16, 0, 0);
     }
 }
 
@@ -117,7 +102,7 @@ template <typename T, int P>
 __device__ __forceinline__ void compute_and_store(const FGroupD *__restrict__ g, const Blk &b, int base, T *lds) {
     const int nloops = g->nloops;
     for (int l = 0; l < nloops; ++l) {
-        const FLoopD &L = g->loops[l];
+        const FLoopRec &L = g->lrec[l];
         const int ya = max(L.ylo, b.Y0 - L.vlo), yb = min(L.yhi, b.Y0 + b.Hseg + L.vhi);
         const int y0 = base - L.lag;
         if (y0 + P <= ya || y0 >= yb) continue;  // uniform across the thread row
@@ -125,15 +110,17 @@ __device__ __forceinline__ void compute_and_store(const FGroupD *__restrict__ g,
         T acc[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) acc[p] = (T)0;
-        for (int i = 0; i < L.nin; ++i) {
-            const FInD I = g->ins[L.in0 + i];
-            const FRingD &Rg = g->rings[I.ring];
-            const int depth = Rg.depth;
-            const int s0 = slot_of(y0, depth, Rg.inv_depth);
-            const T *ring = lds + Rg.lds_off + b.col;
-            const double *w = g->w + I.ent0;
+        const int nin = L.nin;
+#pragma unroll
+        for (int i = 0; i < kFMaxIn; ++i) {
+            if (i >= nin) break;
+            const FInRec &I = L.in[i];
+            const int depth = I.depth;
+            const int s0 = slot_of(y0, depth, I.inv);
+            const T *ring = lds + I.off + b.col;
             if (I.star) {
                 const int r = I.star;
+                const double *w = L.w[i];
                 // column values of rows y0-r .. y0+P-1+r, then the x neighbours of each row
                 T cv[P + 4];
 #pragma unroll
@@ -182,39 +169,37 @@ __device__ __forceinline__ void compute_and_store(const FGroupD *__restrict__ g,
             } else {
                 for (int k = 0; k < I.nent; ++k) {
                     const FEnt E = g->ent[I.ent0 + k];
-                    const T wk = (T)w[k];
+                    const T wk = (T)g->w[I.ent0 + k];
 #pragma unroll
                     for (int p = 0; p < P; ++p)
                         acc[p] = fmaT<T>(wk, ring[wrap(s0 + p + E.dy, depth) * kFCols + E.dx], acc[p]);
                 }
             }
         }
-        const FRingD &O = g->rings[L.out_ring];
-        T *out = lds + O.lds_off + b.col;
-        int so = slot_of(y0, O.depth, O.inv_depth);
+        T *out = lds + L.out_off + b.col;
+        int so = slot_of(y0, L.out_depth, L.out_inv);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int y = y0 + p;
             if (col && y >= ya && y < yb) out[so * kFCols] = acc[p];
-            so = wrap(so + 1, O.depth);
+            so = wrap(so + 1, L.out_depth);
         }
     }
     const int nstore = g->nstore;
     for (int i = 0; i < nstore; ++i) {
-        const int r = g->store_list[i];
-        const FRingD &Rg = g->rings[r];
-        const int ya = max(Rg.hull_ylo, b.Y0), yb = min(Rg.hull_yhi, b.Y0 + b.Hseg);
-        const int y0 = base - Rg.store_lag;
+        const FStoreRec &Q = g->st[i];
+        const int ya = max(Q.hylo, b.Y0), yb = min(Q.hyhi, b.Y0 + b.Hseg);
+        const int y0 = base - Q.lag;
         if (y0 + P <= ya || y0 >= yb) continue;
-        const bool col = (b.cstore >> r) & 1u;
-        const T *ring = lds + Rg.lds_off + b.col;
-        gmut<T> dst = (gmut<T>)Rg.dst + b.x;
-        int sl = slot_of(y0, Rg.depth, Rg.inv_depth);
+        const bool col = (b.cstore >> i) & 1u;
+        const T *ring = lds + Q.off + b.col;
+        gmut<T> dst = (gmut<T>)Q.dst + b.x;
+        int sl = slot_of(y0, Q.depth, Q.inv);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int y = y0 + p;
-            if (col && y >= ya && y < yb) dst[(int64_t)y * Rg.sy] = ring[sl * kFCols];
-            sl = wrap(sl + 1, Rg.depth);
+            if (col && y >= ya && y < yb) dst[(int64_t)y * Q.sy] = ring[sl * kFCols];
+            sl = wrap(sl + 1, Q.depth);
         }
     }
 }
@@ -253,40 +238,32 @@ __global__ void __launch_bounds__(kFCols * kFThreadRows) fused_kernel(const FGro
             s_hi = max(s_hi, floor_div<R>(e - 1 + L.lag));
         }
     }
-    for (int r = 0; r < g->nrings; ++r) {
-        const FRingD &Rg = g->rings[r];
-        if (b.x >= Rg.ext_xlo && b.x < Rg.ext_xhi) b.cload |= 1u << r;
-        if (b.x >= Rg.fw_xlo && b.x < Rg.fw_xhi) b.cfw |= 1u << r;
-        if (b.x >= max(Rg.hull_xlo, b.X0) && b.x < min(Rg.hull_xhi, b.X0 + b.W)) b.cstore |= 1u << r;
-        if (Rg.load) {
-            const int a = max(Rg.ext_ylo, b.Y0 - Rg.ld_below), e = min(Rg.ext_yhi, b.Y0 + b.Hseg + Rg.ld_above);
-            if (a < e) {
-                s_lo = min(s_lo, floor_div<R>(a + Rg.load_lag));
-                s_hi = max(s_hi, floor_div<R>(e - 1 + Rg.load_lag));
-            }
+    for (int i = 0; i < g->nload; ++i) {
+        const FLoadRec &Q = g->ld[i];
+        if (b.x >= Q.ext_xlo && b.x < Q.ext_xhi) b.cload |= 1u << i;
+        if (Q.fw && b.x >= Q.fw_xlo && b.x < Q.fw_xhi) b.cfw |= 1u << i;
+        const int a = max(Q.ext_ylo, b.Y0 - Q.ld_below), e = min(Q.ext_yhi, b.Y0 + b.Hseg + Q.ld_above);
+        if (a < e) {
+            s_lo = min(s_lo, floor_div<R>(a + Q.lag));
+            s_hi = max(s_hi, floor_div<R>(e - 1 + Q.lag));
         }
-        if (Rg.store) {
-            const int a = max(Rg.hull_ylo, b.Y0), e = min(Rg.hull_yhi, b.Y0 + b.Hseg);
-            if (a < e) {
-                s_lo = min(s_lo, floor_div<R>(a + Rg.store_lag));
-                s_hi = max(s_hi, floor_div<R>(e - 1 + Rg.store_lag));
-            }
+    }
+    for (int i = 0; i < g->nstore; ++i) {
+        const FStoreRec &Q = g->st[i];
+        if (b.x >= max(Q.hxlo, b.X0) && b.x < min(Q.hxhi, b.X0 + b.W)) b.cstore |= 1u << i;
+        const int a = max(Q.hylo, b.Y0), e = min(Q.hyhi, b.Y0 + b.Hseg);
+        if (a < e) {
+            s_lo = min(s_lo, floor_div<R>(a + Q.lag));
+            s_hi = max(s_hi, floor_div<R>(e - 1 + Q.lag));
         }
     }
     if (s_lo > s_hi) return;  // uniform: nothing to do for this block
 
     const int sub0 = b.sub * P;
-    T bufA[kFMaxLoaded][P], bufB[kFMaxLoaded][P];
-    issue_loads<T, P>(g, b, R * s_lo + sub0, bufA);
-    for (int s = s_lo; s <= s_hi; s += 2) {
-        issue_loads<T, P>(g, b, R * (s + 1) + sub0, bufB);
+    for (int s = s_lo; s <= s_hi; ++s) {
+        issue_row_loads<T, R>(g, b, s, lds);
         compute_and_store<T, P>(g, b, R * s + sub0, lds);
-        write_loads<T, P>(g, b, R * s + sub0, lds, bufA);
-        __syncthreads();
-        if (s + 1 > s_hi) break;
-        issue_loads<T, P>(g, b, R * (s + 2) + sub0, bufA);
-        compute_and_store<T, P>(g, b, R * (s + 1) + sub0, lds);
-        write_loads<T, P>(g, b, R * (s + 1) + sub0, lds, bufB);
+        __builtin_amdgcn_s_waitcnt(0);  // this step's row loads have landed in LDS
         __syncthreads();
     }
 }

@@ -167,6 +167,10 @@ struct CachedPlan {
     std::vector<std::shared_ptr<FusedGroup>> groups;  // fused mode
     double build_seconds = 0.0;
     int max_skew[3] = {0, 0, 0};
+    // per-loop schedules replayed as a HIP graph once the same launch
+    // arguments have been seen on two consecutive flushes
+    hipGraphExec_t gexec = nullptr;
+    uint64_t ghash = 0, ghash_prev = 0;
 };
 
 struct Ctx {
@@ -204,8 +208,11 @@ struct Ctx {
     // weighted-sum loops on canonical 2D star stencils use the register-window
     // kernel (TC_WSUM_MARCH=0 in the environment selects the generic kernel)
     bool march_enabled = true;
-    int march_ty = 16;            // rows per workgroup of the register-window kernel
+    int march_ty = 8;             // rows per workgroup of the register-window kernel
     int64_t stagger_unit = 0;     // dataset i's base is offset by (i % 16) * stagger_unit bytes
+
+    bool use_graphs = true;              // TC_GRAPHS=0 disables graph replay
+    hipStream_t cap_stream = nullptr;    // private stream used only for graph capture
 
     // per-launch kernel timing (tc_set_profiling)
     bool profiling = false;

@@ -81,7 +81,7 @@ def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
     from paper_1704_00693_amd.apps import ChainRunner
     ch = make_chain(ndim, n, ndat, nloops, seed=1 + ndim)
     data = chain_data(ch)
-    ref = oracle.run_chain(ch, oracle.run_chain(ch, data))
+    ref = oracle.run_chain(ch, oracle.run_chain(ch, oracle.run_chain(ch, data)))
     results = {}
     fused = [(tc.TC_TILING_FUSED, t) for t in [(0, 0, 0), (0, 9, 0), (0, 40, 64), (0, 0, 24)]] if ndim == 2 else []
     for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0))] + [(tc.TC_TILING_SKEWED, t) for t in tiles] + fused:
@@ -91,6 +91,7 @@ def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
             r = ChainRunner(c, ch, data)
             r.run()
             r.run()  # a second flush reuses the cached plan (and the ping-pong buffers)
+            r.run()  # a third replays the captured graph (per-loop schedules)
             results[(mode, tile)] = [r.read(d) for d in range(ndat)]
             st = c.tc_get_stats()
             if mode == tc.TC_TILING_FUSED:
@@ -103,6 +104,7 @@ def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
     try:
         with tc.Context() as c:
             r = ChainRunner(c, ch, data)
+            r.run()
             r.run()
             r.run()
             results["generic"] = [r.read(d) for d in range(ndat)]
