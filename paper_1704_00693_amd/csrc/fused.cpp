@@ -277,8 +277,8 @@ void group_domain(const Ctx &c, const std::vector<LoopRec> &chain, const FusedGr
 std::vector<std::shared_ptr<FusedGroup>> fused_split(const Ctx &c, const std::vector<LoopRec> &chain,
                                                      const int tile[3]) {
     std::vector<std::shared_ptr<FusedGroup>> out;
-    const int budget = (tile[2] > 0 ? tile[2] : 156) * 1024;
-    const int rows = (tile[0] == 2 || tile[0] == 8) ? tile[0] : 4;
+    const int budget = (tile[2] > 0 ? tile[2] : 158) * 1024 - kFDescLds;
+    const int rows = (tile[0] == 2 || tile[0] == 8 || tile[0] == 16) ? tile[0] : 4;
     const int L = (int)chain.size();
     int g0 = 0;
     while (g0 < L) {
@@ -358,6 +358,7 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
     FGroupD &D = *G.host;
     std::memcpy(&D, &T, sizeof(FGroupD));
     D.Hseg = Hseg;
+    D.ring_bytes = G.lds_bytes;
     D.dom_xlo = dom[0];
     D.dom_ylo = dom[2];
     D.nbx = nbx;
@@ -465,7 +466,7 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
         return fail(c, TC_ERR_DEVICE, "hipMemcpyAsync (fused descriptor) failed");
     if (hipEventRecord(G.uploaded, c.stream) != hipSuccess) return fail(c, TC_ERR_DEVICE, "hipEventRecord failed");
     G.nblocks = nbx * nby;
-    hipError_t e = launch_fused(G.dev, G.dtype, G.rows, G.nblocks, G.lds_bytes, c.stream);
+    hipError_t e = launch_fused(G.dev, G.dtype, G.rows, G.nblocks, G.lds_bytes + kFDescLds, c.stream);
     if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "fused kernel launch failed: %s", hipGetErrorString(e));
     // the written datasets now live in their second buffers
     for (int r = 0; r < D.nrings; ++r)

@@ -24,9 +24,9 @@ constexpr int kFMaxRings = 16;
 constexpr int kFMaxLoaded = 12;  // rings with a loader (register buffers per thread)
 constexpr int kFMaxEnt = 384;
 constexpr int kFCols = 128;     // ring width in columns = threads per row
-// Workgroup: 128 columns x 2 thread rows (256 threads); every thread computes
-// 1, 2 or 4 consecutive rows per step, so a step covers 2, 4 or 8 rows.
-constexpr int kFThreadRows = 2;
+// Workgroup: 128 columns x TR thread rows (256, 512 or 1024 threads); every
+// thread computes P consecutive rows per step: rows per step 2 (TR 2), 4
+// (TR 4), 8 (TR 8) or 16 (TR 8, P 2).
 
 struct FLoopD {
     int out_ring;
@@ -100,9 +100,16 @@ struct FStoreRec {
     int hxlo, hxhi, hylo, hyhi;
 };
 
+// bytes of LDS after the rings holding the step records (copied there at
+// kernel start: LDS broadcast reads are much cheaper than scalar loads that
+// miss the scalar cache)
+constexpr int kFDescLds = ((int)(sizeof(FLoopRec) * kFMaxLoops + sizeof(FLoadRec) * kFMaxLoaded +
+                                 sizeof(FStoreRec) * kFMaxRings) + 255) / 256 * 256;
+
 struct FGroupD {
     int nloops, nrings, nin;
-    int R;  // rows per step
+    int R;           // rows per step
+    int ring_bytes;  // LDS bytes of the rings (step records follow)
     int nload, nstore;
     int load_list[kFMaxRings], store_list[kFMaxRings];  // rings with a loader / a storer
     FLoopRec lrec[kFMaxLoops];

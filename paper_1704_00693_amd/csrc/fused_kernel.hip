@@ -2,8 +2,9 @@
 // domain through every loop of the group, with each dataset's rows held in a
 // ring buffer in LDS (see fused.hpp for the scheme).
 //
-// Workgroup: 128 columns x 2 thread rows; each thread computes P = 1, 2 or 4
-// consecutive rows, so a step covers R = 2P rows.  Per step:
+// Workgroup: 128 columns x TR thread rows (TR = 2, 4 or 8 wavefront pairs);
+// each thread computes P = 1 or 2 consecutive rows, so a step covers R = TR*P
+// rows.  Per step:
 //   1. loaders issue the global loads for the NEXT step's rows (two register
 //      sets alternate, so a load has a whole step to arrive),
 //   2. every loop computes its R rows from the rings and writes its output
@@ -61,6 +62,9 @@ template <typename T>
 using gmut = T __attribute__((address_space(1))) *;
 
 struct Blk {
+    const FLoopRec *lrec;   // step records copied into LDS
+    const FLoadRec *ld;
+    const FStoreRec *st;
     int X0, Y0, W, Hseg, HR, x, col, sub;
     uint32_t cload, cfw, cstore, cloop;  // per-thread column tests, one bit per ring / loop
 };
@@ -71,18 +75,18 @@ struct Blk {
 // lane: one wave instruction moves one 128-column FP64 row).  Rows are spread
 // over the wavefronts; a lane loads only if its column pair is needed.  The
 // loads of step s complete before the barrier that ends step s.
-template <typename T, int R>
+template <typename T, int R, int TR>
 __device__ __forceinline__ void issue_row_loads(const FGroupD *__restrict__ g, const Blk &b, int s, T *lds) {
     constexpr int EPL = 16 / sizeof(T);           // elements per lane
     constexpr int LANES_PER_ROW = kFCols / EPL;   // 64 (FP64) or 32 (FP32)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nwaves = (kFCols * kFThreadRows) >> 6;
+    const int nwaves = (kFCols * TR) >> 6;
     const int nitems = g->nload * R;
     const int x0 = b.X0 - b.HR;
     for (int it = wave; it < nitems; it += nwaves) {  // one row per wavefront
         const int l = lane;
         const int i = it / R, p = it % R;
-        const FLoadRec &Q = g->ld[i];
+        const FLoadRec &Q = b.ld[i];
         const int y = R * s + p - Q.lag;
         const int ra = max(Q.ext_ylo, b.Y0 - Q.ld_below), rb = min(Q.ext_yhi, b.Y0 + b.Hseg + Q.ld_above);
         if (y < ra || y >= rb) continue;
@@ -98,11 +102,58 @@ __device__ __forceinline__ void issue_row_loads(const FGroupD *__restrict__ g, c
     }
 }
 
+// One input read through a canonical radius-RAD star, for P consecutive rows
+// starting at ring slot s0: every LDS read is issued first (rows s0-RAD ..
+// s0+P-1+RAD of the thread's column, then the x neighbours of each row), then
+// the fmas in the listed order (centre, -x, +x, [-2x, +2x,] -y, +y, [-2y, +2y]).
+template <typename T, int P, int RAD>
+__device__ __forceinline__ void star_input(const T *ring, int s0, int depth, const double *w, T (&acc)[P]) {
+    T cv[P + 2 * RAD];
+    int sl[P + 2 * RAD];
+#pragma unroll
+    for (int j = 0; j < P + 2 * RAD; ++j) sl[j] = wrap(s0 + j - RAD, depth) * kFCols;
+#pragma unroll
+    for (int j = 0; j < P + 2 * RAD; ++j) cv[j] = ring[sl[j]];
+    T xn[P][2 * RAD];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const T *c = ring + sl[p + RAD];
+        xn[p][0] = c[-1];
+        xn[p][1] = c[1];
+        if (RAD == 2) {
+            xn[p][2] = c[-2];
+            xn[p][3] = c[2];
+        }
+    }
+    T wt[RAD == 1 ? 5 : 9];
+#pragma unroll
+    for (int k = 0; k < (RAD == 1 ? 5 : 9); ++k) wt[k] = (T)w[k];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        T a = acc[p];
+        a = fmaT<T>(wt[0], cv[p + RAD], a);
+        a = fmaT<T>(wt[1], xn[p][0], a);
+        a = fmaT<T>(wt[2], xn[p][1], a);
+        if (RAD == 1) {
+            a = fmaT<T>(wt[3], cv[p], a);
+            a = fmaT<T>(wt[4], cv[p + 2], a);
+        } else {
+            a = fmaT<T>(wt[3], xn[p][2], a);
+            a = fmaT<T>(wt[4], xn[p][3], a);
+            a = fmaT<T>(wt[5], cv[p + 1], a);
+            a = fmaT<T>(wt[6], cv[p + 3], a);
+            a = fmaT<T>(wt[7], cv[p], a);
+            a = fmaT<T>(wt[8], cv[p + 4], a);
+        }
+        acc[p] = a;
+    }
+}
+
 template <typename T, int P>
 __device__ __forceinline__ void compute_and_store(const FGroupD *__restrict__ g, const Blk &b, int base, T *lds) {
     const int nloops = g->nloops;
     for (int l = 0; l < nloops; ++l) {
-        const FLoopRec &L = g->lrec[l];
+        const FLoopRec &L = b.lrec[l];
         const int ya = max(L.ylo, b.Y0 - L.vlo), yb = min(L.yhi, b.Y0 + b.Hseg + L.vhi);
         const int y0 = base - L.lag;
         if (y0 + P <= ya || y0 >= yb) continue;  // uniform across the thread row
@@ -118,54 +169,10 @@ __device__ __forceinline__ void compute_and_store(const FGroupD *__restrict__ g,
             const int depth = I.depth;
             const int s0 = slot_of(y0, depth, I.inv);
             const T *ring = lds + I.off + b.col;
-            if (I.star) {
-                const int r = I.star;
-                const double *w = L.w[i];
-                // column values of rows y0-r .. y0+P-1+r, then the x neighbours of each row
-                T cv[P + 4];
-#pragma unroll
-                for (int j = 0; j < P + 4; ++j)
-                    if (j < P + 2 * r) cv[j] = ring[wrap(s0 + j - r, depth) * kFCols];
-                T xn[P][4];
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const T *c = ring + wrap(s0 + p, depth) * kFCols;
-                    xn[p][0] = c[-1];
-                    xn[p][1] = c[1];
-                    if (r == 2) {
-                        xn[p][2] = c[-2];
-                        xn[p][3] = c[2];
-                    }
-                }
-                const T w0 = (T)w[0], w1 = (T)w[1], w2 = (T)w[2], w3 = (T)w[3], w4 = (T)w[4];
-                if (r == 1) {
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        T a = acc[p];
-                        a = fmaT<T>(w0, cv[p + 1], a);
-                        a = fmaT<T>(w1, xn[p][0], a);
-                        a = fmaT<T>(w2, xn[p][1], a);
-                        a = fmaT<T>(w3, cv[p], a);
-                        a = fmaT<T>(w4, cv[p + 2], a);
-                        acc[p] = a;
-                    }
-                } else {
-                    const T w5 = (T)w[5], w6 = (T)w[6], w7 = (T)w[7], w8 = (T)w[8];
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        T a = acc[p];
-                        a = fmaT<T>(w0, cv[p + 2], a);
-                        a = fmaT<T>(w1, xn[p][0], a);
-                        a = fmaT<T>(w2, xn[p][1], a);
-                        a = fmaT<T>(w3, xn[p][2], a);
-                        a = fmaT<T>(w4, xn[p][3], a);
-                        a = fmaT<T>(w5, cv[p + 1], a);
-                        a = fmaT<T>(w6, cv[p + 3], a);
-                        a = fmaT<T>(w7, cv[p], a);
-                        a = fmaT<T>(w8, cv[p + 4], a);
-                        acc[p] = a;
-                    }
-                }
+            if (I.star == 2) {
+                star_input<T, P, 2>(ring, s0, depth, L.w[i], acc);
+            } else if (I.star == 1) {
+                star_input<T, P, 1>(ring, s0, depth, L.w[i], acc);
             } else {
                 for (int k = 0; k < I.nent; ++k) {
                     const FEnt E = g->ent[I.ent0 + k];
@@ -187,7 +194,7 @@ __device__ __forceinline__ void compute_and_store(const FGroupD *__restrict__ g,
     }
     const int nstore = g->nstore;
     for (int i = 0; i < nstore; ++i) {
-        const FStoreRec &Q = g->st[i];
+        const FStoreRec &Q = b.st[i];
         const int ya = max(Q.hylo, b.Y0), yb = min(Q.hyhi, b.Y0 + b.Hseg);
         const int y0 = base - Q.lag;
         if (y0 + P <= ya || y0 >= yb) continue;
@@ -209,12 +216,27 @@ __device__ __forceinline__ int floor_div(int v) {
     return v >= 0 ? v / R : -((-v + R - 1) / R);
 }
 
-template <typename T, int P>
-__global__ void __launch_bounds__(kFCols * kFThreadRows) fused_kernel(const FGroupD *__restrict__ g) {
-    constexpr int R = kFThreadRows * P;
+template <typename T, int TR, int P>
+__global__ void __launch_bounds__(kFCols * TR) fused_kernel(const FGroupD *__restrict__ g) {
+    constexpr int R = TR * P;
     extern __shared__ __align__(16) unsigned char smem[];
     T *lds = (T *)smem;
     Blk b;
+    {
+        // step records into LDS after the rings
+        unsigned char *d = smem + g->ring_bytes;
+        const int n0 = g->nloops * (int)sizeof(FLoopRec), n1 = g->nload * (int)sizeof(FLoadRec),
+                  n2 = g->nstore * (int)sizeof(FStoreRec);
+        const int o1 = (int)sizeof(FLoopRec) * kFMaxLoops, o2 = o1 + (int)sizeof(FLoadRec) * kFMaxLoaded;
+        const uint32_t *s0 = (const uint32_t *)g->lrec, *s1 = (const uint32_t *)g->ld, *s2 = (const uint32_t *)g->st;
+        for (int k = threadIdx.x; k < n0 / 4; k += blockDim.x) ((uint32_t *)d)[k] = s0[k];
+        for (int k = threadIdx.x; k < n1 / 4; k += blockDim.x) ((uint32_t *)(d + o1))[k] = s1[k];
+        for (int k = threadIdx.x; k < n2 / 4; k += blockDim.x) ((uint32_t *)(d + o2))[k] = s2[k];
+        b.lrec = (const FLoopRec *)d;
+        b.ld = (const FLoadRec *)(d + o1);
+        b.st = (const FStoreRec *)(d + o2);
+        __syncthreads();
+    }
     b.W = g->W;
     b.HR = g->HR;
     b.Hseg = g->Hseg;
@@ -239,7 +261,7 @@ __global__ void __launch_bounds__(kFCols * kFThreadRows) fused_kernel(const FGro
         }
     }
     for (int i = 0; i < g->nload; ++i) {
-        const FLoadRec &Q = g->ld[i];
+        const FLoadRec &Q = b.ld[i];
         if (b.x >= Q.ext_xlo && b.x < Q.ext_xhi) b.cload |= 1u << i;
         if (Q.fw && b.x >= Q.fw_xlo && b.x < Q.fw_xhi) b.cfw |= 1u << i;
         const int a = max(Q.ext_ylo, b.Y0 - Q.ld_below), e = min(Q.ext_yhi, b.Y0 + b.Hseg + Q.ld_above);
@@ -249,7 +271,7 @@ __global__ void __launch_bounds__(kFCols * kFThreadRows) fused_kernel(const FGro
         }
     }
     for (int i = 0; i < g->nstore; ++i) {
-        const FStoreRec &Q = g->st[i];
+        const FStoreRec &Q = b.st[i];
         if (b.x >= max(Q.hxlo, b.X0) && b.x < min(Q.hxhi, b.X0 + b.W)) b.cstore |= 1u << i;
         const int a = max(Q.hylo, b.Y0), e = min(Q.hyhi, b.Y0 + b.Hseg);
         if (a < e) {
@@ -261,28 +283,29 @@ __global__ void __launch_bounds__(kFCols * kFThreadRows) fused_kernel(const FGro
 
     const int sub0 = b.sub * P;
     for (int s = s_lo; s <= s_hi; ++s) {
-        issue_row_loads<T, R>(g, b, s, lds);
+        issue_row_loads<T, R, TR>(g, b, s, lds);
         compute_and_store<T, P>(g, b, R * s + sub0, lds);
         __builtin_amdgcn_s_waitcnt(0);  // this step's row loads have landed in LDS
         __syncthreads();
     }
 }
 
-template <typename T, int P>
+template <typename T, int TR, int P>
 hipError_t go(const FGroupD *dev_desc, int nblocks, int lds_bytes, hipStream_t s) {
-    hipError_t e = hipFuncSetAttribute((const void *)fused_kernel<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       lds_bytes);
+    hipError_t e = hipFuncSetAttribute((const void *)fused_kernel<T, TR, P>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((fused_kernel<T, P>), dim3(nblocks), dim3(kFCols * kFThreadRows), lds_bytes, s, dev_desc);
+    hipLaunchKernelGGL((fused_kernel<T, TR, P>), dim3(nblocks), dim3(kFCols * TR), lds_bytes, s, dev_desc);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t go_rows(const FGroupD *dev_desc, int rows, int nblocks, int lds_bytes, hipStream_t s) {
     switch (rows) {
-    case 2: return go<T, 1>(dev_desc, nblocks, lds_bytes, s);
-    case 8: return go<T, 4>(dev_desc, nblocks, lds_bytes, s);
-    default: return go<T, 2>(dev_desc, nblocks, lds_bytes, s);
+    case 2: return go<T, 2, 1>(dev_desc, nblocks, lds_bytes, s);
+    case 8: return go<T, 8, 1>(dev_desc, nblocks, lds_bytes, s);
+    case 16: return go<T, 8, 2>(dev_desc, nblocks, lds_bytes, s);
+    default: return go<T, 4, 1>(dev_desc, nblocks, lds_bytes, s);
     }
 }
 
