@@ -547,7 +547,15 @@ tc_status flush(Ctx &c) {
 
     tc_tiling mode = c.mode;
     int tile[3] = {c.tile[0], c.tile[1], c.tile[2]};
-    if (mode == TC_TILING_AUTO) mode = autotune_choose(c, chain, tile);
+    const bool tuning_flush = mode == TC_TILING_AUTO;
+    if (tuning_flush) {
+        mode = autotune_choose(c, chain, tile);
+        if (c.tune_cand >= 0) {
+            for (auto &e : c.tune_ev)
+                if (!e) HIPCHK(c, hipEventCreate(&e));
+            HIPCHK(c, hipEventRecord(c.tune_ev[0], c.stream));
+        }
+    }
 
     tc_status st = TC_OK;
     int64_t bytes = 0, cells = 0;
@@ -619,6 +627,14 @@ tc_status flush(Ctx &c) {
             }
             r.touched = true;
         }
+    }
+    if (tuning_flush && c.tune_cand >= 0) {
+        HIPCHK(c, hipEventRecord(c.tune_ev[1], c.stream));
+        HIPCHK(c, hipEventSynchronize(c.tune_ev[1]));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c.tune_ev[0], c.tune_ev[1]));
+        autotune_record(c, ms * 1e-3);
+        autotune_finish(c, autotune_candidates(chain));
     }
     c.stats.flushes++;
     c.stats.last_launches = launches;
@@ -720,6 +736,8 @@ tc_status tc_finalize(tc_ctx *ctx) {
             if (kv.second->gexec) (void)hipGraphExecDestroy(kv.second->gexec);
         if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
         for (auto e : c.events) (void)hipEventDestroy(e);
+        for (auto e : c.tune_ev)
+            if (e) (void)hipEventDestroy(e);
         dev_free(c, c.partials);
         dev_free(c, c.red_out);
         if (c.red_host) (void)hipHostFree(c.red_host);

@@ -157,8 +157,13 @@ hipError_t launch_fused(const FGroupD *dev_desc, int dtype, int rows, int nblock
 // Release device memory held for fused execution.
 void fused_release(Ctx &c);
 
-// AUTO mode: the execution mode (and tile, written back) to use for this chain.
+// AUTO mode: the execution mode (and tile, written back) to use for this
+// chain; while candidates are being measured, autotune_record receives the
+// flush's device time and autotune_finish picks the fastest when all ran.
 tc_tiling autotune_choose(Ctx &c, const std::vector<LoopRec> &chain, int tile[3]);
+void autotune_record(Ctx &c, double seconds);
+void autotune_finish(Ctx &c, size_t ncand);
+size_t autotune_candidates(const std::vector<LoopRec> &chain);
 
 // shared helpers (api.cpp)
 int canonical_star2(const Stencil &st);

@@ -194,7 +194,17 @@ struct Ctx {
     int tile[3] = {0, 0, 0};
 
     std::unordered_map<uint64_t, std::shared_ptr<CachedPlan>> plans;
-    std::unordered_map<uint64_t, int> tuned;  // AUTO: chain key -> chosen candidate index
+    // AUTO mode: per chain structure, the candidates tried so far, their
+    // measured device times and the choice once every candidate has run
+    struct Tune {
+        int next = 0;
+        int best = -1;
+        std::vector<double> seconds;
+    };
+    std::unordered_map<uint64_t, Tune> tuned;
+    int tune_cand = -1;          // candidate being timed by the current flush
+    uint64_t tune_key = 0;
+    hipEvent_t tune_ev[2] = {nullptr, nullptr};
 
     // reduction partials (device) and host staging
     double *partials = nullptr;

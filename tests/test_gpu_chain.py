@@ -186,3 +186,27 @@ def test_full_size_2d_chain_sampled(tc):
     for d in range(ch.ndat):
         assert np.array_equal(outs[0][d], outs[1][d])
         assert np.array_equal(outs[0][d], outs[2][d])
+
+
+def test_autotuner_results_identical(tc):
+    """AUTO mode measures every candidate schedule on successive flushes,
+    then keeps the fastest; each flush must give the untiled answer."""
+    from paper_1704_00693_amd.apps import ChainRunner
+    ch = make_chain(2, 200, 8, 12, seed=9)
+    data = chain_data(ch)
+    ref = data
+    modes = []
+    with tc.Context() as c, tc.Context() as u:
+        c.tc_set_tiling(tc.TC_TILING_AUTO, (0, 0, 0))
+        r = ChainRunner(c, ch, data)
+        ru = ChainRunner(u, ch, data)
+        for k in range(8):
+            say(f"autotune flush {k}")
+            r.run()
+            ru.run()
+            modes.append(c.tc_get_stats()["last_mode"])
+            for d in range(ch.ndat):
+                assert np.array_equal(r.read(d), ru.read(d))
+    say(f"  modes used: {modes}")
+    assert len(set(modes[:5])) >= 2          # several candidates were tried
+    assert modes[-1] == modes[-2] == modes[-3]  # then one was kept
