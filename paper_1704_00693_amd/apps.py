@@ -232,3 +232,142 @@ class HeatSolver:
         a = self.ctx.tc_dat_read(self.f[name])
         h, n = self.h, self.n
         return a[tuple([slice(h, h + n)] * self.D)]
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: FP32 stencil sweeps, FP64 reductions, FP64 refinement
+# ---------------------------------------------------------------------------
+class MixedHeatSolver:
+    """Heat-conduction solve to a true FP64 relative residual.
+
+    Iterative refinement: the solution x, the right-hand side b and the true
+    residual r = b - A x live in FP64; every correction A d = r is solved by
+    PPCG with FP32 storage and FP32 stencil sweeps (operator coefficients,
+    directions, preconditioner state), while its dot products and norms
+    accumulate in FP64 (the library's reductions always do).  x += d in FP64.
+    """
+
+    F64 = ("rho", "e", "u0", "u", "kx", "ky", "kz", "r", "d")
+    F32 = ("kx", "ky", "kz", "r", "p", "w", "z", "rt", "sd", "d")
+
+    def __init__(self, ctx: Context, density: np.ndarray, energy: np.ndarray, dt: float = 0.004, halo: int = 2):
+        self.ctx = ctx
+        self.D = density.ndim
+        self.n = n = density.shape[0]
+        self.h = halo
+        self.rx = dt * n * n
+        D = self.D
+        self.blk = ctx.tc_decl_block(D, "heat")
+        shape = tuple([n + 2 * halo] * D)
+        inner = tuple([slice(halo, halo + n)] * D)
+        self.f64: Dict[str, int] = {}
+        self.f32: Dict[str, int] = {}
+        for k in self.F64:
+            if k == "kz" and D < 3:
+                continue
+            init = None
+            if k in ("rho", "e"):
+                init = np.zeros(shape)
+                init[inner] = density if k == "rho" else energy
+            self.f64[k] = ctx.tc_decl_dat(self.blk, [n] * D, [halo] * D, [halo] * D, init, TC_F64, k)
+        for k in self.F32:
+            if k == "kz" and D < 3:
+                continue
+            self.f32[k] = ctx.tc_decl_dat(self.blk, [n] * D, [halo] * D, [halo] * D, None, TC_F32, k + "32")
+        # the FP64 driver shares stencils and helpers with HeatSolver
+        self.H = HeatSolver.__new__(HeatSolver)
+        H = self.H
+        H.ctx, H.D, H.n, H.h, H.rx, H.blk = ctx, D, n, halo, self.rx, self.blk
+        H.f = self.f64
+        z = [0] * D
+
+        def unit(d, s):
+            p = [0] * D
+            p[d] = s
+            return tuple(p)
+
+        H.S_c = ctx.tc_decl_stencil([tuple(z)])
+        H.S_star = ctx.tc_decl_stencil([tuple(z)] + [unit(d, s) for d in range(D) for s in (-1, 1)])
+        H.S_kface = [ctx.tc_decl_stencil([tuple(z), unit(d, 1)]) for d in range(D)]
+        H.S_rho = ctx.tc_decl_stencil([tuple(z)] + [unit(d, -1) for d in range(D)])
+        H.S_reflect = {}
+        for axis in range(D):
+            for side in (0, 1):
+                sgn = 1 if side == 0 else -1
+                H.S_reflect[(axis, side)] = ctx.tc_decl_stencil([tuple(z), unit(axis, sgn * 1), unit(axis, sgn * 3)])
+        H.r_sum = [ctx.tc_decl_reduction(TC_RED_SUM, f"s{i}") for i in range(3)]
+        H.r_max = ctx.tc_decl_reduction(TC_RED_MAX, "lmax")
+        H.interior = [v for _ in range(D) for v in (0, n)]
+
+    def _with(self, fields):
+        self.H.f = fields
+
+    def solve(self, tol: float = 1e-8, inner_tol: float = 1e-4, inner: int = 10, max_refine: int = 50,
+              max_inner_iter: int = 500):
+        """Refine until ||b - A x|| <= tol ||b|| (FP64); each correction runs
+        PPCG in FP32 until its recursive residual falls by ``inner_tol``."""
+        ctx, H = self.ctx, self.H
+        D = self.D
+        self._with(self.f64)
+        lmax = H.setup()
+        theta, delta, al, be = chebyshev_coefs(1.0, lmax, inner)
+        s0, s1, s2 = H.r_sum
+        H.dot("u0", "u0", s0)
+        bnorm = math.sqrt(ctx.tc_reduction_result(s0))
+        # FP32 operator coefficients
+        for k in ["kx", "ky", "kz"][:D]:
+            H.loop("COPY", [(self.f32[k], H.S_c, "W"), (self.f64[k], H.S_c, "R")],
+                   rng=[v for _ in range(D) for v in (0, self.n + 1)], name=f"{k}32")
+        history = []
+        inner_total = 0
+        for it in range(max_refine + 1):
+            # true residual in FP64
+            self._with(self.f64)
+            H.halo_fill("u")
+            H.loop("TEA_RESID", H.K() + [H.F("u", "R", H.S_star), H.F("u0", "R"), H.F("r", "W")])
+            H.dot("r", "r", s0)
+            rnorm = math.sqrt(ctx.tc_reduction_result(s0))
+            history.append(rnorm / bnorm)
+            if rnorm <= tol * bnorm or it == max_refine:
+                break
+            # correction solve in FP32 sweeps: A d = r, d0 = 0
+            H.loop("COPY", [(self.f32["r"], H.S_c, "W"), (self.f64["r"], H.S_c, "R")], name="r32")
+            self._with(self.f32)
+            H.loop("AXPBY", [H.F("d", "RW"), H.F("r", "R")], [0.0, 0.0], name="d=0")
+            H.precondition(theta, al, be, inner)
+            H.loop("COPY", [H.F("p", "W"), H.F("z", "R")])
+            H.dot("r", "z", s0)
+            rz = ctx.tc_reduction_result(s0)
+            r0 = rnorm
+            k = 0
+            while k < max_inner_iter:
+                H.halo_fill("p")
+                H.loop("TEA_MATVEC_DOT", H.K() + [H.F("p", "R", H.S_star), H.F("w", "W"), ("red", s0)])
+                pw = ctx.tc_reduction_result(s0)
+                alpha = rz / pw
+                H.loop("TEA_CG_UPDATE", [H.F("d", "RW"), H.F("r", "RW"), H.F("p", "R"), H.F("w", "R")], [alpha])
+                H.precondition(theta, al, be, inner)
+                H.dot("r", "z", s1)
+                H.dot("r", "r", s2)
+                rz_new = ctx.tc_reduction_result(s1)
+                rr = ctx.tc_reduction_result(s2)
+                k += 1
+                if math.sqrt(rr) <= inner_tol * r0:
+                    break
+                beta = rz_new / rz
+                rz = rz_new
+                H.loop("TEA_CG_P", [H.F("p", "RW"), H.F("z", "R")], [beta])
+            inner_total += k
+            # x += d in FP64
+            self._with(self.f64)
+            H.loop("COPY", [(self.f64["d"], H.S_c, "W"), (self.f32["d"], H.S_c, "R")], name="d64")
+            H.loop("AXPBY", [H.F("u", "RW"), H.F("d", "R")], [1.0, 1.0], name="x+=d")
+        ctx.tc_flush()
+        self._with(self.f64)
+        return {"refinements": len(history) - 1, "inner_iterations": inner_total, "history": history,
+                "lmax": lmax, "bnorm": bnorm}
+
+    def field(self, name: str) -> np.ndarray:
+        a = self.ctx.tc_dat_read(self.f64[name])
+        h, n = self.h, self.n
+        return a[tuple([slice(h, h + n)] * self.D)]

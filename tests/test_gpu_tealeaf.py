@@ -83,3 +83,39 @@ def test_ppcg_converges_to_tolerance(tc):
     x, info, _ = gpu_solve(tc, hp, 0, tol=1e-10)
     assert info["iterations"] == ref.iterations
     assert rel(x, ref.x) <= TOL
+
+
+def true_residual(hp, x):
+    """||b - A x|| / ||b|| evaluated by the oracle's FP64 operator."""
+    from oracle.tealeaf import HeatOracle
+    o = HeatOracle(hp.density, hp.energy)
+    lmax = o.setup()
+    h, n = o.halo, o.n
+    o.f["u"][tuple([slice(h, h + n)] * o.ndim)] = x
+    b = o.inner("u0")
+    return float(np.linalg.norm(b - o.apply_A("u")) / np.linalg.norm(b)), lmax
+
+
+@pytest.mark.parametrize("n,ndim,tol", [(40, 2, 1e-8), (96, 2, 1e-10), (16, 3, 1e-8)])
+def test_mixed_precision_refinement(tc, n, ndim, tol):
+    """FP32 sweeps + FP64 reductions + FP64 refinement reach the FP64 residual
+    tolerance; the error against the FP64 solution is bounded by the condition
+    number (lmax / lmin, lmin = 1) times the two residuals."""
+    from paper_1704_00693_amd.apps import MixedHeatSolver
+    hp = heat_problem(n, seed=3, ndim=ndim)
+    say(f"mixed n={n} ndim={ndim} tol={tol}")
+    with tc.Context() as c:
+        s = MixedHeatSolver(c, hp.density, hp.energy)
+        info = s.solve(tol=tol)
+        x = s.field("u")
+    say(f"  refinements {info['refinements']} inner {info['inner_iterations']} history {info['history']}")
+    assert info["history"][-1] <= tol
+    res, lmax = true_residual(hp, x)
+    say(f"  oracle residual {res:.3e}")
+    assert res <= tol * (1 + 1e-6) + 1e-14
+    ref = ppcg_solve(hp.density, hp.energy, tol=1e-13, max_iter=3000)
+    bound = lmax * (res + 1e-13) * 1.01
+    err = float(np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x))
+    say(f"  error vs FP64 solve {err:.3e} (bound {bound:.3e})")
+    assert err <= bound
+    assert info["refinements"] >= 2  # FP32 alone cannot reach the tolerance
