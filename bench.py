@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--cpu-sample", type=int, default=2048, help="grid edge of the oracle's timed sample (0: skip)")
     ap.add_argument("--fused-tile", default="0,0,0",
-                    help="fused mode tile: rows per step (2 or 4), rows per workgroup (0 auto), LDS KiB (0 auto)")
+                    help="fused mode tile: rows per wavefront segment, window-register budget, most loops per group (0: automatic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "

@@ -212,8 +212,12 @@ tc_status tc_dat_device_view(tc_ctx *ctx, tc_dat dat, void **origin, int64_t str
 /* Choose how the following flushes are tiled (Section 4.3: manual tile sizes
  * or automatic choice).  tile[d] <= 0 means "choose automatically" for that
  * dimension (skewed: the whole extent along x, a cache-sized height along the
- * slowest dimension).  For TC_TILING_FUSED, tile[0] is the workgroup's owned
- * width in x, tile[1] the streamed height, tile[2] the LDS budget in KiB. */
+ * slowest dimension).  For TC_TILING_FUSED (Section 4.4, overlapped tiles
+ * fused per wavefront): tile[0] is the number of rows one wavefront streams
+ * (its segment), tile[1] the budget of register-window words per lane that
+ * bounds a fusion group, tile[2] the most loops in one group; 0 chooses
+ * automatically.  Fused groups are generated and compiled (hipRTC) when a
+ * chain structure is first planned. */
 tc_status tc_set_tiling(tc_ctx *ctx, tc_tiling mode, const int32_t *tile);
 
 typedef struct {

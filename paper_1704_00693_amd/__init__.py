@@ -309,5 +309,18 @@ class Context:
         return num, start, end
 
 
+    def tc_fused_groups(self, tile: Sequence[int] = (0, 0, 0)):
+        """Fusion groups the fused mode would form for the pending chain, as
+        (first, last + 1) loop indices; their kernels are generated and
+        compiled (also on host-only contexts), nothing runs."""
+        t = list(tile) + [0] * (3 - len(tile))
+        nt = (ctypes.c_int32 * 3)()
+        lib().tc_chain_plan(self.ptr, TC_TILING_FUSED, _i32(t), nt, None, 0)
+        cap = max(2 * nt[0], 1)
+        buf = (ctypes.c_int32 * cap)()
+        self._ck(lib().tc_chain_plan(self.ptr, TC_TILING_FUSED, _i32(t), nt, buf, cap), "tc_chain_plan")
+        return [(int(buf[2 * g]), int(buf[2 * g + 1])) for g in range(nt[0])]
+
+
 def tc_status_string(status: int) -> str:
     return lib().tc_status_string(status).decode()

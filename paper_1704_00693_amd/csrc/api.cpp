@@ -580,6 +580,10 @@ tc_status flush(Ctx &c) {
         } else {
             const double pb = now_s();
             P = build_plan(c, chain, mode, tile);
+            if (mode == TC_TILING_FUSED) {
+                st = fused_compile(c, P->groups);
+                if (st != TC_OK) return st;
+            }
             P->build_seconds = now_s() - pb;
             c.stats.plan_seconds += P->build_seconds;
             c.stats.plan_misses++;
@@ -696,6 +700,9 @@ tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (const char *e = getenv("TC_MARCH_TY")) c.march_ty = std::max(1, atoi(e));
     if (const char *e = getenv("TC_GRAPHS")) c.use_graphs = atoi(e) != 0;
     if (const char *e = getenv("TC_STAGGER")) c.stagger_unit = std::max(0ll, atoll(e)) / 256 * 256;
+    if (const char *e = getenv("TC_JIT_UNROLL")) c.jit_unroll = std::min(16, std::max(1, atoi(e)));
+    if (const char *e = getenv("TC_JIT_PREFETCH")) c.jit_prefetch = std::min(8, std::max(1, atoi(e)));
+    if (const char *e = getenv("TC_JIT_BAKE")) c.jit_bake = atoi(e) != 0;
     if (!c.host_only) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || n <= 0 || c.device < 0 || c.device >= n) {
@@ -1051,8 +1058,21 @@ tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_
                         int64_t cap) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
-    if (mode != TC_TILING_SKEWED || !num_tiles) return fail(c, TC_ERR_UNSUPPORTED, "tc_chain_plan: skewed mode only");
+    if ((mode != TC_TILING_SKEWED && mode != TC_TILING_FUSED) || !num_tiles)
+        return fail(c, TC_ERR_UNSUPPORTED, "tc_chain_plan: skewed or fused mode only");
     int t3[3] = {tile ? tile[0] : 0, tile ? tile[1] : 0, tile ? tile[2] : 0};
+    if (mode == TC_TILING_FUSED) {
+        auto groups = fused_split(c, c.chain, t3);
+        num_tiles[0] = (int32_t)groups.size();
+        num_tiles[1] = num_tiles[2] = 1;
+        if (!ranges || cap < 2 * (int64_t)groups.size())
+            return fail(c, TC_ERR_ARG, "tc_chain_plan: need %lld slots", (long long)(2 * groups.size()));
+        for (size_t g = 0; g < groups.size(); ++g) {
+            ranges[2 * g] = groups[g]->g0;
+            ranges[2 * g + 1] = groups[g]->g1;
+        }
+        return fused_compile(c, groups);
+    }
     SkewedPlan P = build_skewed_plan(c, c.chain, t3);
     int maxT = 1;
     for (int d = 0; d < 3; ++d) {

@@ -1,477 +1,764 @@
-// Fusion-group analysis (host) and per-flush launch of fused groups.
-//
-// Dependency analysis follows the overlapped tiling of Section 4.4: a tile
-// extends each loop's range by what the later loops of the tile read from its
-// output (read dependencies only; the tiles run concurrently), so the first
-// loops of a group compute a halo around the owned block that shrinks loop by
-// loop.  Along the streamed dimension the same extents become lags: a loop
-// runs behind the loops it reads from by their read extent plus one step, and
-// a loop that overwrites a dataset runs behind the earlier readers of the old
-// values (the write-after-read rule of Algorithm 1 in streaming form).
+// Fusion groups: analysis, split, kernel generation, hipRTC compilation and
+// launch (the scheme is described in fused.hpp).
+#include "fused.hpp"
+
+#include <hip/hiprtc.h>
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
-
-#include "fused.hpp"
+#include <sstream>
+#include <tuple>
+#include <unordered_map>
 
 namespace tc {
 
 namespace {
 
-struct Ext {
-    int xlo = INT_MIN, xhi = INT_MIN, ylo = INT_MIN, yhi = INT_MIN;  // INT_MIN: not read
-    void add(int a, int b, int c, int d) {
-        xlo = std::max(xlo, a);
-        xhi = std::max(xhi, b);
-        ylo = std::max(ylo, c);
-        yhi = std::max(yhi, d);
-    }
-    bool set() const { return xlo != INT_MIN; }
+int esize_of(int dtype) { return dtype == TC_F64 ? 8 : 4; }
+
+struct SplitParams {
+    int hseg = 0;      // rows per wavefront segment (0: automatic)
+    int regs = 192;    // budget of window registers per lane
+    int max_loops = 32;
+    int U = 4, PF = 2;
+    bool bake = false;
 };
 
-bool fusable(const Ctx &c, const LoopRec &lp) {
-    if (lp.op != TC_OP_WSUM || lp.ndim != 2) return false;
-    if (lp.args.size() > 1 + kFMaxIn) return false;
-    for (const auto &a : lp.args)
-        if (a.kind != TC_ARG_DAT) return false;
-    // stencil reach within what a signed byte and the ring width allow
-    for (const auto &a : lp.args) {
-        const Stencil &st = c.stencils[a.stencil];
-        if (st.lo[0] < -8 || st.hi[0] > 8 || st.lo[1] < -8 || st.hi[1] > 8) return false;
-    }
-    return true;
-}
-
-// Analyse loops [g0, g1); returns false if they cannot form one group.
-bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, const int tile[3], int lds_budget,
+// ---------------------------------------------------------------------------
+// analysis of one candidate group: versions, liveness, extents (Section 4.4:
+// each loop computes what its later readers need beyond the owned block),
+// lags, register windows and the wavefront layout.  False if the loops
+// cannot form a group.
+// ---------------------------------------------------------------------------
+bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, const SplitParams &sp,
              FusedGroup &G) {
-    const int n = g1 - g0;
-    if (n < 1 || n > kFMaxLoops) return false;
-    const int dtype = c.dats[chain[g0].args[0].handle].dtype;
-    const int es = dtype == TC_F64 ? 8 : 4;
-    std::map<int, int> ring_of;
-    std::vector<int> ring_dat;
-    int nent = 0, nin = 0;
-    for (int l = g0; l < g1; ++l) {
-        const LoopRec &lp = chain[l];
-        if (!fusable(c, lp) || lp.block != chain[g0].block) return false;
-        for (const auto &a : lp.args) {
-            if (c.dats[a.handle].dtype != dtype) return false;
-            if (!ring_of.count(a.handle)) {
-                ring_of[a.handle] = (int)ring_dat.size();
-                ring_dat.push_back(a.handle);
-            }
-            if (a.access == TC_READ) {
-                nent += c.stencils[a.stencil].npoints();
-                ++nin;
-            }
-        }
-    }
-    const int nr = (int)ring_dat.size();
-    if (nr > kFMaxRings || nent > kFMaxEnt || nin > kFMaxLoops * 8) return false;
-
-    FGroupD &D = G.tmpl;
-    std::memset(&D, 0, sizeof D);
-    D.nloops = n;
-    D.nrings = nr;
-
-    // backward pass: extents each loop must compute beyond the owned block
-    std::vector<Ext> need(nr);
-    std::vector<int> hlo(n), hhi(n), vlo(n), vhi(n);
-    for (int i = n - 1; i >= 0; --i) {
-        const LoopRec &lp = chain[g0 + i];
-        const int o = ring_of[lp.args[0].handle];
-        const Ext &e = need[o];
-        hlo[i] = e.set() ? std::max(0, e.xlo) : 0;
-        hhi[i] = e.set() ? std::max(0, e.xhi) : 0;
-        vlo[i] = e.set() ? std::max(0, e.ylo) : 0;
-        vhi[i] = e.set() ? std::max(0, e.yhi) : 0;
-        for (size_t a = 1; a < lp.args.size(); ++a) {
-            const Stencil &st = c.stencils[lp.args[a].stencil];
-            need[ring_of[lp.args[a].handle]].add(hlo[i] - st.lo[0], hhi[i] + st.hi[0], vlo[i] - st.lo[1],
-                                                 vhi[i] + st.hi[1]);
-        }
-    }
-    int HR = 0;
-    for (int i = 0; i < n; ++i) {
-        HR = std::max({HR, hlo[i], hhi[i]});
-        const LoopRec &lp = chain[g0 + i];
-        for (size_t a = 1; a < lp.args.size(); ++a) {
-            const Stencil &st = c.stencils[lp.args[a].stencil];
-            HR = std::max({HR, hlo[i] - st.lo[0], hhi[i] + st.hi[0]});
-        }
-    }
-    const int W = kFCols - 2 * HR;
-    if (W < 32) return false;
-
-    // forward pass: lags (rows)
-    const int R = G.rows;
-    std::vector<int> lag(n, 0);
-    std::vector<int> lastw(nr, -1);
-    std::vector<std::vector<std::pair<int, int>>> readers(nr);  // (lag, dymin) of every earlier reader
-    std::vector<int> live_lag(nr, INT_MAX);   // min over live-in readers of lag - dymax
-    std::vector<int> bot(nr, INT_MIN);        // max over readers of lag - dymin
-    std::vector<int> wmin(nr, INT_MAX), wmax(nr, INT_MIN);
-    std::vector<int> first_write(nr, -1);     // loop (group index) whose WRITE is the ring's first access
-    std::vector<char> accessed(nr, 0);
-    std::vector<int> ld_below(nr, 0), ld_above(nr, 0);
-    for (int i = 0; i < n; ++i) {
-        const LoopRec &lp = chain[g0 + i];
-        int lam = 0;
-        for (size_t a = 1; a < lp.args.size(); ++a) {
-            const int r = ring_of[lp.args[a].handle];
-            const Stencil &st = c.stencils[lp.args[a].stencil];
-            if (lastw[r] >= 0) lam = std::max(lam, lag[lastw[r]] + st.hi[1] + R);
-        }
-        const int o = ring_of[lp.args[0].handle];
-        for (auto &pr : readers[o]) lam = std::max(lam, pr.first - pr.second + R);
-        if (lastw[o] >= 0) lam = std::max(lam, lag[lastw[o]] + R);
-        lag[i] = lam;
-        for (size_t a = 1; a < lp.args.size(); ++a) {
-            const int r = ring_of[lp.args[a].handle];
-            const Stencil &st = c.stencils[lp.args[a].stencil];
-            readers[r].push_back({lam, st.lo[1]});
-            if (lastw[r] < 0) live_lag[r] = std::min(live_lag[r], lam - st.hi[1]);
-            bot[r] = std::max(bot[r], lam - st.lo[1]);
-            ld_below[r] = std::max(ld_below[r], vlo[i] - st.lo[1]);
-            ld_above[r] = std::max(ld_above[r], vhi[i] + st.hi[1]);
-            accessed[r] = 1;
-        }
-        if (!accessed[o]) first_write[o] = i;
-        accessed[o] = 1;
-        lastw[o] = i;
-        wmin[o] = std::min(wmin[o], lam);
-        wmax[o] = std::max(wmax[o], lam);
-        ld_below[o] = std::max(ld_below[o], vlo[i]);
-        ld_above[o] = std::max(ld_above[o], vhi[i]);
-    }
-
-    // rings: loader, storer, depth, LDS offsets
-    int lds = 0;
-    G.ring_dat = ring_dat;
-    G.ring_store.assign(nr, 0);
-    for (int r = 0; r < nr; ++r) {
-        FRingD &rd = D.rings[r];
-        const Dataset &ds = c.dats[ring_dat[r]];
-        const bool written = wmin[r] != INT_MAX;
-        const bool live = live_lag[r] != INT_MAX;
-        rd.load = live ? 1 : (written ? 2 : 0);
-        rd.store = written ? 1 : 0;
-        G.ring_store[r] = rd.store;
-        int top = INT_MAX, bottom = INT_MIN;
-        if (rd.load) {
-            int l = INT_MAX;
-            if (live) l = live_lag[r] - R;
-            if (written) l = std::min(l, wmin[r] - R);
-            rd.load_lag = l;
-            top = std::min(top, rd.load_lag);
-        }
-        if (written) {
-            top = std::min(top, wmin[r]);
-            rd.store_lag = wmax[r] + R;
-            bottom = std::max(bottom, rd.store_lag);
-        }
-        if (bot[r] != INT_MIN) bottom = std::max(bottom, bot[r]);
-        if (top == INT_MAX || bottom == INT_MIN) {
-            top = 0;
-            bottom = 0;
-        }
-        rd.depth = bottom - top + R;
-        rd.inv_depth = 1.0f / (float)rd.depth;
-        rd.lds_off = lds / es;
-        lds += rd.depth * kFCols * es;
-        rd.ld_below = ld_below[r];
-        rd.ld_above = ld_above[r];
-        rd.sy = ds.sy();
-        rd.ext_xlo = -ds.hneg[0];
-        rd.ext_xhi = ds.size[0] + ds.hpos[0];
-        rd.ext_ylo = -ds.hneg[1];
-        rd.ext_yhi = ds.size[1] + ds.hpos[1];
-        if (rd.load == 2) {
-            const LoopRec &fw = chain[g0 + first_write[r]];
-            rd.fw_xlo = fw.lo[0];
-            rd.fw_xhi = fw.hi[0];
-            rd.fw_ylo = fw.lo[1];
-            rd.fw_yhi = fw.hi[1];
-        }
-    }
-    if (lds > lds_budget) return false;
-    D.nload = D.nstore = 0;
-    for (int r = 0; r < nr; ++r) {
-        if (D.rings[r].load) D.load_list[D.nload++] = r;
-        if (D.rings[r].store) D.store_list[D.nstore++] = r;
-    }
-    if (D.nload > kFMaxLoaded) return false;
-
-    // loops and their entries
-    int e = 0, in = 0;
-    for (int i = 0; i < n; ++i) {
-        const LoopRec &lp = chain[g0 + i];
-        FLoopD &L = D.loops[i];
-        L.out_ring = ring_of[lp.args[0].handle];
-        L.lag = lag[i];
-        L.xlo = lp.lo[0];
-        L.xhi = lp.hi[0];
-        L.ylo = lp.lo[1];
-        L.yhi = lp.hi[1];
-        L.hlo = hlo[i];
-        L.hhi = hhi[i];
-        L.vlo = vlo[i];
-        L.vhi = vhi[i];
-        L.ent0 = e;
-        L.in0 = in;
-        for (size_t a = 1; a < lp.args.size(); ++a) {
-            const Stencil &st = c.stencils[lp.args[a].stencil];
-            FInD &I = D.ins[in++];
-            I.ring = ring_of[lp.args[a].handle];
-            I.ent0 = e;
-            I.nent = st.npoints();
-            I.star = canonical_star2(st);
-            if (I.star < 0) I.star = 0;
-            for (int p = 0; p < st.npoints(); ++p, ++e) {
-                D.ent[e].ring = (short)I.ring;
-                D.ent[e].dx = (signed char)st.pts[3 * p];
-                D.ent[e].dy = (signed char)st.pts[3 * p + 1];
-            }
-        }
-        L.nent = e - L.ent0;
-        L.nin = in - L.in0;
-    }
-    D.nin = in;
-    D.R = R;
-    D.HR = HR;
-    D.W = W;
+    G = FusedGroup();
     G.g0 = g0;
     G.g1 = g1;
-    G.dtype = dtype;
-    G.lds_bytes = lds;
-    (void)tile;
+    G.U = sp.U;
+    G.PF = sp.PF;
+    G.baked = sp.bake;
+    const LoopRec &f = chain[g0];
+    if (f.op != TC_OP_WSUM || f.ndim != 2 || f.points() == 0) return false;
+    G.xlo = f.lo[0];
+    G.xhi = f.hi[0];
+    G.ylo = f.lo[1];
+    G.yhi = f.hi[1];
+    G.dtype = c.dats[f.args[0].handle].dtype;
+    std::unordered_map<int, int> cur;    // dataset -> current version
+    std::unordered_map<int, int> first;  // dataset -> chain-start version
+    auto start_version = [&](int d) {
+        JVer v;
+        v.dat = d;
+        G.vers.push_back(v);
+        const int id = (int)G.vers.size() - 1;
+        cur[d] = id;
+        first[d] = id;
+        return id;
+    };
+    int wcount = 0;
+    for (int l = g0; l < g1; ++l) {
+        const LoopRec &lp = chain[l];
+        if (lp.op != TC_OP_WSUM || lp.ndim != 2) return false;
+        if (lp.lo[0] != G.xlo || lp.hi[0] != G.xhi || lp.lo[1] != G.ylo || lp.hi[1] != G.yhi) return false;
+        if (lp.args.size() < 2) return false;
+        JLoop J;
+        J.loop = l;
+        for (size_t a = 1; a < lp.args.size(); ++a) {
+            const ArgRec &A = lp.args[a];
+            if (c.dats[A.handle].dtype != G.dtype) return false;
+            const Stencil &st = c.stencils[A.stencil];
+            JRead R;
+            R.ver = cur.count(A.handle) ? cur[A.handle] : start_version(A.handle);
+            R.dxmin = R.dymin = INT_MAX;
+            R.dxmax = R.dymax = INT_MIN;
+            for (int k = 0; k < st.npoints(); ++k) {
+                const int dx = st.pts[3 * k], dy = st.pts[3 * k + 1];
+                if (std::abs(dx) > kJMaxOff || std::abs(dy) > kJMaxOff) return false;
+                R.pts.push_back({dx, dy, wcount++});
+                R.dxmin = std::min(R.dxmin, dx);
+                R.dxmax = std::max(R.dxmax, dx);
+                R.dymin = std::min(R.dymin, dy);
+                R.dymax = std::max(R.dymax, dy);
+            }
+            if (R.pts.empty()) return false;
+            J.in.push_back(R);
+        }
+        const int o = lp.args[0].handle;
+        if (c.dats[o].dtype != G.dtype) return false;
+        if (!cur.count(o)) start_version(o);
+        JVer v;
+        v.dat = o;
+        v.producer = (int)G.loops.size();
+        G.vers.push_back(v);
+        J.out = (int)G.vers.size() - 1;
+        cur[o] = J.out;
+        G.loops.push_back(J);
+    }
+    if (wcount > kJMaxW) return false;
+    G.nweights = wcount;
+    for (int l = g0; l < g1; ++l) G.wvals.insert(G.wvals.end(), chain[l].params.begin(), chain[l].params.end());
+    for (auto &kv : cur)
+        if (G.vers[kv.second].producer >= 0) G.vers[kv.second].stored = true;
+
+    // backward: which loops matter and the columns / rows each computes
+    // beyond the owned block
+    for (auto &v : G.vers)
+        if (v.stored) {
+            v.needed = true;
+            v.extL = v.extR = v.extB = v.extT = 0;
+        }
+    for (int j = (int)G.loops.size() - 1; j >= 0; --j) {
+        JLoop &J = G.loops[j];
+        const JVer &o = G.vers[J.out];
+        if (!o.needed) continue;
+        J.needed = true;
+        J.extL = o.extL;
+        J.extR = o.extR;
+        J.extB = o.extB;
+        J.extT = o.extT;
+        for (auto &R : J.in) {
+            JVer &v = G.vers[R.ver];
+            v.needed = true;
+            v.extL = std::max(v.extL, std::max(0, J.extL - R.dxmin));
+            v.extR = std::max(v.extR, std::max(0, J.extR + R.dxmax));
+            v.extB = std::max(v.extB, std::max(0, J.extB - R.dymin));
+            v.extT = std::max(v.extT, std::max(0, J.extT + R.dymax));
+            for (const auto &p : R.pts)
+                if ((p.dx != 0 || p.dy != 0) && v.producer >= 0) v.sel = true;
+        }
+    }
+    int nneeded = 0;
+    for (auto &J : G.loops) nneeded += J.needed;
+    if (nneeded == 0) return false;
+
+    // forward: lags (a reader runs at least its largest y offset behind the
+    // producer of every version it reads)
+    for (auto &J : G.loops) {
+        if (!J.needed) continue;
+        int lag = 0;
+        for (const auto &R : J.in) {
+            const JVer &v = G.vers[R.ver];
+            if (v.producer >= 0) lag = std::max(lag, G.loops[v.producer].lag + R.dymax);
+        }
+        J.lag = lag;
+        G.vers[J.out].lag = lag;
+    }
+
+    // lanes: columns loaded left / right of the owned ones; computed extents
+    int HL = 0, HR = 0, CL = 0, CR = 0, CB = 0, CT = 0;
+    for (const auto &v : G.vers)
+        if (v.needed && v.producer < 0) {
+            HL = std::max(HL, v.extL);
+            HR = std::max(HR, v.extR);
+        }
+    for (const auto &J : G.loops)
+        if (J.needed) {
+            CL = std::max(CL, J.extL);
+            CR = std::max(CR, J.extR);
+            CB = std::max(CB, J.extB);
+            CT = std::max(CT, J.extT);
+        }
+    G.HL = HL;
+    G.HR = HR;
+    G.Wo = kJLanes - HL - HR;
+    if (G.Wo < 8) return false;
+    G.BMAX = CB;
+    G.TMAX = CT;
+
+    // variants: 0 interior, 1 edge (keeps chain-start values outside the range)
+    const int words = esize_of(G.dtype) / 4;
+    for (int var = 0; var < 2; ++var) {
+        JVariant &V = G.var[var];
+        const size_t nv = G.vers.size();
+        V.win.assign(nv, 0);
+        V.load_lag.assign(nv, 0);
+        V.loaded.assign(nv, 0);
+        V.pseudo.clear();
+        // per version: smallest (lag - dymax) over its readers bounds the
+        // arrival step of a row; largest (lag - dymin) the oldest row kept
+        std::vector<int> lo(nv, INT_MAX), hi(nv, INT_MIN), eb(nv, -1), et(nv, -1);
+        for (const auto &J : G.loops) {
+            if (!J.needed) continue;
+            for (const auto &R : J.in) {
+                lo[R.ver] = std::min(lo[R.ver], J.lag - R.dymax);
+                hi[R.ver] = std::max(hi[R.ver], J.lag - R.dymin);
+            }
+        }
+        if (var == 1) {
+            for (size_t j = 0; j < G.loops.size(); ++j) {
+                const JLoop &J = G.loops[j];
+                if (!J.needed || !G.vers[J.out].sel) continue;
+                const int c0 = first.at(G.vers[J.out].dat);
+                V.pseudo.push_back({(int)j, c0});
+                lo[c0] = std::min(lo[c0], J.lag);
+                hi[c0] = std::max(hi[c0], J.lag);
+                eb[c0] = std::max(eb[c0], J.extB);
+                et[c0] = std::max(et[c0], J.extT);
+            }
+        }
+        int pre = 0, post = 0, regs = 0;
+        for (size_t v = 0; v < nv; ++v) {
+            const JVer &X = G.vers[v];
+            if (X.producer >= 0) {
+                if (!X.needed) continue;
+                const int oldest = hi[v] == INT_MIN ? X.lag : std::max(hi[v], X.lag);
+                V.win[v] = oldest - X.lag + 1;
+                regs += V.win[v] * words;
+                if (X.stored) post = std::max(post, X.lag);
+            } else {
+                if (lo[v] == INT_MAX) continue;  // not read in this variant
+                V.loaded[v] = 1;
+                V.load_lag[v] = lo[v];
+                V.win[v] = hi[v] - lo[v] + 1;
+                regs += (V.win[v] + G.PF) * words;
+                const int b = std::max(X.needed ? X.extB : -1, eb[v]);
+                const int t = std::max(X.needed ? X.extT : -1, et[v]);
+                pre = std::max(pre, b - lo[v]);
+                post = std::max(post, t + lo[v]);
+            }
+        }
+        for (const auto &J : G.loops) {
+            if (!J.needed) continue;
+            pre = std::max(pre, J.extB - J.lag);
+            post = std::max(post, J.extT + J.lag);
+        }
+        V.pre = pre;
+        V.post = post + 1;
+        V.regs = regs;
+    }
+    if (G.var[0].regs > sp.regs) return false;
+    // datasets loaded / stored, in kernel argument order
+    for (size_t v = 0; v < G.vers.size(); ++v)
+        if (G.vers[v].producer < 0 && (G.var[0].loaded[v] || G.var[1].loaded[v])) G.src_dat.push_back(G.vers[v].dat);
+    for (size_t v = 0; v < G.vers.size(); ++v)
+        if (G.vers[v].stored) {
+            G.dst_dat.push_back(G.vers[v].dat);
+            G.dst_twin.push_back(G.vers[first.at(G.vers[v].dat)].needed ? 1 : 0);
+        }
+    if ((int)G.src_dat.size() > kJMaxSrc || (int)G.dst_dat.size() > kJMaxDst) return false;
+
+    // wavefront layout: strips of Wo columns by segments of Hseg rows
+    const int width = G.xhi - G.xlo, height = G.yhi - G.ylo;
+    G.nstrips = (width + G.Wo - 1) / G.Wo;
+    int Hseg = sp.hseg;
+    if (Hseg <= 0) {
+        const int target = 2048;  // wavefronts: 8 per compute unit
+        const int nsegs = std::max(1, (int)std::lround((double)target / G.nstrips));
+        Hseg = std::max(32, (height + nsegs - 1) / nsegs);
+    }
+    G.Hseg = std::min(Hseg, height);
+    G.nsegs = (height + G.Hseg - 1) / G.Hseg;
+    // interior rectangle: strip i computes columns [i Wo - CL, (i + 1) Wo + CR)
+    // of the range, segment k rows [k Hseg - CB, (k + 1) Hseg + CT); both
+    // must stay inside it
+    auto cdiv = [](int a, int b) { return a <= 0 ? 0 : (a + b - 1) / b; };
+    auto fdiv = [](int a, int b) { return a < 0 ? -((-a + b - 1) / b) : a / b; };
+    int si0 = cdiv(CL, G.Wo), si1 = fdiv(width - CR, G.Wo);
+    int gi0 = cdiv(CB, G.Hseg), gi1 = fdiv(height - CT, G.Hseg);
+    {
+        // the interior kernel reads without clamping: every lane column and
+        // every row it loads must lie inside the allocation
+        const JVariant &V = G.var[0];
+        const int nsteps = (G.Hseg + V.pre + V.post + G.U - 1) / G.U * G.U;
+        for (size_t v = 0; v < G.vers.size(); ++v) {
+            if (!V.loaded[v]) continue;
+            const Dataset &ds = c.dats[G.vers[v].dat];
+            // columns X0 - HL + [0, 64) with X0 = xlo + i Wo
+            si0 = std::max(si0, cdiv(-ds.hneg[0] - G.xlo + HL, G.Wo));
+            si1 = std::min(si1, fdiv(ds.size[0] + ds.hpos[0] - kJLanes - G.xlo + HL, G.Wo) + 1);
+            // rows Y0 - pre - lag .. Y0 - pre + nsteps - 1 + PF - lag with Y0 = ylo + k Hseg
+            gi0 = std::max(gi0, cdiv(-ds.hneg[1] - G.ylo + V.pre + V.load_lag[v], G.Hseg));
+            gi1 = std::min(gi1, fdiv(ds.size[1] + ds.hpos[1] - 1 - G.ylo + V.pre - nsteps + 1 - G.PF +
+                                         V.load_lag[v], G.Hseg) + 1);
+        }
+        si1 = std::min(si1, G.nstrips);
+        gi1 = std::min(gi1, G.nsegs);
+    }
+    if (si1 > si0 && gi1 > gi0) {
+        G.si0 = si0;
+        G.si1 = si1;
+        G.gi0 = gi0;
+        G.gi1 = gi1;
+    } else {
+        G.si0 = G.si1 = G.gi0 = G.gi1 = 0;
+    }
+    G.nwaves_in = (G.si1 - G.si0) * (G.gi1 - G.gi0);
+    G.nwaves_edge = G.nstrips * G.nsegs - G.nwaves_in;
+    G.nblocks = (G.nwaves_in + 3) / 4 + (G.nwaves_edge + 3) / 4;
+
+    // modelled time (split choice): HBM bytes of the loads and stores
+    // against VALU work, both scaled by the recomputed lanes and rows
+    const double cells = (double)width * height;
+    const double fy = (double)(G.Hseg + G.var[0].pre + G.var[0].post) / G.Hseg;
+    const double fx = (double)kJLanes / G.Wo;
+    int nload = 0;
+    for (size_t v = 0; v < G.vers.size(); ++v) nload += G.var[0].loaded[v];
+    double ops = 0.0;
+    for (const auto &J : G.loops) {
+        if (!J.needed) continue;
+        for (const auto &R : J.in)
+            for (const auto &p : R.pts) ops += 1.0 + (p.dx != 0 ? words : 0);
+        ops += 2.0;
+    }
+    const double bytes =
+        cells * esize_of(G.dtype) * (nload * (1.0 + 0.5 * (HL + HR) / G.Wo) + (double)G.dst_dat.size()) * fy;
+    const double valu = cells * fx * fy * ops / (256.0 * 64.0 * 2.4e9);
+    G.cost = std::max(bytes / 5.0e12, valu) + 4e-6;
     return true;
 }
 
-// Group domain: bounding box of the loops' ranges and of the store regions.
-void group_domain(const Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &G, int dom[4]) {
-    dom[0] = dom[2] = INT_MAX;
-    dom[1] = dom[3] = INT_MIN;
-    for (int l = G.g0; l < G.g1; ++l) {
-        dom[0] = std::min(dom[0], chain[l].lo[0]);
-        dom[1] = std::max(dom[1], chain[l].hi[0]);
-        dom[2] = std::min(dom[2], chain[l].lo[1]);
-        dom[3] = std::max(dom[3], chain[l].hi[1]);
+double single_loop_cost(const Ctx &c, const LoopRec &lp) {
+    double b = 0.0;
+    for (const auto &a : lp.args)
+        if (a.kind == TC_ARG_DAT) b += (a.access == TC_RW || a.access == TC_INC ? 2.0 : 1.0) * c.dats[a.handle].esize();
+    return (double)lp.points() * b / 4.2e12 + 3e-6;
+}
+
+// ---------------------------------------------------------------------------
+// code generation
+// ---------------------------------------------------------------------------
+// Cross-lane moves: wave_shr:1 gives every lane the value of the lane below
+// it (column x-1), wave_shl:1 the value of the lane above (column x+1).
+const char *kPrelude = R"(
+typedef long long i64;
+typedef const double __attribute__((address_space(4))) *tcj_cw;
+typedef const double __attribute__((address_space(1))) *tcj_gcd;
+typedef double __attribute__((address_space(1))) *tcj_gd;
+typedef const float __attribute__((address_space(1))) *tcj_gcf;
+typedef float __attribute__((address_space(1))) *tcj_gf;
+__device__ __forceinline__ double tcj_shr(double v) {
+    const i64 u = __builtin_bit_cast(i64, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)u, 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0x138, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, (i64)(unsigned)lo | ((i64)hi << 32));
+}
+__device__ __forceinline__ double tcj_shl(double v) {
+    const i64 u = __builtin_bit_cast(i64, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)u, 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0x130, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, (i64)(unsigned)lo | ((i64)hi << 32));
+}
+__device__ __forceinline__ float tcj_shr(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float tcj_shl(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double tcj_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float tcj_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ int tcj_lin(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+)";
+
+struct Gen {
+    const Ctx &c;
+    const FusedGroup &G;
+    int var;
+    const JVariant &V;
+    std::ostringstream o;
+    const char *T, *GC, *GM;
+    std::vector<int> src_index;  // version -> source argument
+    std::vector<int> dst_index;  // version -> destination argument
+    std::map<std::tuple<int, int, int>, std::string> sh;  // shifted values of the current step
+    int ntmp = 0;
+
+    Gen(const Ctx &cc, const FusedGroup &g, int v) : c(cc), G(g), var(v), V(g.var[v]) {
+        T = G.dtype == TC_F64 ? "double" : "float";
+        GC = G.dtype == TC_F64 ? "tcj_gcd" : "tcj_gcf";
+        GM = G.dtype == TC_F64 ? "tcj_gd" : "tcj_gf";
+        src_index.assign(G.vers.size(), -1);
+        dst_index.assign(G.vers.size(), -1);
+        for (size_t k = 0; k < G.vers.size(); ++k) {
+            const JVer &X = G.vers[k];
+            if (X.producer < 0)
+                for (size_t i = 0; i < G.src_dat.size(); ++i)
+                    if (G.src_dat[i] == X.dat) src_index[k] = (int)i;
+            if (X.stored)
+                for (size_t i = 0; i < G.dst_dat.size(); ++i)
+                    if (G.dst_dat[i] == X.dat) dst_index[k] = (int)i;
+        }
     }
-    for (size_t r = 0; r < G.ring_dat.size(); ++r) {
-        if (!G.ring_store[r]) continue;
-        const Dataset &ds = c.dats[G.ring_dat[r]];
-        if (!ds.ever_written) continue;
-        dom[0] = std::min(dom[0], ds.wlo[0]);
-        dom[1] = std::max(dom[1], ds.whi[0]);
-        dom[2] = std::min(dom[2], ds.wlo[1]);
-        dom[3] = std::max(dom[3], ds.whi[1]);
+
+    int lag_of(int v) const { return G.vers[v].producer >= 0 ? G.vers[v].lag : V.load_lag[v]; }
+
+    // window entry of version v holding the row that a loop at `lag` reads at offset dy
+    std::string entry(int v, int lag, int dy) const {
+        const int m = lag - dy - lag_of(v);
+        if (m < 0 || m >= V.win[v]) {
+            std::fprintf(stderr, "tilechain: fused window error (version %d, m %d, window %d)\n", v, m, V.win[v]);
+            std::abort();
+        }
+        return "w" + std::to_string(v) + "[" + std::to_string(V.win[v] - 1 - m) + "]";
     }
+
+    std::string shifted(int v, int lag, int dy, int dx) {
+        if (dx == 0) return entry(v, lag, dy);
+        const int m = lag - dy - lag_of(v);
+        const auto key = std::make_tuple(v, m, dx);
+        auto it = sh.find(key);
+        if (it != sh.end()) return it->second;
+        const std::string base = shifted(v, lag, dy, dx < 0 ? dx + 1 : dx - 1);
+        const std::string name = "x" + std::to_string(ntmp++);
+        o << "      const " << T << " " << name << " = " << (dx < 0 ? "tcj_shr(" : "tcj_shl(") << base << ");\n";
+        sh[key] = name;
+        return name;
+    }
+
+    // One row of a loaded version into a window slot.  Interior kernel: a
+    // uniform pointer to the row's first lane column, advanced by one row per
+    // step (every row it touches lies inside the allocation).  Edge kernel:
+    // row and column clamped to the allocation (clamped values only feed
+    // points that are not needed).
+    void load_row(int v, const std::string &step, int slot, const char *indent) {
+        const Dataset &ds = c.dats[G.vers[v].dat];
+        if (var == 0) {
+            o << indent << "w" << v << "[" << slot << "] = q" << v << "[lane]; q" << v << " += " << ds.pitch
+              << "; asm volatile(\"\" : \"+s\"(q" << v << "));\n";
+        } else {
+            o << indent << "{ const int y = __builtin_amdgcn_readfirstlane(min(max(" << step << " - "
+              << V.load_lag[v] << ", " << -ds.hneg[1] << "), " << (ds.size[1] + ds.hpos[1] - 1) << ")); " << GC
+              << " r = (" << GC << ")(a.s[" << src_index[v] << "] + (i64)y * " << ds.pitch
+              << "); asm volatile(\"\" : \"+s\"(r)); w" << v << "[" << slot << "] = r[cx" << src_index[v]
+              << "]; }\n";
+        }
+    }
+
+    void step(const std::string &tt) {
+        sh.clear();
+        o << "    {\n      const int tt = " << tt << ";\n";
+        // rows arriving PF steps ahead
+        for (size_t v = 0; v < G.vers.size(); ++v)
+            if (V.loaded[v]) load_row((int)v, "(tt + " + std::to_string(G.PF) + ")", V.win[v] + G.PF - 1, "      ");
+        // loops in chain order
+        for (size_t j = 0; j < G.loops.size(); ++j) {
+            const JLoop &J = G.loops[j];
+            if (!J.needed) continue;
+            std::vector<std::string> terms;
+            for (const auto &R : J.in)
+                for (const auto &p : R.pts) terms.push_back(shifted(R.ver, J.lag, p.dy, p.dx));
+            // the weights are read from the kernel arguments right before
+            // the loop that uses them (the empty asm hides the pointer's
+            // origin, so they are not all kept live in scalar registers)
+            o << "      {\n      " << T << " acc = (" << T << ")0;\n";
+            size_t q = 0;
+            for (const auto &R : J.in) {
+                if (G.baked) {
+                    for (const auto &p : R.pts) {
+                        char lit[64];
+                        std::snprintf(lit, sizeof lit, "%a", G.wvals[p.w]);
+                        o << "      acc = tcj_fma((" << T << ")" << lit << ", " << terms[q++] << ", acc);\n";
+                    }
+                    continue;
+                }
+                o << "      { tcj_cw wl = wk; asm volatile(\"\" : \"+s\"(wl));\n";
+                for (const auto &p : R.pts)
+                    o << "      acc = tcj_fma((" << T << ")wl[" << p.w << "], " << terms[q++] << ", acc);\n";
+                o << "      }\n";
+            }
+            const int out = J.out;
+            if (var == 1 && G.vers[out].sel) {
+                int c0 = -1;
+                for (const auto &ps : V.pseudo)
+                    if (ps.first == (int)j) c0 = ps.second;
+                o << "      { const int y = tt - " << J.lag << "; const bool in = inx & ((unsigned)(y - (" << G.ylo
+                  << ")) < " << (unsigned)(G.yhi - G.ylo) << "u); acc = in ? acc : " << entry(c0, J.lag, 0)
+                  << "; }\n";
+            }
+            o << "      w" << out << "[" << (V.win[out] - 1) << "] = acc;\n      }\n";
+        }
+        // final values of the owned columns (uniform row pointers advanced
+        // by one row per step)
+        for (size_t v = 0; v < G.vers.size(); ++v) {
+            if (!G.vers[v].stored || !G.vers[v].needed) continue;
+            const Dataset &ds = c.dats[G.vers[v].dat];
+            o << "      { const int y = tt - " << G.vers[v].lag << "; if (y >= Y0 && y < yend && own) p" << v
+              << "[lane] = w" << v << "[" << (V.win[v] - 1) << "]; p" << v << " += " << ds.pitch
+              << "; asm volatile(\"\" : \"+s\"(p" << v << ")); }\n";
+        }
+        // advance the windows by one row
+        for (size_t v = 0; v < G.vers.size(); ++v) {
+            if (!V.win[v]) continue;
+            const int n = V.win[v] + (V.loaded[v] ? G.PF : 0);
+            for (int k = 0; k + 1 < n; ++k) o << "      w" << v << "[" << k << "] = w" << v << "[" << k + 1 << "];\n";
+        }
+        o << "    }\n";
+    }
+
+    void body() {
+        o << "  const tcj_cw wk = (tcj_cw)((const char __attribute__((address_space(4))) *)__builtin_amdgcn_kernarg_segment_ptr() + "
+          << 8 * (std::max<size_t>(1, G.src_dat.size()) + std::max<size_t>(1, G.dst_dat.size())) << ");\n";
+        o << "  const int lane = threadIdx.x & 63;\n";
+        o << "  const int col = X0 - " << G.HL << " + lane;\n";
+        o << "  const bool own = (lane >= " << G.HL << ") & (lane < " << (G.HL + G.Wo) << ") & (col < " << G.xhi
+          << ");\n";
+        if (var == 1) o << "  const bool inx = (col >= " << G.xlo << ") & (col < " << G.xhi << ");\n";
+        o << "  const int yend = min(Y0 + " << G.Hseg << ", " << G.yhi << ");\n";
+        const int nsteps = G.Hseg + V.pre + V.post;
+        const int nit = (nsteps + G.U - 1) / G.U;
+        o << "  int t = Y0 - " << V.pre << ";\n";
+        if (var == 1)
+            for (size_t i = 0; i < G.src_dat.size(); ++i) {
+                const Dataset &ds = c.dats[G.src_dat[i]];
+                o << "  const int cx" << i << " = min(max(col, " << -ds.hneg[0] << "), "
+                  << (ds.size[0] + ds.hpos[0] - 1) << ");\n";
+            }
+        for (size_t v = 0; v < G.vers.size(); ++v) {
+            const Dataset &ds = c.dats[G.vers[v].dat];
+            if (var == 0 && V.loaded[v])
+                o << "  " << GC << " q" << v << " = (" << GC << ")(a.s[" << src_index[v] << "] + (i64)(t - "
+                  << V.load_lag[v] << ") * " << ds.pitch << " + (X0 - " << G.HL << "));\n";
+            if (G.vers[v].stored && G.vers[v].needed)
+                o << "  " << GM << " p" << v << " = (" << GM << ")(a.d[" << dst_index[v] << "] + (i64)(t - "
+                  << G.vers[v].lag << ") * " << ds.pitch << " + (X0 - " << G.HL << "));\n";
+        }
+        for (size_t v = 0; v < G.vers.size(); ++v) {
+            if (!V.win[v]) continue;
+            o << "  " << T << " w" << v << "[" << (V.win[v] + (V.loaded[v] ? G.PF : 0)) << "];\n";
+        }
+        // prologue: rows arriving at the first PF steps
+        for (int k = 0; k < G.PF; ++k)
+            for (size_t v = 0; v < G.vers.size(); ++v)
+                if (V.loaded[v]) load_row((int)v, "(t + " + std::to_string(k) + ")", V.win[v] - 1 + k, "  ");
+        o << "  for (int it = 0; it < " << nit << "; ++it, t += " << G.U << ") {\n";
+        for (int u = 0; u < G.U; ++u) step("t + " + std::to_string(u));
+        o << "  }\n";
+    }
+};
+
+void gen_group(const Ctx &c, FusedGroup &G, int gi, std::ostringstream &o) {
+    const char *T = G.dtype == TC_F64 ? "double" : "float";
+    const std::string S = "tcj_args" + std::to_string(gi);
+    o << "struct " << S << " { const " << T << "* s[" << std::max<size_t>(1, G.src_dat.size()) << "]; " << T
+      << "* d[" << std::max<size_t>(1, G.dst_dat.size()) << "]; double w[" << std::max(1, G.nweights) << "]; };\n";
+    G.kname_in = "tcj_g" + std::to_string(gi) + "_in";
+    G.kname_edge = "tcj_g" + std::to_string(gi) + "_edge";
+    for (int var = 0; var < 2; ++var) {
+        if ((var == 0 ? G.nwaves_in : G.nwaves_edge) == 0) continue;
+        Gen g(c, G, var);
+        o << "extern \"C\" __global__ void __launch_bounds__(256) " << (var == 0 ? G.kname_in : G.kname_edge) << "("
+          << S << " a) {\n";
+        o << "  const int wid = tcj_lin(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n";
+        const int ns = G.nstrips;
+        if (var == 0) {
+            const int nsi = G.si1 - G.si0;
+            o << "  if (wid >= " << G.nwaves_in << ") return;\n";
+            o << "  const int strip = " << G.si0 << " + wid % " << nsi << ", seg = " << G.gi0 << " + wid / " << nsi
+              << ";\n";
+        } else {
+            // the frame around the interior rectangle: bottom segments, top
+            // segments, then the side strips of the middle segments
+            const int nb = G.gi0 * ns, nt = (G.nsegs - G.gi1) * ns, side = G.si0 + (ns - G.si1);
+            o << "  if (wid >= " << G.nwaves_edge << ") return;\n";
+            o << "  int strip, seg;\n";
+            o << "  if (wid < " << nb << ") { seg = wid / " << ns << "; strip = wid % " << ns << "; }\n";
+            o << "  else if (wid < " << nb + nt << ") { const int w = wid - " << nb << "; seg = " << G.gi1
+              << " + w / " << ns << "; strip = w % " << ns << "; }\n";
+            o << "  else { const int w = wid - " << nb + nt << "; seg = " << G.gi0 << " + w / " << std::max(1, side)
+              << "; const int k = w % " << std::max(1, side) << "; strip = k < " << G.si0 << " ? k : " << G.si1
+              << " + (k - " << G.si0 << "); }\n";
+        }
+        o << "  const int X0 = __builtin_amdgcn_readfirstlane(" << G.xlo << " + strip * " << G.Wo
+          << "), Y0 = __builtin_amdgcn_readfirstlane(" << G.ylo << " + seg * " << G.Hseg << ");\n";
+        g.body();
+        o << g.o.str();
+        o << "}\n";
+    }
+}
+
+uint64_t fnv1a(const std::string &s) {
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char ch : s) {
+        h ^= ch;
+        h *= 1099511628211ull;
+    }
+    return h;
 }
 
 }  // namespace
 
-std::vector<std::shared_ptr<FusedGroup>> fused_split(const Ctx &c, const std::vector<LoopRec> &chain,
-                                                     const int tile[3]) {
-    std::vector<std::shared_ptr<FusedGroup>> out;
-    const int budget = (tile[2] > 0 ? tile[2] : 158) * 1024 - kFDescLds;
-    const int rows = (tile[0] == 2 || tile[0] == 8 || tile[0] == 16) ? tile[0] : 4;
+std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3]) {
+    SplitParams sp;
+    sp.bake = c.jit_bake;
+    sp.hseg = tile[0] > 0 ? tile[0] : 0;
+    sp.regs = tile[1] > 0 ? tile[1] : 192;
+    sp.max_loops = tile[2] > 0 ? tile[2] : 32;
+    sp.U = std::max(1, c.jit_unroll);
+    sp.PF = std::max(1, c.jit_prefetch);
     const int L = (int)chain.size();
-    int g0 = 0;
-    while (g0 < L) {
-        auto best = std::make_shared<FusedGroup>();
-        int g1 = g0;
-        for (int cand = g0 + 1; cand <= L; ++cand) {
-            FusedGroup G;
-            G.rows = rows;
-            if (!analyse(c, chain, g0, cand, tile, budget, G)) break;
-            *best = G;
-            g1 = cand;
+    // best[j]: least modelled time of loops [0, j); from[j]: start of the last piece
+    std::vector<double> best(L + 1, 1e300);
+    std::vector<int> from(L + 1, -1);
+    std::vector<std::shared_ptr<FusedGroup>> piece(L + 1);
+    best[0] = 0.0;
+    for (int j = 1; j <= L; ++j) {
+        const double s = best[j - 1] + single_loop_cost(c, chain[j - 1]);
+        if (s < best[j]) {
+            best[j] = s;
+            from[j] = j - 1;
+            piece[j] = nullptr;
         }
-        if (g1 - g0 >= 2) {
-            best->hseg_req = tile[1];
-            out.push_back(best);
-            g0 = g1;
-        } else {
-            g0 += 1;  // runs as a single-loop kernel
+        for (int i = j - 2; i >= 0 && j - i <= sp.max_loops; --i) {
+            if (chain[i].op != TC_OP_WSUM || chain[i].ndim != 2) break;
+            auto G = std::make_shared<FusedGroup>();
+            if (!analyse(c, chain, i, j, sp, *G)) continue;
+            if (best[i] + G->cost < best[j]) {
+                best[j] = best[i] + G->cost;
+                from[j] = i;
+                piece[j] = G;
+            }
         }
     }
+    std::vector<std::shared_ptr<FusedGroup>> out;
+    for (int j = L; j > 0; j = from[j])
+        if (piece[j]) out.push_back(piece[j]);
+    std::reverse(out.begin(), out.end());
+    if (getenv("TC_JIT_VERBOSE"))
+        for (const auto &g : out) {
+            int nl = 0, nld = 0;
+            for (const auto &J : g->loops) nl += J.needed;
+            for (char x : g->var[0].loaded) nld += x;
+            std::fprintf(stderr,
+                         "fused group [%d,%d): %d loops, HL %d HR %d Wo %d, loads %d stores %d, regs %d/%d, "
+                         "pre %d post %d, Hseg %d, strips %d segs %d, waves %d+%d, cost %.1f us\n",
+                         g->g0, g->g1, nl, g->HL, g->HR, g->Wo, nld, (int)g->dst_dat.size(), g->var[0].regs,
+                         g->var[1].regs, g->var[0].pre, g->var[0].post, g->Hseg, g->nstrips, g->nsegs, g->nwaves_in,
+                         g->nwaves_edge, g->cost * 1e6);
+        }
     return out;
 }
 
-tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
-    FGroupD &T = G.tmpl;
-    int dom[4];
-    // store regions after this group: hull of earlier writes and this group's writes
-    std::vector<int> hull(4 * T.nrings);
-    for (int r = 0; r < T.nrings; ++r) {
-        const Dataset &ds = c.dats[G.ring_dat[r]];
-        int h[4] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
-        if (ds.ever_written) {
-            h[0] = ds.wlo[0];
-            h[1] = ds.whi[0];
-            h[2] = ds.wlo[1];
-            h[3] = ds.whi[1];
+tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups) {
+    if (groups.empty()) return TC_OK;
+    std::ostringstream src;
+    src << kPrelude;
+    for (size_t gi = 0; gi < groups.size(); ++gi) gen_group(c, *groups[gi], (int)gi, src);
+    const std::string s = src.str();
+    if (const char *dump = getenv("TC_JIT_DUMP")) {
+        if (FILE *fp = std::fopen(dump, "w")) {
+            std::fwrite(s.data(), 1, s.size(), fp);
+            std::fclose(fp);
         }
-        for (int l = G.g0; l < G.g1; ++l)
-            if (chain[l].args[0].handle == G.ring_dat[r]) {
-                h[0] = std::min(h[0], chain[l].lo[0]);
-                h[1] = std::max(h[1], chain[l].hi[0]);
-                h[2] = std::min(h[2], chain[l].lo[1]);
-                h[3] = std::max(h[3], chain[l].hi[1]);
-            }
-        for (int k = 0; k < 4; ++k) hull[4 * r + k] = h[k];
     }
-    group_domain(c, chain, G, dom);
-    for (int r = 0; r < T.nrings; ++r)
-        if (G.ring_store[r]) {
-            dom[0] = std::min(dom[0], hull[4 * r]);
-            dom[1] = std::max(dom[1], hull[4 * r + 1]);
-            dom[2] = std::min(dom[2], hull[4 * r + 2]);
-            dom[3] = std::max(dom[3], hull[4 * r + 3]);
+    const uint64_t key = fnv1a(s) ^ ((uint64_t)c.device << 56);
+    hipModule_t mod = nullptr;
+    auto it = c.jit_modules.find(key);
+    if (it != c.jit_modules.end()) {
+        mod = it->second;
+    } else {
+        const double t0 = now_s();
+        hiprtcProgram prog;
+        if (hiprtcCreateProgram(&prog, s.c_str(), "tilechain_fused.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+            return fail(c, TC_ERR_DEVICE, "hiprtcCreateProgram failed");
+        const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+                              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+        const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+        if (r != HIPRTC_SUCCESS) {
+            size_t n = 0;
+            hiprtcGetProgramLogSize(prog, &n);
+            std::string log(n + 1, '\0');
+            hiprtcGetProgramLog(prog, &log[0]);
+            hiprtcDestroyProgram(&prog);
+            return fail(c, TC_ERR_DEVICE, "fused kernel compilation failed: %.2000s", log.c_str());
         }
-    // the first column of every workgroup's ring rows must be even (16-byte
-    // aligned row loads straight into LDS)
-    if (((dom[0] - T.HR) & 1) != 0) dom[0] -= 1;
-    const int width = dom[1] - dom[0], height = dom[3] - dom[2];
-    const int nbx = (width + T.W - 1) / T.W;
-    int Hseg = G.hseg_req;
-    if (Hseg <= 0) {
-        int nby = std::max(1, (int)std::lround(256.0 / nbx));
-        Hseg = std::max(16, (height + nby - 1) / nby);
+        size_t n = 0;
+        hiprtcGetCodeSize(prog, &n);
+        std::vector<char> code(n);
+        hiprtcGetCode(prog, code.data());
+        hiprtcDestroyProgram(&prog);
+        if (!c.host_only && hipModuleLoadData(&mod, code.data()) != hipSuccess)
+            return fail(c, TC_ERR_DEVICE, "hipModuleLoadData of the fused kernels failed");
+        c.jit_modules[key] = mod;
+        c.jit_compile_seconds += now_s() - t0;
     }
-    const int nby = (height + Hseg - 1) / Hseg;
+    if (c.host_only) return TC_OK;
+    for (auto &g : groups) {
+        if (g->nwaves_in > 0 && hipModuleGetFunction(&g->fin, mod, g->kname_in.c_str()) != hipSuccess)
+            return fail(c, TC_ERR_DEVICE, "fused kernel %s not found", g->kname_in.c_str());
+        if (g->nwaves_edge > 0 && hipModuleGetFunction(&g->fedge, mod, g->kname_edge.c_str()) != hipSuccess)
+            return fail(c, TC_ERR_DEVICE, "fused kernel %s not found", g->kname_edge.c_str());
+    }
+    return TC_OK;
+}
 
-    if (!G.host) {
-        if (hipHostMalloc((void **)&G.host, sizeof(FGroupD), hipHostMallocDefault) != hipSuccess)
-            return fail(c, TC_ERR_DEVICE, "hipHostMalloc of a fused descriptor failed");
-        G.dev = (FGroupD *)dev_alloc(c, sizeof(FGroupD));
-        if (!G.dev) return fail(c, TC_ERR_NOMEM, "cannot allocate a fused descriptor");
-        if (hipEventCreateWithFlags(&G.uploaded, hipEventDisableTiming) != hipSuccess)
-            return fail(c, TC_ERR_DEVICE, "hipEventCreate failed");
-    } else if (hipEventSynchronize(G.uploaded) != hipSuccess) {
-        return fail(c, TC_ERR_DEVICE, "hipEventSynchronize failed");
-    }
-    FGroupD &D = *G.host;
-    std::memcpy(&D, &T, sizeof(FGroupD));
-    D.Hseg = Hseg;
-    D.ring_bytes = G.lds_bytes;
-    D.dom_xlo = dom[0];
-    D.dom_ylo = dom[2];
-    D.nbx = nbx;
-    D.nby = nby;
-    // weights
-    for (int i = 0; i < D.nloops; ++i) {
-        const LoopRec &lp = chain[G.g0 + i];
-        for (int k = 0; k < D.loops[i].nent; ++k) D.w[D.loops[i].ent0 + k] = lp.params[k];
-    }
-    // buffers: read from the current buffer, write written datasets to the twin
-    for (int r = 0; r < D.nrings; ++r) {
-        Dataset &ds = c.dats[G.ring_dat[r]];
-        FRingD &rd = D.rings[r];
-        rd.src = ds.origin(ds.cur);
-        rd.dst = nullptr;
-        if (rd.store) {
-            const int tw = 1 - ds.cur;
-            if (!ds.raw[tw]) {
-                ds.raw[tw] = dev_alloc(c, (size_t)(ds.bytes + ds.stagger));
-                if (!ds.raw[tw]) return fail(c, TC_ERR_NOMEM, "cannot allocate the second buffer of %s", ds.name.c_str());
-                ds.buf[tw] = (char *)ds.raw[tw] + ds.stagger;
-                ds.twin_synced = false;
-            }
-            if (!ds.twin_synced) {
-                if (hipMemcpyAsync(ds.buf[tw], ds.buf[ds.cur], (size_t)ds.bytes, hipMemcpyDeviceToDevice, c.stream) !=
-                    hipSuccess)
-                    return fail(c, TC_ERR_DEVICE, "hipMemcpyAsync (second buffer) failed");
-                ds.twin_synced = true;
-            }
-            rd.dst = ds.origin(tw);
-            rd.hull_xlo = hull[4 * r];
-            rd.hull_xhi = hull[4 * r + 1];
-            rd.hull_ylo = hull[4 * r + 2];
-            rd.hull_yhi = hull[4 * r + 3];
+tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
+    if (G.baked) {
+        // kernels with the weights compiled in serve only the weights they
+        // were generated for; on a change the group falls back for good to
+        // kernels that read the weights from their arguments
+        size_t k = 0;
+        bool same = true;
+        for (int l = G.g0; l < G.g1 && same; ++l)
+            for (double w : chain[l].params) same = same && k < G.wvals.size() && G.wvals[k++] == w;
+        if (!same) {
+            G.baked = false;
+            std::vector<std::shared_ptr<FusedGroup>> one{std::shared_ptr<FusedGroup>(&G, [](FusedGroup *) {})};
+            const tc_status st = fused_compile(c, one);
+            if (st != TC_OK) return st;
         }
     }
-    // flat records for the kernel's steps
-    for (int i = 0; i < D.nloops; ++i) {
-        const FLoopD &L = D.loops[i];
-        FLoopRec &Q = D.lrec[i];
-        std::memset(&Q, 0, sizeof Q);
-        Q.lag = L.lag;
-        Q.ylo = L.ylo;
-        Q.yhi = L.yhi;
-        Q.vlo = L.vlo;
-        Q.vhi = L.vhi;
-        const FRingD &O = D.rings[L.out_ring];
-        Q.out_off = O.lds_off;
-        Q.out_depth = O.depth;
-        Q.out_inv = O.inv_depth;
-        Q.nin = L.nin;
-        for (int k = 0; k < L.nin; ++k) {
-            const FInD &I = D.ins[L.in0 + k];
-            const FRingD &Rg = D.rings[I.ring];
-            FInRec &J = Q.in[k];
-            J.off = Rg.lds_off;
-            J.depth = Rg.depth;
-            J.inv = Rg.inv_depth;
-            J.star = I.star;
-            J.ent0 = I.ent0;
-            J.nent = I.nent;
-            if (I.star)
-                for (int q = 0; q < I.nent; ++q) Q.w[k][q] = D.w[I.ent0 + q];
+    if ((G.nwaves_in > 0 && !G.fin) || (G.nwaves_edge > 0 && !G.fedge))
+        return fail(c, TC_ERR_STATE, "fused group kernels are not loaded");
+    // kernel arguments: source pointers, destination pointers, weights
+    const size_t ns = std::max<size_t>(1, G.src_dat.size()), nd = std::max<size_t>(1, G.dst_dat.size());
+    std::vector<unsigned char> buf(8 * (ns + nd + (size_t)std::max(1, G.nweights)), 0);
+    auto put = [&](size_t slot, const void *p) { std::memcpy(&buf[8 * slot], &p, 8); };
+    for (size_t i = 0; i < G.src_dat.size(); ++i) {
+        const Dataset &ds = c.dats[G.src_dat[i]];
+        put(i, ds.origin(ds.cur));
+    }
+    for (size_t i = 0; i < G.dst_dat.size(); ++i) {
+        Dataset &ds = c.dats[G.dst_dat[i]];
+        if (!G.dst_twin[i]) {
+            put(ns + i, ds.origin(ds.cur));
+            continue;
         }
+        const int tw = 1 - ds.cur;
+        if (!ds.raw[tw]) {
+            ds.raw[tw] = dev_alloc(c, (size_t)(ds.bytes + ds.stagger));
+            if (!ds.raw[tw]) return fail(c, TC_ERR_NOMEM, "cannot allocate the second buffer of %s", ds.name.c_str());
+            ds.buf[tw] = (char *)ds.raw[tw] + ds.stagger;
+            ds.twin_synced = false;
+        }
+        // the second buffer must equal the current one outside the range
+        // written here; it does outside the hull of earlier writes
+        const bool inside = !ds.ever_written || (ds.wlo[0] >= G.xlo && ds.whi[0] <= G.xhi && ds.wlo[1] >= G.ylo &&
+                                                 ds.whi[1] <= G.yhi);
+        if (!ds.twin_synced || !inside) {
+            if (hipMemcpyAsync(ds.buf[tw], ds.buf[ds.cur], (size_t)ds.bytes, hipMemcpyDeviceToDevice, c.stream) !=
+                hipSuccess)
+                return fail(c, TC_ERR_DEVICE, "hipMemcpyAsync (second buffer) failed");
+            ds.twin_synced = true;
+        }
+        put(ns + i, ds.origin(tw));
     }
-    for (int i = 0; i < D.nload; ++i) {
-        const FRingD &Rg = D.rings[D.load_list[i]];
-        FLoadRec &Q = D.ld[i];
-        std::memset(&Q, 0, sizeof Q);
-        Q.src = Rg.src;
-        Q.sy = Rg.sy;
-        Q.off = Rg.lds_off;
-        Q.depth = Rg.depth;
-        Q.inv = Rg.inv_depth;
-        Q.lag = Rg.load_lag;
-        Q.ext_ylo = Rg.ext_ylo;
-        Q.ext_yhi = Rg.ext_yhi;
-        Q.ld_below = Rg.ld_below;
-        Q.ld_above = Rg.ld_above;
-        Q.ext_xlo = Rg.ext_xlo;
-        Q.ext_xhi = Rg.ext_xhi;
-        Q.fw = Rg.load == 2;
-        Q.fw_xlo = Rg.fw_xlo;
-        Q.fw_xhi = Rg.fw_xhi;
-        Q.fw_ylo = Rg.fw_ylo;
-        Q.fw_yhi = Rg.fw_yhi;
-        Q.alloc_xlo = -(int)c.dats[G.ring_dat[D.load_list[i]]].xorg;
+    {
+        size_t k = 0;
+        for (int l = G.g0; l < G.g1; ++l)
+            for (double w : chain[l].params) std::memcpy(&buf[8 * (ns + nd + k++)], &w, 8);
     }
-    for (int i = 0; i < D.nstore; ++i) {
-        const FRingD &Rg = D.rings[D.store_list[i]];
-        FStoreRec &Q = D.st[i];
-        std::memset(&Q, 0, sizeof Q);
-        Q.dst = Rg.dst;
-        Q.sy = Rg.sy;
-        Q.off = Rg.lds_off;
-        Q.depth = Rg.depth;
-        Q.inv = Rg.inv_depth;
-        Q.lag = Rg.store_lag;
-        Q.hxlo = Rg.hull_xlo;
-        Q.hxhi = Rg.hull_xhi;
-        Q.hylo = Rg.hull_ylo;
-        Q.hyhi = Rg.hull_yhi;
+    size_t sz = buf.size();
+    void *cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, buf.data(), HIP_LAUNCH_PARAM_BUFFER_SIZE, &sz, HIP_LAUNCH_PARAM_END};
+    if (G.nwaves_edge > 0) {
+        const unsigned nb = (unsigned)((G.nwaves_edge + 3) / 4);
+        const hipError_t e = hipModuleLaunchKernel(G.fedge, nb, 1, 1, 256, 1, 1, 0, c.stream, nullptr, cfg);
+        if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "fused kernel launch failed: %s", hipGetErrorString(e));
     }
-    if (hipMemcpyAsync(G.dev, G.host, sizeof(FGroupD), hipMemcpyHostToDevice, c.stream) != hipSuccess)
-        return fail(c, TC_ERR_DEVICE, "hipMemcpyAsync (fused descriptor) failed");
-    if (hipEventRecord(G.uploaded, c.stream) != hipSuccess) return fail(c, TC_ERR_DEVICE, "hipEventRecord failed");
-    G.nblocks = nbx * nby;
-    hipError_t e = launch_fused(G.dev, G.dtype, G.rows, G.nblocks, G.lds_bytes + kFDescLds, c.stream);
-    if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "fused kernel launch failed: %s", hipGetErrorString(e));
-    // the written datasets now live in their second buffers
-    for (int r = 0; r < D.nrings; ++r)
-        if (D.rings[r].store) {
-            Dataset &ds = c.dats[G.ring_dat[r]];
+    if (G.nwaves_in > 0) {
+        const unsigned nb = (unsigned)((G.nwaves_in + 3) / 4);
+        const hipError_t e = hipModuleLaunchKernel(G.fin, nb, 1, 1, 256, 1, 1, 0, c.stream, nullptr, cfg);
+        if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "fused kernel launch failed: %s", hipGetErrorString(e));
+    }
+    for (size_t i = 0; i < G.dst_dat.size(); ++i)
+        if (G.dst_twin[i]) {
+            Dataset &ds = c.dats[G.dst_dat[i]];
             ds.cur = 1 - ds.cur;
         }
     return TC_OK;
@@ -479,84 +766,10 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
 
 void fused_release(Ctx &c) {
     for (auto &kv : c.plans)
-        for (auto &g : kv.second->groups) {
-            if (g->host) (void)hipHostFree(g->host);
-            if (g->dev) dev_free(c, g->dev);
-            if (g->uploaded) (void)hipEventDestroy(g->uploaded);
-            g->host = nullptr;
-            g->dev = nullptr;
-            g->uploaded = nullptr;
-        }
+        for (auto &g : kv.second->groups) g->fin = g->fedge = nullptr;
+    for (auto &kv : c.jit_modules)
+        if (kv.second) (void)hipModuleUnload(kv.second);
+    c.jit_modules.clear();
 }
-
-// AUTO mode (Section 4.3 chooses a tile size from the cache size; here the
-// cache-based choice is one candidate and every candidate is measured): the
-// first flushes of a chain structure each run one candidate schedule while
-// its device time is measured; afterwards the fastest is used.  Every
-// candidate computes bit-identical results, so tuning never changes answers.
-namespace {
-struct Cand {
-    tc_tiling mode;
-    int tile[3];
-};
-std::vector<Cand> candidates(const std::vector<LoopRec> &chain) {
-    std::vector<Cand> v;
-    v.push_back({TC_TILING_NONE, {0, 0, 0}});
-    v.push_back({TC_TILING_SKEWED, {0, 0, 0}});
-    const int nd = chain.empty() ? 2 : chain[0].ndim;
-    if (nd >= 2) {
-        int t[3] = {0, 0, 0};
-        t[nd - 1] = 128;
-        v.push_back({TC_TILING_SKEWED, {t[0], t[1], t[2]}});
-    }
-    bool any2d = false;
-    for (const auto &lp : chain) any2d = any2d || (lp.ndim == 2 && lp.op == TC_OP_WSUM);
-    if (any2d) {
-        v.push_back({TC_TILING_FUSED, {4, 0, 0}});
-        v.push_back({TC_TILING_FUSED, {8, 0, 0}});
-    }
-    return v;
-}
-}  // namespace
-
-tc_tiling autotune_choose(Ctx &c, const std::vector<LoopRec> &chain, int tile[3]) {
-    const int zero[3] = {0, 0, 0};
-    const uint64_t key = chain_key(c, chain, TC_TILING_AUTO, zero);
-    auto cands = candidates(chain);
-    Ctx::Tune &T = c.tuned[key];
-    int pick;
-    if (T.best >= 0) {
-        pick = T.best;
-        c.tune_cand = -1;
-    } else {
-        pick = T.next;
-        c.tune_cand = pick;
-        c.tune_key = key;
-    }
-    for (int d = 0; d < 3; ++d) tile[d] = cands[pick].tile[d];
-    return cands[pick].mode;
-}
-
-void autotune_record(Ctx &c, double seconds) {
-    if (c.tune_cand < 0) return;
-    Ctx::Tune &T = c.tuned[c.tune_key];
-    T.seconds.push_back(seconds);
-    T.next = c.tune_cand + 1;
-    // the candidate list depends only on the chain structure, so its length
-    // is recovered from the number of candidates of any chain with this key
-    c.tune_cand = -1;
-}
-
-void autotune_finish(Ctx &c, size_t ncand) {
-    Ctx::Tune &T = c.tuned[c.tune_key];
-    if (T.best < 0 && T.seconds.size() >= ncand) {
-        int b = 0;
-        for (size_t i = 1; i < T.seconds.size(); ++i)
-            if (T.seconds[i] < T.seconds[b]) b = (int)i;
-        T.best = b;
-    }
-}
-
-size_t autotune_candidates(const std::vector<LoopRec> &chain) { return candidates(chain).size(); }
 
 }  // namespace tc

@@ -1,160 +1,119 @@
-// Fused execution of a loop chain: overlapped tiles (Section 4.4 of the
-// paper, applied to GPU workgroups instead of MPI ranks) streamed through
-// LDS.
+// Fused execution of a loop chain with overlapped tiles (Section 4.4 of the
+// paper, applied to GPU wavefronts instead of MPI ranks).
 //
-// A fusion group is a run of consecutive 2D weighted-sum loops.  Every
-// workgroup owns a block of W columns by Hseg rows of the group's domain and
-// marches up y two rows per step.  At every step each loop of the group
-// computes one row pair at its own lag, reading its inputs from per-dataset
-// ring buffers in LDS; loaders bring chain-start values of datasets into their
-// rings ahead of their first readers, storers write each dataset's final
-// values for the owned block back to HBM.  A loop recomputes the points its
-// later readers need beyond the owned block (its x and y extents), so blocks
-// run concurrently with no communication; datasets the group writes are
-// written to a second buffer (ping-pong) so that no workgroup overwrites
-// values another one still loads.
+// A fusion group is a run of consecutive 2D weighted-sum loops over one
+// common range.  The library generates a HIP kernel for the group at plan
+// time and compiles it with hipRTC.  Every wavefront owns a strip of Wo
+// columns by Hseg rows of the range; its 64 lanes hold 64 consecutive
+// columns (the owned ones plus HL to the left and HR to the right) and it
+// marches up the rows.  At every step each loop of the group computes one
+// row at its own lag, reading its inputs from per-version register windows
+// (x neighbours through cross-lane moves, y neighbours from older window
+// entries); chain-start values of datasets are loaded a few rows ahead of
+// their first reader and the final value of every written dataset is stored
+// for the owned columns.  A loop computes the columns and rows its later
+// readers need beyond the owned block, so wavefronts run with no
+// communication at all.  A dataset whose chain-start value is read and which
+// is also written is written to its second buffer (ping-pong), so that no
+// wavefront overwrites a value another one still loads.
+//
+// Wavefronts whose reads stay inside the range run the "interior" kernel;
+// those near the range boundary run the "edge" kernel, which additionally
+// keeps the chain-start value of every written dataset where the range does
+// not cover a point (such points are never written by the group).
 #pragma once
+
+#include <string>
+#include <vector>
 
 #include "tc_internal.hpp"
 
 namespace tc {
 
-constexpr int kFMaxLoops = 16;
-constexpr int kFMaxRings = 16;
-constexpr int kFMaxLoaded = 12;  // rings with a loader (register buffers per thread)
-constexpr int kFMaxEnt = 384;
-constexpr int kFCols = 128;     // ring width in columns = threads per row
-// Workgroup: 128 columns x TR thread rows (256, 512 or 1024 threads); every
-// thread computes P consecutive rows per step: rows per step 2 (TR 2), 4
-// (TR 4), 8 (TR 8) or 16 (TR 8, P 2).
+constexpr int kJLanes = 64;      // columns held by one wavefront
+constexpr int kJMaxSrc = 24;     // datasets loaded by one group
+constexpr int kJMaxDst = 16;     // datasets stored by one group
+constexpr int kJMaxW = 384;      // weights of one group (kernel arguments)
+constexpr int kJMaxOff = 8;      // largest stencil offset in x or y
 
-struct FLoopD {
-    int out_ring;
-    int ent0, nent;      // stencil-point entries of the inputs, listed order
-    int in0, nin;        // inputs (for per-input slot computation)
-    int lag;
-    int xlo, xhi, ylo, yhi;  // iteration range
-    int hlo, hhi, vlo, vhi;  // columns left/right and rows below/above the owned block it computes
+struct JPt {
+    int dx, dy, w;  // offset and index of the weight in the group's weight list
 };
 
-struct FInD {   // one input of a loop: ring and its entries
-    int ring, ent0, nent;
-    int star;   // 1 or 2: canonical radius-1/2 star (centre, -x, +x, [-2x, +2x,] -y, +y, [-2y, +2y]); 0: entries
+struct JRead {
+    int ver;
+    std::vector<JPt> pts;
+    int dxmin, dxmax, dymin, dymax;
 };
 
-struct FRingD {
-    void *src;    // logical (0,0) of the buffer holding the chain-start values
-    void *dst;    // logical (0,0) of the buffer receiving the final values
-    int64_t sy;   // row pitch (elements)
-    int depth;    // rows
-    int lds_off;  // elements
-    float inv_depth;
-    int load;     // 0: none, 1: every point, 2: points outside the first write's range
-    int load_lag, ld_below, ld_above;
-    int fw_xlo, fw_xhi, fw_ylo, fw_yhi;
-    int store, store_lag;
-    int hull_xlo, hull_xhi, hull_ylo, hull_yhi;  // store region
-    int ext_xlo, ext_xhi, ext_ylo, ext_yhi;      // allocated extent
+struct JLoop {
+    int loop;  // chain index
+    int out;   // version written
+    std::vector<JRead> in;
+    int lag = 0;
+    bool needed = false;
+    int extL = -1, extR = -1, extB = -1, extT = -1;  // extra columns/rows computed (-1: not needed)
 };
 
-struct FEnt {
-    short ring;
-    signed char dx, dy;
+struct JVer {
+    int dat;
+    int producer = -1;   // group loop index, -1 for the chain-start value
+    int lag = 0;         // produced: loop lag; loaded: row y arrives at step y + lag
+    bool stored = false;
+    bool needed = false;
+    bool sel = false;    // read at a non-zero offset (edge kernel keeps the chain-start value outside the range)
+    int extL = -1, extR = -1, extB = -1, extT = -1;
 };
 
-// Flat per-step records read by the kernel (built per flush): one record per
-// loop, per loaded ring and per stored ring, so that a step reads each with a
-// few wide scalar loads and no indirection.
-constexpr int kFMaxIn = 4;  // inputs of a fused loop
-struct FInRec {
-    int off, depth;
-    float inv;
-    int star;  // 1 or 2: canonical star, weights in FLoopRec::w; 0: entries ent0..ent0+nent
-    int ent0, nent;
-};
-struct FLoopRec {
-    int lag, ylo, yhi, vlo, vhi;
-    int out_off, out_depth;
-    float out_inv;
-    int nin, pad[3];
-    FInRec in[kFMaxIn];
-    double w[kFMaxIn][9];
-};
-struct FLoadRec {
-    const void *src;
-    int64_t sy;
-    int off, depth;
-    float inv;
-    int lag;
-    int ext_ylo, ext_yhi, ld_below, ld_above;
-    int ext_xlo, ext_xhi;
-    int fw, fw_xlo, fw_xhi, fw_ylo, fw_yhi;
-    int alloc_xlo;  // first column of the allocated row (aligned to 16 elements)
-};
-struct FStoreRec {
-    void *dst;
-    int64_t sy;
-    int off, depth;
-    float inv;
-    int lag;
-    int hxlo, hxhi, hylo, hyhi;
+// Per-variant schedule: which chain-start versions are loaded and the
+// register window (rows) of every version.
+struct JVariant {
+    std::vector<int> win;         // per version, 0 if not held
+    std::vector<int> load_lag;    // per version (loaded only)
+    std::vector<char> loaded;     // per version
+    std::vector<std::pair<int, int>> pseudo;  // (producer loop, chain-start version): edge selects
+    int pre = 0, post = 0;        // steps before / after the owned rows
+    int regs = 0;                 // estimated VGPRs of the windows
 };
 
-// bytes of LDS after the rings holding the step records (copied there at
-// kernel start: LDS broadcast reads are much cheaper than scalar loads that
-// miss the scalar cache)
-constexpr int kFDescLds = ((int)(sizeof(FLoopRec) * kFMaxLoops + sizeof(FLoadRec) * kFMaxLoaded +
-                                 sizeof(FStoreRec) * kFMaxRings) + 255) / 256 * 256;
-
-struct FGroupD {
-    int nloops, nrings, nin;
-    int R;           // rows per step
-    int ring_bytes;  // LDS bytes of the rings (step records follow)
-    int nload, nstore;
-    int load_list[kFMaxRings], store_list[kFMaxRings];  // rings with a loader / a storer
-    FLoopRec lrec[kFMaxLoops];
-    FLoadRec ld[kFMaxLoaded];
-    FStoreRec st[kFMaxRings];
-    int W, HR, Hseg;
-    int dom_xlo, dom_ylo, nbx, nby;
-    FLoopD loops[kFMaxLoops];
-    FRingD rings[kFMaxRings];
-    FInD ins[kFMaxLoops * 8];
-    FEnt ent[kFMaxEnt];
-    double w[kFMaxEnt];
-};
-
-// Static analysis of one fusion group (cached with the plan).
 struct FusedGroup {
-    int g0, g1;               // loops [g0, g1) of the chain
-    int dtype;
-    int rows = 2;             // rows per step (2 or 4)
-    int hseg_req = 0;         // requested rows per workgroup (0: automatic)
-    std::vector<int> ring_dat;  // dataset of every ring
-    std::vector<int> ring_store;
-    FGroupD tmpl;             // descriptor without pointers, store regions or weights
-    int lds_bytes = 0;
+    int g0 = 0, g1 = 0;  // loops [g0, g1) of the chain
+    int dtype = TC_F64;
+    int xlo = 0, xhi = 0, ylo = 0, yhi = 0;
+    std::vector<JLoop> loops;
+    std::vector<JVer> vers;
+    JVariant var[2];  // 0 interior, 1 edge
+    int HL = 0, HR = 0, Wo = 0;
+    int BMAX = 0, TMAX = 0;  // rows below / above the owned rows that are read
+    int Hseg = 0, U = 4, PF = 2;
+    int nstrips = 0, nsegs = 0;
+    int si0 = 0, si1 = 0, gi0 = 0, gi1 = 0;  // interior rectangle of strips x segments
+    int nwaves_in = 0, nwaves_edge = 0;
     int nblocks = 0;
-    // per-group staging: pinned host copy and device copy of the descriptor,
-    // and an event marking the end of the last upload from the host copy
-    FGroupD *host = nullptr;
-    FGroupD *dev = nullptr;
-    hipEvent_t uploaded = nullptr;
+    std::vector<int> src_dat;   // datasets loaded (kernel argument order)
+    std::vector<int> dst_dat;   // datasets stored
+    std::vector<char> dst_twin; // store to the second buffer
+    int nweights = 0;
+    std::vector<double> wvals;  // weights at analysis time
+    bool baked = false;         // weights compiled into the kernels
+    double cost = 0.0;          // modelled seconds per flush (split choice)
+    std::string source;         // generated kernels
+    std::string kname_in, kname_edge;
+    hipFunction_t fin = nullptr, fedge = nullptr;
 };
 
-// Split a chain into fusion groups; loops outside any group run one kernel
-// each.  Returns the groups in chain order.
-std::vector<std::shared_ptr<FusedGroup>> fused_split(const Ctx &c, const std::vector<LoopRec> &chain,
-                                                     const int tile[3]);
+// Split a chain into fusion groups (loops outside any group run one kernel
+// each) and generate their kernels; returns the groups in chain order.
+std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3]);
+
+// Compile (and, on a device context, load) the kernels of a plan's groups.
+tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups);
 
 // Run one fusion group on the context's stream (ping-pong buffers are
 // prepared and swapped here).
 tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &g);
 
-// Kernel launch (fused_kernel.hip).
-hipError_t launch_fused(const FGroupD *dev_desc, int dtype, int rows, int nblocks, int lds_bytes, hipStream_t s);
-
-// Release device memory held for fused execution.
+// Release modules held for fused execution.
 void fused_release(Ctx &c);
 
 // AUTO mode: the execution mode (and tile, written back) to use for this

@@ -224,6 +224,13 @@ struct Ctx {
     bool use_graphs = true;              // TC_GRAPHS=0 disables graph replay
     hipStream_t cap_stream = nullptr;    // private stream used only for graph capture
 
+    // fused groups: generated kernels compiled at plan time, cached by source
+    std::unordered_map<uint64_t, hipModule_t> jit_modules;
+    int jit_unroll = 4;      // steps per iteration of the generated march loop (TC_JIT_UNROLL)
+    int jit_prefetch = 2;    // rows loaded ahead of their arrival step (TC_JIT_PREFETCH)
+    bool jit_bake = true;    // compile the weights into the kernels (TC_JIT_BAKE=0: read them from arguments)
+    double jit_compile_seconds = 0.0;
+
     // per-launch kernel timing (tc_set_profiling)
     bool profiling = false;
     std::vector<hipEvent_t> events;

@@ -115,3 +115,24 @@ def test_paper_example_through_abi():
     assert num == [2]
     assert [[start[0][t][0], end[0][t][0]] for t in range(2)] == [[0, 5], [5, 8]]
     assert [[start[0][t][1], end[0][t][1]] for t in range(2)] == [[0, 4], [4, 8]]
+
+
+def test_fused_groups_generate_and_compile_host_only():
+    """The fused mode's kernels are generated and compiled for gfx950 without
+    a device (host-only context); groups are ordered, disjoint runs of at
+    least two loops."""
+    from paper_1704_00693_amd.apps import ChainRunner
+    from synthgen import chain_2d
+    ch = chain_2d(n=256)
+    with tc.Context(host_only=True) as c:
+        r = ChainRunner(c, ch, None)
+        r.record()
+        groups = c.tc_fused_groups()
+        small = c.tc_fused_groups((16, 48, 3))
+    for gs in (groups, small):
+        assert gs
+        last = 0
+        for g0, g1 in gs:
+            assert g0 >= last and g1 - g0 >= 2
+            last = g1
+    assert all(g1 - g0 <= 3 for g0, g1 in small)
