@@ -12,11 +12,17 @@ kernel (timed with HIP events inside the run) and the oracle timed on the
 host's cores on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes none,skewed,fused]
+
+Measured HBM traffic comes from rocprofv3 counter runs of this script (one
+run per counter and mode, ingested with --ingest-counters on the host),
+scaled by what the same counters read for a plain copy kernel of known size
+(--modes copy).
 """
 import argparse
+import csv
+import glob
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -27,6 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "tiled vs untiled cell-updates/s & HBM GB/s; batched solves/s + p99 latency"
 HBM_PEAK_GBS = 8000.0
 MODE_NAMES = {"none": 0, "skewed": 1, "fused": 2}
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def log(*a):
@@ -42,23 +49,21 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(mode_name: str):
-    """HBM traffic per launch of the dominant kernel from the committed rocprofv3
-    counter summary, or None if absent or taken on different kernel sources."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(p):
+def traffic_entry(mode_name: str):
+    """Counter-derived HBM traffic of a mode from the committed summary, or
+    None if absent or taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_JSON):
         return None
     try:
-        t = json.load(open(p))
+        t = json.load(open(TRAFFIC_JSON))
     except ValueError:
         return None
-    ent = t.get(mode_name)
-    if not ent or ent.get("source_sha") != kernel_source_sha():
+    if t.get("source_sha") != kernel_source_sha():
         return None
-    return ent.get("hbm_bytes_per_launch")
+    return t.get("modes", {}).get(mode_name)
 
 
-def time_mode(tc, ctx, runner, mode, tile, steps, warmup, cells_per_step):
+def time_mode(ctx, runner, mode, tile, steps, warmup, cells_per_step):
     import torch
     ctx.tc_set_tiling(mode, tile)
     for _ in range(warmup):
@@ -78,9 +83,8 @@ def time_mode(tc, ctx, runner, mode, tile, steps, warmup, cells_per_step):
     ctx.tc_flush()
     prof = ctx.tc_get_stats()
     ctx.tc_set_profiling(False)
-    ms = dt / steps * 1e3
-    res = {
-        "ms_per_step": ms,
+    return {
+        "ms_per_step": dt / steps * 1e3,
         "cell_updates_per_s": cells_per_step * steps / dt,
         "effective_GBps": st["modelled_bytes"] * steps / dt / 1e9,
         "launches_per_step": st["last_launches"],
@@ -88,11 +92,42 @@ def time_mode(tc, ctx, runner, mode, tile, steps, warmup, cells_per_step):
         "groups": st["last_groups"],
         "max_skew": st["max_skew"],
         "plan_seconds": st["plan_seconds"],
+        "jit_compile_seconds": st["jit_compile_seconds"],
         "modelled_bytes": st["modelled_bytes"],
+        "fused_bytes": st["fused_bytes"],
         "kernel_seconds": prof["prof_kernel_seconds"],
         "kernel_launches": prof["prof_launches"],
+        "fused_kernel_seconds": prof["prof_fused_seconds"],
     }
-    return res
+
+
+def copy_probe(tc, n: int, steps: int, warmup: int):
+    """A plain copy of one n^2 FP64 dataset into another (the library's COPY
+    loop): the counter calibration kernel and the achievable-bandwidth probe."""
+    import torch
+    with tc.Context(0) as c:
+        blk = c.tc_decl_block(2, "copy")
+        a = c.tc_decl_dat(blk, [n, n], [2, 2], [2, 2], None, tc.TC_F64, "a")
+        b = c.tc_decl_dat(blk, [n, n], [2, 2], [2, 2], None, tc.TC_F64, "b")
+        s0 = c.tc_decl_stencil([(0, 0)])
+
+        def rec():
+            c.tc_par_loop("COPY", blk, [0, n, 0, n], [(b, s0, "W"), (a, s0, "R")], [], name="copy")
+
+        for _ in range(warmup):
+            rec()
+            c.tc_flush()
+        torch.cuda.synchronize()
+        c.tc_set_profiling(True)
+        tot = 0.0
+        for _ in range(steps):
+            rec()
+            c.tc_flush()
+            tot += c.tc_get_stats()["prof_kernel_seconds"]
+        c.tc_set_profiling(False)
+    alg = 2 * n * n * 8
+    return {"alg_bytes_per_launch": alg, "launches": steps + warmup, "avg_launch_us": tot / steps * 1e6,
+            "GBps": alg * steps / tot / 1e9}
 
 
 def cpu_baseline(ch_full, n_sample: int):
@@ -120,17 +155,79 @@ def _cpu_model():
     return "unknown"
 
 
+# ---------------------------------------------------------------------------
+# counter ingestion (host only): rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs
+# ---------------------------------------------------------------------------
+def _family(name: str) -> str:
+    if "tcj_g" in name:
+        return "fused"
+    if "OpCopy" in name:
+        return "copy"
+    if "wsum" in name or "OpWsum" in name:
+        return "wsum"
+    return "other"
+
+
+MODE_FAMILY = {"copy": "copy", "fused": "fused", "none": "wsum", "skewed": "wsum"}
+
+
+def ingest_counters(spec):
+    """spec: MODE:COUNTER:DIR:FLUSHES entries (FLUSHES = flushes of that mode
+    in the profiled run).  Writes profiles/traffic.json: per mode, the HBM
+    bytes per flush and per dispatch of its chain kernels, scaled so that the
+    copy kernel reads and writes exactly its algorithmic bytes."""
+    raw = {}
+    for item in spec:
+        mode, counter, d, flushes = item.split(":")
+        tot, disp = 0.0, 0
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter or _family(r["Kernel_Name"]) != MODE_FAMILY[mode]:
+                    continue
+                tot += float(r["Counter_Value"]) * 1024.0  # counters are in KiB
+                disp += 1
+        raw.setdefault(mode, {})[counter] = {"bytes": tot, "dispatches": disp, "flushes": int(flushes)}
+    cal = raw["copy"]
+    half = json.load(open(os.path.join(ROOT, "profiles", "copy_probe.json")))["alg_bytes_per_launch"] / 2
+    f_fetch = half / (cal["FETCH_SIZE"]["bytes"] / cal["FETCH_SIZE"]["dispatches"])
+    f_write = half / (cal["WRITE_SIZE"]["bytes"] / cal["WRITE_SIZE"]["dispatches"])
+    out = {"source_sha": kernel_source_sha(),
+           "calibration": {"copy_bytes_read_per_launch": half, "copy_bytes_written_per_launch": half,
+                           "factor_fetch": f_fetch, "factor_write": f_write},
+           "modes": {}}
+    for mode, ent in raw.items():
+        if mode == "copy":
+            continue
+        fe, wr = ent["FETCH_SIZE"], ent["WRITE_SIZE"]
+        rd = fe["bytes"] * f_fetch / fe["flushes"]
+        wt = wr["bytes"] * f_write / wr["flushes"]
+        disp = fe["dispatches"] / fe["flushes"]
+        out["modes"][mode] = {"hbm_bytes_per_flush": rd + wt, "read_bytes_per_flush": rd,
+                              "write_bytes_per_flush": wt, "dispatches_per_flush": disp,
+                              "hbm_bytes_per_launch": (rd + wt) / disp}
+    with open(TRAFFIC_JSON, "w") as fp:
+        json.dump(out, fp, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="none,skewed,fused")
+    ap.add_argument("--modes", default="none,skewed,fused",
+                    help="comma list of none, skewed, fused; 'copy' alone runs the copy probe")
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--cpu-sample", type=int, default=2048, help="grid edge of the oracle's timed sample (0: skip)")
     ap.add_argument("--fused-tile", default="0,0,0",
-                    help="fused mode tile: rows per wavefront segment, window-register budget, most loops per group (0: automatic)")
+                    help="fused mode tile: rows per wavefront segment, window-register budget, most loops per group "
+                         "(0: automatic)")
+    ap.add_argument("--ingest-counters", nargs="*", default=None,
+                    help="host only: MODE:COUNTER:DIR:FLUSHES entries from rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.ingest_counters is not None:
+        ingest_counters(args.ingest_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is described in DESIGN.md, not built)", file=sys.stderr)
@@ -142,6 +239,11 @@ def main():
     from synthgen import chain_2d, chain_data
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.modes == "copy":
+        print(json.dumps(copy_probe(tc, args.n, args.steps, args.warmup)))
+        return
+    copy = copy_probe(tc, args.n, 10, 2)
+    log(f"copy probe: {copy['GBps']:.0f} GB/s")
     ch = chain_2d(n=args.n)
     log(f"generating inputs: {ch.ndat} x {ch.n + 4}^2 FP64")
     data = chain_data(ch)
@@ -156,7 +258,7 @@ def main():
             log(f"mode {name}: warmup {args.warmup}, steps {args.steps}")
             try:
                 tile = tuple(int(v) for v in args.fused_tile.split(",")) if name == "fused" else (0, 0, 0)
-                results[name] = time_mode(tc, ctx, runner, mode, tile, args.steps, args.warmup, cells)
+                results[name] = time_mode(ctx, runner, mode, tile, args.steps, args.warmup, cells)
             except tc.TcError as e:
                 if e.status != tc.TC_ERR_UNSUPPORTED:
                     raise
@@ -168,17 +270,29 @@ def main():
     tiled = {k: v for k, v in results.items() if k != "none"}
     best_name = max(tiled, key=lambda k: tiled[k]["cell_updates_per_s"]) if tiled else "none"
     best = results[best_name]
-    # dominant kernel of the reported mode: the per-loop / fused kernel
-    avg = best["kernel_seconds"] / max(best["kernel_launches"], 1)
-    bytes_per_launch = best["modelled_bytes"] / max(best["kernel_launches"], 1)
-    achieved = bytes_per_launch / avg / 1e9 if avg > 0 else 0.0
-    traffic = load_traffic(best_name)
+    if best_name == "fused" and best["groups"] > 0:
+        # dominant kernels: the generated fused-group kernels (one interior and
+        # one edge launch per group); algorithmic bytes = chain-start datasets
+        # read + datasets written, once over the group's range
+        launches = best["groups"]
+        secs = best["fused_kernel_seconds"]
+        alg = best["fused_bytes"] / launches
+        kname = "tcj_g*_in + tcj_g*_edge (generated fused-group kernels), per group"
+    else:
+        launches = max(best["kernel_launches"], 1)
+        secs = best["kernel_seconds"]
+        alg = best["modelled_bytes"] / launches
+        kname = "wsum_march_kernel (per-loop weighted sum)"
+    avg = secs / launches
+    achieved = alg / avg / 1e9 if avg > 0 else 0.0
+    tr = traffic_entry(best_name)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "fused_group_kernel" if best_name == "fused" else "loop_kernel<OpWsum<double>>",
-                "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch}
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None if tr is None else tr["hbm_bytes_per_flush"] / launches,
+                "kernel": kname, "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": alg}
     cpu = cpu_baseline(ch, args.cpu_sample) if args.cpu_sample > 0 else None
     untiled = results.get("none")
+    tr_none = traffic_entry("none")
     line = {
         "metric": METRIC,
         "value": best["cell_updates_per_s"],
@@ -198,8 +312,13 @@ def main():
         "effective_GBps": best["effective_GBps"],
         "untiled": None if untiled is None else {
             "cell_updates_per_s": untiled["cell_updates_per_s"], "ms_per_step": untiled["ms_per_step"],
-            "effective_GBps": untiled["effective_GBps"]},
+            "effective_GBps": untiled["effective_GBps"],
+            "hbm_bytes_per_flush": None if tr_none is None else tr_none["hbm_bytes_per_flush"]},
         "speedup_vs_untiled": None if untiled is None else best["cell_updates_per_s"] / untiled["cell_updates_per_s"],
+        "hbm_bytes_per_flush": None if tr is None else tr["hbm_bytes_per_flush"],
+        "hbm_byte_ratio_untiled_over_tiled": (None if tr is None or tr_none is None
+                                              else tr_none["hbm_bytes_per_flush"] / tr["hbm_bytes_per_flush"]),
+        "copy_probe_GBps": copy["GBps"],
         "modes": results,
         "roofline": roofline,
         "cpu_baseline": cpu,

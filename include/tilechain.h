@@ -241,6 +241,13 @@ typedef struct {
        timed; the main kernels only (reduction finalisation excluded) */
     double prof_kernel_seconds;
     int64_t prof_launches;
+    /* fused groups of the last flush: their algorithmic HBM bytes (every
+       dataset whose chain-start value a group reads, plus every dataset it
+       writes, once over the group's range) and, with profiling on, the
+       device time of their kernels */
+    int64_t fused_bytes;
+    double prof_fused_seconds;
+    double jit_compile_seconds; /* total host time spent compiling fused kernels */
 } tc_stats;
 
 tc_status tc_get_stats(tc_ctx *ctx, tc_stats *out);

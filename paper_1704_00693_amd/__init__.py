@@ -67,7 +67,8 @@ class Stats(ctypes.Structure):
                 ("last_launches", ctypes.c_int32), ("last_mode", ctypes.c_int32),
                 ("modelled_bytes", ctypes.c_int64), ("cell_updates", ctypes.c_int64),
                 ("last_flush_seconds", ctypes.c_double), ("prof_kernel_seconds", ctypes.c_double),
-                ("prof_launches", ctypes.c_int64)]
+                ("prof_launches", ctypes.c_int64), ("fused_bytes", ctypes.c_int64),
+                ("prof_fused_seconds", ctypes.c_double), ("jit_compile_seconds", ctypes.c_double)]
 
     def as_dict(self):
         out = {}

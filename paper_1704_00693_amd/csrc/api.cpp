@@ -525,13 +525,15 @@ tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, CachedPlan &P)
     }
     if (c.profiling) {
         HIPCHK(c, hipStreamSynchronize(c.stream));
-        double tot = 0.0;
+        double tot = 0.0, fused = 0.0;
         for (size_t k = 0; k < i; ++k) {
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, c.events[2 * k], c.events[2 * k + 1]));
             tot += ms * 1e-3;
+            if (P.steps[k].kind == 1) fused += ms * 1e-3;
         }
         c.stats.prof_kernel_seconds = tot;
+        c.stats.prof_fused_seconds = fused;
         c.stats.prof_launches = (int64_t)i;
     }
     return TC_OK;
@@ -599,9 +601,13 @@ tc_status flush(Ctx &c) {
         launches = (int)P->steps.size();
         tiles = P->skewed.num_tiles[0] * P->skewed.num_tiles[1] * P->skewed.num_tiles[2];
         groups = (int)P->groups.size();
+        c.stats.fused_bytes = 0;
         if (mode == TC_TILING_FUSED) {
             tiles = 0;
-            for (auto &g : P->groups) tiles += g->nblocks;
+            for (auto &g : P->groups) {
+                tiles += g->nblocks;
+                c.stats.fused_bytes += g->alg_bytes;
+            }
         }
         for (int d = 0; d < 3; ++d) c.stats.max_skew[d] = P->max_skew[d];
     }
@@ -1051,6 +1057,7 @@ tc_status tc_get_stats(tc_ctx *ctx, tc_stats *out) {
     CHECK_CTX(ctx);
     if (!out) return TC_ERR_ARG;
     *out = ctx->c.stats;
+    out->jit_compile_seconds = ctx->c.jit_compile_seconds;
     return TC_OK;
 }
 

@@ -23,7 +23,7 @@ int esize_of(int dtype) { return dtype == TC_F64 ? 8 : 4; }
 
 struct SplitParams {
     int hseg = 0;      // rows per wavefront segment (0: automatic)
-    int regs = 192;    // budget of window registers per lane
+    int regs = 160;    // budget of window registers per lane
     int max_loops = 32;
     int U = 4, PF = 2;
     bool bake = false;
@@ -248,9 +248,9 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     G.nstrips = (width + G.Wo - 1) / G.Wo;
     int Hseg = sp.hseg;
     if (Hseg <= 0) {
-        const int target = 2048;  // wavefronts: 8 per compute unit
+        const int target = 4096;  // wavefronts: 16 per compute unit
         const int nsegs = std::max(1, (int)std::lround((double)target / G.nstrips));
-        Hseg = std::max(32, (height + nsegs - 1) / nsegs);
+        Hseg = std::max(48, (height + nsegs - 1) / nsegs);
     }
     G.Hseg = std::min(Hseg, height);
     G.nsegs = (height + G.Hseg - 1) / G.Hseg;
@@ -306,6 +306,7 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
             for (const auto &p : R.pts) ops += 1.0 + (p.dx != 0 ? words : 0);
         ops += 2.0;
     }
+    G.alg_bytes = (int64_t)width * height * esize_of(G.dtype) * (int64_t)(nload + (int)G.dst_dat.size());
     const double bytes =
         cells * esize_of(G.dtype) * (nload * (1.0 + 0.5 * (HL + HR) / G.Wo) + (double)G.dst_dat.size()) * fy;
     const double valu = cells * fx * fy * ops / (256.0 * 64.0 * 2.4e9);
@@ -588,7 +589,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
     SplitParams sp;
     sp.bake = c.jit_bake;
     sp.hseg = tile[0] > 0 ? tile[0] : 0;
-    sp.regs = tile[1] > 0 ? tile[1] : 192;
+    sp.regs = tile[1] > 0 ? tile[1] : 160;
     sp.max_loops = tile[2] > 0 ? tile[2] : 32;
     sp.U = std::max(1, c.jit_unroll);
     sp.PF = std::max(1, c.jit_prefetch);

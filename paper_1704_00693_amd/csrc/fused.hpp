@@ -97,6 +97,7 @@ struct FusedGroup {
     std::vector<double> wvals;  // weights at analysis time
     bool baked = false;         // weights compiled into the kernels
     double cost = 0.0;          // modelled seconds per flush (split choice)
+    int64_t alg_bytes = 0;      // chain-start datasets read plus datasets written, once over the range
     std::string source;         // generated kernels
     std::string kname_in, kname_edge;
     hipFunction_t fin = nullptr, fedge = nullptr;
