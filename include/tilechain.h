@@ -269,6 +269,86 @@ tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_
 /* Number of loops currently recorded and not yet executed. */
 tc_status tc_pending(tc_ctx *ctx, int32_t *nloops);
 
+/* ---------------------------------------------------------------------------
+ * Batched and served heat-conduction solves.
+ *
+ * Not in the paper: many independent implicit heat-conduction solves (the
+ * TeaLeaf-style PPCG workload of Section 5 and Section 6.4, with the
+ * operator, reflective boundaries, Gershgorin bound and Chebyshev
+ * preconditioner of the library's TEA_* loops) advanced together on one
+ * GPU.  Every solver phase is one kernel launch over all resident instances;
+ * the phases of one iteration are captured once in a HIP graph and replayed.
+ * Each instance keeps its state machine, scalars and convergence test on the
+ * device; the host admits new solves into free slots by HBM footprint
+ * (continuous batching), retires finished ones and rebuilds the tile list
+ * between replays.
+ *
+ * Instance inputs are generated on the device from the seed: density
+ * uniform [0.1, 1) for every interior cell (draw k + 1 of the SplitMix64
+ * stream with state `seed`, cell k in row-major order, x fastest), then
+ * energy uniform [1, 2) (draws cells + k + 1); dx = 1/n, rx = dt * n * n.
+ * --------------------------------------------------------------------------- */
+typedef struct tc_batch tc_batch;
+
+typedef struct {
+    int32_t mixed;            /* 0: FP64 sweeps; 1: FP32 sweeps with FP64 reductions inside FP64
+                                 iterative refinement (x, b and the true residual in FP64) */
+    int32_t max_instances;    /* resident solves at once (slots), >= 1 */
+    int64_t max_cells;        /* cells of all resident solves at once (sizes the tile list) */
+    int64_t hbm_budget;       /* bytes of instance fields resident at once; admission stops above it */
+    int32_t cheb_steps;       /* Chebyshev steps per preconditioner application (0: 10) */
+    int32_t replays_per_step; /* iterations replayed per tc_batch_step (0: 4) */
+    double inner_tol;         /* mixed: relative drop of the FP32 residual per correction (0: 1e-4) */
+} tc_batch_opts;
+
+typedef struct {
+    int32_t ndim;      /* 2 or 3 */
+    int32_t n;         /* cells per axis, >= 2 */
+    uint64_t seed;     /* instance input stream */
+    double tol;        /* stop at ||r|| <= tol ||b|| (FP64 mode: recursive residual, then the true
+                          residual is reported; mixed: true residual) */
+    int32_t max_iter;  /* PPCG iteration cap (mixed: per correction) */
+    int32_t max_outer; /* mixed: refinement steps cap */
+    double dt;         /* time step (dx = 1/n) */
+    int32_t keep_x;    /* keep the solution for tc_batch_read_x */
+    int32_t pad;
+} tc_solve_desc;
+
+enum { TC_SOLVE_PENDING = 0, TC_SOLVE_RUNNING = 1, TC_SOLVE_DONE = 2, TC_SOLVE_REJECTED = -1 };
+
+typedef struct {
+    int32_t state;        /* TC_SOLVE_* */
+    int32_t iterations;   /* PPCG iterations (mixed: summed over corrections) */
+    int32_t outer;        /* mixed: refinement steps */
+    int32_t converged;    /* true residual <= tol ||b|| */
+    double rel_residual;  /* FP64 true residual ||b - A x|| / ||b|| */
+    double bnorm;         /* ||b|| */
+    double lmax;          /* Gershgorin bound used by the preconditioner */
+    double seconds;       /* submission to completion (host clock) */
+    double queue_seconds; /* submission to admission */
+} tc_solve_result;
+
+/* Create a batch engine on a context (its stream and allocator).  Device
+ * arrays for max_instances slots and max_cells cells are allocated here. */
+tc_status tc_batch_create(tc_ctx *ctx, const tc_batch_opts *opts, tc_batch **out);
+/* Queue one solve; returns its ticket.  TC_ERR_ARG for a bad description. */
+tc_status tc_batch_submit(tc_batch *b, const tc_solve_desc *desc, int64_t *ticket);
+/* One scheduling round: wait for the previous replays, retire finished
+ * solves, admit queued ones that fit, replay replays_per_step iterations.
+ * *unfinished = solves queued or resident afterwards.  A solve that can never
+ * fit (footprint above the budget or cells above max_cells) is rejected. */
+tc_status tc_batch_step(tc_batch *b, int32_t *unfinished);
+/* Result of a ticket (state TC_SOLVE_PENDING / RUNNING while unfinished). */
+tc_status tc_batch_poll(tc_batch *b, int64_t ticket, tc_solve_result *out);
+/* Step until every submitted solve has finished. */
+tc_status tc_batch_wait(tc_batch *b);
+/* Copy a finished solve's kept solution (n^ndim doubles, x fastest) to host
+ * memory; cap is the number of doubles available.  TC_ERR_STATE if the solve
+ * did not keep x or has not finished. */
+tc_status tc_batch_read_x(tc_batch *b, int64_t ticket, double *host, int64_t cap);
+/* Release the engine (resident solves are dropped). */
+tc_status tc_batch_destroy(tc_batch *b);
+
 const char *tc_status_string(tc_status s);
 const char *tc_last_error(tc_ctx *ctx);
 

@@ -37,7 +37,10 @@ OPS = {
 ACCESS = {"R": TC_READ, "W": TC_WRITE, "RW": TC_RW, "INC": TC_INC}
 EXPORTS = ["tc_init", "tc_finalize", "tc_decl_block", "tc_decl_dat", "tc_decl_stencil", "tc_decl_reduction",
            "tc_par_loop", "tc_reduction_result", "tc_flush", "tc_dat_read", "tc_dat_write", "tc_dat_device_view",
-           "tc_set_tiling", "tc_set_profiling", "tc_get_stats", "tc_chain_plan", "tc_pending", "tc_status_string", "tc_last_error"]
+           "tc_set_tiling", "tc_set_profiling", "tc_get_stats", "tc_chain_plan", "tc_pending", "tc_status_string",
+           "tc_last_error", "tc_batch_create", "tc_batch_submit", "tc_batch_step", "tc_batch_poll", "tc_batch_wait",
+           "tc_batch_read_x", "tc_batch_destroy"]
+TC_SOLVE_PENDING, TC_SOLVE_RUNNING, TC_SOLVE_DONE, TC_SOLVE_REJECTED = 0, 1, 2, -1
 
 
 class TcError(RuntimeError):
@@ -78,6 +81,27 @@ class Stats(ctypes.Structure):
         return out
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("mixed", ctypes.c_int32), ("max_instances", ctypes.c_int32), ("max_cells", ctypes.c_int64),
+                ("hbm_budget", ctypes.c_int64), ("cheb_steps", ctypes.c_int32), ("replays_per_step", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double)]
+
+
+class SolveDesc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32), ("seed", ctypes.c_uint64), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("keep_x", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("iterations", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("bnorm", ctypes.c_double),
+                ("lmax", ctypes.c_double), ("seconds", ctypes.c_double), ("queue_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -113,6 +137,13 @@ def lib() -> ctypes.CDLL:
         "tc_pending": [P, i32p],
         "tc_status_string": [i32],
         "tc_last_error": [P],
+        "tc_batch_create": [P, ctypes.POINTER(BatchOpts), ctypes.POINTER(P)],
+        "tc_batch_submit": [P, ctypes.POINTER(SolveDesc), ctypes.POINTER(i64)],
+        "tc_batch_step": [P, i32p],
+        "tc_batch_poll": [P, i64, ctypes.POINTER(SolveResult)],
+        "tc_batch_wait": [P],
+        "tc_batch_read_x": [P, i64, ctypes.POINTER(ctypes.c_double), i64],
+        "tc_batch_destroy": [P],
     }
     for name, argtypes in sig.items():
         f = getattr(L, name)
@@ -321,6 +352,60 @@ class Context:
         buf = (ctypes.c_int32 * cap)()
         self._ck(lib().tc_chain_plan(self.ptr, TC_TILING_FUSED, _i32(t), nt, buf, cap), "tc_chain_plan")
         return [(int(buf[2 * g]), int(buf[2 * g + 1])) for g in range(nt[0])]
+
+
+class Batch:
+    """A batch engine (``tc_batch*``) on a context: batched and served
+    heat-conduction solves."""
+
+    def __init__(self, ctx: Context, mixed: bool = False, max_instances: int = 64, max_cells: int = 1 << 22,
+                 hbm_budget: int = 8 << 30, cheb_steps: int = 10, replays_per_step: int = 4, inner_tol: float = 1e-4):
+        self.ctx = ctx
+        o = BatchOpts(int(mixed), int(max_instances), int(max_cells), int(hbm_budget), int(cheb_steps),
+                      int(replays_per_step), float(inner_tol))
+        self.ptr = ctypes.c_void_p()
+        ctx._ck(lib().tc_batch_create(ctx.ptr, ctypes.byref(o), ctypes.byref(self.ptr)), "tc_batch_create")
+        self.sizes: Dict[int, tuple] = {}
+
+    def tc_batch_submit(self, ndim: int, n: int, seed: int, tol: float = 1e-8, max_iter: int = 10000,
+                        max_outer: int = 50, dt: float = 0.004, keep_x: bool = False) -> int:
+        d = SolveDesc(int(ndim), int(n), int(seed) & ((1 << 64) - 1), float(tol), int(max_iter), int(max_outer),
+                      float(dt), int(keep_x), 0)
+        t = ctypes.c_int64()
+        self.ctx._ck(lib().tc_batch_submit(self.ptr, ctypes.byref(d), ctypes.byref(t)), "tc_batch_submit")
+        self.sizes[t.value] = (ndim, n)
+        return t.value
+
+    def tc_batch_step(self) -> int:
+        left = ctypes.c_int32()
+        self.ctx._ck(lib().tc_batch_step(self.ptr, ctypes.byref(left)), "tc_batch_step")
+        return left.value
+
+    def tc_batch_poll(self, ticket: int) -> dict:
+        r = SolveResult()
+        self.ctx._ck(lib().tc_batch_poll(self.ptr, int(ticket), ctypes.byref(r)), "tc_batch_poll")
+        return r.as_dict()
+
+    def tc_batch_wait(self):
+        self.ctx._ck(lib().tc_batch_wait(self.ptr), "tc_batch_wait")
+
+    def tc_batch_read_x(self, ticket: int) -> np.ndarray:
+        ndim, n = self.sizes[ticket]
+        out = np.empty([n] * ndim, dtype=np.float64)
+        self.ctx._ck(lib().tc_batch_read_x(self.ptr, int(ticket), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            out.size), "tc_batch_read_x")
+        return out
+
+    def close(self):
+        if self.ptr:
+            lib().tc_batch_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def tc_status_string(status: int) -> str:

@@ -14,10 +14,6 @@
 #include "kernels.hpp"
 #include "tc_internal.hpp"
 
-struct tc_ctx {
-    tc::Ctx c;
-};
-
 using namespace tc;
 
 namespace tc {

@@ -1,0 +1,471 @@
+// Kernels of the batched heat-conduction solves (scheme in batch.hpp).
+//
+// Every kernel strides over the current tile list (its length is read from
+// device memory, so a captured graph stays valid while the list changes);
+// a tile is 64 x 4 cells of one instance, one workgroup, and the workgroup
+// skips tiles whose instance is not in a state the kernel serves.  Per-tile
+// reduction partials (double-double) go to part[4 * tile + {0,1}] and
+// part[4 * tile + {2,3}]; per-instance finalize kernels (one workgroup per
+// instance slot) combine them in tile order and advance the state machine.
+#include <hip/hip_runtime.h>
+
+#include "batch.hpp"
+#include "dd.hpp"
+
+namespace tc {
+
+namespace {
+
+constexpr unsigned long long kGamma = 0x9E3779B97F4A7C15ull;
+constexpr unsigned long long kM1 = 0xBF58476D1CE4E5B9ull;
+constexpr unsigned long long kM2 = 0x94D049BB133111EBull;
+
+// Output number k (k >= 1) of the SplitMix64 stream with state s (Steele,
+// Lea, Flood 2014), as a double in [0, 1) from its top 53 bits.
+__device__ __forceinline__ double splitmix_unit(unsigned long long s, unsigned long long k) {
+    unsigned long long z = s + k * kGamma;
+    z = (z ^ (z >> 30)) * kM1;
+    z = (z ^ (z >> 27)) * kM2;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+template <typename T>
+__device__ __forceinline__ T fmaB(T a, T b, T c) {
+    return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fmaB<float>(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+}
+
+struct Cell {
+    int x, y, z;
+    bool ok;
+    int64_t c;
+    int64_t e, w, n, s, t, b;  // offsets of the neighbours, mirrored at the domain boundary
+};
+
+__device__ __forceinline__ Cell cell_of(const BInst &I, const BTile &tl) {
+    Cell k;
+    k.x = tl.tx * kBTX + (int)(threadIdx.x & (kBTX - 1));
+    k.y = tl.ty * kBTY + (int)(threadIdx.x / kBTX);
+    k.z = tl.tz;
+    k.ok = k.x < I.n && k.y < I.n;
+    k.c = I.org + k.x + (int64_t)k.y * I.sy + (int64_t)k.z * I.sz;
+    // a reflective ghost cell holds the value of the cell it mirrors
+    k.e = k.x + 1 < I.n ? 1 : 0;
+    k.w = k.x > 0 ? -1 : 0;
+    k.n = k.y + 1 < I.n ? I.sy : 0;
+    k.s = k.y > 0 ? -I.sy : 0;
+    k.t = (I.ndim == 3 && k.z + 1 < I.n) ? I.sz : 0;
+    k.b = (I.ndim == 3 && k.z > 0) ? -I.sz : 0;
+    return k;
+}
+
+// (A v) at a cell: diagonal 1 + sum of face coefficients (left to right),
+// then the neighbour terms E, W, N, S[, T, B] as fmas.
+template <typename T>
+__device__ __forceinline__ T apply_A(const BInst &I, const T *kx, const T *ky, const T *kz, const T *v,
+                                     const Cell &k) {
+    const int64_t c = k.c;
+    const T ke = kx[c + 1], kw = kx[c];
+    const T kn = ky[c + I.sy], ks = ky[c];
+    T diag = (T)1 + ke;
+    diag = diag + kw;
+    diag = diag + kn;
+    diag = diag + ks;
+    T kt = 0, kb = 0;
+    const bool three = I.ndim == 3;
+    if (three) {
+        kt = kz[c + I.sz];
+        kb = kz[c];
+        diag = diag + kt;
+        diag = diag + kb;
+    }
+    T av = diag * v[c];
+    av = fmaB<T>(-ke, v[c + k.e], av);
+    av = fmaB<T>(-kw, v[c + k.w], av);
+    av = fmaB<T>(-kn, v[c + k.n], av);
+    av = fmaB<T>(-ks, v[c + k.s], av);
+    if (three) {
+        av = fmaB<T>(-kt, v[c + k.t], av);
+        av = fmaB<T>(-kb, v[c + k.b], av);
+    }
+    return av;
+}
+
+__device__ __forceinline__ bool serves(const BInst &I, unsigned mask) { return (mask >> I.state) & 1u; }
+
+__device__ __forceinline__ void write_partial(double *part, int64_t t, int slot, DD v) {
+    if (threadIdx.x == 0) {
+        part[4 * t + 2 * slot] = v.hi;
+        part[4 * t + 2 * slot + 1] = v.lo;
+    }
+}
+
+// ---- set-up ---------------------------------------------------------------
+// density -> r, energy -> u (counter-based draws, density first), then
+// u0 = u = e * rho; partial u0 . u0 (slot 0).
+__global__ void __launch_bounds__(256) bk_init(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part) {
+    const int64_t nt = *ntiles;
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, 1u << B_INIT)) continue;
+        const Cell k = cell_of(I, tl);
+        DD acc = red_identity(TC_RED_SUM);
+        if (k.ok) {
+            const unsigned long long cells = (unsigned long long)I.n * I.n * (I.ndim == 3 ? I.n : 1);
+            const unsigned long long id = (unsigned long long)k.x + (unsigned long long)I.n * (k.y + (unsigned long long)I.n * k.z);
+            const double a0 = 0.1, b0 = 1.0, a1 = 1.0, b1 = 2.0;
+            const double rho = a0 + (b0 - a0) * splitmix_unit(I.seed, id + 1);
+            const double e = a1 + (b1 - a1) * splitmix_unit(I.seed, cells + id + 1);
+            I.r[k.c] = rho;
+            const double v = e * rho;
+            I.u0[k.c] = v;
+            I.u[k.c] = v;
+            // the first search direction is p = 0 * p + z
+            if (I.mixed)
+                ((float *)I.p)[k.c] = 0.0f;
+            else
+                ((double *)I.p)[k.c] = 0.0;
+            dd_add_prod(acc, v, v);
+        }
+        write_partial(part, t, 0, block_reduce(TC_RED_SUM, acc));
+    }
+}
+
+// Face coefficients K = 2 rx / (rho_left + rho_right) on faces 0..n of every
+// axis (face i lies between cells i-1 and i; ghost densities mirror).
+template <typename T>
+__global__ void __launch_bounds__(256) bk_faces(BInst *insts, const BTile *tiles, const int64_t *ntiles) {
+    const int64_t nt = *ntiles;
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, 1u << B_INIT)) continue;
+        const Cell k = cell_of(I, tl);
+        if (!k.ok) continue;
+        const double two_r = 2.0 * I.rx;
+        const double *rho = I.r;
+        const double rc = rho[k.c];
+        T *kxi = (T *)I.kxi, *kyi = (T *)I.kyi, *kzi = (T *)I.kzi;
+        const bool mixed = I.mixed != 0;
+        auto put = [&](double *K, T *Ki, int64_t at, double v) {
+            K[at] = v;
+            if (mixed) Ki[at] = (T)v;
+        };
+        put(I.kx, kxi, k.c, two_r / (rho[k.c + k.w] + rc));
+        put(I.ky, kyi, k.c, two_r / (rho[k.c + k.s] + rc));
+        if (I.ndim == 3) put(I.kz, kzi, k.c, two_r / (rho[k.c + k.b] + rc));
+        // the last face of each axis: both sides are the boundary cell
+        if (k.x == I.n - 1) put(I.kx, kxi, k.c + 1, two_r / (rc + rc));
+        if (k.y == I.n - 1) put(I.ky, kyi, k.c + I.sy, two_r / (rc + rc));
+        if (I.ndim == 3 && k.z == I.n - 1) put(I.kz, kzi, k.c + I.sz, two_r / (rc + rc));
+    }
+}
+
+// Gershgorin bound of every cell, 1 + 2 * (sum of its face coefficients);
+// partial maximum (slot 1).
+__global__ void __launch_bounds__(256) bk_gersh(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part) {
+    const int64_t nt = *ntiles;
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, 1u << B_INIT)) continue;
+        const Cell k = cell_of(I, tl);
+        DD m = red_identity(TC_RED_MAX);
+        if (k.ok) {
+            double s = I.kx[k.c + 1] + I.kx[k.c];
+            s = s + I.ky[k.c + I.sy];
+            s = s + I.ky[k.c];
+            if (I.ndim == 3) {
+                s = s + I.kz[k.c + I.sz];
+                s = s + I.kz[k.c];
+            }
+            m.hi = __builtin_fma(2.0, s, 1.0);
+        }
+        write_partial(part, t, 1, block_reduce(TC_RED_MAX, m));
+    }
+}
+
+// ---- FP64 residual: r = b - A x; partial r . r (slot 0) -------------------
+// Mixed mode also writes the FP32 copy of r and clears the correction d.
+template <typename T>
+__global__ void __launch_bounds__(256) bk_resid(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part) {
+    const int64_t nt = *ntiles;
+    const unsigned mask = (1u << B_RESID) | (1u << B_OUTER) | (1u << B_VERIFY);
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, mask)) continue;
+        const Cell k = cell_of(I, tl);
+        DD acc = red_identity(TC_RED_SUM);
+        if (k.ok) {
+            const double av = apply_A<double>(I, I.kx, I.ky, I.kz, I.u, k);
+            const double rv = I.u0[k.c] - av;
+            I.r[k.c] = rv;
+            dd_add_prod(acc, rv, rv);
+            if (I.mixed && I.state != B_VERIFY) {
+                ((T *)I.ri)[k.c] = (T)rv;
+                ((T *)I.xi)[k.c] = (T)0;
+            }
+        }
+        write_partial(part, t, 0, block_reduce(TC_RED_SUM, acc));
+    }
+}
+
+// Mixed mode, start of a refinement step: x += d in FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) bk_apply_correction(BInst *insts, const BTile *tiles, const int64_t *ntiles) {
+    const int64_t nt = *ntiles;
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, 1u << B_OUTER)) continue;
+        const Cell k = cell_of(I, tl);
+        if (!k.ok) continue;
+        const double d = (double)((const T *)I.xi)[k.c];
+        I.u[k.c] = __builtin_fma(1.0, d, 1.0 * I.u[k.c]);
+    }
+}
+
+// ---- PPCG sweeps (type T) -------------------------------------------------
+// p = beta p + z
+template <typename T>
+__global__ void __launch_bounds__(256) bk_cg_p(BInst *insts, const BTile *tiles, const int64_t *ntiles) {
+    const int64_t nt = *ntiles;
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, 1u << B_INNER)) continue;
+        const Cell k = cell_of(I, tl);
+        if (!k.ok) continue;
+        T *p = (T *)I.p;
+        p[k.c] = fmaB<T>((T)I.beta, p[k.c], ((const T *)I.z)[k.c]);
+    }
+}
+
+// w = A p; partial p . w (slot 0)
+template <typename T>
+__global__ void __launch_bounds__(256) bk_matvec(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part) {
+    const int64_t nt = *ntiles;
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, 1u << B_INNER)) continue;
+        const Cell k = cell_of(I, tl);
+        DD acc = red_identity(TC_RED_SUM);
+        if (k.ok) {
+            const T *p = (const T *)I.p;
+            const T av = apply_A<T>(I, (const T *)I.kxi, (const T *)I.kyi, (const T *)I.kzi, p, k);
+            ((T *)I.w)[k.c] = av;
+            dd_add_prod(acc, (double)p[k.c], (double)av);
+        }
+        write_partial(part, t, 0, block_reduce(TC_RED_SUM, acc));
+    }
+}
+
+// INNER: x += alpha p, r -= alpha w; then (INNER and INNER_START) the
+// preconditioner's start: rt = r, sd = rt / theta, z = 0.
+template <typename T>
+__global__ void __launch_bounds__(256) bk_update_init(BInst *insts, const BTile *tiles, const int64_t *ntiles) {
+    const int64_t nt = *ntiles;
+    const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, mask)) continue;
+        const Cell k = cell_of(I, tl);
+        if (!k.ok) continue;
+        T *x = (T *)I.xi, *r = (T *)I.ri;
+        T rv = r[k.c];
+        if (I.state == B_INNER) {
+            const T al = (T)I.alpha;
+            x[k.c] = fmaB<T>(al, ((const T *)I.p)[k.c], x[k.c]);
+            rv = fmaB<T>(-al, ((const T *)I.w)[k.c], rv);
+            r[k.c] = rv;
+        }
+        ((T *)I.rt)[k.c] = rv;
+        ((T *)I.sd0)[k.c] = rv / (T)I.theta;
+        ((T *)I.z)[k.c] = (T)0;
+    }
+}
+
+// Chebyshev step j (1-based): rt -= A sd, z += sd, then for j < steps the
+// next direction sd' = al_j sd + be_j rt (into the other sd buffer); the last
+// step adds the partials r . z (slot 0) and r . r (slot 1).
+template <typename T>
+__global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part,
+                                               int j) {
+    const int64_t nt = *ntiles;
+    const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, mask) || j > I.cheb_steps) continue;
+        const bool last = j == I.cheb_steps;
+        const Cell k = cell_of(I, tl);
+        DD rz = red_identity(TC_RED_SUM), rr = red_identity(TC_RED_SUM);
+        if (k.ok) {
+            const T *sd = (const T *)((j & 1) ? I.sd0 : I.sd1);
+            T *sdn = (T *)((j & 1) ? I.sd1 : I.sd0);
+            const T av = apply_A<T>(I, (const T *)I.kxi, (const T *)I.kyi, (const T *)I.kzi, sd, k);
+            T *rt = (T *)I.rt, *z = (T *)I.z;
+            const T rtv = rt[k.c] - av;
+            rt[k.c] = rtv;
+            const T zv = z[k.c] + sd[k.c];
+            z[k.c] = zv;
+            if (!last) {
+                sdn[k.c] = fmaB<T>((T)I.al[j - 1], sd[k.c], (T)I.be[j - 1] * rtv);
+            } else {
+                const T rv = ((const T *)I.ri)[k.c];
+                dd_add_prod(rz, (double)rv, (double)zv);
+                dd_add_prod(rr, (double)rv, (double)rv);
+            }
+        }
+        if (last) {
+            write_partial(part, t, 0, block_reduce(TC_RED_SUM, rz));
+            write_partial(part, t, 1, block_reduce(TC_RED_SUM, rr));
+        }
+    }
+}
+
+// ---- per-instance finalize ------------------------------------------------
+// Combine slot `slot` of the instance's tile partials in tile order (the
+// same order and grouping as the library's finalize kernel); value = hi + lo
+// for sums, hi for max.
+__device__ double combine(const BInst &I, const double *part, int slot, int op) {
+    DD a = red_identity(op);
+    for (int64_t i = threadIdx.x; i < I.ntile; i += kRedThreads) {
+        DD b;
+        b.hi = part[4 * (I.tile0 + i) + 2 * slot];
+        b.lo = part[4 * (I.tile0 + i) + 2 * slot + 1];
+        a = red_combine(op, a, b);
+    }
+    a = block_reduce(op, a);
+    return op == TC_RED_SUM ? a.hi + a.lo : a.hi;
+}
+
+// phase 0: after the set-up kernels (INIT -> RESID)
+// phase 1: after the residual (RESID/OUTER/VERIFY)
+// phase 2: after the matrix-vector product (INNER: alpha)
+// phase 3: after the preconditioner (INNER_START/INNER: beta, convergence)
+__global__ void __launch_bounds__(256) bk_finalize(BInst *insts, int ninst, const double *part, int phase) {
+    BInst &I = insts[blockIdx.x];
+    const int st = I.state;
+    if (phase == 0) {
+        if (st != B_INIT) return;
+        const double bb = combine(I, part, 0, TC_RED_SUM);
+        const double lmax = combine(I, part, 1, TC_RED_MAX);
+        if (threadIdx.x == 0) {
+            I.bnorm = sqrt(bb);
+            I.lmax = lmax;
+            // Chebyshev scalars for the spectrum [1, lmax]
+            const double lmin = 1.0;
+            const double theta = (lmax + lmin) / 2.0;
+            const double delta = (lmax - lmin) / 2.0;
+            const double sigma = theta / delta;
+            double r_old = 1.0 / sigma;
+            for (int j = 1; j < I.cheb_steps; ++j) {
+                const double r_new = 1.0 / (2.0 * sigma - r_old);
+                I.al[j - 1] = r_new * r_old;
+                I.be[j - 1] = 2.0 * r_new / delta;
+                r_old = r_new;
+            }
+            I.theta = theta;
+            I.state = B_RESID;
+        }
+    } else if (phase == 1) {
+        if (st != B_RESID && st != B_OUTER && st != B_VERIFY) return;
+        const double rr = combine(I, part, 0, TC_RED_SUM);
+        if (threadIdx.x == 0) {
+            I.true_rr = rr;
+            const double rn = sqrt(rr);
+            if (st == B_VERIFY) {
+                I.state = B_DONE;
+            } else if (!I.mixed) {
+                I.state = B_INNER_START;
+            } else if (rn <= I.tol * I.bnorm || I.outer >= I.max_outer) {
+                I.converged = rn <= I.tol * I.bnorm;
+                I.state = B_DONE;
+            } else {
+                I.r0 = rn;
+                I.outer += 1;
+                I.state = B_INNER_START;
+            }
+        }
+    } else if (phase == 2) {
+        if (st != B_INNER) return;
+        const double pw = combine(I, part, 0, TC_RED_SUM);
+        if (threadIdx.x == 0) I.alpha = I.rz / pw;
+    } else {
+        if (st != B_INNER && st != B_INNER_START) return;
+        const double rz_new = combine(I, part, 0, TC_RED_SUM);
+        const double rr = combine(I, part, 1, TC_RED_SUM);
+        if (threadIdx.x == 0) {
+            I.rr = rr;
+            if (st == B_INNER_START) {
+                I.rz = rz_new;
+                I.beta = 0.0;
+                I.inner_k = 0;
+                I.state = B_INNER;
+            } else {
+                I.iters += 1;
+                I.inner_k += 1;
+                const bool done = I.mixed ? sqrt(rr) <= I.inner_tol * I.r0 : sqrt(rr) <= I.tol * I.bnorm;
+                if (done) {
+                    if (I.mixed) {
+                        I.state = B_OUTER;
+                    } else {
+                        I.converged = 1;
+                        I.state = B_VERIFY;
+                    }
+                } else if (I.inner_k >= I.max_iter) {
+                    // iteration cap of one solve (mixed: of one correction)
+                    I.state = I.mixed ? B_OUTER : B_VERIFY;
+                } else {
+                    I.beta = rz_new / I.rz;
+                    I.rz = rz_new;
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles, double *part,
+                               int grid, int cheb_steps, bool mixed, hipStream_t s) {
+    const dim3 g(grid), b(256), f(ninst);
+    // set-up of newly admitted instances
+    hipLaunchKernelGGL(bk_init, g, b, 0, s, insts, tiles, ntiles, part);
+    hipLaunchKernelGGL(bk_faces<T>, g, b, 0, s, insts, tiles, ntiles);
+    hipLaunchKernelGGL(bk_gersh, g, b, 0, s, insts, tiles, ntiles, part);
+    hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 0);
+    // refinement step (mixed) / first and verifying residuals
+    if (mixed) hipLaunchKernelGGL(bk_apply_correction<T>, g, b, 0, s, insts, tiles, ntiles);
+    hipLaunchKernelGGL(bk_resid<T>, g, b, 0, s, insts, tiles, ntiles, part);
+    hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 1);
+    // one PPCG iteration
+    hipLaunchKernelGGL(bk_cg_p<T>, g, b, 0, s, insts, tiles, ntiles);
+    hipLaunchKernelGGL(bk_matvec<T>, g, b, 0, s, insts, tiles, ntiles, part);
+    hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 2);
+    hipLaunchKernelGGL(bk_update_init<T>, g, b, 0, s, insts, tiles, ntiles);
+    for (int j = 1; j <= cheb_steps; ++j) hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, j);
+    hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 3);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// One round of every solver phase for every resident instance, in order
+// (set-up, residual, one PPCG iteration); each instance advances according
+// to its own state.
+hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles, double *part,
+                                   int grid, int cheb_steps, bool mixed, hipStream_t s) {
+    return mixed ? enqueue_iteration_t<float>(insts, ninst, tiles, ntiles, part, grid, cheb_steps, true, s)
+                 : enqueue_iteration_t<double>(insts, ninst, tiles, ntiles, part, grid, cheb_steps, false, s);
+}
+
+}  // namespace tc

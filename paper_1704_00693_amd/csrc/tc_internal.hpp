@@ -241,3 +241,8 @@ SkewedPlan build_skewed_plan(const Ctx &c, const std::vector<LoopRec> &chain, co
 uint64_t chain_key(const Ctx &c, const std::vector<LoopRec> &chain, int mode, const int tile[3]);
 
 }  // namespace tc
+
+// The C ABI's context object.
+struct tc_ctx {
+    tc::Ctx c;
+};

@@ -1,0 +1,158 @@
+"""GPU tests of the batched and served heat-conduction solves (tc_batch_*).
+
+Every instance is checked against the oracle's FP64 PPCG solve of the same
+problem (inputs drawn from the same SplitMix64 stream on the host):
+FP64 batches must take the same number of iterations and agree to 1e-12
+relative; mixed-precision batches must reach the FP64 true residual and stay
+within cond(A) * residual of the FP64 solution.  A solve must give the same
+bits alone and inside a mix of other solves admitted at other times."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.tealeaf import HeatOracle, ppcg_solve
+from synthgen import heat_problem
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1704_00693_amd as tcm
+    tcm.lib()
+    return tcm
+
+
+def true_residual(hp, x):
+    o = HeatOracle(hp.density, hp.energy)
+    lmax = o.setup()
+    h, n = o.halo, o.n
+    o.f["u"][tuple([slice(h, h + n)] * o.ndim)] = x
+    b = o.inner("u0")
+    return float(np.linalg.norm(b - o.apply_A("u")) / np.linalg.norm(b)), lmax
+
+
+CASES = [(2, 20, 11), (2, 33, 12), (2, 70, 13), (2, 129, 14), (3, 12, 15), (3, 17, 16)]
+
+
+def test_batch_fp64_matches_oracle(tc):
+    tol = 1e-10
+    with tc.Context() as c, tc.Batch(c, mixed=False, max_instances=8) as b:
+        tickets = [b.tc_batch_submit(nd, n, seed, tol=tol, keep_x=True) for nd, n, seed in CASES]
+        say(f"fp64 batch of {len(CASES)} solves")
+        b.tc_batch_wait()
+        for (nd, n, seed), t in zip(CASES, tickets):
+            r = b.tc_batch_poll(t)
+            x = b.tc_batch_read_x(t)
+            hp = heat_problem(n, seed=seed, ndim=nd)
+            ref = ppcg_solve(hp.density, hp.energy, tol=tol, max_iter=5000)
+            err = float(np.abs(x - ref.x).max() / np.abs(ref.x).max())
+            say(f"  ndim={nd} n={n}: iterations {r['iterations']} (oracle {ref.iterations}), error {err:.2e}, "
+                f"true residual {r['rel_residual']:.2e}")
+            assert r["state"] == tc.TC_SOLVE_DONE
+            assert r["iterations"] == ref.iterations
+            assert abs(r["lmax"] - ref.lmax) <= 1e-15 * ref.lmax
+            assert err <= TOL
+            res, _ = true_residual(hp, x)
+            assert abs(res - r["rel_residual"]) <= 1e-6 * res + 1e-15
+
+
+def test_batch_fp64_equals_per_loop_solver(tc):
+    """The batched solve and the per-loop solver (TEA_* loops through the
+    chain API) compute the same arithmetic; for n > 16 their reductions use
+    the same tile order, so the solutions are bit-identical."""
+    from paper_1704_00693_amd.apps import HeatSolver
+    nd, n, seed = 2, 96, 21
+    hp = heat_problem(n, seed=seed, ndim=nd)
+    with tc.Context() as c:
+        s = HeatSolver(c, hp.density, hp.energy)
+        info = s.solve(outer=0, inner=10, tol=1e-9)
+        x_loop = s.field("u")
+    with tc.Context() as c, tc.Batch(c) as b:
+        t = b.tc_batch_submit(nd, n, seed, tol=1e-9, keep_x=True)
+        b.tc_batch_wait()
+        r = b.tc_batch_poll(t)
+        x = b.tc_batch_read_x(t)
+    assert r["iterations"] == info["iterations"]
+    assert np.array_equal(x, x_loop)
+
+
+@pytest.mark.parametrize("tol", [1e-8, 1e-10])
+def test_batch_mixed_reaches_fp64_residual(tc, tol):
+    with tc.Context() as c, tc.Batch(c, mixed=True, max_instances=8) as b:
+        tickets = [b.tc_batch_submit(nd, n, seed, tol=tol, keep_x=True) for nd, n, seed in CASES]
+        b.tc_batch_wait()
+        for (nd, n, seed), t in zip(CASES, tickets):
+            r = b.tc_batch_poll(t)
+            x = b.tc_batch_read_x(t)
+            hp = heat_problem(n, seed=seed, ndim=nd)
+            res, lmax = true_residual(hp, x)
+            ref = ppcg_solve(hp.density, hp.energy, tol=1e-13, max_iter=5000)
+            err = float(np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x))
+            say(f"  mixed ndim={nd} n={n}: corrections {r['outer']} iterations {r['iterations']} "
+                f"residual {res:.2e} error {err:.2e}")
+            assert r["state"] == tc.TC_SOLVE_DONE and r["converged"] == 1
+            assert res <= tol * (1 + 1e-6)
+            assert abs(res - r["rel_residual"]) <= 1e-6 * res + 1e-15
+            assert err <= lmax * (res + 1e-13) * 1.01
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_same_result_alone_and_in_a_mix(tc, mixed):
+    """Continuous batching: a solve admitted alone and the same solve admitted
+    while others are running (and others arriving after it) give the same
+    bits."""
+    probe = (2, 77, 31)
+    with tc.Context() as c, tc.Batch(c, mixed=mixed, max_instances=4, replays_per_step=2) as b:
+        t = b.tc_batch_submit(*probe, tol=1e-9, keep_x=True)
+        b.tc_batch_wait()
+        alone = b.tc_batch_read_x(t)
+        r_alone = b.tc_batch_poll(t)
+    with tc.Context() as c, tc.Batch(c, mixed=mixed, max_instances=4, replays_per_step=2) as b:
+        others = [b.tc_batch_submit(2, 150, 41, tol=1e-9), b.tc_batch_submit(3, 20, 42, tol=1e-9)]
+        b.tc_batch_step()
+        b.tc_batch_step()
+        t = b.tc_batch_submit(*probe, tol=1e-9, keep_x=True)
+        b.tc_batch_step()
+        late = [b.tc_batch_submit(2, 40, 43, tol=1e-9), b.tc_batch_submit(2, 64, 44, tol=1e-9),
+                b.tc_batch_submit(3, 9, 45, tol=1e-9)]
+        b.tc_batch_wait()
+        mixed_x = b.tc_batch_read_x(t)
+        r_mix = b.tc_batch_poll(t)
+        for o in others + late:
+            assert b.tc_batch_poll(o)["state"] == tc.TC_SOLVE_DONE
+    assert r_mix["iterations"] == r_alone["iterations"]
+    assert np.array_equal(alone, mixed_x)
+
+
+def test_admission_by_footprint_and_rejection(tc):
+    """With an HBM budget that holds two 64^2 solves at once, eight of them
+    still all finish (admitted as earlier ones retire); a solve larger than
+    the budget is rejected."""
+    with tc.Context() as c:
+        per = 11 * ((66 * 66 * 8 + 255) // 256 * 256)  # FP64 fields of one 64^2 solve
+        with tc.Batch(c, max_instances=8, hbm_budget=2 * per + 100) as b:
+            ts = [b.tc_batch_submit(2, 64, 100 + i, tol=1e-8) for i in range(8)]
+            big = b.tc_batch_submit(2, 512, 7, tol=1e-8)
+            peak = 0
+            left = 1
+            while left:
+                left = b.tc_batch_step()
+                running = sum(b.tc_batch_poll(t)["state"] == tc.TC_SOLVE_RUNNING for t in ts)
+                peak = max(peak, running)
+            b.tc_batch_step()
+            assert peak <= 2
+            for t in ts:
+                r = b.tc_batch_poll(t)
+                assert r["state"] == tc.TC_SOLVE_DONE and r["converged"] == 1
+            assert b.tc_batch_poll(big)["state"] == tc.TC_SOLVE_REJECTED
