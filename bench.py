@@ -13,6 +13,9 @@ host's cores on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes none,skewed,fused]
 
+Each mode is warmed for W flushes and at least WARM_SECONDS of wall time
+before its K timed flushes (the GPU's clocks ramp up under sustained load).
+
 Measured HBM traffic comes from rocprofv3 counter runs of this script (one
 run per counter and mode, ingested with --ingest-counters on the host),
 scaled by what the same counters read for a plain copy kernel of known size
@@ -63,12 +66,20 @@ def traffic_entry(mode_name: str):
     return t.get("modes", {}).get(mode_name)
 
 
+WARM_SECONDS = 0.5  # the GPU's clocks ramp up under sustained load: warm every mode at least this long
+
+
 def time_mode(ctx, runner, mode, tile, steps, warmup, cells_per_step):
     import torch
     ctx.tc_set_tiling(mode, tile)
-    for _ in range(warmup):
+    t0 = time.perf_counter()
+    k = 0
+    while k < warmup or time.perf_counter() - t0 < WARM_SECONDS:
         runner.record()
         ctx.tc_flush()
+        k += 1
+        if k % 8 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -128,6 +139,65 @@ def copy_probe(tc, n: int, steps: int, warmup: int):
     alg = 2 * n * n * 8
     return {"alg_bytes_per_launch": alg, "launches": steps + warmup, "avg_launch_us": tot / steps * 1e6,
             "GBps": alg * steps / tot / 1e9}
+
+
+def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8):
+    """Batched heat-conduction solves: `count` instances of log-uniform size
+    64^2..1024^2 (synthgen.batch_sizes), all submitted at once, to `tol`
+    relative residual; FP64 sweeps, FP32 sweeps with FP64 reductions and
+    refinement, and FP64 solves one at a time (the sequential baseline)."""
+    import numpy as np
+    from synthgen import batch_sizes
+    sizes = batch_sizes(count, seed)
+    cells = sum((n + 2) ** 2 for n, _ in sizes)
+    out = {"instances": count, "sizes": "n log-uniform in [64, 1024), 2D", "tol": tol}
+    for mode in ("fp64", "mixed", "fp64_sequential"):
+        seq = mode == "fp64_sequential"
+        with tc.Context(0) as c, tc.Batch(c, mixed=(mode == "mixed"), max_instances=1 if seq else count,
+                                         max_cells=max(n * n for n, _ in sizes) if seq else cells,
+                                         hbm_budget=200 << 30, replays_per_step=8 if seq else 4) as b:
+            t0 = time.perf_counter()
+            tickets = [b.tc_batch_submit(2, n, s, tol=tol) for n, s in sizes]
+            b.tc_batch_wait()
+            dt = time.perf_counter() - t0
+            rs = [b.tc_batch_poll(t) for t in tickets]
+        lat = np.array([r["seconds"] for r in rs])
+        out[mode] = {"solves_per_s": count / dt, "makespan_s": dt, "p50_latency_s": float(np.percentile(lat, 50)),
+                     "p99_latency_s": float(np.percentile(lat, 99)),
+                     "iterations": int(sum(r["iterations"] for r in rs)),
+                     "converged": int(sum(r["converged"] for r in rs)),
+                     "max_rel_residual": float(max(r["rel_residual"] for r in rs))}
+        log(f"batch {mode}: {out[mode]['solves_per_s']:.1f} solves/s, makespan {dt:.2f} s, "
+            f"converged {out[mode]['converged']}/{count}")
+    out["mixed_over_sequential_fp64"] = out["mixed"]["solves_per_s"] / out["fp64_sequential"]["solves_per_s"]
+    out["fp64_batched_over_sequential"] = out["fp64"]["solves_per_s"] / out["fp64_sequential"]["solves_per_s"]
+    return out
+
+
+def serve_bench(tc, rate: float, seconds: float, drain: float, seed: int = 4, tol: float = 1e-8):
+    """Serving: Poisson arrivals at `rate` solves/s for `seconds` seconds, each
+    a 2D (128^2..2048^2) or 3D (64^3..256^3) solve (synthgen.serving_requests),
+    replayed in real time against a batch engine (continuous batching,
+    admission by HBM footprint); unfinished work is drained for at most
+    `drain` seconds.  Latency = completion - arrival of completed solves."""
+    import numpy as np
+    from paper_1704_00693_amd.apps import serve
+    from synthgen import serving_requests
+    reqs = serving_requests(rate, seconds, seed)
+    out = {"rate_per_s": rate, "window_s": seconds, "requests": len(reqs), "tol": tol}
+    for mode in ("fp64", "mixed"):
+        with tc.Context(0) as c:
+            r = serve(c, reqs, mixed=(mode == "mixed"), tol=tol, max_instances=512, hbm_budget=160 << 30,
+                      max_cells=1 << 29, horizon=seconds, drain=drain)
+        lat = np.array([v for v in r["latency"] if v is not None])
+        done = len(lat)
+        out[mode] = {"completed": done, "submitted": r["submitted"], "wall_s": r["wall_s"],
+                     "solves_per_s": done / r["wall_s"],
+                     "p50_latency_s": float(np.percentile(lat, 50)) if done else None,
+                     "p99_latency_s": float(np.percentile(lat, 99)) if done else None}
+        log(f"serve {mode}: {done}/{len(reqs)} completed in {r['wall_s']:.1f} s, "
+            f"p50 {out[mode]['p50_latency_s']} s, p99 {out[mode]['p99_latency_s']} s")
+    return out
 
 
 def cpu_baseline(ch_full, n_sample: int):
@@ -222,6 +292,12 @@ def main():
     ap.add_argument("--fused-tile", default="0,0,0",
                     help="fused mode tile: rows per wavefront segment, window-register budget, most loops per group "
                          "(0: automatic)")
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="batched heat-conduction solves to run after the chain (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-drain", type=float, default=60.0)
     ap.add_argument("--ingest-counters", nargs="*", default=None,
                     help="host only: MODE:COUNTER:DIR:FLUSHES entries from rocprofv3 --pmc runs")
     args = ap.parse_args()
@@ -290,6 +366,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": None if tr is None else tr["hbm_bytes_per_flush"] / launches,
                 "kernel": kname, "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": alg}
+    batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
+    served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None
     cpu = cpu_baseline(ch, args.cpu_sample) if args.cpu_sample > 0 else None
     untiled = results.get("none")
     tr_none = traffic_entry("none")
@@ -322,6 +400,8 @@ def main():
         "modes": results,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_solves": batched,
+        "serving": served,
     }
     print(json.dumps(line))
 

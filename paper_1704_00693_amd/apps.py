@@ -371,3 +371,58 @@ class MixedHeatSolver:
         a = self.ctx.tc_dat_read(self.f64[name])
         h, n = self.h, self.n
         return a[tuple([slice(h, h + n)] * self.D)]
+
+
+# ---------------------------------------------------------------------------
+# serving: a request trace replayed against a batch engine in real time
+# ---------------------------------------------------------------------------
+def serve(ctx: Context, requests, mixed: bool = False, tol: float = 1e-8, max_instances: int = 256,
+          hbm_budget: int = 64 << 30, max_cells: int = 1 << 27, horizon: Optional[float] = None,
+          drain: float = 120.0, keep_x: Sequence[int] = (), replays_per_step: int = 2):
+    """Submit request i when the wall clock passes its arrival time; the
+    engine (``tc_batch_step``) admits solves into free slots as memory frees
+    up, advances every resident solve, and retires finished ones (continuous
+    batching).  Arrivals after `horizon` seconds are not submitted; resident
+    and queued work is then drained for at most `drain` seconds.  Returns a
+    dict with per-request latency (completion - arrival, seconds, None if
+    unfinished), engine results, and the solutions of the requests listed in
+    `keep_x`."""
+    import time
+    from . import Batch, TC_SOLVE_DONE
+    keep = set(keep_x)
+    b = Batch(ctx, mixed=mixed, max_instances=max_instances, max_cells=max_cells, hbm_budget=hbm_budget,
+              replays_per_step=replays_per_step)
+    try:
+        t0 = time.perf_counter()
+        nxt = 0
+        sub = {}  # request index -> (ticket, submit time since t0)
+        horizon = requests[-1].arrival + 1e-9 if horizon is None and requests else horizon
+        while True:
+            now = time.perf_counter() - t0
+            while nxt < len(requests) and requests[nxt].arrival <= now and requests[nxt].arrival <= horizon:
+                q = requests[nxt]
+                tk = b.tc_batch_submit(q.ndim, q.n, q.seed, tol=tol, keep_x=nxt in keep)
+                sub[nxt] = (tk, time.perf_counter() - t0)
+                nxt += 1
+            left = b.tc_batch_step()
+            arrivals_left = nxt < len(requests) and requests[nxt].arrival <= horizon
+            if not arrivals_left and left == 0:
+                break
+            if now > horizon + drain:
+                break
+            if left == 0 and arrivals_left:
+                time.sleep(max(0.0, min(requests[nxt].arrival - (time.perf_counter() - t0), 0.01)))
+        b.tc_batch_step()
+        wall = time.perf_counter() - t0
+        out = {"latency": [None] * len(requests), "results": [None] * len(requests), "x": {}, "wall_s": wall,
+               "submitted": len(sub)}
+        for i, (tk, ts) in sub.items():
+            r = b.tc_batch_poll(tk)
+            out["results"][i] = r
+            if r["state"] == TC_SOLVE_DONE:
+                out["latency"][i] = ts + r["seconds"] - requests[i].arrival
+                if i in keep:
+                    out["x"][i] = b.tc_batch_read_x(tk)
+        return out
+    finally:
+        b.close()

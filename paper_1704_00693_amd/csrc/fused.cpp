@@ -699,6 +699,9 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
         for (int l = G.g0; l < G.g1 && same; ++l)
             for (double w : chain[l].params) same = same && k < G.wvals.size() && G.wvals[k++] == w;
         if (!same) {
+            if (getenv("TC_JIT_VERBOSE"))
+                std::fprintf(stderr, "fused group [%d,%d): weights changed, switching to argument weights\n", G.g0,
+                             G.g1);
             G.baked = false;
             std::vector<std::shared_ptr<FusedGroup>> one{std::shared_ptr<FusedGroup>(&G, [](FusedGroup *) {})};
             const tc_status st = fused_compile(c, one);

@@ -156,3 +156,33 @@ def test_admission_by_footprint_and_rejection(tc):
                 r = b.tc_batch_poll(t)
                 assert r["state"] == tc.TC_SOLVE_DONE and r["converged"] == 1
             assert b.tc_batch_poll(big)["state"] == tc.TC_SOLVE_REJECTED
+
+
+def test_serving_trace_small(tc):
+    """A short Poisson trace (mixed 2D/3D sizes) served in real time: every
+    request completes, latencies are measured from arrival, and sampled
+    requests give the same bits as the same solve run alone."""
+    from paper_1704_00693_amd.apps import serve
+    from synthgen import Request, SplitMix64
+    rng = SplitMix64(77)
+    reqs, t = [], 0.0
+    for i in range(24):
+        t += -math.log(1.0 - rng.unit()) / 40.0
+        nd = 2 if rng.randint(2) == 0 else 3
+        n = int(round(math.exp(rng.uniform(math.log(16), math.log(96 if nd == 2 else 24)))))
+        reqs.append(Request(t, nd, n, rng.next()))
+    sample = [0, 5, 11, 23]
+    for mixed in (False, True):
+        with tc.Context() as c:
+            out = serve(c, reqs, mixed=mixed, tol=1e-9, max_instances=8, keep_x=sample)
+        lat = [v for v in out["latency"] if v is not None]
+        say(f"served mixed={mixed}: {len(lat)}/{len(reqs)} in {out['wall_s']:.2f} s, "
+            f"p50 {np.percentile(lat, 50) * 1e3:.1f} ms p99 {np.percentile(lat, 99) * 1e3:.1f} ms")
+        assert len(lat) == len(reqs) and min(lat) > 0
+        for i in sample:
+            q = reqs[i]
+            with tc.Context() as c, tc.Batch(c, mixed=mixed) as b:
+                tk = b.tc_batch_submit(q.ndim, q.n, q.seed, tol=1e-9, keep_x=True)
+                b.tc_batch_wait()
+                alone = b.tc_batch_read_x(tk)
+            assert np.array_equal(alone, out["x"][i])
