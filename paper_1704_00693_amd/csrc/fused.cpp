@@ -27,6 +27,8 @@ struct SplitParams {
     int max_loops = 32;
     int U = 4, PF = 2;
     bool bake = false;
+    int cpl = 1;       // columns per lane
+    int wpe = 2;       // wavefronts per SIMD requested for the interior kernels (0: compiler's choice)
 };
 
 // ---------------------------------------------------------------------------
@@ -43,6 +45,8 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     G.U = sp.U;
     G.PF = sp.PF;
     G.baked = sp.bake;
+    G.cpl = sp.cpl;
+    G.wpe = sp.wpe;
     const LoopRec &f = chain[g0];
     if (f.op != TC_OP_WSUM || f.ndim != 2 || f.points() == 0) return false;
     G.xlo = f.lo[0];
@@ -164,9 +168,17 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
             CB = std::max(CB, J.extB);
             CT = std::max(CT, J.extT);
         }
+    const int wcols = kJLanes * G.cpl;
+    if (G.cpl == 2) {
+        // two-column loads stay 16-byte aligned: the first lane column
+        // X0 - HL and the strip width are even (the x origin is 16-aligned)
+        if (G.xlo % 2 != 0) return false;
+        HL += HL & 1;
+    }
     G.HL = HL;
     G.HR = HR;
-    G.Wo = kJLanes - HL - HR;
+    G.Wo = wcols - HL - HR;
+    if (G.cpl == 2) G.Wo -= G.Wo & 1;
     if (G.Wo < 8) return false;
     G.BMAX = CB;
     G.TMAX = CT;
@@ -209,14 +221,14 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
                 if (!X.needed) continue;
                 const int oldest = hi[v] == INT_MIN ? X.lag : std::max(hi[v], X.lag);
                 V.win[v] = oldest - X.lag + 1;
-                regs += V.win[v] * words;
+                regs += V.win[v] * words * G.cpl;
                 if (X.stored) post = std::max(post, X.lag);
             } else {
                 if (lo[v] == INT_MAX) continue;  // not read in this variant
                 V.loaded[v] = 1;
                 V.load_lag[v] = lo[v];
                 V.win[v] = hi[v] - lo[v] + 1;
-                regs += (V.win[v] + G.PF) * words;
+                regs += (V.win[v] + G.PF) * words * G.cpl;
                 const int b = std::max(X.needed ? X.extB : -1, eb[v]);
                 const int t = std::max(X.needed ? X.extT : -1, et[v]);
                 pre = std::max(pre, b - lo[v]);
@@ -271,7 +283,7 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
             const Dataset &ds = c.dats[G.vers[v].dat];
             // columns X0 - HL + [0, 64) with X0 = xlo + i Wo
             si0 = std::max(si0, cdiv(-ds.hneg[0] - G.xlo + HL, G.Wo));
-            si1 = std::min(si1, fdiv(ds.size[0] + ds.hpos[0] - kJLanes - G.xlo + HL, G.Wo) + 1);
+            si1 = std::min(si1, fdiv(ds.size[0] + ds.hpos[0] - wcols - G.xlo + HL, G.Wo) + 1);
             // rows Y0 - pre - lag .. Y0 - pre + nsteps - 1 + PF - lag with Y0 = ylo + k Hseg
             gi0 = std::max(gi0, cdiv(-ds.hneg[1] - G.ylo + V.pre + V.load_lag[v], G.Hseg));
             gi1 = std::min(gi1, fdiv(ds.size[1] + ds.hpos[1] - 1 - G.ylo + V.pre - nsteps + 1 - G.PF +
@@ -296,14 +308,14 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     // against VALU work, both scaled by the recomputed lanes and rows
     const double cells = (double)width * height;
     const double fy = (double)(G.Hseg + G.var[0].pre + G.var[0].post) / G.Hseg;
-    const double fx = (double)kJLanes / G.Wo;
+    const double fx = (double)wcols / G.Wo;
     int nload = 0;
     for (size_t v = 0; v < G.vers.size(); ++v) nload += G.var[0].loaded[v];
     double ops = 0.0;
     for (const auto &J : G.loops) {
         if (!J.needed) continue;
         for (const auto &R : J.in)
-            for (const auto &p : R.pts) ops += 1.0 + (p.dx != 0 ? words : 0);
+            for (const auto &p : R.pts) ops += 1.0 + (p.dx != 0 ? (double)words / G.cpl : 0.0);
         ops += 2.0;
     }
     G.alg_bytes = (int64_t)width * height * esize_of(G.dtype) * (int64_t)(nload + (int)G.dst_dat.size());
@@ -333,6 +345,10 @@ typedef const double __attribute__((address_space(1))) *tcj_gcd;
 typedef double __attribute__((address_space(1))) *tcj_gd;
 typedef const float __attribute__((address_space(1))) *tcj_gcf;
 typedef float __attribute__((address_space(1))) *tcj_gf;
+typedef double tcj_d2 __attribute__((ext_vector_type(2)));
+typedef float tcj_f2 __attribute__((ext_vector_type(2)));
+typedef const tcj_d2 __attribute__((address_space(1))) *tcj_gcd2;
+typedef const tcj_f2 __attribute__((address_space(1))) *tcj_gcf2;
 __device__ __forceinline__ double tcj_shr(double v) {
     const i64 u = __builtin_bit_cast(i64, v);
     const int lo = __builtin_amdgcn_mov_dpp((int)u, 0x138, 0xf, 0xf, true);
@@ -359,22 +375,26 @@ __device__ __forceinline__ int tcj_lin(int b, int nb) {
 }
 )";
 
+// Lane layout: lane l holds columns X0 - HL + cpl*l + e, e < cpl, of every
+// row it keeps; window w<v>_<e>[k] is element e of version v's row at slot k.
 struct Gen {
     const Ctx &c;
     const FusedGroup &G;
     int var;
     const JVariant &V;
+    int cpl;
     std::ostringstream o;
-    const char *T, *GC, *GM;
+    const char *T, *GC, *GM, *V2;
     std::vector<int> src_index;  // version -> source argument
     std::vector<int> dst_index;  // version -> destination argument
-    std::map<std::tuple<int, int, int>, std::string> sh;  // shifted values of the current step
+    std::map<std::tuple<int, int, int, int>, std::string> sh;  // shifted values of the current step
     int ntmp = 0;
 
-    Gen(const Ctx &cc, const FusedGroup &g, int v) : c(cc), G(g), var(v), V(g.var[v]) {
+    Gen(const Ctx &cc, const FusedGroup &g, int v) : c(cc), G(g), var(v), V(g.var[v]), cpl(g.cpl) {
         T = G.dtype == TC_F64 ? "double" : "float";
         GC = G.dtype == TC_F64 ? "tcj_gcd" : "tcj_gcf";
         GM = G.dtype == TC_F64 ? "tcj_gd" : "tcj_gf";
+        V2 = G.dtype == TC_F64 ? "tcj_gcd2" : "tcj_gcf2";
         src_index.assign(G.vers.size(), -1);
         dst_index.assign(G.vers.size(), -1);
         for (size_t k = 0; k < G.vers.size(); ++k) {
@@ -390,45 +410,64 @@ struct Gen {
 
     int lag_of(int v) const { return G.vers[v].producer >= 0 ? G.vers[v].lag : V.load_lag[v]; }
 
-    // window entry of version v holding the row that a loop at `lag` reads at offset dy
-    std::string entry(int v, int lag, int dy) const {
+    static std::string W(int v, int e) { return "w" + std::to_string(v) + "_" + std::to_string(e); }
+
+    // slot of version v holding the row that a loop at `lag` reads at offset dy
+    int slot(int v, int lag, int dy) const {
         const int m = lag - dy - lag_of(v);
         if (m < 0 || m >= V.win[v]) {
             std::fprintf(stderr, "tilechain: fused window error (version %d, m %d, window %d)\n", v, m, V.win[v]);
             std::abort();
         }
-        return "w" + std::to_string(v) + "[" + std::to_string(V.win[v] - 1 - m) + "]";
+        return V.win[v] - 1 - m;
     }
 
-    std::string shifted(int v, int lag, int dy, int dx) {
-        if (dx == 0) return entry(v, lag, dy);
-        const int m = lag - dy - lag_of(v);
-        const auto key = std::make_tuple(v, m, dx);
+    std::string entry(int v, int e, int sl) const { return W(v, e) + "[" + std::to_string(sl) + "]"; }
+
+    // element e of the lane `ls` lanes away (ls < 0: lower lanes) at slot sl
+    std::string lane_value(int v, int sl, int e, int ls) {
+        if (ls == 0) return entry(v, e, sl);
+        const auto key = std::make_tuple(v, sl, e, ls);
         auto it = sh.find(key);
         if (it != sh.end()) return it->second;
-        const std::string base = shifted(v, lag, dy, dx < 0 ? dx + 1 : dx - 1);
+        const std::string base = lane_value(v, sl, e, ls < 0 ? ls + 1 : ls - 1);
         const std::string name = "x" + std::to_string(ntmp++);
-        o << "      const " << T << " " << name << " = " << (dx < 0 ? "tcj_shr(" : "tcj_shl(") << base << ");\n";
+        o << "      const " << T << " " << name << " = " << (ls < 0 ? "tcj_shr(" : "tcj_shl(") << base << ");\n";
         sh[key] = name;
         return name;
     }
 
+    // value of version v at column offset dx, row offset dy, for element e
+    std::string term(int v, int lag, int dy, int dx, int e) {
+        const int sl = slot(v, lag, dy);
+        const int t = e + dx;
+        const int ls = t >= 0 ? t / cpl : -((-t + cpl - 1) / cpl);
+        return lane_value(v, sl, t - ls * cpl, ls);
+    }
+
     // One row of a loaded version into a window slot.  Interior kernel: a
     // uniform pointer to the row's first lane column, advanced by one row per
-    // step (every row it touches lies inside the allocation).  Edge kernel:
-    // row and column clamped to the allocation (clamped values only feed
-    // points that are not needed).
-    void load_row(int v, const std::string &step, int slot, const char *indent) {
+    // step (every row it touches lies inside the allocation); two columns per
+    // lane load as one 16-byte access.  Edge kernel: row and column clamped to
+    // the allocation (clamped values only feed points that are not needed).
+    void load_row(int v, const std::string &step, int sl, const char *indent) {
         const Dataset &ds = c.dats[G.vers[v].dat];
         if (var == 0) {
-            o << indent << "w" << v << "[" << slot << "] = q" << v << "[lane]; q" << v << " += " << ds.pitch
-              << "; asm volatile(\"\" : \"+s\"(q" << v << "));\n";
+            if (cpl == 2) {
+                o << indent << "{ const auto u = *(" << V2 << ")(q" << v << " + 2 * lane); " << entry(v, 0, sl)
+                  << " = u.x; " << entry(v, 1, sl) << " = u.y; }";
+            } else {
+                o << indent << entry(v, 0, sl) << " = q" << v << "[lane];";
+            }
+            o << " q" << v << " += " << ds.pitch << "; asm volatile(\"\" : \"+s\"(q" << v << "));\n";
         } else {
             o << indent << "{ const int y = __builtin_amdgcn_readfirstlane(min(max(" << step << " - "
               << V.load_lag[v] << ", " << -ds.hneg[1] << "), " << (ds.size[1] + ds.hpos[1] - 1) << ")); " << GC
               << " r = (" << GC << ")(a.s[" << src_index[v] << "] + (i64)y * " << ds.pitch
-              << "); asm volatile(\"\" : \"+s\"(r)); w" << v << "[" << slot << "] = r[cx" << src_index[v]
-              << "]; }\n";
+              << "); asm volatile(\"\" : \"+s\"(r));";
+            for (int e = 0; e < cpl; ++e)
+                o << " " << entry(v, e, sl) << " = r[cx" << src_index[v] << "_" << e << "];";
+            o << " }\n";
         }
     }
 
@@ -442,26 +481,35 @@ struct Gen {
         for (size_t j = 0; j < G.loops.size(); ++j) {
             const JLoop &J = G.loops[j];
             if (!J.needed) continue;
-            std::vector<std::string> terms;
-            for (const auto &R : J.in)
-                for (const auto &p : R.pts) terms.push_back(shifted(R.ver, J.lag, p.dy, p.dx));
-            // the weights are read from the kernel arguments right before
-            // the loop that uses them (the empty asm hides the pointer's
-            // origin, so they are not all kept live in scalar registers)
-            o << "      {\n      " << T << " acc = (" << T << ")0;\n";
+            std::vector<std::string> terms[2];
+            for (int e = 0; e < cpl; ++e)
+                for (const auto &R : J.in)
+                    for (const auto &p : R.pts) terms[e].push_back(term(R.ver, J.lag, p.dy, p.dx, e));
+            o << "      {\n";
+            for (int e = 0; e < cpl; ++e) o << "      " << T << " acc" << e << " = (" << T << ")0;\n";
             size_t q = 0;
             for (const auto &R : J.in) {
                 if (G.baked) {
                     for (const auto &p : R.pts) {
                         char lit[64];
                         std::snprintf(lit, sizeof lit, "%a", G.wvals[p.w]);
-                        o << "      acc = tcj_fma((" << T << ")" << lit << ", " << terms[q++] << ", acc);\n";
+                        for (int e = 0; e < cpl; ++e)
+                            o << "      acc" << e << " = tcj_fma((" << T << ")" << lit << ", " << terms[e][q]
+                              << ", acc" << e << ");\n";
+                        ++q;
                     }
                     continue;
                 }
+                // weights read from the kernel arguments right before use
+                // (the empty asm hides the pointer's origin, so they are not
+                // all kept live in scalar registers)
                 o << "      { tcj_cw wl = wk; asm volatile(\"\" : \"+s\"(wl));\n";
-                for (const auto &p : R.pts)
-                    o << "      acc = tcj_fma((" << T << ")wl[" << p.w << "], " << terms[q++] << ", acc);\n";
+                for (const auto &p : R.pts) {
+                    for (int e = 0; e < cpl; ++e)
+                        o << "      acc" << e << " = tcj_fma((" << T << ")wl[" << p.w << "], " << terms[e][q] << ", acc"
+                          << e << ");\n";
+                    ++q;
+                }
                 o << "      }\n";
             }
             const int out = J.out;
@@ -469,26 +517,33 @@ struct Gen {
                 int c0 = -1;
                 for (const auto &ps : V.pseudo)
                     if (ps.first == (int)j) c0 = ps.second;
-                o << "      { const int y = tt - " << J.lag << "; const bool in = inx & ((unsigned)(y - (" << G.ylo
-                  << ")) < " << (unsigned)(G.yhi - G.ylo) << "u); acc = in ? acc : " << entry(c0, J.lag, 0)
-                  << "; }\n";
+                const int sl = slot(c0, J.lag, 0);
+                o << "      { const int y = tt - " << J.lag << "; const bool iny = (unsigned)(y - (" << G.ylo << ")) < "
+                  << (unsigned)(G.yhi - G.ylo) << "u;";
+                for (int e = 0; e < cpl; ++e)
+                    o << " acc" << e << " = (inx" << e << " & iny) ? acc" << e << " : " << entry(c0, e, sl) << ";";
+                o << " }\n";
             }
-            o << "      w" << out << "[" << (V.win[out] - 1) << "] = acc;\n      }\n";
+            for (int e = 0; e < cpl; ++e) o << "      " << entry(out, e, V.win[out] - 1) << " = acc" << e << ";\n";
+            o << "      }\n";
         }
         // final values of the owned columns (uniform row pointers advanced
         // by one row per step)
         for (size_t v = 0; v < G.vers.size(); ++v) {
             if (!G.vers[v].stored || !G.vers[v].needed) continue;
             const Dataset &ds = c.dats[G.vers[v].dat];
-            o << "      { const int y = tt - " << G.vers[v].lag << "; if (y >= Y0 && y < yend && own) p" << v
-              << "[lane] = w" << v << "[" << (V.win[v] - 1) << "]; p" << v << " += " << ds.pitch
-              << "; asm volatile(\"\" : \"+s\"(p" << v << ")); }\n";
+            o << "      { const int y = tt - " << G.vers[v].lag << "; if (y >= Y0 && y < yend) {";
+            for (int e = 0; e < cpl; ++e)
+                o << " if (own" << e << ") p" << v << "[" << cpl << " * lane + " << e << "] = "
+                  << entry((int)v, e, V.win[v] - 1) << ";";
+            o << " } p" << v << " += " << ds.pitch << "; asm volatile(\"\" : \"+s\"(p" << v << ")); }\n";
         }
         // advance the windows by one row
         for (size_t v = 0; v < G.vers.size(); ++v) {
             if (!V.win[v]) continue;
             const int n = V.win[v] + (V.loaded[v] ? G.PF : 0);
-            for (int k = 0; k + 1 < n; ++k) o << "      w" << v << "[" << k << "] = w" << v << "[" << k + 1 << "];\n";
+            for (int e = 0; e < cpl; ++e)
+                for (int k = 0; k + 1 < n; ++k) o << "      " << entry((int)v, e, k) << " = " << entry((int)v, e, k + 1) << ";\n";
         }
         o << "    }\n";
     }
@@ -497,10 +552,14 @@ struct Gen {
         o << "  const tcj_cw wk = (tcj_cw)((const char __attribute__((address_space(4))) *)__builtin_amdgcn_kernarg_segment_ptr() + "
           << 8 * (std::max<size_t>(1, G.src_dat.size()) + std::max<size_t>(1, G.dst_dat.size())) << ");\n";
         o << "  const int lane = threadIdx.x & 63;\n";
-        o << "  const int col = X0 - " << G.HL << " + lane;\n";
-        o << "  const bool own = (lane >= " << G.HL << ") & (lane < " << (G.HL + G.Wo) << ") & (col < " << G.xhi
-          << ");\n";
-        if (var == 1) o << "  const bool inx = (col >= " << G.xlo << ") & (col < " << G.xhi << ");\n";
+        for (int e = 0; e < cpl; ++e) {
+            o << "  const int col" << e << " = X0 - " << G.HL << " + " << cpl << " * lane + " << e << ";\n";
+            o << "  const bool own" << e << " = (col" << e << " >= X0) & (col" << e << " < X0 + " << G.Wo << ") & (col"
+              << e << " < " << G.xhi << ");\n";
+            if (var == 1)
+                o << "  const bool inx" << e << " = (col" << e << " >= " << G.xlo << ") & (col" << e << " < " << G.xhi
+                  << ");\n";
+        }
         o << "  const int yend = min(Y0 + " << G.Hseg << ", " << G.yhi << ");\n";
         const int nsteps = G.Hseg + V.pre + V.post;
         const int nit = (nsteps + G.U - 1) / G.U;
@@ -508,8 +567,9 @@ struct Gen {
         if (var == 1)
             for (size_t i = 0; i < G.src_dat.size(); ++i) {
                 const Dataset &ds = c.dats[G.src_dat[i]];
-                o << "  const int cx" << i << " = min(max(col, " << -ds.hneg[0] << "), "
-                  << (ds.size[0] + ds.hpos[0] - 1) << ");\n";
+                for (int e = 0; e < cpl; ++e)
+                    o << "  const int cx" << i << "_" << e << " = min(max(col" << e << ", " << -ds.hneg[0] << "), "
+                      << (ds.size[0] + ds.hpos[0] - 1) << ");\n";
             }
         for (size_t v = 0; v < G.vers.size(); ++v) {
             const Dataset &ds = c.dats[G.vers[v].dat];
@@ -522,7 +582,8 @@ struct Gen {
         }
         for (size_t v = 0; v < G.vers.size(); ++v) {
             if (!V.win[v]) continue;
-            o << "  " << T << " w" << v << "[" << (V.win[v] + (V.loaded[v] ? G.PF : 0)) << "];\n";
+            for (int e = 0; e < cpl; ++e)
+                o << "  " << T << " " << W((int)v, e) << "[" << (V.win[v] + (V.loaded[v] ? G.PF : 0)) << "];\n";
         }
         // prologue: rows arriving at the first PF steps
         for (int k = 0; k < G.PF; ++k)
@@ -544,8 +605,12 @@ void gen_group(const Ctx &c, FusedGroup &G, int gi, std::ostringstream &o) {
     for (int var = 0; var < 2; ++var) {
         if ((var == 0 ? G.nwaves_in : G.nwaves_edge) == 0) continue;
         Gen g(c, G, var);
-        o << "extern \"C\" __global__ void __launch_bounds__(256) " << (var == 0 ? G.kname_in : G.kname_edge) << "("
-          << S << " a) {\n";
+        // interior kernels: ask for two wavefronts per SIMD (the register
+        // windows then fit in 256 registers without spilling, and a second
+        // wavefront hides latencies and co-issues scalar work)
+        o << "extern \"C\" __global__ void __launch_bounds__(256) ";
+        if (var == 0 && G.wpe > 0) o << "__attribute__((amdgpu_waves_per_eu(" << G.wpe << ", " << G.wpe << "))) ";
+        o << (var == 0 ? G.kname_in : G.kname_edge) << "(" << S << " a) {\n";
         o << "  const int wid = tcj_lin(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n";
         const int ns = G.nstrips;
         if (var == 0) {
@@ -593,6 +658,8 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
     sp.max_loops = tile[2] > 0 ? tile[2] : 32;
     sp.U = std::max(1, c.jit_unroll);
     sp.PF = std::max(1, c.jit_prefetch);
+    sp.cpl = c.jit_cpl;
+    sp.wpe = c.jit_wpe;
     const int L = (int)chain.size();
     // best[j]: least modelled time of loops [0, j); from[j]: start of the last piece
     std::vector<double> best(L + 1, 1e300);
@@ -674,6 +741,12 @@ tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups
         std::vector<char> code(n);
         hiprtcGetCode(prog, code.data());
         hiprtcDestroyProgram(&prog);
+        if (const char *dump = getenv("TC_JIT_DUMP_CO")) {
+            if (FILE *fp = std::fopen(dump, "wb")) {
+                std::fwrite(code.data(), 1, code.size(), fp);
+                std::fclose(fp);
+            }
+        }
         if (!c.host_only && hipModuleLoadData(&mod, code.data()) != hipSuccess)
             return fail(c, TC_ERR_DEVICE, "hipModuleLoadData of the fused kernels failed");
         c.jit_modules[key] = mod;

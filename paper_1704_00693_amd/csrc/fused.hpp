@@ -83,6 +83,8 @@ struct FusedGroup {
     std::vector<JLoop> loops;
     std::vector<JVer> vers;
     JVariant var[2];  // 0 interior, 1 edge
+    int cpl = 1;      // consecutive columns held by one lane (1 or 2); a wavefront holds 64 * cpl
+    int wpe = 2;      // wavefronts per SIMD requested for the interior kernel
     int HL = 0, HR = 0, Wo = 0;
     int BMAX = 0, TMAX = 0;  // rows below / above the owned rows that are read
     int Hseg = 0, U = 4, PF = 2;

@@ -238,3 +238,37 @@ def test_fused_weight_change(tc):
     for d in range(ch.ndat):
         assert rel_err(outs[0][d], ref[d]) <= TOL
         assert np.array_equal(outs[0][d], outs[2][d])
+
+
+@pytest.mark.parametrize("env", [{"TC_JIT_CPL": "2"}, {"TC_JIT_WPE": "0", "TC_JIT_UNROLL": "3", "TC_JIT_PREFETCH": "1"},
+                                 {"TC_JIT_BAKE": "0"}])
+def test_fused_generator_variants(tc, env):
+    """Kernel-generation variants (two columns per lane, compiler-chosen
+    occupancy with another unroll and prefetch distance, weights read from
+    the kernel arguments) give the untiled bits."""
+    import os
+    from paper_1704_00693_amd.apps import ChainRunner
+    ch = make_chain(2, 130, 10, 24, seed=17)
+    data = chain_data(ch)
+    with tc.Context() as c:
+        r = ChainRunner(c, ch, data)
+        r.run()
+        ref = [r.read(d) for d in range(ch.ndat)]
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        with tc.Context() as c:
+            c.tc_set_tiling(tc.TC_TILING_FUSED, (0, 0, 0))
+            r = ChainRunner(c, ch, data)
+            r.run()
+            got = [r.read(d) for d in range(ch.ndat)]
+            say(f"generator variant {env}: groups {c.tc_get_stats()['last_groups']}")
+            assert c.tc_get_stats()["last_groups"] >= 1
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    for d in range(ch.ndat):
+        assert np.array_equal(ref[d], got[d])
