@@ -20,6 +20,9 @@ Codes at Run-time with OPS"):
 * ``tealeaf``   -- the heat-conduction PPCG solve used as the workload of the
                    TeaLeaf experiment (Section 5/6.4), written from textbook
                    CG and Chebyshev iterations.
+* ``euler``     -- a compressible-Euler Runge-Kutta step with fourth-order
+                   central differences, the stand-in for the OpenSBLI
+                   Taylor-Green experiment (Section 5/6.4).
 
 Point arithmetic runs in ``csrc/oracle.c`` (plain C, explicit fma, FP64).
 """
@@ -63,7 +66,8 @@ def lib():
         I64A = ctypes.POINTER(ctypes.c_int64)
         for name in ("orc_wsum", "orc_copy", "orc_axpby", "orc_halo_reflect", "orc_tea_init",
                      "orc_tea_k", "orc_tea_resid", "orc_tea_matvec_dot", "orc_tea_p1", "orc_tea_p2",
-                     "orc_tea_precon_init", "orc_tea_cg_update", "orc_tea_cg_p", "orc_dot_terms"):
+                     "orc_tea_precon_init", "orc_tea_cg_update", "orc_tea_cg_p", "orc_dot_terms",
+                     "orc_euler_prim", "orc_euler_rhs", "orc_rk_stage"):
             getattr(L, name).restype = ctypes.c_int
         L.orc_tea_gersh.restype = ctypes.c_double
         _lib = L

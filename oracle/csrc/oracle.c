@@ -270,3 +270,83 @@ int orc_dot_terms(const int64_t lo[3], const int64_t hi[3], ov a, ov b, double *
             }
     return 0;
 }
+
+/* ---- compressible Euler, conserved variables Q = (rho, rho u_1..rho u_D, E) ----
+ * (the stand-in for the OpenSBLI Taylor-Green experiment, Section 5 and
+ * Section 6.4: explicit Runge-Kutta stages of central-difference sweeps).
+ *
+ * Primitive variables at a point:
+ *   ri = 1 / rho;  u_d = (rho u_d) * ri;
+ *   k = sum over d from the last to the first of (rho u_d) u_d, accumulated
+ *       as k = (rho u_D) u_D, then k = fma(rho u_d, u_d, k) for d = D-1..1;
+ *   p = gm1 * fma(-0.5, k, E)              (gm1 = gamma - 1)
+ * q[] holds the D + 2 conserved arrays, vel[] the D velocities. */
+int orc_euler_prim(int ndim, const int64_t lo[3], const int64_t hi[3], const ov *q, const ov *vel, ov p, double gm1)
+{
+    for (int64_t z = lo[2]; z < hi[2]; ++z)
+        for (int64_t y = lo[1]; y < hi[1]; ++y)
+            for (int64_t x = lo[0]; x < hi[0]; ++x) {
+                const double ri = 1.0 / AT(q[0], x, y, z);
+                double u[3];
+                for (int d = 0; d < ndim; ++d) u[d] = AT(q[1 + d], x, y, z) * ri;
+                double k = AT(q[ndim], x, y, z) * u[ndim - 1];
+                for (int d = ndim - 2; d >= 0; --d) k = fma(AT(q[1 + d], x, y, z), u[d], k);
+                for (int d = 0; d < ndim; ++d) AT(vel[d], x, y, z) = u[d];
+                AT(p, x, y, z) = gm1 * fma(-0.5, k, AT(q[ndim + 1], x, y, z));
+            }
+    return 0;
+}
+
+/* Flux of conserved component c along axis d at a point:
+ *   f = Q_c u_d;  momentum along d (c == d + 1): f = f + p;
+ *   energy (c == D + 1): f = fma(p, u_d, f). */
+static double euler_flux(int ndim, int c, int d, ov qc, const ov *vel, ov p, int64_t x, int64_t y, int64_t z)
+{
+    const double ud = AT(vel[d], x, y, z);
+    double f = AT(qc, x, y, z) * ud;
+    if (c == d + 1) f = f + AT(p, x, y, z);
+    if (c == ndim + 1) f = fma(AT(p, x, y, z), ud, f);
+    return f;
+}
+
+/* Right-hand side of component c with fourth-order central differences,
+ * differences first:  for each axis d (in order), with f(o) the flux at
+ * offset o along d:  t1 = f(+1) - f(-1);  t2 = f(+2) - f(-2);
+ * g_d = 8 t1 - t2;  acc = g_0 (+ g_1 (+ g_2)) summed in axis order;
+ * R = -acc * s   with s = 1 / (12 h). */
+int orc_euler_rhs(int ndim, const int64_t lo[3], const int64_t hi[3], int c, ov r, ov qc, const ov *vel, ov p,
+                  double s)
+{
+    for (int64_t z = lo[2]; z < hi[2]; ++z)
+        for (int64_t y = lo[1]; y < hi[1]; ++y)
+            for (int64_t x = lo[0]; x < hi[0]; ++x) {
+                double acc = 0.0;
+                for (int d = 0; d < ndim; ++d) {
+                    int64_t e[3] = {0, 0, 0};
+                    e[d] = 1;
+                    const double fp1 = euler_flux(ndim, c, d, qc, vel, p, x + e[0], y + e[1], z + e[2]);
+                    const double fm1 = euler_flux(ndim, c, d, qc, vel, p, x - e[0], y - e[1], z - e[2]);
+                    const double fp2 = euler_flux(ndim, c, d, qc, vel, p, x + 2 * e[0], y + 2 * e[1], z + 2 * e[2]);
+                    const double fm2 = euler_flux(ndim, c, d, qc, vel, p, x - 2 * e[0], y - 2 * e[1], z - 2 * e[2]);
+                    const double t1 = fp1 - fm1;
+                    const double t2 = fp2 - fm2;
+                    const double g = 8.0 * t1 - t2;
+                    acc = d == 0 ? g : acc + g;
+                }
+                AT(r, x, y, z) = -acc * s;
+            }
+    return 0;
+}
+
+/* One Runge-Kutta stage of one component (Shu-Osher form):
+ *   t = fma(dt, R, Q);  Q = fma(a, Q0, b t). */
+int orc_rk_stage(const int64_t lo[3], const int64_t hi[3], ov q0, ov q, ov r, double a, double b, double dt)
+{
+    for (int64_t z = lo[2]; z < hi[2]; ++z)
+        for (int64_t y = lo[1]; y < hi[1]; ++y)
+            for (int64_t x = lo[0]; x < hi[0]; ++x) {
+                const double t = fma(dt, AT(r, x, y, z), AT(q, x, y, z));
+                AT(q, x, y, z) = fma(a, AT(q0, x, y, z), b * t);
+            }
+    return 0;
+}

@@ -272,3 +272,49 @@ def test_fused_generator_variants(tc, env):
                 os.environ[k] = v
     for d in range(ch.ndat):
         assert np.array_equal(ref[d], got[d])
+
+
+def test_full_size_3d_chain_sampled(tc):
+    """The 3D workload at its full size (384^3 FP64, 25 datasets, 60 loops of
+    7- and 13-point stars, a final SUM) untiled and skewed-tiled: a corner
+    window and an edge window of every dataset against the window oracle,
+    all datasets identical across modes, and the SUM equal to the exactly
+    rounded sum of the read-back dataset (within the double-double bound)."""
+    import math
+    from paper_1704_00693_amd.apps import ChainRunner
+    from synthgen import chain_3d
+    ch = chain_3d()
+    say("generating 3D inputs")
+    data = chain_data(ch)
+    n, h = ch.n, ch.halo
+    wins = [(0, 0, 0), (n - 1, n // 2, 0)]
+    say("window oracles")
+    refs = [window_oracle(ch, data, c, 124) for c in wins]
+    sums, outs = {}, {}
+    for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0)), (tc.TC_TILING_SKEWED, (0, 0, 0))]:
+        say(f"3D chain 384^3 mode={mode}")
+        with tc.Context() as c:
+            c.tc_set_tiling(mode, tile)
+            r = ChainRunner(c, ch, data)
+            sums[mode] = r.run()
+            last = r.read(ch.last_written())
+            kept = {}
+            for d in range(ch.ndat):
+                a = r.read(d)
+                for k, (arrs, lo, glo, ghi) in enumerate(refs):
+                    sl = tuple(slice(glo[i] + h, ghi[i] + h) for i in reversed(range(3)))
+                    want = arrs[d][tuple(slice(glo[i] - lo[i], ghi[i] - lo[i]) for i in reversed(range(3)))]
+                    got = a[sl]
+                    assert got.size > 0
+                    assert rel_err(got, want) <= TOL
+                kept[d] = a[::7, ::5, ::3].copy()
+            outs[mode] = kept
+        inner = last[h:h + n, h:h + n, h:h + n]
+        exact = math.fsum(inner.ravel().tolist())
+        bound = 1e-15 * float(np.abs(inner).sum())
+        say(f"  sum {sums[mode]!r} exact {exact!r}")
+        assert abs(sums[mode] - exact) <= bound
+        del last, inner
+    assert sums[0] == sums[1]
+    for d in range(ch.ndat):
+        assert np.array_equal(outs[0][d], outs[1][d])
