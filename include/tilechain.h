@@ -99,6 +99,18 @@ typedef enum { TC_TILING_NONE = 0, TC_TILING_SKEWED = 1, TC_TILING_FUSED = 2, TC
  *  TC_OP_TEA_CG_UPDATE args: x(RW), r(RW), p(R), w(R) params alpha   x = fma(alpha,p,x); r = fma(-alpha,w,r)
  *  TC_OP_TEA_CG_P    args: p(RW), z(R)                params beta    p = fma(beta, p, z)
  *  TC_OP_TEA_GERSH   args: K..(R: centre, +e_d), red(MAX)         red = max(red, fma(2, sum of face K, 1))
+ *
+ * Compressible Euler (stand-in for the OpenSBLI Taylor-Green runs of Section 5
+ * and Section 6.4; D = block dimension, Q = (rho, rho u_1..rho u_D, E)):
+ *  TC_OP_EULER_PRIM  args: Q_0..Q_{D+1}(R), u_1..u_D(W), p(W)   params gm1 = gamma - 1
+ *                    ri = 1/rho; u_d = (rho u_d) ri; k = (rho u_D) u_D, then
+ *                    k = fma(rho u_d, u_d, k) for d = D-1..1; p = gm1 * fma(-0.5, k, E)
+ *  TC_OP_EULER_RHS   args: R(W), Q_c(R: +-2 along every axis), u_1..u_D(R: same), p(R: same)
+ *                    params c (component), s = 1/(12h).  Flux along axis d at a point:
+ *                    f = Q_c u_d; f = f + p if c == d; f = fma(p, u_d, f) if c == D+1.
+ *                    Per axis (in order) g_d = 8 (f(+1) - f(-1)) - (f(+2) - f(-2)),
+ *                    acc = g_1 (+ g_2 (+ g_3)); R = -acc * s
+ *  TC_OP_RK_STAGE    args: Q0(R), Q(RW), R(R)   params a, b, dt   t = fma(dt, R, Q); Q = fma(a, Q0, b t)
  *  where (A v) = diag*v - K_E v_E - K_W v_W - K_N v_N - K_S v_S [- K_T v_T - K_B v_B],
  *  diag = 1 + K_E + K_W + K_N + K_S [+ K_T + K_B] summed left to right, the
  *  off-diagonal terms applied with fma in the order E, W, N, S[, T, B].
@@ -119,7 +131,10 @@ typedef enum {
     TC_OP_TEA_PRECON_INIT = 16,
     TC_OP_TEA_CG_UPDATE = 17,
     TC_OP_TEA_CG_P = 18,
-    TC_OP_TEA_GERSH = 19
+    TC_OP_TEA_GERSH = 19,
+    TC_OP_EULER_PRIM = 20,
+    TC_OP_EULER_RHS = 21,
+    TC_OP_RK_STAGE = 22
 } tc_op;
 
 /* One loop argument: a dataset through a stencil with an access mode, or a

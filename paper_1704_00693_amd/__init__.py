@@ -33,6 +33,7 @@ OPS = {
     "WSUM": 0, "COPY": 1, "AXPBY": 2, "DOT": 3, "SUM": 4, "HALO_REFLECT": 5,
     "TEA_INIT": 10, "TEA_K": 11, "TEA_RESID": 12, "TEA_MATVEC_DOT": 13, "TEA_P1": 14, "TEA_P2": 15,
     "TEA_PRECON_INIT": 16, "TEA_CG_UPDATE": 17, "TEA_CG_P": 18, "TEA_GERSH": 19,
+    "EULER_PRIM": 20, "EULER_RHS": 21, "RK_STAGE": 22,
 }
 ACCESS = {"R": TC_READ, "W": TC_WRITE, "RW": TC_RW, "INC": TC_INC}
 EXPORTS = ["tc_init", "tc_finalize", "tc_decl_block", "tc_decl_dat", "tc_decl_stencil", "tc_decl_reduction",

@@ -426,3 +426,75 @@ def serve(ctx: Context, requests, mixed: bool = False, tol: float = 1e-8, max_in
         return out
     finally:
         b.close()
+
+
+# ---------------------------------------------------------------------------
+# compressible Euler: one SSP-RK3 step with fourth-order central differences
+# ---------------------------------------------------------------------------
+class EulerRunner:
+    """Q = (rho, rho u_1..rho u_D, E) on a block with halo `halo` whose ghost
+    cells hold fixed boundary values; ``record_step(dt)`` enqueues one RK3
+    step: Q0 = Q, then per stage the primitive variables over the padded grid,
+    one right-hand-side loop per component and one Runge-Kutta update per
+    component over the interior."""
+
+    RK3 = [(0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0)]
+
+    def __init__(self, ctx: Context, q: Sequence[np.ndarray], n: int, h: float, gamma: float = 1.4, halo: int = 2,
+                 dtype: int = TC_F64):
+        self.ctx, self.n, self.h, self.halo = ctx, n, h, halo
+        D = self.D = q[0].ndim
+        self.gm1 = gamma - 1.0
+        self.blk = ctx.tc_decl_block(D, "euler")
+        size, hh = [n] * D, [halo] * D
+
+        def dat(init, name):
+            return ctx.tc_decl_dat(self.blk, size, hh, hh, init, dtype, name)
+
+        self.Q = [dat(q[c], f"q{c}") for c in range(D + 2)]
+        self.Q0 = [dat(q[c], f"q0_{c}") for c in range(D + 2)]
+        self.R = [dat(None, f"r{c}") for c in range(D + 2)]
+        self.vel = [dat(None, f"u{d}") for d in range(D)]
+        self.p = dat(None, "p")
+        z = [0] * D
+        pts = [tuple(z)]
+        for d in range(D):
+            for o in (-1, 1, -2, 2):
+                e = list(z)
+                e[d] = o
+                pts.append(tuple(e))
+        self.S_c = ctx.tc_decl_stencil([tuple(z)])
+        self.S_x = ctx.tc_decl_stencil(pts)
+        self.red = ctx.tc_decl_reduction(TC_RED_SUM, "energy")
+        self.interior = [v for _ in range(D) for v in (0, n)]
+        self.padded = [v for _ in range(D) for v in (-halo, n + halo)]
+
+    def record_step(self, dt: float):
+        ctx, D = self.ctx, self.D
+        for c in range(D + 2):
+            ctx.tc_par_loop("COPY", self.blk, self.interior, [(self.Q0[c], self.S_c, "W"), (self.Q[c], self.S_c, "R")],
+                            name=f"q0_{c}")
+        s = 1.0 / (12.0 * self.h)
+        for st, (a, b) in enumerate(self.RK3):
+            ctx.tc_par_loop("EULER_PRIM", self.blk, self.padded,
+                            [(q, self.S_c, "R") for q in self.Q] + [(u, self.S_c, "W") for u in self.vel] +
+                            [(self.p, self.S_c, "W")], [self.gm1], name=f"prim{st}")
+            for c in range(D + 2):
+                ctx.tc_par_loop("EULER_RHS", self.blk, self.interior,
+                                [(self.R[c], self.S_c, "W"), (self.Q[c], self.S_x, "R")] +
+                                [(u, self.S_x, "R") for u in self.vel] + [(self.p, self.S_x, "R")],
+                                [float(c), s], name=f"rhs{st}_{c}")
+            for c in range(D + 2):
+                ctx.tc_par_loop("RK_STAGE", self.blk, self.interior,
+                                [(self.Q0[c], self.S_c, "R"), (self.Q[c], self.S_c, "RW"), (self.R[c], self.S_c, "R")],
+                                [a, b, dt], name=f"rk{st}_{c}")
+
+    def step(self, dt: float) -> float:
+        """One RK3 step; returns the sum of E over the interior (the flush)."""
+        self.record_step(dt)
+        self.ctx.tc_par_loop("SUM", self.blk, self.interior, [(self.Q[self.D + 1], self.S_c, "R"), ("red", self.red)],
+                             name="sumE")
+        return self.ctx.tc_reduction_result(self.red)
+
+    def loops_per_step(self) -> int:
+        return (self.D + 2) + 3 * (1 + 2 * (self.D + 2)) + 1

@@ -92,6 +92,9 @@ bool op_sig(int op, int ndim, Sig &s) {
     case TC_OP_TEA_CG_UPDATE: s = {4, 4, 0, -1, 1}; return true;
     case TC_OP_TEA_CG_P: s = {2, 2, 0, -1, 1}; return true;
     case TC_OP_TEA_GERSH: s = {ndim, ndim, 1, TC_RED_MAX, 0}; return true;
+    case TC_OP_EULER_PRIM: s = {2 * ndim + 3, 2 * ndim + 3, 0, -1, 1}; return true;
+    case TC_OP_EULER_RHS: s = {ndim + 3, ndim + 3, 0, -1, 2}; return true;
+    case TC_OP_RK_STAGE: s = {3, 3, 0, -1, 3}; return true;
     default: return false;
     }
 }
@@ -116,6 +119,9 @@ int op_access(int op, int ndim, int i) {
     case TC_OP_TEA_CG_UPDATE: return i < 2 ? RW : R;
     case TC_OP_TEA_CG_P: return i == 0 ? RW : R;
     case TC_OP_TEA_GERSH: return R;
+    case TC_OP_EULER_PRIM: return i < ndim + 2 ? R : W;
+    case TC_OP_EULER_RHS: return i == 0 ? W : R;
+    case TC_OP_RK_STAGE: return i == 1 ? RW : R;
     default: return -2;
     }
 }
@@ -145,6 +151,13 @@ bool op_footprint(int op, int ndim, int i, int lo[3], int hi[3]) {
                 hi[d] = 1;
             }
         }
+        return true;
+    case TC_OP_EULER_RHS:
+        if (i > 0)
+            for (int d = 0; d < ndim; ++d) {
+                lo[d] = -2;
+                hi[d] = 2;
+            }
         return true;
     default: return true;
     }

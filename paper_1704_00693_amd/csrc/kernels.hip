@@ -261,6 +261,63 @@ struct OpTeaGersh {  // K.., red(max)
     }
 };
 
+// ---- compressible Euler ----------------------------------------------------
+template <typename T>
+struct OpEulerPrim {  // Q_0..Q_{D+1}, u_1..u_D, p; gm1
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        const int D = d.ndim;
+        const T ri = (T)1 / P<T>(d, 0)[IX(d, 0, x, y, z)];
+        T u[3], m[3];
+        for (int k = 0; k < D; ++k) {
+            m[k] = P<T>(d, 1 + k)[IX(d, 1 + k, x, y, z)];
+            u[k] = m[k] * ri;
+        }
+        T ke = m[D - 1] * u[D - 1];
+        for (int k = D - 2; k >= 0; --k) ke = fmaT<T>(m[k], u[k], ke);
+        for (int k = 0; k < D; ++k) P<T>(d, D + 2 + k)[IX(d, D + 2 + k, x, y, z)] = u[k];
+        const T e = P<T>(d, D + 1)[IX(d, D + 1, x, y, z)];
+        P<T>(d, 2 * D + 2)[IX(d, 2 * D + 2, x, y, z)] = (T)d.prm[0] * fmaT<T>((T)-0.5, ke, e);
+    }
+};
+
+template <typename T>
+struct OpEulerRhs {  // R, Q_c, u_1..u_D, p; c, s
+    static __device__ __forceinline__ T flux(const LoopDesc &d, int c, int ax, int x, int y, int z) {
+        const int D = d.ndim;
+        const T ud = P<T>(d, 2 + ax)[IX(d, 2 + ax, x, y, z)];
+        T f = P<T>(d, 1)[IX(d, 1, x, y, z)] * ud;
+        if (c == ax + 1) f = f + P<T>(d, 2 + D)[IX(d, 2 + D, x, y, z)];
+        if (c == D + 1) f = fmaT<T>(P<T>(d, 2 + D)[IX(d, 2 + D, x, y, z)], ud, f);
+        return f;
+    }
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        const int D = d.ndim;
+        const int c = (int)d.prm[0];
+        T acc = (T)0;
+        for (int ax = 0; ax < D; ++ax) {
+            const int ex = ax == 0, ey = ax == 1, ez = ax == 2;
+            const T fp1 = flux(d, c, ax, x + ex, y + ey, z + ez);
+            const T fm1 = flux(d, c, ax, x - ex, y - ey, z - ez);
+            const T fp2 = flux(d, c, ax, x + 2 * ex, y + 2 * ey, z + 2 * ez);
+            const T fm2 = flux(d, c, ax, x - 2 * ex, y - 2 * ey, z - 2 * ez);
+            const T t1 = fp1 - fm1;
+            const T t2 = fp2 - fm2;
+            const T g = (T)8 * t1 - t2;
+            acc = ax == 0 ? g : acc + g;
+        }
+        P<T>(d, 0)[IX(d, 0, x, y, z)] = -acc * (T)d.prm[1];
+    }
+};
+
+template <typename T>
+struct OpRkStage {  // Q0, Q, R; a, b, dt
+    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+        T *q = P<T>(d, 1) + IX(d, 1, x, y, z);
+        const T t = fmaT<T>((T)d.prm[2], P<T>(d, 2)[IX(d, 2, x, y, z)], *q);
+        *q = fmaT<T>((T)d.prm[0], P<T>(d, 0)[IX(d, 0, x, y, z)], (T)d.prm[1] * t);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // the loop kernel
 // ---------------------------------------------------------------------------
@@ -362,6 +419,9 @@ static hipError_t dispatch_t(const LoopDesc &d, const Box &b, hipStream_t s) {
     case TC_OP_TEA_CG_UPDATE: return go<OpTeaCgUpdate<T>>(d, b, s);
     case TC_OP_TEA_CG_P: return go<OpTeaCgP<T>>(d, b, s);
     case TC_OP_TEA_GERSH: return go<OpTeaGersh<T>>(d, b, s);
+    case TC_OP_EULER_PRIM: return go<OpEulerPrim<T>>(d, b, s);
+    case TC_OP_EULER_RHS: return go<OpEulerRhs<T>>(d, b, s);
+    case TC_OP_RK_STAGE: return go<OpRkStage<T>>(d, b, s);
     default: return hipErrorInvalidValue;
     }
 }

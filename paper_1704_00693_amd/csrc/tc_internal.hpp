@@ -14,8 +14,8 @@
 
 namespace tc {
 
-constexpr int kMaxArgs = 8;      // dataset + reduction arguments of one loop
-constexpr int kMaxPts = 64;      // stencil points over all dataset arguments of one loop
+constexpr int kMaxArgs = 12;     // dataset + reduction arguments of one loop
+constexpr int kMaxPts = 96;      // stencil points over all dataset arguments of one loop
 constexpr int kMaxParams = 64;   // scalar parameters of one loop
 constexpr int kMaxHalo = 16;
 constexpr int kXAlign = 16;      // x origin and row pitch aligned to 16 elements
@@ -119,7 +119,7 @@ struct LoopDesc {
     DArg arg[kMaxArgs];
     int64_t off[kMaxPts];  // linear element offset of every stencil point
     unsigned char qarg[kMaxPts];  // dataset argument of every stencil point
-    double prm[kMaxParams];  // WSUM: weight of stencil point i at prm[i] (aligned with off[])
+    double prm[kMaxPts > kMaxParams ? kMaxPts : kMaxParams];  // WSUM: weight of stencil point i at prm[i] (aligned with off[])
     int nred;            // reduction arguments (0..2)
     int red_op[2];
     double *partials[2];  // per-block (hi, lo) partial results, indexed from part_base

@@ -95,3 +95,25 @@ def test_rk3_linear_rhs_is_third_order_taylor():
     for a, b in zip(start, o.q):
         got = o.interior(b)
         assert np.allclose(got, a * amp, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("zlo,zhi", [(0, 3), (10, 14), (21, 24)])
+def test_euler_window_equals_full_step(zlo, zhi):
+    """The z-slab window oracle used for full-size checks gives exactly the
+    full oracle's values on its planes."""
+    import sys
+    sys.path.insert(0, "tests")
+    from synthgen import taylor_green
+    from windows import euler_window
+    n = 24
+    h = 2 * math.pi / n
+    q = taylor_green(n)
+    full = EulerOracle(q, n, h)
+    full.step(1e-3)
+    wq, wr = euler_window(q, n, h, zlo, zhi, 1e-3)
+    hh = 2
+    for c in range(5):
+        a = full.q[c][zlo + hh:zhi + hh, hh:hh + n, hh:hh + n]
+        b = wq[c][:, hh:hh + n, hh:hh + n]
+        assert np.array_equal(a, b)
+        assert np.array_equal(full.r[c][zlo + hh:zhi + hh, hh:hh + n, hh:hh + n], wr[c][:, hh:hh + n, hh:hh + n])

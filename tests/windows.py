@@ -37,3 +37,47 @@ def window_oracle(ch, data, centre, half):
     good_lo = [max(0, a + m) if a > -h else 0 for a in lo]
     good_hi = [min(n, b - m) if b < n + h else n for b in hi]
     return arrs, lo, good_lo, good_hi
+
+
+def euler_window(q, n, h, zlo, zhi, dt, gamma=1.4, halo=2, margin=8):
+    """Oracle RK3 step of a 3D Euler state restricted to the planes
+    [zlo, zhi): the step runs on a z-crop of the padded arrays with `margin`
+    extra planes each side (three stages of a radius-2 stencil need 6).
+    Returns (Q after the step, R of the last stage), each a list of arrays
+    (z in [zlo, zhi), all y and x including halos)."""
+    import ctypes
+    from oracle import OV, Grid, lib
+    from oracle.euler import RK3
+    clo, chi = max(zlo - margin, -halo), min(zhi + margin, n + halo)
+    crop = [np.ascontiguousarray(a[clo + halo:chi + halo]) for a in q]
+    D = 3
+
+    class ZGrid(Grid):
+        def view(self, a):
+            v = super().view(a)
+            v.origin = -clo * a.shape[1] * a.shape[2] + halo * a.shape[2] + halo
+            return v
+
+    g = ZGrid(D, n, halo)
+    L = lib()
+    qs = [a.copy() for a in crop]
+    q0 = [a.copy() for a in crop]
+    vel = [np.zeros_like(crop[0]) for _ in range(D)]
+    p = np.zeros_like(crop[0])
+    r = [np.zeros_like(crop[0]) for _ in range(D + 2)]
+
+    def views(arrs):
+        return (OV * len(arrs))(*[g.view(a) for a in arrs])
+
+    plo, phi = g.box([-halo, -halo, clo], [n + halo, n + halo, chi])
+    ilo, ihi = g.box([0, 0, max(clo + 2, 0)], [n, n, min(chi - 2, n)])
+    s = 1.0 / (12.0 * h)
+    for a, b in RK3:
+        L.orc_euler_prim(D, plo, phi, views(qs), views(vel), g.view(p), ctypes.c_double(gamma - 1.0))
+        for c in range(D + 2):
+            L.orc_euler_rhs(D, ilo, ihi, c, g.view(r[c]), g.view(qs[c]), views(vel), g.view(p), ctypes.c_double(s))
+        for c in range(D + 2):
+            L.orc_rk_stage(ilo, ihi, g.view(q0[c]), g.view(qs[c]), g.view(r[c]), ctypes.c_double(a),
+                           ctypes.c_double(b), ctypes.c_double(dt))
+    sl = slice(zlo - clo, zhi - clo)
+    return [a[sl] for a in qs], [a[sl] for a in r]
