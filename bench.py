@@ -26,6 +26,7 @@ import csv
 import glob
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -200,6 +201,80 @@ def serve_bench(tc, rate: float, seconds: float, drain: float, seed: int = 4, to
     return out
 
 
+def _timed(fn, steps, warm=0.5):
+    import torch
+    t0 = time.perf_counter()
+    k = 0
+    while k < 2 or time.perf_counter() - t0 < warm:
+        fn()
+        k += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def other_workloads(tc, which, steps):
+    """The other configurations, each in the execution modes that apply:
+    heat-conduction PPCG 256^2 (50 iterations of 10 Chebyshev steps), the
+    256^3 Taylor-Green RK3 step, and (optionally) the 384^3 synthetic chain."""
+    out = {}
+    modes = [("none", tc.TC_TILING_NONE, (0, 0, 0)), ("skewed", tc.TC_TILING_SKEWED, (0, 0, 0))]
+    if "tealeaf" in which:
+        from paper_1704_00693_amd.apps import HeatSolver
+        from synthgen import heat_problem
+        hp = heat_problem(256, seed=0)
+        res = {}
+        for name, m, tile in modes:
+            with tc.Context(0) as c:
+                c.tc_set_tiling(m, tile)
+                s = HeatSolver(c, hp.density, hp.energy)
+                dt = _timed(lambda: s.solve(outer=50, inner=10), max(1, steps // 10))
+                st = c.tc_get_stats()
+            res[name] = {"seconds_per_solve": dt, "loops_recorded": st["loops_recorded"]}
+        out["tealeaf_256"] = {"workload": "heat conduction 256^2 FP64, PPCG 50 x 10 Chebyshev steps, seed 0",
+                              "modes": res}
+        log(f"tealeaf 256^2: {res}")
+    if "euler" in which:
+        from paper_1704_00693_amd.apps import EulerRunner
+        from synthgen import taylor_green
+        n = 256
+        q = taylor_green(n)
+        res = {}
+        for name, m, tile in modes:
+            with tc.Context(0) as c:
+                c.tc_set_tiling(m, tile)
+                r = EulerRunner(c, q, n, 2 * math.pi / n)
+                dt = _timed(lambda: r.step(1e-3), steps)
+                st = c.tc_get_stats()
+            res[name] = {"ms_per_step": dt * 1e3, "cell_updates_per_s": st["cell_updates"] / dt,
+                         "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"]}
+        out["euler_rk3_256"] = {"workload": "Taylor-Green vortex 256^3 FP64, one SSP-RK3 step of 4th-order central "
+                                            "differences (40 loops + energy sum)", "modes": res}
+        log(f"euler 256^3: {res}")
+    if "chain3d" in which:
+        from paper_1704_00693_amd.apps import ChainRunner
+        from synthgen import chain_3d, chain_data
+        ch = chain_3d()
+        data = chain_data(ch)
+        res = {}
+        with tc.Context(0) as c:
+            r = ChainRunner(c, ch, data)
+            del data
+            for name, m, tile in modes:
+                c.tc_set_tiling(m, tile)
+                dt = _timed(lambda: r.run(), steps)
+                st = c.tc_get_stats()
+                res[name] = {"ms_per_step": dt * 1e3, "cell_updates_per_s": st["cell_updates"] / dt,
+                             "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"]}
+        out["chain_384_3d"] = {"workload": "3D synthetic chain 384^3 FP64, 25 datasets, 60 loops of 7/13-point "
+                                           "stars + final sum, seed 2", "modes": res}
+        log(f"chain 384^3: {res}")
+    return out
+
+
 def cpu_baseline(ch_full, n_sample: int):
     """The oracle (single-threaded C, FP64) on the same chain over an
     n_sample^2 grid (a bounded sample of the workload)."""
@@ -294,6 +369,8 @@ def main():
                          "(0: automatic)")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="batched heat-conduction solves to run after the chain (0: skip)")
+    ap.add_argument("--other", default="tealeaf,euler",
+                    help="other workloads to time: comma list of tealeaf, euler, chain3d ('' to skip)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
                     help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -366,6 +443,7 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": None if tr is None else tr["hbm_bytes_per_flush"] / launches,
                 "kernel": kname, "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": alg}
+    others = other_workloads(tc, args.other.split(","), 10) if args.other else None
     batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
     served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None
     cpu = cpu_baseline(ch, args.cpu_sample) if args.cpu_sample > 0 else None
@@ -400,6 +478,7 @@ def main():
         "modes": results,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "other_workloads": others,
         "batched_solves": batched,
         "serving": served,
     }

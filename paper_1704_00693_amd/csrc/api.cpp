@@ -248,12 +248,33 @@ int canonical_star2(const Stencil &st) {
 }
 
 // Radius mask for the register-window weighted-sum kernel, or -1.
+// Radius of a 3D star stencil listed in the canonical order (centre, then
+// per axis x, y, z the offsets -1, +1[, -2, +2]), or -1.
+int canonical_star3(const Stencil &st) {
+    if (st.ndim != 3) return -1;
+    const int n = st.npoints();
+    if (n != 7 && n != 13) return -1;
+    const int r = n == 7 ? 1 : 2;
+    int q = 0;
+    if (st.pts[0] != 0 || st.pts[1] != 0 || st.pts[2] != 0) return -1;
+    ++q;
+    for (int ax = 0; ax < 3; ++ax)
+        for (int d = 1; d <= r; ++d)
+            for (int sgn : {-1, 1}) {
+                for (int k = 0; k < 3; ++k)
+                    if (st.pts[3 * q + k] != (k == ax ? sgn * d : 0)) return -1;
+                ++q;
+            }
+    return r;
+}
+
 int wsum_march_mask(const Ctx &c, const LoopRec &lp) {
-    if (lp.op != TC_OP_WSUM || lp.ndim != 2 || lp.args.size() > 5) return -1;
+    if (lp.op != TC_OP_WSUM || (lp.ndim != 2 && lp.ndim != 3) || lp.args.size() > 5) return -1;
     if (!c.stencils[lp.args[0].stencil].centre_only() || c.stencils[lp.args[0].stencil].npoints() != 1) return -1;
     int mask = 0;
     for (size_t a = 1; a < lp.args.size(); ++a) {
-        const int r = canonical_star2(c.stencils[lp.args[a].stencil]);
+        const Stencil &st = c.stencils[lp.args[a].stencil];
+        const int r = lp.ndim == 2 ? canonical_star2(st) : canonical_star3(st);
         if (r < 0) return -1;
         if (r == 2) mask |= 1 << (a - 1);
     }

@@ -137,6 +137,119 @@ __global__ void __launch_bounds__(kMarchW) wsum_march_kernel(LoopDesc d, int lo0
     }
 }
 
+// 3D: a workgroup covers 60 columns x 4 rows (one wavefront per row, lanes
+// as in the 2D march) and marches up z over `tz` planes.  Each lane keeps the
+// z window of its own column for every input in registers; x neighbours come
+// from adjacent lanes, y neighbours are loaded from the rows above and below
+// (the workgroup's four wavefronts read overlapping rows at the same plane,
+// so those loads hit the L1/L2 caches).
+template <typename T, int K, int MASK>
+__global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo0, int hi0, int lo1, int hi1, int lo2,
+                                                              int hi2, int nbx, int nby, int nb, int tz) {
+    constexpr int TB = kMarchBatch;
+    const int lin = xcd_linear(blockIdx.x, nb);
+    const int bx = lin % nbx, rest = lin / nbx, by = rest % nby, bz = rest / nby;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = lo0 + bx * kWaveOut - 2 + lane;
+    const int y = lo1 + by * 4 + wave;
+    const bool active = lane >= 2 && lane < 62 && x < hi0 && y < hi1;
+    const int z0 = lo2 + bz * tz;
+    const int z1 = min(z0 + tz, hi2);
+
+    const T *ptr[K];
+    int64_t sy[K], sz[K];
+    T win[K][TB + 4];
+    T pf[K][TB];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        const int r = (MASK >> a) & 1 ? 2 : 1;
+        // columns and rows outside the reach are clamped; no output uses them
+        const int xc = min(max(x, lo0 - r), hi0 - 1 + r);
+        const int yc = min(y, hi1 - 1);
+        sy[a] = d.arg[a + 1].sy;
+        sz[a] = d.arg[a + 1].sz;
+        ptr[a] = (const T *)d.arg[a + 1].ptr + xc + (int64_t)yc * sy[a];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j >= 2 - r && j < 2 + r) win[a][j] = ptr[a][(int64_t)(z0 - 2 + j) * sz[a]];
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+            if (z0 + r + t <= z1 - 1 + r) pf[a][t] = ptr[a][(int64_t)(z0 + r + t) * sz[a]];
+    }
+    T *out = (T *)d.arg[0].ptr + x + (int64_t)min(y, hi1 - 1) * d.arg[0].sy;
+    const int64_t osz = d.arg[0].sz;
+    for (int z = z0; z < z1; z += TB) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int r = (MASK >> a) & 1 ? 2 : 1;
+#pragma unroll
+            for (int t = 0; t < TB; ++t) win[a][2 + r + t] = pf[a][t];
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const int pl = z + TB + r + t;
+                if (pl <= z1 - 1 + r) pf[a][t] = ptr[a][(int64_t)pl * sz[a]];
+            }
+        }
+        // y neighbours of the batch's planes (rows y-2..y+2), all issued first
+        T yn[K][TB][4];
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int r = (MASK >> a) & 1 ? 2 : 1;
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const int pl = min(z + t, z1 - 1);
+                const T *row = ptr[a] + (int64_t)pl * sz[a];
+                yn[a][t][0] = row[-sy[a]];
+                yn[a][t][1] = row[sy[a]];
+                if (r == 2) {
+                    yn[a][t][2] = row[-2 * sy[a]];
+                    yn[a][t][3] = row[2 * sy[a]];
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            T acc = (T)0;
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const int r = (MASK >> a) & 1 ? 2 : 1;
+                const T c = win[a][2 + t];
+                const T xm1 = shfl_up(c, 1), xp1 = shfl_down(c, 1);
+                const int q = d.pt0[a + 1];
+                if (r == 1) {
+                    acc = fmaT<T>((T)d.prm[q + 0], c, acc);
+                    acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 2], xp1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 3], yn[a][t][0], acc);
+                    acc = fmaT<T>((T)d.prm[q + 4], yn[a][t][1], acc);
+                    acc = fmaT<T>((T)d.prm[q + 5], win[a][1 + t], acc);
+                    acc = fmaT<T>((T)d.prm[q + 6], win[a][3 + t], acc);
+                } else {
+                    const T xm2 = shfl_up(c, 2), xp2 = shfl_down(c, 2);
+                    acc = fmaT<T>((T)d.prm[q + 0], c, acc);
+                    acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 2], xp1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 3], xm2, acc);
+                    acc = fmaT<T>((T)d.prm[q + 4], xp2, acc);
+                    acc = fmaT<T>((T)d.prm[q + 5], yn[a][t][0], acc);
+                    acc = fmaT<T>((T)d.prm[q + 6], yn[a][t][1], acc);
+                    acc = fmaT<T>((T)d.prm[q + 7], yn[a][t][2], acc);
+                    acc = fmaT<T>((T)d.prm[q + 8], yn[a][t][3], acc);
+                    acc = fmaT<T>((T)d.prm[q + 9], win[a][1 + t], acc);
+                    acc = fmaT<T>((T)d.prm[q + 10], win[a][3 + t], acc);
+                    acc = fmaT<T>((T)d.prm[q + 11], win[a][t], acc);
+                    acc = fmaT<T>((T)d.prm[q + 12], win[a][4 + t], acc);
+                }
+            }
+            if (active && z + t < z1) out[(int64_t)(z + t) * osz] = acc;
+        }
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) win[a][j] = win[a][j + TB];
+    }
+}
+
 constexpr int kGenericMaxQ = 40;  // stencil points handled by the unrolled generic path
 
 template <typename T>
@@ -187,12 +300,29 @@ hipError_t go_march(const LoopDesc &d, const int lo[3], const int hi[3], int ty,
     return hipGetLastError();
 }
 
+template <typename T, int K, int MASK>
+hipError_t go_march3(const LoopDesc &d, const int lo[3], const int hi[3], hipStream_t s) {
+    constexpr int tz = 32;
+    const int nbx = (hi[0] - lo[0] + kWaveOut - 1) / kWaveOut;
+    const int nby = (hi[1] - lo[1] + 3) / 4;
+    const int nbz = (hi[2] - lo[2] + tz - 1) / tz;
+    const int nb = nbx * nby * nbz;
+    hipLaunchKernelGGL((wsum_march3_kernel<T, K, MASK>), dim3(nb), dim3(kMarchW), 0, s, d, lo[0], hi[0], lo[1], hi[1],
+                       lo[2], hi[2], nbx, nby, nb, tz);
+    return hipGetLastError();
+}
+
+template <typename T, int K, int MASK>
+hipError_t go_march_nd(const LoopDesc &d, const int lo[3], const int hi[3], int ty, hipStream_t s) {
+    return d.ndim == 3 ? go_march3<T, K, MASK>(d, lo, hi, s) : go_march<T, K, MASK>(d, lo, hi, ty, s);
+}
+
 template <typename T, int K>
 hipError_t march_k(const LoopDesc &d, int mask, const int lo[3], const int hi[3], int ty, hipStream_t s) {
     switch (mask) {
-#define M(m)                                                                     \
-    case m:                                                                      \
-        if constexpr ((m >> K) == 0) return go_march<T, K, m>(d, lo, hi, ty, s);  \
+#define M(m)                                                                        \
+    case m:                                                                         \
+        if constexpr ((m >> K) == 0) return go_march_nd<T, K, m>(d, lo, hi, ty, s);  \
         break;
         M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15)
 #undef M
@@ -203,7 +333,7 @@ hipError_t march_k(const LoopDesc &d, int mask, const int lo[3], const int hi[3]
 template <typename T>
 hipError_t wsum_t(const LoopDesc &d, const Box &b, int march_mask, int ty, hipStream_t s) {
     const int k = d.nargs - 1;
-    if (march_mask >= 0 && d.ndim == 2 && b.hi[2] - b.lo[2] == 1) {
+    if (march_mask >= 0 && ((d.ndim == 2 && b.hi[2] - b.lo[2] == 1) || d.ndim == 3)) {
         switch (k) {
         case 1: return march_k<T, 1>(d, march_mask, b.lo, b.hi, ty, s);
         case 2: return march_k<T, 2>(d, march_mask, b.lo, b.hi, ty, s);
