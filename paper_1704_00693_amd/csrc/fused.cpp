@@ -29,6 +29,9 @@ struct SplitParams {
     bool bake = false;
     int cpl = 1;       // columns per lane
     int wpe = 2;       // wavefronts per SIMD requested for the interior kernels (0: compiler's choice)
+    int max_window = 0; // longest register window of a loaded version before its readers split (0: never)
+    bool cse_steps = true;  // share shifted values between the loops of a step
+    bool sched_fence = false;  // keep the instruction scheduler from mixing the loops of a step
 };
 
 // ---------------------------------------------------------------------------
@@ -47,6 +50,8 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     G.baked = sp.bake;
     G.cpl = sp.cpl;
     G.wpe = sp.wpe;
+    G.cse_steps = sp.cse_steps;
+    G.sched_fence = sp.sched_fence;
     const LoopRec &f = chain[g0];
     if (f.op != TC_OP_WSUM || f.ndim != 2 || f.points() == 0) return false;
     G.xlo = f.lo[0];
@@ -154,6 +159,38 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
         G.vers[J.out].lag = lag;
     }
 
+    // load streams: a chain-start version read by loops far apart in lag
+    // would need a long register window; its readers are split into groups
+    // of nearby lags, each with a window (and loads) of its own -- the extra
+    // loads of the same rows are cheaper than the registers
+    if (sp.max_window > 0) {
+        const size_t nv0 = G.vers.size();
+        for (size_t v = 0; v < nv0; ++v) {
+            if (G.vers[v].producer >= 0 || !G.vers[v].needed) continue;
+            std::vector<std::pair<int, JRead *>> rd;
+            for (auto &J : G.loops)
+                if (J.needed)
+                    for (auto &R : J.in)
+                        if (R.ver == (int)v) rd.push_back({J.lag, &R});
+            std::sort(rd.begin(), rd.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+            int lo = INT_MAX, hi = INT_MIN, cur = (int)v;
+            for (auto &e : rd) {
+                const int l2 = std::min(lo, e.first - e.second->dymax), h2 = std::max(hi, e.first - e.second->dymin);
+                if (lo != INT_MAX && h2 - l2 + 1 > sp.max_window) {
+                    JVer nv = G.vers[v];
+                    G.vers.push_back(nv);
+                    cur = (int)G.vers.size() - 1;
+                    lo = e.first - e.second->dymax;
+                    hi = e.first - e.second->dymin;
+                } else {
+                    lo = l2;
+                    hi = h2;
+                }
+                e.second->ver = cur;
+            }
+        }
+    }
+
     // lanes: columns loaded left / right of the owned ones; computed extents
     int HL = 0, HR = 0, CL = 0, CR = 0, CB = 0, CT = 0;
     for (const auto &v : G.vers)
@@ -247,7 +284,9 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     if (G.var[0].regs > sp.regs) return false;
     // datasets loaded / stored, in kernel argument order
     for (size_t v = 0; v < G.vers.size(); ++v)
-        if (G.vers[v].producer < 0 && (G.var[0].loaded[v] || G.var[1].loaded[v])) G.src_dat.push_back(G.vers[v].dat);
+        if (G.vers[v].producer < 0 && (G.var[0].loaded[v] || G.var[1].loaded[v]) &&
+            std::find(G.src_dat.begin(), G.src_dat.end(), G.vers[v].dat) == G.src_dat.end())
+            G.src_dat.push_back(G.vers[v].dat);
     for (size_t v = 0; v < G.vers.size(); ++v)
         if (G.vers[v].stored) {
             G.dst_dat.push_back(G.vers[v].dat);
@@ -481,6 +520,8 @@ struct Gen {
         for (size_t j = 0; j < G.loops.size(); ++j) {
             const JLoop &J = G.loops[j];
             if (!J.needed) continue;
+            if (!G.cse_steps) sh.clear();  // shifted values are shared within one loop only
+            if (G.sched_fence) o << "      __builtin_amdgcn_sched_barrier(0);\n";
             std::vector<std::string> terms[2];
             for (int e = 0; e < cpl; ++e)
                 for (const auto &R : J.in)
@@ -660,6 +701,9 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
     sp.PF = std::max(1, c.jit_prefetch);
     sp.cpl = c.jit_cpl;
     sp.wpe = c.jit_wpe;
+    sp.max_window = c.jit_max_window;
+    sp.cse_steps = c.jit_cse_steps;
+    sp.sched_fence = c.jit_sched_fence;
     const int L = (int)chain.size();
     // best[j]: least modelled time of loops [0, j); from[j]: start of the last piece
     std::vector<double> best(L + 1, 1e300);

@@ -85,6 +85,8 @@ struct FusedGroup {
     JVariant var[2];  // 0 interior, 1 edge
     int cpl = 1;      // consecutive columns held by one lane (1 or 2); a wavefront holds 64 * cpl
     int wpe = 2;      // wavefronts per SIMD requested for the interior kernel
+    bool cse_steps = true;  // shifted values shared by all loops of a step (else per loop)
+    bool sched_fence = false;  // scheduling barrier between the loops of a step
     int HL = 0, HR = 0, Wo = 0;
     int BMAX = 0, TMAX = 0;  // rows below / above the owned rows that are read
     int Hseg = 0, U = 4, PF = 2;

@@ -229,6 +229,9 @@ struct Ctx {
     int jit_unroll = 4;      // steps per iteration of the generated march loop (TC_JIT_UNROLL)
     int jit_prefetch = 2;    // rows loaded ahead of their arrival step (TC_JIT_PREFETCH)
     int jit_wpe = 2;         // wavefronts per SIMD asked of the interior fused kernels (TC_JIT_WPE, 0: compiler's choice)
+    int jit_max_window = 0;  // split the readers of a loaded dataset above this window (TC_JIT_MAXWIN, 0: never)
+    bool jit_cse_steps = true;  // TC_JIT_CSE=0: shifted values recomputed per loop
+    bool jit_sched_fence = false;  // TC_JIT_FENCE=1: scheduling barrier between loops
     int jit_cpl = 1;         // consecutive columns per lane in fused kernels (TC_JIT_CPL: 1 or 2)
     bool jit_bake = true;    // compile the weights into the kernels (TC_JIT_BAKE=0: read them from arguments)
     double jit_compile_seconds = 0.0;
