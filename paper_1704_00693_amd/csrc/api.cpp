@@ -744,6 +744,7 @@ tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (const char *e = getenv("TC_JIT_MAXWIN")) c.jit_max_window = std::max(0, atoi(e));
     if (const char *e = getenv("TC_JIT_CSE")) c.jit_cse_steps = atoi(e) != 0;
     if (const char *e = getenv("TC_JIT_FENCE")) c.jit_sched_fence = atoi(e) != 0;
+    if (const char *e = getenv("TC_JIT_ALIGN")) c.jit_align_store = atoi(e) != 0;
     if (!c.host_only) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || n <= 0 || c.device < 0 || c.device >= n) {

@@ -32,6 +32,7 @@ struct SplitParams {
     int max_window = 0; // longest register window of a loaded version before its readers split (0: never)
     bool cse_steps = true;  // share shifted values between the loops of a step
     bool sched_fence = false;  // keep the instruction scheduler from mixing the loops of a step
+    bool align_store = false;  // owned strip width a multiple of 16 columns
 };
 
 // ---------------------------------------------------------------------------
@@ -216,6 +217,9 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     G.HR = HR;
     G.Wo = wcols - HL - HR;
     if (G.cpl == 2) G.Wo -= G.Wo & 1;
+    // whole 128-byte lines per stored row: owned strips start and end on
+    // multiples of 16 columns (the x origin of every dataset is 16-aligned)
+    if (sp.align_store && G.xlo % 16 == 0) G.Wo -= G.Wo % 16;
     if (G.Wo < 8) return false;
     G.BMAX = CB;
     G.TMAX = CT;
@@ -704,6 +708,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
     sp.max_window = c.jit_max_window;
     sp.cse_steps = c.jit_cse_steps;
     sp.sched_fence = c.jit_sched_fence;
+    sp.align_store = c.jit_align_store;
     const int L = (int)chain.size();
     // best[j]: least modelled time of loops [0, j); from[j]: start of the last piece
     std::vector<double> best(L + 1, 1e300);

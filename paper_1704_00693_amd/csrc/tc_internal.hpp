@@ -232,6 +232,7 @@ struct Ctx {
     int jit_max_window = 0;  // split the readers of a loaded dataset above this window (TC_JIT_MAXWIN, 0: never)
     bool jit_cse_steps = true;  // TC_JIT_CSE=0: shifted values recomputed per loop
     bool jit_sched_fence = false;  // TC_JIT_FENCE=1: scheduling barrier between loops
+    bool jit_align_store = true;   // TC_JIT_ALIGN=0: owned strips of any width (else whole 128-byte lines)
     int jit_cpl = 1;         // consecutive columns per lane in fused kernels (TC_JIT_CPL: 1 or 2)
     bool jit_bake = true;    // compile the weights into the kernels (TC_JIT_BAKE=0: read them from arguments)
     double jit_compile_seconds = 0.0;
