@@ -70,12 +70,12 @@ def traffic_entry(mode_name: str):
 WARM_SECONDS = 0.5  # the GPU's clocks ramp up under sustained load: warm every mode at least this long
 
 
-def time_mode(ctx, runner, mode, tile, steps, warmup, cells_per_step):
+def time_mode(ctx, runner, mode, tile, steps, warmup, cells_per_step, warm_seconds=WARM_SECONDS):
     import torch
     ctx.tc_set_tiling(mode, tile)
     t0 = time.perf_counter()
     k = 0
-    while k < warmup or time.perf_counter() - t0 < WARM_SECONDS:
+    while k < warmup or time.perf_counter() - t0 < warm_seconds:
         runner.record()
         ctx.tc_flush()
         k += 1
@@ -363,6 +363,8 @@ def main():
     ap.add_argument("--modes", default="none,skewed,fused",
                     help="comma list of none, skewed, fused; 'copy' alone runs the copy probe")
     ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--warm-seconds", type=float, default=WARM_SECONDS,
+                    help="least wall time each chain mode is warmed before timing (counter runs use 0)")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="grid edge of the oracle's timed sample (0: skip)")
     ap.add_argument("--fused-tile", default="0,0,0",
                     help="fused mode tile: rows per wavefront segment, window-register budget, most loops per group "
@@ -411,7 +413,7 @@ def main():
             log(f"mode {name}: warmup {args.warmup}, steps {args.steps}")
             try:
                 tile = tuple(int(v) for v in args.fused_tile.split(",")) if name == "fused" else (0, 0, 0)
-                results[name] = time_mode(ctx, runner, mode, tile, args.steps, args.warmup, cells)
+                results[name] = time_mode(ctx, runner, mode, tile, args.steps, args.warmup, cells, args.warm_seconds)
             except tc.TcError as e:
                 if e.status != tc.TC_ERR_UNSUPPORTED:
                     raise

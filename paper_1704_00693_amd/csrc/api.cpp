@@ -740,6 +740,7 @@ tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (const char *e = getenv("TC_JIT_PREFETCH")) c.jit_prefetch = std::min(8, std::max(1, atoi(e)));
     if (const char *e = getenv("TC_JIT_BAKE")) c.jit_bake = atoi(e) != 0;
     if (const char *e = getenv("TC_JIT_CPL")) c.jit_cpl = atoi(e) == 2 ? 2 : 1;
+    if (const char *e = getenv("TC_JIT_EDGE_DIV")) c.jit_edge_div = std::min(16, std::max(1, atoi(e)));
     if (const char *e = getenv("TC_JIT_WPE")) c.jit_wpe = std::min(8, std::max(0, atoi(e)));
     if (const char *e = getenv("TC_JIT_MAXWIN")) c.jit_max_window = std::max(0, atoi(e));
     if (const char *e = getenv("TC_JIT_CSE")) c.jit_cse_steps = atoi(e) != 0;

@@ -33,6 +33,7 @@ struct SplitParams {
     bool cse_steps = true;  // share shifted values between the loops of a step
     bool sched_fence = false;  // keep the instruction scheduler from mixing the loops of a step
     bool align_store = false;  // owned strip width a multiple of 16 columns
+    int edge_div = 4;  // edge wavefronts march Hseg / edge_div rows (1: as many as interior ones)
 };
 
 // ---------------------------------------------------------------------------
@@ -302,13 +303,19 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     const int width = G.xhi - G.xlo, height = G.yhi - G.ylo;
     G.nstrips = (width + G.Wo - 1) / G.Wo;
     int Hseg = sp.hseg;
+    const int ediv = std::max(1, sp.edge_div);
     if (Hseg <= 0) {
         const int target = 4096;  // wavefronts: 16 per compute unit
         const int nsegs = std::max(1, (int)std::lround((double)target / G.nstrips));
         Hseg = std::max(48, (height + nsegs - 1) / nsegs);
+        Hseg = (Hseg + ediv - 1) / ediv * ediv;
     }
     G.Hseg = std::min(Hseg, height);
     G.nsegs = (height + G.Hseg - 1) / G.Hseg;
+    // edge wavefronts are few and run at low occupancy, so each is latency
+    // bound: give them shorter segments (whole fractions of Hseg, so the
+    // frame's rows line up with the interior segments)
+    G.Hedge = G.Hseg % ediv == 0 && G.Hseg / ediv >= 8 ? G.Hseg / ediv : G.Hseg;
     // interior rectangle: strip i computes columns [i Wo - CL, (i + 1) Wo + CR)
     // of the range, segment k rows [k Hseg - CB, (k + 1) Hseg + CT); both
     // must stay inside it
@@ -344,7 +351,16 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
         G.si0 = G.si1 = G.gi0 = G.gi1 = 0;
     }
     G.nwaves_in = (G.si1 - G.si0) * (G.gi1 - G.gi0);
-    G.nwaves_edge = G.nstrips * G.nsegs - G.nwaves_in;
+    // the frame around the interior rectangle in edge segments: bottom rows,
+    // top rows, then the side strips of the interior segments' rows
+    {
+        const int d = G.Hseg / G.Hedge;
+        G.ne_bottom = G.gi0 * d * G.nstrips;
+        G.ne_top = (height - G.gi1 * G.Hseg + G.Hedge - 1) / G.Hedge * G.nstrips;
+        G.ne_side_strips = G.si0 + (G.nstrips - G.si1);
+        const int side = G.nwaves_in > 0 ? G.ne_side_strips * (G.gi1 - G.gi0) * d : 0;
+        G.nwaves_edge = G.ne_bottom + G.ne_top + side;
+    }
     G.nblocks = (G.nwaves_in + 3) / 4 + (G.nwaves_edge + 3) / 4;
 
     // modelled time (split choice): HBM bytes of the loads and stores
@@ -605,8 +621,9 @@ struct Gen {
                 o << "  const bool inx" << e << " = (col" << e << " >= " << G.xlo << ") & (col" << e << " < " << G.xhi
                   << ");\n";
         }
-        o << "  const int yend = min(Y0 + " << G.Hseg << ", " << G.yhi << ");\n";
-        const int nsteps = G.Hseg + V.pre + V.post;
+        const int H = var == 0 ? G.Hseg : G.Hedge;
+        o << "  const int yend = min(Y0 + " << H << ", " << G.yhi << ");\n";
+        const int nsteps = H + V.pre + V.post;
         const int nit = (nsteps + G.U - 1) / G.U;
         o << "  int t = Y0 - " << V.pre << ";\n";
         if (var == 1)
@@ -663,25 +680,71 @@ void gen_group(const Ctx &c, FusedGroup &G, int gi, std::ostringstream &o) {
             o << "  if (wid >= " << G.nwaves_in << ") return;\n";
             o << "  const int strip = " << G.si0 << " + wid % " << nsi << ", seg = " << G.gi0 << " + wid / " << nsi
               << ";\n";
+            o << "  const int X0 = __builtin_amdgcn_readfirstlane(" << G.xlo << " + strip * " << G.Wo
+              << "), Y0 = __builtin_amdgcn_readfirstlane(" << G.ylo << " + seg * " << G.Hseg << ");\n";
         } else {
-            // the frame around the interior rectangle: bottom segments, top
-            // segments, then the side strips of the middle segments
-            const int nb = G.gi0 * ns, nt = (G.nsegs - G.gi1) * ns, side = G.si0 + (ns - G.si1);
+            // the frame around the interior rectangle in segments of Hedge
+            // rows: bottom rows, top rows, then the side strips of the
+            // interior segments' rows
+            const int nb = G.ne_bottom, nt = G.ne_top, side = std::max(1, G.ne_side_strips);
             o << "  if (wid >= " << G.nwaves_edge << ") return;\n";
-            o << "  int strip, seg;\n";
-            o << "  if (wid < " << nb << ") { seg = wid / " << ns << "; strip = wid % " << ns << "; }\n";
-            o << "  else if (wid < " << nb + nt << ") { const int w = wid - " << nb << "; seg = " << G.gi1
-              << " + w / " << ns << "; strip = w % " << ns << "; }\n";
-            o << "  else { const int w = wid - " << nb + nt << "; seg = " << G.gi0 << " + w / " << std::max(1, side)
-              << "; const int k = w % " << std::max(1, side) << "; strip = k < " << G.si0 << " ? k : " << G.si1
-              << " + (k - " << G.si0 << "); }\n";
+            o << "  int strip, row;\n";
+            o << "  if (wid < " << nb << ") { row = (wid / " << ns << ") * " << G.Hedge << "; strip = wid % " << ns
+              << "; }\n";
+            o << "  else if (wid < " << nb + nt << ") { const int w = wid - " << nb << "; row = " << G.gi1 * G.Hseg
+              << " + (w / " << ns << ") * " << G.Hedge << "; strip = w % " << ns << "; }\n";
+            o << "  else { const int w = wid - " << nb + nt << "; row = " << G.gi0 * G.Hseg << " + (w / " << side
+              << ") * " << G.Hedge << "; const int k = w % " << side << "; strip = k < " << G.si0 << " ? k : "
+              << G.si1 << " + (k - " << G.si0 << "); }\n";
+            o << "  const int X0 = __builtin_amdgcn_readfirstlane(" << G.xlo << " + strip * " << G.Wo
+              << "), Y0 = __builtin_amdgcn_readfirstlane(" << G.ylo << " + row);\n";
         }
-        o << "  const int X0 = __builtin_amdgcn_readfirstlane(" << G.xlo << " + strip * " << G.Wo
-          << "), Y0 = __builtin_amdgcn_readfirstlane(" << G.ylo << " + seg * " << G.Hseg << ");\n";
         g.body();
         o << g.o.str();
         o << "}\n";
     }
+}
+
+// Every (strip, row) of the group's range must belong to exactly one
+// wavefront: the interior rectangle's waves plus the frame's edge waves, laid
+// out as the generated kernels lay them out.
+bool layout_covers_once(const FusedGroup &G) {
+    const int height = G.yhi - G.ylo, ns = G.nstrips;
+    if (G.Hedge <= 0 || G.Hseg % G.Hedge != 0) return false;
+    std::vector<int> d((size_t)ns * (height + 1), 0);
+    auto add = [&](int strip, int row, int h) {
+        if (strip < 0 || strip >= ns || row < 0 || row >= height) return false;
+        d[(size_t)strip * (height + 1) + row] += 1;
+        d[(size_t)strip * (height + 1) + std::min(row + h, height)] -= 1;
+        return true;
+    };
+    const int nsi = G.si1 - G.si0;
+    for (int w = 0; w < G.nwaves_in; ++w)
+        if (!add(G.si0 + w % nsi, (G.gi0 + w / nsi) * G.Hseg, G.Hseg)) return false;
+    const int side = std::max(1, G.ne_side_strips);
+    for (int w = 0; w < G.nwaves_edge; ++w) {
+        int strip, row;
+        if (w < G.ne_bottom) {
+            row = (w / ns) * G.Hedge;
+            strip = w % ns;
+        } else if (w < G.ne_bottom + G.ne_top) {
+            row = G.gi1 * G.Hseg + ((w - G.ne_bottom) / ns) * G.Hedge;
+            strip = (w - G.ne_bottom) % ns;
+        } else {
+            const int k = (w - G.ne_bottom - G.ne_top) % side;
+            row = G.gi0 * G.Hseg + ((w - G.ne_bottom - G.ne_top) / side) * G.Hedge;
+            strip = k < G.si0 ? k : G.si1 + (k - G.si0);
+        }
+        if (!add(strip, row, G.Hedge)) return false;
+    }
+    for (int s = 0; s < ns; ++s) {
+        int cover = 0;
+        for (int r = 0; r < height; ++r) {
+            cover += d[(size_t)s * (height + 1) + r];
+            if (cover != 1) return false;
+        }
+    }
+    return true;
 }
 
 uint64_t fnv1a(const std::string &s) {
@@ -709,6 +772,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
     sp.cse_steps = c.jit_cse_steps;
     sp.sched_fence = c.jit_sched_fence;
     sp.align_store = c.jit_align_store;
+    sp.edge_div = c.jit_edge_div;
     const int L = (int)chain.size();
     // best[j]: least modelled time of loops [0, j); from[j]: start of the last piece
     std::vector<double> best(L + 1, 1e300);
@@ -744,9 +808,9 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
             for (char x : g->var[0].loaded) nld += x;
             std::fprintf(stderr,
                          "fused group [%d,%d): %d loops, HL %d HR %d Wo %d, loads %d stores %d, regs %d/%d, "
-                         "pre %d post %d, Hseg %d, strips %d segs %d, waves %d+%d, cost %.1f us\n",
+                         "pre %d post %d, Hseg %d Hedge %d, strips %d segs %d, waves %d+%d, cost %.1f us\n",
                          g->g0, g->g1, nl, g->HL, g->HR, g->Wo, nld, (int)g->dst_dat.size(), g->var[0].regs,
-                         g->var[1].regs, g->var[0].pre, g->var[0].post, g->Hseg, g->nstrips, g->nsegs, g->nwaves_in,
+                         g->var[1].regs, g->var[0].pre, g->var[0].post, g->Hseg, g->Hedge, g->nstrips, g->nsegs, g->nwaves_in,
                          g->nwaves_edge, g->cost * 1e6);
         }
     return out;
@@ -754,6 +818,10 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
 
 tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups) {
     if (groups.empty()) return TC_OK;
+    for (const auto &g : groups)
+        if (!layout_covers_once(*g))
+            return fail(c, TC_ERR_STATE, "fused group [%d,%d): wavefront layout does not cover its range once", g->g0,
+                        g->g1);
     std::ostringstream src;
     src << kPrelude;
     for (size_t gi = 0; gi < groups.size(); ++gi) gen_group(c, *groups[gi], (int)gi, src);

@@ -93,6 +93,8 @@ struct FusedGroup {
     int nstrips = 0, nsegs = 0;
     int si0 = 0, si1 = 0, gi0 = 0, gi1 = 0;  // interior rectangle of strips x segments
     int nwaves_in = 0, nwaves_edge = 0;
+    int Hedge = 0;  // rows per edge wavefront (a whole fraction of Hseg)
+    int ne_bottom = 0, ne_top = 0, ne_side_strips = 0;  // edge wavefronts below / above the interior rectangle; side strips
     int nblocks = 0;
     std::vector<int> src_dat;   // datasets loaded (kernel argument order)
     std::vector<int> dst_dat;   // datasets stored

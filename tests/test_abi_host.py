@@ -136,3 +136,19 @@ def test_fused_groups_generate_and_compile_host_only():
             assert g0 >= last and g1 - g0 >= 2
             last = g1
     assert all(g1 - g0 <= 3 for g0, g1 in small)
+
+
+@pytest.mark.parametrize("n", [9, 77, 333])
+@pytest.mark.parametrize("hseg", [0, 20, 33])
+def test_fused_layout_covers_range_once(n, hseg):
+    """Interior wavefronts (segments of hseg rows) plus edge wavefronts
+    (shorter segments around the interior rectangle) own every cell of each
+    group's range exactly once; the library checks this before generating a
+    group's kernels and refuses the plan otherwise."""
+    from paper_1704_00693_amd.apps import ChainRunner
+    from synthgen import chain_2d
+    ch = chain_2d(n=n)
+    with tc.Context(host_only=True) as c:
+        r = ChainRunner(c, ch, None)
+        r.record()
+        assert c.tc_fused_groups((hseg, 0, 0))
