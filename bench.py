@@ -113,7 +113,7 @@ def time_mode(ctx, runner, mode, tile, steps, warmup, cells_per_step, warm_secon
     }
 
 
-def copy_probe(tc, n: int, steps: int, warmup: int):
+def copy_probe(tc, n: int, steps: int, warmup: int, reference: bool = True):
     """A plain copy of one n^2 FP64 dataset into another (the library's COPY
     loop): the counter calibration kernel and the achievable-bandwidth probe."""
     import torch
@@ -139,7 +139,30 @@ def copy_probe(tc, n: int, steps: int, warmup: int):
         c.tc_set_profiling(False)
     alg = 2 * n * n * 8
     return {"alg_bytes_per_launch": alg, "launches": steps + warmup, "avg_launch_us": tot / steps * 1e6,
-            "GBps": alg * steps / tot / 1e9}
+            "GBps": alg * steps / tot / 1e9, "reference_copy_GBps": reference_copy_GBps() if reference else None}
+
+
+def reference_copy_GBps(nbytes: int = 1 << 31, reps: int = 20) -> float:
+    """Device-to-device copy of a 2 GiB buffer by the runtime's own copy
+    kernel (torch's ``copy_``), warmed for 0.5 s: the bandwidth a copy reaches
+    on this part, as a reference for the library's kernels."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.5:
+        b.copy_(a)
+        torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
 
 
 def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8):
@@ -397,8 +420,8 @@ def main():
     if args.modes == "copy":
         print(json.dumps(copy_probe(tc, args.n, args.steps, args.warmup)))
         return
-    copy = copy_probe(tc, args.n, 10, 2)
-    log(f"copy probe: {copy['GBps']:.0f} GB/s")
+    copy = copy_probe(tc, args.n, 10, 2, reference=args.warm_seconds > 0)
+    log(f"copy probe: {copy['GBps']:.0f} GB/s (runtime's copy of 2 GiB: {copy['reference_copy_GBps']} GB/s)")
     ch = chain_2d(n=args.n)
     log(f"generating inputs: {ch.ndat} x {ch.n + 4}^2 FP64")
     data = chain_data(ch)
@@ -477,6 +500,7 @@ def main():
         "hbm_byte_ratio_untiled_over_tiled": (None if tr is None or tr_none is None
                                               else tr_none["hbm_bytes_per_flush"] / tr["hbm_bytes_per_flush"]),
         "copy_probe_GBps": copy["GBps"],
+        "reference_copy_GBps": copy["reference_copy_GBps"],
         "modes": results,
         "roofline": roofline,
         "cpu_baseline": cpu,
