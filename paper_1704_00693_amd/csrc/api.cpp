@@ -268,7 +268,8 @@ int canonical_star3(const Stencil &st) {
     return r;
 }
 
-int wsum_march_mask(const Ctx &c, const LoopRec &lp) {
+int march_mask_of(const Ctx &c, const LoopRec &lp) {
+    if (lp.op == TC_OP_EULER_RHS) return lp.ndim == 3 ? 0 : -1;  // the z-marching 3D kernel
     if (lp.op != TC_OP_WSUM || (lp.ndim != 2 && lp.ndim != 3) || lp.args.size() > 5) return -1;
     if (!c.stencils[lp.args[0].stencil].centre_only() || c.stencils[lp.args[0].stencil].npoints() != 1) return -1;
     int mask = 0;
@@ -448,7 +449,7 @@ tc_status run_per_loop_graph(Ctx &c, const std::vector<LoopRec> &chain, CachedPl
     std::vector<int> march(chain.size());
     for (size_t l = 0; l < chain.size(); ++l) {
         build_desc(c, chain[l], descs[l]);
-        march[l] = c.march_enabled ? wsum_march_mask(c, chain[l]) : -1;
+        march[l] = c.march_enabled ? march_mask_of(c, chain[l]) : -1;
     }
     struct Item {
         LoopDesc d;
@@ -523,7 +524,7 @@ tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, CachedPlan &P)
     std::vector<LoopDesc> descs(chain.size());
     std::vector<char> built(chain.size(), 0);
     std::vector<int> march(chain.size());
-    for (size_t l = 0; l < chain.size(); ++l) march[l] = c.march_enabled ? wsum_march_mask(c, chain[l]) : -1;
+    for (size_t l = 0; l < chain.size(); ++l) march[l] = c.march_enabled ? march_mask_of(c, chain[l]) : -1;
     if (c.profiling) {
         tc_status st = ensure_events(c, 2 * P.steps.size());
         if (st != TC_OK) return st;

@@ -26,6 +26,8 @@ hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, 
 
 // Weighted-sum kernels (wsum.hip).
 hipError_t launch_wsum(const LoopDesc &d, const Box &b, int dtype, int march_mask, int march_ty, hipStream_t s);
+// 3D EULER_RHS marching up z (same arithmetic as the per-point kernel)
+hipError_t launch_euler_rhs3(const LoopDesc &d, const Box &b, int dtype, hipStream_t s);
 
 // Combine `count` (hi, lo) partials into out[0..1] with one workgroup.
 hipError_t launch_finalize(const double *part, int64_t count, int op, double *out, hipStream_t s);

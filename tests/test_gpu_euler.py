@@ -48,7 +48,7 @@ def state_2d(n, h):
     return [np.ascontiguousarray(a) for a in (rho, rho * u, rho * v, E)]
 
 
-@pytest.mark.parametrize("ndim,n", [(3, 20), (2, 37)])
+@pytest.mark.parametrize("ndim,n", [(3, 20), (3, 67), (2, 37)])
 def test_rk3_step_small(tc, ndim, n):
     from paper_1704_00693_amd.apps import EulerRunner
     h = 2 * math.pi / n
@@ -72,6 +72,26 @@ def test_rk3_step_small(tc, ndim, n):
         assert abs(esum - math.fsum(e.ravel().tolist())) <= 1e-15 * float(np.abs(e).sum())
         outs[mode] = got
     for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_rhs_march_kernel_equals_per_point_kernel(tc, monkeypatch):
+    """The z-marching 3D right-hand-side kernel and the per-point loop kernel
+    (selected with TC_WSUM_MARCH=0 at context creation) give the same bits on
+    a ragged grid: two x blocks, a partial row block and three z blocks."""
+    from paper_1704_00693_amd.apps import EulerRunner
+    n = 67
+    h = 2 * math.pi / n
+    q = taylor_green(n)
+    outs = []
+    for march in ("1", "0"):
+        monkeypatch.setenv("TC_WSUM_MARCH", march)
+        say(f"euler rhs n={n} march={march}")
+        with tc.Context() as c:
+            r = EulerRunner(c, q, n, h)
+            r.step(1e-3)
+            outs.append([c.tc_dat_read(d) for d in r.Q + r.R])
+    for a, b in zip(*outs):
         assert np.array_equal(a, b)
 
 
