@@ -230,6 +230,7 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     for (int var = 0; var < 2; ++var) {
         JVariant &V = G.var[var];
         const size_t nv = G.vers.size();
+        V.PF = sp.PF;
         V.win.assign(nv, 0);
         V.load_lag.assign(nv, 0);
         V.loaded.assign(nv, 0);
@@ -270,7 +271,7 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
                 V.loaded[v] = 1;
                 V.load_lag[v] = lo[v];
                 V.win[v] = hi[v] - lo[v] + 1;
-                regs += (V.win[v] + G.PF) * words * G.cpl;
+                regs += (V.win[v] + V.PF) * words * G.cpl;
                 const int b = std::max(X.needed ? X.extB : -1, eb[v]);
                 const int t = std::max(X.needed ? X.extT : -1, et[v]);
                 pre = std::max(pre, b - lo[v]);
@@ -312,54 +313,61 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     }
     G.Hseg = std::min(Hseg, height);
     G.nsegs = (height + G.Hseg - 1) / G.Hseg;
-    // edge wavefronts are few and run at low occupancy, so each is latency
-    // bound: give them shorter segments (whole fractions of Hseg, so the
-    // frame's rows line up with the interior segments)
-    G.Hedge = G.Hseg % ediv == 0 && G.Hseg / ediv >= 8 ? G.Hseg / ediv : G.Hseg;
-    // interior rectangle: strip i computes columns [i Wo - CL, (i + 1) Wo + CR)
-    // of the range, segment k rows [k Hseg - CB, (k + 1) Hseg + CT); both
-    // must stay inside it
-    auto cdiv = [](int a, int b) { return a <= 0 ? 0 : (a + b - 1) / b; };
-    auto fdiv = [](int a, int b) { return a < 0 ? -((-a + b - 1) / b) : a / b; };
-    int si0 = cdiv(CL, G.Wo), si1 = fdiv(width - CR, G.Wo);
-    int gi0 = cdiv(CB, G.Hseg), gi1 = fdiv(height - CT, G.Hseg);
+    // edge wavefronts are few and run at low occupancy: give them shorter
+    // segments
+    G.Hedge = std::max(8, G.Hseg / ediv);
+    // Interior waves run without bounds logic.  Strip origin X0 = xlo + rx
+    // computes columns [X0 - CL, X0 + Wo + CR) and segment origin Y0 = ylo + ry
+    // rows [Y0 - CB, Y0 + Hseg + CT): both inside the range.  Every lane
+    // column and every row they load must lie inside the allocation.  That
+    // bounds rx to [LX, UX] and ry to [LY, UY]; the interior grid starts at a
+    // feasible origin and the frame around it goes to edge waves.
+    int LX = CL, UX = width - CR - G.Wo, LY = CB, UY = height - CT - G.Hseg;
     {
-        // the interior kernel reads without clamping: every lane column and
-        // every row it loads must lie inside the allocation
         const JVariant &V = G.var[0];
         const int nsteps = (G.Hseg + V.pre + V.post + G.U - 1) / G.U * G.U;
         for (size_t v = 0; v < G.vers.size(); ++v) {
             if (!V.loaded[v]) continue;
             const Dataset &ds = c.dats[G.vers[v].dat];
-            // columns X0 - HL + [0, 64) with X0 = xlo + i Wo
-            si0 = std::max(si0, cdiv(-ds.hneg[0] - G.xlo + HL, G.Wo));
-            si1 = std::min(si1, fdiv(ds.size[0] + ds.hpos[0] - wcols - G.xlo + HL, G.Wo) + 1);
-            // rows Y0 - pre - lag .. Y0 - pre + nsteps - 1 + PF - lag with Y0 = ylo + k Hseg
-            gi0 = std::max(gi0, cdiv(-ds.hneg[1] - G.ylo + V.pre + V.load_lag[v], G.Hseg));
-            gi1 = std::min(gi1, fdiv(ds.size[1] + ds.hpos[1] - 1 - G.ylo + V.pre - nsteps + 1 - G.PF +
-                                         V.load_lag[v], G.Hseg) + 1);
+            // columns X0 - HL + [0, wcols)
+            LX = std::max(LX, -ds.hneg[0] - G.xlo + HL);
+            UX = std::min(UX, ds.size[0] + ds.hpos[0] - wcols - G.xlo + HL);
+            // rows Y0 - pre - lag .. Y0 - pre + nsteps - 1 + PF - lag
+            LY = std::max(LY, -ds.hneg[1] - G.ylo + V.pre + V.load_lag[v]);
+            UY = std::min(UY, ds.size[1] + ds.hpos[1] - 1 - G.ylo + V.pre - nsteps + 1 - V.PF + V.load_lag[v]);
         }
-        si1 = std::min(si1, G.nstrips);
-        gi1 = std::min(gi1, G.nsegs);
     }
-    if (si1 > si0 && gi1 > gi0) {
-        G.si0 = si0;
-        G.si1 = si1;
-        G.gi0 = gi0;
-        G.gi1 = gi1;
+    // owned strips stay on 128-byte lines when the strip width is a multiple of 16
+    if (sp.align_store && G.xlo % 16 == 0 && G.Wo % 16 == 0) LX = (LX + 15) / 16 * 16;
+    G.in_ns = UX >= LX ? (UX - LX) / G.Wo + 1 : 0;
+    G.in_ng = UY >= LY ? (UY - LY) / G.Hseg + 1 : 0;
+    if (G.in_ns == 0 || G.in_ng == 0) G.in_ns = G.in_ng = 0;
+    if (G.in_ns > 0) {
+        // centre the grid in its slack (whole 16-column steps when aligned)
+        const int sx = UX - LX - (G.in_ns - 1) * G.Wo, sy = UY - LY - (G.in_ng - 1) * G.Hseg;
+        const int step = sp.align_store && G.xlo % 16 == 0 && G.Wo % 16 == 0 ? 16 : 1;
+        G.in_x = LX + sx / 2 / step * step;
+        G.in_y = LY + sy / 2;
+        G.e_yb = G.in_y;
+        G.e_yt = G.in_y + G.in_ng * G.Hseg;
+        G.e_xr = G.in_x + G.in_ns * G.Wo;
     } else {
-        G.si0 = G.si1 = G.gi0 = G.gi1 = 0;
+        G.in_x = G.in_y = 0;
+        G.e_yb = height;  // everything is the bottom band
+        G.e_yt = height;
+        G.e_xr = width;
     }
-    G.nwaves_in = (G.si1 - G.si0) * (G.gi1 - G.gi0);
-    // the frame around the interior rectangle in edge segments: bottom rows,
-    // top rows, then the side strips of the interior segments' rows
+    G.nwaves_in = G.in_ns * G.in_ng;
     {
-        const int d = G.Hseg / G.Hedge;
-        G.ne_bottom = G.gi0 * d * G.nstrips;
-        G.ne_top = (height - G.gi1 * G.Hseg + G.Hedge - 1) / G.Hedge * G.nstrips;
-        G.ne_side_strips = G.si0 + (G.nstrips - G.si1);
-        const int side = G.nwaves_in > 0 ? G.ne_side_strips * (G.gi1 - G.gi0) * d : 0;
-        G.nwaves_edge = G.ne_bottom + G.ne_top + side;
+        auto cd = [](int a, int b) { return a <= 0 ? 0 : (a + b - 1) / b; };
+        G.e_ns = cd(width, G.Wo);
+        G.e_ngb = cd(G.e_yb, G.Hedge);
+        G.e_ngt = cd(height - G.e_yt, G.Hedge);
+        const bool mid = G.nwaves_in > 0;
+        G.e_nsl = mid ? cd(G.in_x, G.Wo) : 0;
+        G.e_nsr = mid ? cd(width - G.e_xr, G.Wo) : 0;
+        G.e_ngm = mid ? cd(G.e_yt - G.in_y, G.Hedge) : 0;
+        G.nwaves_edge = G.e_ns * (G.e_ngb + G.e_ngt) + (G.e_nsl + G.e_nsr) * G.e_ngm;
     }
     G.nblocks = (G.nwaves_in + 3) / 4 + (G.nwaves_edge + 3) / 4;
 
@@ -535,7 +543,7 @@ struct Gen {
         o << "    {\n      const int tt = " << tt << ";\n";
         // rows arriving PF steps ahead
         for (size_t v = 0; v < G.vers.size(); ++v)
-            if (V.loaded[v]) load_row((int)v, "(tt + " + std::to_string(G.PF) + ")", V.win[v] + G.PF - 1, "      ");
+            if (V.loaded[v]) load_row((int)v, "(tt + " + std::to_string(V.PF) + ")", V.win[v] + V.PF - 1, "      ");
         // loops in chain order
         for (size_t j = 0; j < G.loops.size(); ++j) {
             const JLoop &J = G.loops[j];
@@ -602,7 +610,7 @@ struct Gen {
         // advance the windows by one row
         for (size_t v = 0; v < G.vers.size(); ++v) {
             if (!V.win[v]) continue;
-            const int n = V.win[v] + (V.loaded[v] ? G.PF : 0);
+            const int n = V.win[v] + (V.loaded[v] ? V.PF : 0);
             for (int e = 0; e < cpl; ++e)
                 for (int k = 0; k + 1 < n; ++k) o << "      " << entry((int)v, e, k) << " = " << entry((int)v, e, k + 1) << ";\n";
         }
@@ -615,14 +623,20 @@ struct Gen {
         o << "  const int lane = threadIdx.x & 63;\n";
         for (int e = 0; e < cpl; ++e) {
             o << "  const int col" << e << " = X0 - " << G.HL << " + " << cpl << " * lane + " << e << ";\n";
-            o << "  const bool own" << e << " = (col" << e << " >= X0) & (col" << e << " < X0 + " << G.Wo << ") & (col"
-              << e << " < " << G.xhi << ");\n";
+            if (var == 0)
+                o << "  const bool own" << e << " = (col" << e << " >= X0) & (col" << e << " < X0 + " << G.Wo
+                  << ");\n";
+            else
+                o << "  const bool own" << e << " = (col" << e << " >= X0) & (col" << e << " < XE);\n";
             if (var == 1)
                 o << "  const bool inx" << e << " = (col" << e << " >= " << G.xlo << ") & (col" << e << " < " << G.xhi
                   << ");\n";
         }
         const int H = var == 0 ? G.Hseg : G.Hedge;
-        o << "  const int yend = min(Y0 + " << H << ", " << G.yhi << ");\n";
+        if (var == 0)
+            o << "  const int yend = Y0 + " << H << ";\n";
+        else
+            o << "  const int yend = YE;\n";
         const int nsteps = H + V.pre + V.post;
         const int nit = (nsteps + G.U - 1) / G.U;
         o << "  int t = Y0 - " << V.pre << ";\n";
@@ -645,10 +659,10 @@ struct Gen {
         for (size_t v = 0; v < G.vers.size(); ++v) {
             if (!V.win[v]) continue;
             for (int e = 0; e < cpl; ++e)
-                o << "  " << T << " " << W((int)v, e) << "[" << (V.win[v] + (V.loaded[v] ? G.PF : 0)) << "];\n";
+                o << "  " << T << " " << W((int)v, e) << "[" << (V.win[v] + (V.loaded[v] ? V.PF : 0)) << "];\n";
         }
         // prologue: rows arriving at the first PF steps
-        for (int k = 0; k < G.PF; ++k)
+        for (int k = 0; k < V.PF; ++k)
             for (size_t v = 0; v < G.vers.size(); ++v)
                 if (V.loaded[v]) load_row((int)v, "(t + " + std::to_string(k) + ")", V.win[v] - 1 + k, "  ");
         o << "  for (int it = 0; it < " << nit << "; ++it, t += " << G.U << ") {\n";
@@ -674,30 +688,37 @@ void gen_group(const Ctx &c, FusedGroup &G, int gi, std::ostringstream &o) {
         if (var == 0 && G.wpe > 0) o << "__attribute__((amdgpu_waves_per_eu(" << G.wpe << ", " << G.wpe << "))) ";
         o << (var == 0 ? G.kname_in : G.kname_edge) << "(" << S << " a) {\n";
         o << "  const int wid = tcj_lin(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n";
-        const int ns = G.nstrips;
         if (var == 0) {
-            const int nsi = G.si1 - G.si0;
+            const int nsi = G.in_ns;
             o << "  if (wid >= " << G.nwaves_in << ") return;\n";
-            o << "  const int strip = " << G.si0 << " + wid % " << nsi << ", seg = " << G.gi0 << " + wid / " << nsi
-              << ";\n";
-            o << "  const int X0 = __builtin_amdgcn_readfirstlane(" << G.xlo << " + strip * " << G.Wo
-              << "), Y0 = __builtin_amdgcn_readfirstlane(" << G.ylo << " + seg * " << G.Hseg << ");\n";
+            o << "  const int strip = wid % " << nsi << ", seg = wid / " << nsi << ";\n";
+            o << "  const int X0 = __builtin_amdgcn_readfirstlane(" << G.xlo + G.in_x << " + strip * " << G.Wo
+              << "), Y0 = __builtin_amdgcn_readfirstlane(" << G.ylo + G.in_y << " + seg * " << G.Hseg << ");\n";
         } else {
-            // the frame around the interior rectangle in segments of Hedge
-            // rows: bottom rows, top rows, then the side strips of the
-            // interior segments' rows
-            const int nb = G.ne_bottom, nt = G.ne_top, side = std::max(1, G.ne_side_strips);
+            // the frame around the interior grid: bottom band, top band (both
+            // across the whole width), then the left and right bands of the
+            // interior rows; owned columns [X0, XE), rows [Y0, YE)
+            const int W = G.xhi - G.xlo, Hh = G.yhi - G.ylo, He = G.Hedge;
+            const int nB = G.e_ns * G.e_ngb, nT = G.e_ns * G.e_ngt, nL = G.e_nsl * G.e_ngm;
+            const int nsl = std::max(1, G.e_nsl), nsr = std::max(1, G.e_nsr);
             o << "  if (wid >= " << G.nwaves_edge << ") return;\n";
-            o << "  int strip, row;\n";
-            o << "  if (wid < " << nb << ") { row = (wid / " << ns << ") * " << G.Hedge << "; strip = wid % " << ns
-              << "; }\n";
-            o << "  else if (wid < " << nb + nt << ") { const int w = wid - " << nb << "; row = " << G.gi1 * G.Hseg
-              << " + (w / " << ns << ") * " << G.Hedge << "; strip = w % " << ns << "; }\n";
-            o << "  else { const int w = wid - " << nb + nt << "; row = " << G.gi0 * G.Hseg << " + (w / " << side
-              << ") * " << G.Hedge << "; const int k = w % " << side << "; strip = k < " << G.si0 << " ? k : "
-              << G.si1 << " + (k - " << G.si0 << "); }\n";
-            o << "  const int X0 = __builtin_amdgcn_readfirstlane(" << G.xlo << " + strip * " << G.Wo
-              << "), Y0 = __builtin_amdgcn_readfirstlane(" << G.ylo << " + row);\n";
+            o << "  int xr, xe, yr, ye;\n";
+            o << "  if (wid < " << nB << ") { xr = (wid % " << G.e_ns << ") * " << G.Wo << "; xe = min(xr + " << G.Wo
+              << ", " << W << "); yr = (wid / " << G.e_ns << ") * " << He << "; ye = min(yr + " << He << ", "
+              << G.e_yb << "); }\n";
+            o << "  else if (wid < " << nB + nT << ") { const int w = wid - " << nB << "; xr = (w % " << G.e_ns
+              << ") * " << G.Wo << "; xe = min(xr + " << G.Wo << ", " << W << "); yr = " << G.e_yt << " + (w / "
+              << G.e_ns << ") * " << He << "; ye = min(yr + " << He << ", " << Hh << "); }\n";
+            o << "  else if (wid < " << nB + nT + nL << ") { const int w = wid - " << nB + nT << "; xr = (w % " << nsl
+              << ") * " << G.Wo << "; xe = min(xr + " << G.Wo << ", " << G.in_x << "); yr = " << G.in_y << " + (w / "
+              << nsl << ") * " << He << "; ye = min(yr + " << He << ", " << G.e_yt << "); }\n";
+            o << "  else { const int w = wid - " << nB + nT + nL << "; xr = " << G.e_xr << " + (w % " << nsr << ") * "
+              << G.Wo << "; xe = min(xr + " << G.Wo << ", " << W << "); yr = " << G.in_y << " + (w / " << nsr
+              << ") * " << He << "; ye = min(yr + " << He << ", " << G.e_yt << "); }\n";
+            o << "  const int X0 = __builtin_amdgcn_readfirstlane(" << G.xlo << " + xr), XE = "
+              << "__builtin_amdgcn_readfirstlane(" << G.xlo << " + xe);\n";
+            o << "  const int Y0 = __builtin_amdgcn_readfirstlane(" << G.ylo << " + yr), YE = "
+              << "__builtin_amdgcn_readfirstlane(" << G.ylo << " + ye);\n";
         }
         g.body();
         o << g.o.str();
@@ -705,45 +726,70 @@ void gen_group(const Ctx &c, FusedGroup &G, int gi, std::ostringstream &o) {
     }
 }
 
-// Every (strip, row) of the group's range must belong to exactly one
-// wavefront: the interior rectangle's waves plus the frame's edge waves, laid
-// out as the generated kernels lay them out.
+// Every cell of the group's range must belong to exactly one wavefront: the
+// interior grid's waves plus the edge bands' waves, decoded as the generated
+// kernels decode them.  Checked on the owned rectangles over the grid of
+// their distinct boundaries.
 bool layout_covers_once(const FusedGroup &G) {
-    const int height = G.yhi - G.ylo, ns = G.nstrips;
-    if (G.Hedge <= 0 || G.Hseg % G.Hedge != 0) return false;
-    std::vector<int> d((size_t)ns * (height + 1), 0);
-    auto add = [&](int strip, int row, int h) {
-        if (strip < 0 || strip >= ns || row < 0 || row >= height) return false;
-        d[(size_t)strip * (height + 1) + row] += 1;
-        d[(size_t)strip * (height + 1) + std::min(row + h, height)] -= 1;
-        return true;
+    const int W = G.xhi - G.xlo, H = G.yhi - G.ylo, He = G.Hedge;
+    struct Rect {
+        int x0, x1, y0, y1;
     };
-    const int nsi = G.si1 - G.si0;
-    for (int w = 0; w < G.nwaves_in; ++w)
-        if (!add(G.si0 + w % nsi, (G.gi0 + w / nsi) * G.Hseg, G.Hseg)) return false;
-    const int side = std::max(1, G.ne_side_strips);
-    for (int w = 0; w < G.nwaves_edge; ++w) {
-        int strip, row;
-        if (w < G.ne_bottom) {
-            row = (w / ns) * G.Hedge;
-            strip = w % ns;
-        } else if (w < G.ne_bottom + G.ne_top) {
-            row = G.gi1 * G.Hseg + ((w - G.ne_bottom) / ns) * G.Hedge;
-            strip = (w - G.ne_bottom) % ns;
+    std::vector<Rect> rects;
+    for (int w = 0; w < G.nwaves_in; ++w) {
+        const int x0 = G.in_x + (w % G.in_ns) * G.Wo, y0 = G.in_y + (w / G.in_ns) * G.Hseg;
+        rects.push_back({x0, x0 + G.Wo, y0, y0 + G.Hseg});
+    }
+    const int nB = G.e_ns * G.e_ngb, nT = G.e_ns * G.e_ngt, nL = G.e_nsl * G.e_ngm;
+    const int nsl = std::max(1, G.e_nsl), nsr = std::max(1, G.e_nsr);
+    for (int wid = 0; wid < G.nwaves_edge; ++wid) {
+        int xr, xe, yr, ye;
+        if (wid < nB) {
+            xr = (wid % G.e_ns) * G.Wo;
+            xe = std::min(xr + G.Wo, W);
+            yr = (wid / G.e_ns) * He;
+            ye = std::min(yr + He, G.e_yb);
+        } else if (wid < nB + nT) {
+            const int w = wid - nB;
+            xr = (w % G.e_ns) * G.Wo;
+            xe = std::min(xr + G.Wo, W);
+            yr = G.e_yt + (w / G.e_ns) * He;
+            ye = std::min(yr + He, H);
+        } else if (wid < nB + nT + nL) {
+            const int w = wid - nB - nT;
+            xr = (w % nsl) * G.Wo;
+            xe = std::min(xr + G.Wo, G.in_x);
+            yr = G.in_y + (w / nsl) * He;
+            ye = std::min(yr + He, G.e_yt);
         } else {
-            const int k = (w - G.ne_bottom - G.ne_top) % side;
-            row = G.gi0 * G.Hseg + ((w - G.ne_bottom - G.ne_top) / side) * G.Hedge;
-            strip = k < G.si0 ? k : G.si1 + (k - G.si0);
+            const int w = wid - nB - nT - nL;
+            xr = G.e_xr + (w % nsr) * G.Wo;
+            xe = std::min(xr + G.Wo, W);
+            yr = G.in_y + (w / nsr) * He;
+            ye = std::min(yr + He, G.e_yt);
         }
-        if (!add(strip, row, G.Hedge)) return false;
+        rects.push_back({xr, xe, yr, ye});
     }
-    for (int s = 0; s < ns; ++s) {
-        int cover = 0;
-        for (int r = 0; r < height; ++r) {
-            cover += d[(size_t)s * (height + 1) + r];
-            if (cover != 1) return false;
-        }
+    std::vector<int> xs{0, W}, ys{0, H};
+    for (const Rect &r : rects) {
+        if (r.x0 < 0 || r.x1 > W || r.y0 < 0 || r.y1 > H || r.x0 >= r.x1 || r.y0 >= r.y1) return false;
+        xs.push_back(r.x0);
+        xs.push_back(r.x1);
+        ys.push_back(r.y0);
+        ys.push_back(r.y1);
     }
+    std::sort(xs.begin(), xs.end());
+    xs.erase(std::unique(xs.begin(), xs.end()), xs.end());
+    std::sort(ys.begin(), ys.end());
+    ys.erase(std::unique(ys.begin(), ys.end()), ys.end());
+    const size_t nx = xs.size() - 1, ny = ys.size() - 1;
+    std::vector<int> cnt(nx * ny, 0);
+    auto at = [](const std::vector<int> &v, int x) { return (size_t)(std::lower_bound(v.begin(), v.end(), x) - v.begin()); };
+    for (const Rect &r : rects)
+        for (size_t i = at(xs, r.x0); i < at(xs, r.x1); ++i)
+            for (size_t j = at(ys, r.y0); j < at(ys, r.y1); ++j) ++cnt[j * nx + i];
+    for (int k : cnt)
+        if (k != 1) return false;
     return true;
 }
 
@@ -808,9 +854,9 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
             for (char x : g->var[0].loaded) nld += x;
             std::fprintf(stderr,
                          "fused group [%d,%d): %d loops, HL %d HR %d Wo %d, loads %d stores %d, regs %d/%d, "
-                         "pre %d post %d, Hseg %d Hedge %d, strips %d segs %d, waves %d+%d, cost %.1f us\n",
+                         "pre %d post %d, Hseg %d Hedge %d, interior %dx%d at (%d,%d), waves %d+%d, cost %.1f us\n",
                          g->g0, g->g1, nl, g->HL, g->HR, g->Wo, nld, (int)g->dst_dat.size(), g->var[0].regs,
-                         g->var[1].regs, g->var[0].pre, g->var[0].post, g->Hseg, g->Hedge, g->nstrips, g->nsegs, g->nwaves_in,
+                         g->var[1].regs, g->var[0].pre, g->var[0].post, g->Hseg, g->Hedge, g->in_ns, g->in_ng, g->in_x, g->in_y, g->nwaves_in,
                          g->nwaves_edge, g->cost * 1e6);
         }
     return out;

@@ -74,6 +74,7 @@ struct JVariant {
     std::vector<std::pair<int, int>> pseudo;  // (producer loop, chain-start version): edge selects
     int pre = 0, post = 0;        // steps before / after the owned rows
     int regs = 0;                 // estimated VGPRs of the windows
+    int PF = 2;                   // steps loads run ahead
 };
 
 struct FusedGroup {
@@ -90,11 +91,18 @@ struct FusedGroup {
     int HL = 0, HR = 0, Wo = 0;
     int BMAX = 0, TMAX = 0;  // rows below / above the owned rows that are read
     int Hseg = 0, U = 4, PF = 2;
-    int nstrips = 0, nsegs = 0;
-    int si0 = 0, si1 = 0, gi0 = 0, gi1 = 0;  // interior rectangle of strips x segments
+    int nstrips = 0, nsegs = 0;  // a plain grid of Wo-column strips and Hseg-row segments over the range
+    // interior waves: in_ns strips by in_ng segments from (xlo + in_x, ylo + in_y)
+    int in_x = 0, in_y = 0, in_ns = 0, in_ng = 0;
     int nwaves_in = 0, nwaves_edge = 0;
-    int Hedge = 0;  // rows per edge wavefront (a whole fraction of Hseg)
-    int ne_bottom = 0, ne_top = 0, ne_side_strips = 0;  // edge wavefronts below / above the interior rectangle; side strips
+    int Hedge = 0;  // rows per edge wavefront
+    // edge bands (relative to xlo, ylo): bottom rows [0, e_yb) and top rows
+    // [e_yt, height) over the whole width; left columns [0, in_x) and right
+    // columns [e_xr, width) of rows [in_y, e_yt).  Strips of Wo columns from
+    // each band's left end, segments of Hedge rows from its bottom.
+    int e_yb = 0, e_yt = 0, e_xr = 0;
+    int e_ns = 0, e_nsl = 0, e_nsr = 0;   // strips: whole width, left band, right band
+    int e_ngb = 0, e_ngt = 0, e_ngm = 0;  // segments: bottom, top and middle bands
     int nblocks = 0;
     std::vector<int> src_dat;   // datasets loaded (kernel argument order)
     std::vector<int> dst_dat;   // datasets stored
