@@ -336,11 +336,15 @@ __global__ void __launch_bounds__(kBlockThreads) loop_kernel(LoopDesc d, Box b) 
     const int x = b.lo[0] + bx * b.bw + (int)(threadIdx.x % b.bw);
     const int y = b.lo[1] + by * b.bh + (int)(threadIdx.x / b.bw);
     const int z = b.lo[2] + bz;
+    // the accumulators are indexed with constants only (the loop below is
+    // unrolled), so they stay in registers rather than in scratch or LDS
     DD red[2];
     red[0] = red_identity(d.red_op[0]);
     red[1] = red_identity(d.red_op[1]);
     if (x < b.hi[0] && y < b.hi[1]) Op::run(d, x, y, z, red);
-    for (int j = 0; j < d.nred; ++j) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        if (j >= d.nred) break;
         DD v = block_reduce(d.red_op[j], red[j]);
         if (threadIdx.x == 0) {
             d.partials[j][2 * (int64_t)lin] = v.hi;

@@ -140,45 +140,62 @@ __global__ void __launch_bounds__(kMarchW) wsum_march_kernel(LoopDesc d, int lo0
 // 3D: a workgroup covers 60 columns x 4 rows (one wavefront per row, lanes
 // as in the 2D march) and marches up z over `tz` planes.  Each lane keeps the
 // z window of its own column for every input in registers; x neighbours come
-// from adjacent lanes, y neighbours are loaded from the rows above and below
-// (the workgroup's four wavefronts read overlapping rows at the same plane,
-// so those loads hit the L1/L2 caches).
+// from adjacent lanes.  For the y neighbours each wavefront puts the centre
+// value of its own row, and of one of the four rows just outside the
+// workgroup (y0-2, y0-1, y0+4, y0+5; loaded one batch ahead), into LDS, where
+// the workgroup's rows read them (one barrier per plane, two LDS buffers).
 template <typename T, int K, int MASK>
 __global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo0, int hi0, int lo1, int hi1, int lo2,
                                                               int hi2, int nbx, int nby, int nb, int tz) {
     constexpr int TB = kMarchBatch;
+    static_assert(TB % 2 == 0, "the LDS buffer of a plane alternates with its parity");
+    __shared__ T yl[2][K][8][64];
     const int lin = xcd_linear(blockIdx.x, nb);
     const int bx = lin % nbx, rest = lin / nbx, by = rest % nby, bz = rest / nby;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x = lo0 + bx * kWaveOut - 2 + lane;
-    const int y = lo1 + by * 4 + wave;
+    const int y0 = lo1 + by * 4;
+    const int y = y0 + wave;
     const bool active = lane >= 2 && lane < 62 && x < hi0 && y < hi1;
     const int z0 = lo2 + bz * tz;
     const int z1 = min(z0 + tz, hi2);
+    const int hslot = wave < 2 ? wave : wave + 4;  // LDS row of this wave's outside row
 
     const T *ptr[K];
-    int64_t sy[K], sz[K];
+    const T *optr[K];
+    int64_t sz[K];
     T win[K][TB + 4];
     T pf[K][TB];
+    T ob[K][TB];
 #pragma unroll
     for (int a = 0; a < K; ++a) {
         const int r = (MASK >> a) & 1 ? 2 : 1;
-        // columns and rows outside the reach are clamped; no output uses them
+        // Positions are clamped to the input's reach [lo - r, hi - 1 + r]:
+        // whenever an output reads a position, it lies in that reach and is
+        // not moved; clamped ones feed no output.
         const int xc = min(max(x, lo0 - r), hi0 - 1 + r);
-        const int yc = min(y, hi1 - 1);
-        sy[a] = d.arg[a + 1].sy;
+        const int yc = min(y, hi1 - 1 + r);
+        const int yh = min(y0 - 2 + hslot, hi1 - 1 + r);
+        const int64_t sy = d.arg[a + 1].sy;
         sz[a] = d.arg[a + 1].sz;
-        ptr[a] = (const T *)d.arg[a + 1].ptr + xc + (int64_t)yc * sy[a];
+        ptr[a] = (const T *)d.arg[a + 1].ptr + xc + (int64_t)yc * sy;
+        optr[a] = (const T *)d.arg[a + 1].ptr + xc + (int64_t)yh * sy;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (j >= 2 - r && j < 2 + r) win[a][j] = ptr[a][(int64_t)(z0 - 2 + j) * sz[a]];
 #pragma unroll
         for (int t = 0; t < TB; ++t)
             if (z0 + r + t <= z1 - 1 + r) pf[a][t] = ptr[a][(int64_t)(z0 + r + t) * sz[a]];
+        // rows y0-2 and y0+5 are read through radius-2 stencils only
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+            if ((r == 2 || (hslot != 0 && hslot != 7)) && z0 + t < z1)
+                ob[a][t] = optr[a][(int64_t)(z0 + t) * sz[a]];
     }
     T *out = (T *)d.arg[0].ptr + x + (int64_t)min(y, hi1 - 1) * d.arg[0].sy;
     const int64_t osz = d.arg[0].sz;
     for (int z = z0; z < z1; z += TB) {
+        T cur_ob[K][TB];
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             const int r = (MASK >> a) & 1 ? 2 : 1;
@@ -186,55 +203,50 @@ __global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo
             for (int t = 0; t < TB; ++t) win[a][2 + r + t] = pf[a][t];
 #pragma unroll
             for (int t = 0; t < TB; ++t) {
+                cur_ob[a][t] = ob[a][t];
                 const int pl = z + TB + r + t;
                 if (pl <= z1 - 1 + r) pf[a][t] = ptr[a][(int64_t)pl * sz[a]];
-            }
-        }
-        // y neighbours of the batch's planes (rows y-2..y+2), all issued first
-        T yn[K][TB][4];
-#pragma unroll
-        for (int a = 0; a < K; ++a) {
-            const int r = (MASK >> a) & 1 ? 2 : 1;
-#pragma unroll
-            for (int t = 0; t < TB; ++t) {
-                const int pl = min(z + t, z1 - 1);
-                const T *row = ptr[a] + (int64_t)pl * sz[a];
-                yn[a][t][0] = row[-sy[a]];
-                yn[a][t][1] = row[sy[a]];
-                if (r == 2) {
-                    yn[a][t][2] = row[-2 * sy[a]];
-                    yn[a][t][3] = row[2 * sy[a]];
-                }
+                const int po = z + TB + t;
+                if ((r == 2 || (hslot != 0 && hslot != 7)) && po < z1) ob[a][t] = optr[a][(int64_t)po * sz[a]];
             }
         }
 #pragma unroll
         for (int t = 0; t < TB; ++t) {
+            const int buf = t & 1;
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                yl[buf][a][wave + 2][lane] = win[a][2 + t];
+                yl[buf][a][hslot][lane] = cur_ob[a][t];
+            }
+            __syncthreads();
             T acc = (T)0;
 #pragma unroll
             for (int a = 0; a < K; ++a) {
                 const int r = (MASK >> a) & 1 ? 2 : 1;
                 const T c = win[a][2 + t];
                 const T xm1 = shfl_up(c, 1), xp1 = shfl_down(c, 1);
+                const T ym1 = yl[buf][a][wave + 1][lane], yp1 = yl[buf][a][wave + 3][lane];
                 const int q = d.pt0[a + 1];
                 if (r == 1) {
                     acc = fmaT<T>((T)d.prm[q + 0], c, acc);
                     acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
                     acc = fmaT<T>((T)d.prm[q + 2], xp1, acc);
-                    acc = fmaT<T>((T)d.prm[q + 3], yn[a][t][0], acc);
-                    acc = fmaT<T>((T)d.prm[q + 4], yn[a][t][1], acc);
+                    acc = fmaT<T>((T)d.prm[q + 3], ym1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 4], yp1, acc);
                     acc = fmaT<T>((T)d.prm[q + 5], win[a][1 + t], acc);
                     acc = fmaT<T>((T)d.prm[q + 6], win[a][3 + t], acc);
                 } else {
                     const T xm2 = shfl_up(c, 2), xp2 = shfl_down(c, 2);
+                    const T ym2 = yl[buf][a][wave][lane], yp2 = yl[buf][a][wave + 4][lane];
                     acc = fmaT<T>((T)d.prm[q + 0], c, acc);
                     acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
                     acc = fmaT<T>((T)d.prm[q + 2], xp1, acc);
                     acc = fmaT<T>((T)d.prm[q + 3], xm2, acc);
                     acc = fmaT<T>((T)d.prm[q + 4], xp2, acc);
-                    acc = fmaT<T>((T)d.prm[q + 5], yn[a][t][0], acc);
-                    acc = fmaT<T>((T)d.prm[q + 6], yn[a][t][1], acc);
-                    acc = fmaT<T>((T)d.prm[q + 7], yn[a][t][2], acc);
-                    acc = fmaT<T>((T)d.prm[q + 8], yn[a][t][3], acc);
+                    acc = fmaT<T>((T)d.prm[q + 5], ym1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 6], yp1, acc);
+                    acc = fmaT<T>((T)d.prm[q + 7], ym2, acc);
+                    acc = fmaT<T>((T)d.prm[q + 8], yp2, acc);
                     acc = fmaT<T>((T)d.prm[q + 9], win[a][1 + t], acc);
                     acc = fmaT<T>((T)d.prm[q + 10], win[a][3 + t], acc);
                     acc = fmaT<T>((T)d.prm[q + 11], win[a][t], acc);

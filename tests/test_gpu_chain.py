@@ -76,6 +76,7 @@ def test_random_op_chains(tc, ndim):
     (2, 67, 12, 40, [(0, 16, 0), (24, 7, 0), (67, 67, 0)]),
     (2, 300, 12, 40, [(0, 0, 0)]),
     (3, 23, 25, 20, [(0, 0, 5), (9, 6, 4)]),
+    (3, 67, 25, 12, [(0, 0, 9)]),
 ])
 def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
     from paper_1704_00693_amd.apps import ChainRunner
