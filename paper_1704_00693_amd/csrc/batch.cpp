@@ -14,8 +14,9 @@
 #include "tc_internal.hpp"
 
 namespace tc {
-hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles, double *part,
-                                   int grid, int cheb_steps, bool mixed, hipStream_t s);
+hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
+                                   const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed,
+                                   bool use_fused, hipStream_t s);
 }
 
 using namespace tc;
@@ -24,8 +25,10 @@ struct tc_batch {
     tc_ctx *ctx = nullptr;
     tc_batch_opts o{};
     BInst *d_inst = nullptr, *h_inst = nullptr;
-    BTile *d_tiles = nullptr, *h_tiles = nullptr;
-    int64_t *d_ntiles = nullptr, *h_ntiles = nullptr;
+    // every resident solve's tiles (kBTX x kBTY), the 3D solves' tiles, and
+    // the 2D solves' fused Chebyshev tiles (kFTX x kFTY)
+    BTileList all, three, fused;
+    bool use_fused = true;
     double *d_part = nullptr;
     int64_t tile_cap = 0;
     int grid = 0;
@@ -75,12 +78,14 @@ int64_t round256(int64_t v) { return (v + 255) / 256 * 256; }
 
 // Bytes of one solve's fields (each field padded by one ghost layer and
 // aligned to 256 bytes): FP64 mode 9 + ndim double fields; mixed mode
-// 3 + ndim double fields and 8 + ndim float fields.
+// 3 + ndim double fields and 8 + ndim float fields; 2D solves one more
+// sweep field (the second rt buffer).
 int64_t footprint(const tc_solve_desc &d, bool mixed) {
     const int64_t cells = padded_cells(d);
     const int64_t f8 = round256(cells * 8), f4 = round256(cells * 4);
-    if (!mixed) return (9 + d.ndim) * f8;
-    return (3 + d.ndim) * f8 + (8 + d.ndim) * f4;
+    const int extra = d.ndim == 2 ? 1 : 0;
+    if (!mixed) return (9 + d.ndim + extra) * f8;
+    return (3 + d.ndim) * f8 + (8 + d.ndim + extra) * f4;
 }
 
 tc_status admit(tc_batch *b, int slot, const tc_batch::Req &q) {
@@ -141,6 +146,7 @@ tc_status admit(tc_batch *b, int slot, const tc_batch::Req &q) {
         I.rt = take(f8);
         I.sd0 = take(f8);
         I.sd1 = take(f8);
+        I.rt2 = d.ndim == 2 ? take(f8) : nullptr;
     } else {
         I.xi = take(f4);
         I.ri = take(f4);
@@ -153,6 +159,7 @@ tc_status admit(tc_batch *b, int slot, const tc_batch::Req &q) {
         I.rt = take(f4);
         I.sd0 = take(f4);
         I.sd1 = take(f4);
+        I.rt2 = d.ndim == 2 ? take(f4) : nullptr;
     }
     b->resident_bytes += bytes;
     b->resident_tiles += S.tiles;
@@ -205,7 +212,7 @@ void retire(tc_batch *b, int slot) {
 // within a solve; every resident record is uploaded with its tile range.
 tc_status rebuild_tiles(tc_batch *b) {
     Ctx &c = C(b);
-    int64_t nt = 0;
+    int64_t nt = 0, n3 = 0, nf = 0;
     for (size_t s = 0; s < b->slots.size(); ++s) {
         BInst &I = b->h_inst[s];
         if (I.state == B_FREE) {
@@ -217,16 +224,29 @@ tc_status rebuild_tiles(tc_batch *b) {
         I.tile0 = nt;
         for (int z = 0; z < tz; ++z)
             for (int y = 0; y < ty; ++y)
-                for (int x = 0; x < tx; ++x) b->h_tiles[nt++] = BTile{(int32_t)s, x, y, z};
+                for (int x = 0; x < tx; ++x) {
+                    b->all.h[nt++] = BTile{(int32_t)s, x, y, z};
+                    if (I.ndim == 3) b->three.h[n3++] = BTile{(int32_t)s, x, y, z};
+                }
         I.ntile = nt - I.tile0;
+        if (I.ndim == 2) {
+            const int fx = (I.n + kFTX - 1) / kFTX, fy = (I.n + kFTY - 1) / kFTY;
+            for (int y = 0; y < fy; ++y)
+                for (int x = 0; x < fx; ++x) b->fused.h[nf++] = BTile{(int32_t)s, x, y, 0};
+        }
     }
-    *b->h_ntiles = nt;
-    if (hipMemcpyAsync(b->d_tiles, b->h_tiles, (size_t)std::max<int64_t>(nt, 1) * sizeof(BTile), hipMemcpyHostToDevice,
-                       c.stream) != hipSuccess ||
-        hipMemcpyAsync(b->d_ntiles, b->h_ntiles, sizeof(int64_t), hipMemcpyHostToDevice, c.stream) != hipSuccess ||
+    *b->all.hn = nt;
+    *b->three.hn = n3;
+    *b->fused.hn = nf;
+    auto up = [&](BTileList &L) {
+        return hipMemcpyAsync(L.d, L.h, (size_t)std::max<int64_t>(*L.hn, 1) * sizeof(BTile), hipMemcpyHostToDevice,
+                              c.stream) == hipSuccess &&
+               hipMemcpyAsync(L.dn, L.hn, sizeof(int64_t), hipMemcpyHostToDevice, c.stream) == hipSuccess;
+    };
+    if (!up(b->all) || !up(b->three) || !up(b->fused) ||
         hipMemcpyAsync(b->d_inst, b->h_inst, b->slots.size() * sizeof(BInst), hipMemcpyHostToDevice, c.stream) !=
             hipSuccess)
-        return fail(c, TC_ERR_DEVICE, "tc_batch: upload of the tile list failed");
+        return fail(c, TC_ERR_DEVICE, "tc_batch: upload of the tile lists failed");
     return TC_OK;
 }
 
@@ -237,8 +257,9 @@ tc_status capture(tc_batch *b) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed to start");
-    const hipError_t e = batch_enqueue_iteration(b->d_inst, (int)b->slots.size(), b->d_tiles, b->d_ntiles, b->d_part,
-                                                 b->grid, b->o.cheb_steps, b->o.mixed != 0, c.cap_stream);
+    const hipError_t e = batch_enqueue_iteration(b->d_inst, (int)b->slots.size(), b->all, b->three, b->fused,
+                                                 b->d_part, b->grid, b->o.cheb_steps, b->o.mixed != 0, b->use_fused,
+                                                 c.cap_stream);
     const hipError_t e2 = hipStreamEndCapture(c.cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed");
     const hipError_t e3 = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
@@ -273,19 +294,23 @@ tc_status tc_batch_create(tc_ctx *ctx, const tc_batch_opts *opts, tc_batch **out
     b->grid = (int)std::min<int64_t>(b->tile_cap, 2048);
     const size_t ib = b->slots.size() * sizeof(BInst);
     b->d_inst = (BInst *)dev_alloc(c, ib);
-    b->d_tiles = (BTile *)dev_alloc(c, (size_t)b->tile_cap * sizeof(BTile));
-    b->d_ntiles = (int64_t *)dev_alloc(c, sizeof(int64_t));
     b->d_part = (double *)dev_alloc(c, (size_t)b->tile_cap * 4 * sizeof(double));
-    bool ok = b->d_inst && b->d_tiles && b->d_ntiles && b->d_part;
+    bool ok = b->d_inst && b->d_part;
     ok = ok && hipHostMalloc((void **)&b->h_inst, ib, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipHostMalloc((void **)&b->h_tiles, (size_t)b->tile_cap * sizeof(BTile), hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipHostMalloc((void **)&b->h_ntiles, sizeof(int64_t), hipHostMallocDefault) == hipSuccess;
+    // a solve's fused tiles and 3D tiles are never more than its kBTX x kBTY tiles
+    for (BTileList *L : {&b->all, &b->three, &b->fused}) {
+        L->d = (BTile *)dev_alloc(c, (size_t)b->tile_cap * sizeof(BTile));
+        L->dn = (int64_t *)dev_alloc(c, sizeof(int64_t));
+        ok = ok && L->d && L->dn;
+        ok = ok && hipHostMalloc((void **)&L->h, (size_t)b->tile_cap * sizeof(BTile), hipHostMallocDefault) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&L->hn, sizeof(int64_t), hipHostMallocDefault) == hipSuccess;
+    }
     if (!ok) {
         tc_batch_destroy(b);
         return fail(c, TC_ERR_NOMEM, "tc_batch_create: cannot allocate the engine's arrays");
     }
     std::memset(b->h_inst, 0, ib);
-    *b->h_ntiles = 0;
+    if (const char *e = getenv("TC_BATCH_FUSED")) b->use_fused = atoi(e) != 0;
     if (rebuild_tiles(b) != TC_OK || capture(b) != TC_OK) {
         tc_batch_destroy(b);
         return TC_ERR_DEVICE;
@@ -404,12 +429,14 @@ tc_status tc_batch_destroy(tc_batch *b) {
         if (S.mem) dev_free(c, S.mem);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->d_inst) dev_free(c, b->d_inst);
-    if (b->d_tiles) dev_free(c, b->d_tiles);
-    if (b->d_ntiles) dev_free(c, b->d_ntiles);
+    for (BTileList *L : {&b->all, &b->three, &b->fused}) {
+        if (L->d) dev_free(c, L->d);
+        if (L->dn) dev_free(c, L->dn);
+        if (L->h) (void)hipHostFree(L->h);
+        if (L->hn) (void)hipHostFree(L->hn);
+    }
     if (b->d_part) dev_free(c, b->d_part);
     if (b->h_inst) (void)hipHostFree(b->h_inst);
-    if (b->h_tiles) (void)hipHostFree(b->h_tiles);
-    if (b->h_ntiles) (void)hipHostFree(b->h_ntiles);
     delete b;
     return TC_OK;
 }

@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256) bk_update_init(BInst *insts, const BTile 
 // step adds the partials r . z (slot 0) and r . r (slot 1).
 template <typename T>
 __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part,
-                                               int j) {
+                                               int j, int rt_alt) {
     const int64_t nt = *ntiles;
     const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
     for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
@@ -312,7 +312,8 @@ __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles,
             const T *sd = (const T *)((j & 1) ? I.sd0 : I.sd1);
             T *sdn = (T *)((j & 1) ? I.sd1 : I.sd0);
             const T av = apply_A<T>(I, (const T *)I.kxi, (const T *)I.kyi, (const T *)I.kzi, sd, k);
-            T *rt = (T *)I.rt, *z = (T *)I.z;
+            // after an odd number of fused launches a 2D instance's rt is in rt2
+            T *rt = (T *)((rt_alt && I.ndim == 2) ? I.rt2 : I.rt), *z = (T *)I.z;
             const T rtv = rt[k.c] - av;
             rt[k.c] = rtv;
             const T zv = z[k.c] + sd[k.c];
@@ -329,6 +330,108 @@ __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles,
             write_partial(part, t, 0, block_reduce(TC_RED_SUM, rz));
             write_partial(part, t, 1, block_reduce(TC_RED_SUM, rr));
         }
+    }
+}
+
+// Chebyshev steps j0 .. j1-1 (j1 - j0 <= H and odd) of 2D instances; the
+// last step, with its reductions, stays with bk_cheb.  A workgroup takes a
+// tile of kFTX x kFTY owned cells and the H cells around it (inside the
+// domain): face coefficients, rt and the direction are loaded once (z for
+// the owned cells only: no neighbour needs it), each step exchanges the
+// direction through LDS, and rt, z and the last direction are stored for the
+// owned cells.  Neighbouring tiles read this tile's cells as their border,
+// so rt alternates between two buffers (rt_alt: read rt2, write rt) and the
+// direction between sd0 and sd1 (an odd number of steps lands in the other
+// one).  A cell at the edge of the loaded region reads itself for a missing
+// neighbour, which makes its value wrong, and each step moves the wrong
+// values one cell inwards; after at most H steps they have not reached the
+// owned cells.  At the domain boundary the mirrored neighbour is the cell
+// itself, as in bk_cheb.  Every cell's operations are bk_cheb's, in the same
+// order.
+template <typename T, int H>
+__global__ void __launch_bounds__(256) bk_cheb_fused(BInst *insts, const BTile *tiles, const int64_t *ntiles, int j0,
+                                                     int j1, int rt_alt) {
+    constexpr int RW = kFTX + 2 * H, RH = kFTY + 2 * H, RC = RW * RH;
+    constexpr int PER = (RC + 255) / 256;
+    __shared__ T sdl[2][RC];
+    const int64_t nt = *ntiles;
+    const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        const int K = I.cheb_steps;
+        if (!serves(I, mask) || I.ndim != 2 || j1 > K) continue;  // the same for the whole workgroup
+        const T *rt_in = (const T *)(rt_alt ? I.rt2 : I.rt);
+        T *rt_out = (T *)(rt_alt ? I.rt : I.rt2);
+        const int rx0 = tl.tx * kFTX - H, ry0 = tl.ty * kFTY - H;  // region origin
+        const T *kx = (const T *)I.kxi, *ky = (const T *)I.kyi;
+        const T *sd = (const T *)((j0 & 1) ? I.sd0 : I.sd1);
+        T ke[PER], kw[PER], kn[PER], ks[PER], rt[PER], z[PER];
+        int oe[PER], ow[PER], on[PER], os[PER];
+        bool act[PER], own[PER];
+        int64_t cc[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            const int lx = i % RW, ly = i / RW;
+            const int x = rx0 + lx, y = ry0 + ly;
+            act[k] = i < RC && x >= 0 && x < I.n && y >= 0 && y < I.n;
+            own[k] = act[k] && lx >= H && lx < H + kFTX && ly >= H && ly < H + kFTY;
+            cc[k] = I.org + x + (int64_t)y * I.sy;
+            oe[k] = (x + 1 < I.n && lx + 1 < RW) ? 1 : 0;
+            ow[k] = (x > 0 && lx > 0) ? -1 : 0;
+            on[k] = (y + 1 < I.n && ly + 1 < RH) ? RW : 0;
+            os[k] = (y > 0 && ly > 0) ? -RW : 0;
+            if (act[k]) {
+                const int64_t c = cc[k];
+                ke[k] = kx[c + 1];
+                kw[k] = kx[c];
+                kn[k] = ky[c + I.sy];
+                ks[k] = ky[c];
+                rt[k] = rt_in[c];
+                if (own[k]) z[k] = ((const T *)I.z)[c];
+                sdl[0][i] = sd[c];
+            }
+        }
+        __syncthreads();
+        int buf = 0;
+        for (int j = j0; j < j1; ++j) {
+            const T al = (T)I.al[j - 1], be = (T)I.be[j - 1];
+            const T *v = sdl[buf];
+            T *vn = sdl[buf ^ 1];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                if (!act[k]) continue;
+                const int i = (int)threadIdx.x + 256 * k;
+                T diag = (T)1 + ke[k];
+                diag = diag + kw[k];
+                diag = diag + kn[k];
+                diag = diag + ks[k];
+                const T vc = v[i];
+                T av = diag * vc;
+                av = fmaB<T>(-ke[k], v[i + oe[k]], av);
+                av = fmaB<T>(-kw[k], v[i + ow[k]], av);
+                av = fmaB<T>(-kn[k], v[i + on[k]], av);
+                av = fmaB<T>(-ks[k], v[i + os[k]], av);
+                const T rtv = rt[k] - av;
+                rt[k] = rtv;
+                if (own[k]) z[k] = z[k] + vc;
+                vn[i] = fmaB<T>(al, vc, be * rtv);
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
+        // step j1 - 1 wrote the direction step j1 reads
+        T *sdo = (T *)(((j1 - 1) & 1) ? I.sd1 : I.sd0);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (!own[k]) continue;
+            const int i = (int)threadIdx.x + 256 * k;
+            rt_out[cc[k]] = rt[k];
+            ((T *)I.z)[cc[k]] = z[k];
+            sdo[cc[k]] = sdl[buf][i];
+        }
+        __syncthreads();  // the next tile reuses the LDS buffers
     }
 }
 
@@ -435,8 +538,10 @@ __global__ void __launch_bounds__(256) bk_finalize(BInst *insts, int ninst, cons
 }
 
 template <typename T>
-hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles, double *part,
-                               int grid, int cheb_steps, bool mixed, hipStream_t s) {
+hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles,
+                               const BTile *tiles3, const int64_t *ntiles3, const BTile *ftiles,
+                               const int64_t *nftiles, double *part, int grid, int cheb_steps, bool mixed,
+                               bool fused, hipStream_t s) {
     const dim3 g(grid), b(256), f(ninst);
     // set-up of newly admitted instances
     hipLaunchKernelGGL(bk_init, g, b, 0, s, insts, tiles, ntiles, part);
@@ -452,7 +557,25 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
     hipLaunchKernelGGL(bk_matvec<T>, g, b, 0, s, insts, tiles, ntiles, part);
     hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 2);
     hipLaunchKernelGGL(bk_update_init<T>, g, b, 0, s, insts, tiles, ntiles);
-    for (int j = 1; j <= cheb_steps; ++j) hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, j);
+    if (fused) {
+        // 2D instances: steps 1 .. cheb_steps-1 in launches of kFH steps (odd),
+        // the remainder one step at a time, on the fused tiles; 3D instances:
+        // one launch per step on their own tiles; then everybody's last step
+        // (with the r.z and r.r partials)
+        int launches = 0;
+        for (int j0 = 1; j0 < cheb_steps;) {
+            const int j1 = cheb_steps - j0 >= kFH ? j0 + kFH : j0 + 1;
+            hipLaunchKernelGGL((bk_cheb_fused<T, kFH>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, launches & 1);
+            ++launches;
+            j0 = j1;
+        }
+        for (int j = 1; j < cheb_steps; ++j)
+            hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles3, ntiles3, part, j, 0);
+        hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, cheb_steps, launches & 1);
+    } else {
+        for (int j = 1; j <= cheb_steps; ++j)
+            hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, j, 0);
+    }
     hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 3);
     return hipGetLastError();
 }
@@ -462,10 +585,13 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
 // One round of every solver phase for every resident instance, in order
 // (set-up, residual, one PPCG iteration); each instance advances according
 // to its own state.
-hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles, double *part,
-                                   int grid, int cheb_steps, bool mixed, hipStream_t s) {
-    return mixed ? enqueue_iteration_t<float>(insts, ninst, tiles, ntiles, part, grid, cheb_steps, true, s)
-                 : enqueue_iteration_t<double>(insts, ninst, tiles, ntiles, part, grid, cheb_steps, false, s);
+hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
+                                   const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed,
+                                   bool use_fused, hipStream_t s) {
+    return mixed ? enqueue_iteration_t<float>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
+                                              grid, cheb_steps, true, use_fused, s)
+                 : enqueue_iteration_t<double>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
+                                               grid, cheb_steps, false, use_fused, s);
 }
 
 }  // namespace tc

@@ -33,6 +33,9 @@ enum BState : int {
 };
 
 constexpr int kBTX = 64, kBTY = 4;  // cells of one tile: one workgroup of 256 threads
+// 2D Chebyshev steps run kFH at a time on tiles of kFTX x kFTY owned cells
+// (plus kFH cells around them, recomputed), with the direction in LDS
+constexpr int kFTX = 64, kFTY = 16, kFH = 3;
 constexpr int kBMaxCheb = 32;
 
 struct BInst {
@@ -49,10 +52,17 @@ struct BInst {
     // fields of the PPCG sweeps (FP64 mode: double, aliasing u, r, kx..;
     // mixed mode: float)
     void *xi, *ri, *p, *w, *z, *rt, *sd0, *sd1, *kxi, *kyi, *kzi;
+    void *rt2;  // 2D: the second rt buffer of the fused Chebyshev steps (neighbouring tiles read rt around theirs)
 };
 
 struct BTile {
     int32_t inst, tx, ty, tz;
+};
+
+// A tile list on the device (length read by the kernels) and its host copy.
+struct BTileList {
+    BTile *d = nullptr, *h = nullptr;
+    int64_t *dn = nullptr, *hn = nullptr;
 };
 
 }  // namespace tc

@@ -140,7 +140,7 @@ def test_admission_by_footprint_and_rejection(tc):
     still all finish (admitted as earlier ones retire); a solve larger than
     the budget is rejected."""
     with tc.Context() as c:
-        per = 11 * ((66 * 66 * 8 + 255) // 256 * 256)  # FP64 fields of one 64^2 solve
+        per = 12 * ((66 * 66 * 8 + 255) // 256 * 256)  # FP64 fields of one 64^2 solve
         with tc.Batch(c, max_instances=8, hbm_budget=2 * per + 100) as b:
             ts = [b.tc_batch_submit(2, 64, 100 + i, tol=1e-8) for i in range(8)]
             big = b.tc_batch_submit(2, 512, 7, tol=1e-8)
