@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <unordered_map>
@@ -15,8 +16,8 @@
 
 namespace tc {
 hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
-                                   const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed,
-                                   bool use_fused, hipStream_t s);
+                                   const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed, int fh,
+                                   int fty, hipStream_t s);
 }
 
 using namespace tc;
@@ -28,7 +29,7 @@ struct tc_batch {
     // every resident solve's tiles (kBTX x kBTY), the 3D solves' tiles, and
     // the 2D solves' fused Chebyshev tiles (kFTX x kFTY)
     BTileList all, three, fused;
-    bool use_fused = true;
+    int fh = kFH, fty = kFTY;  // fused Chebyshev steps per launch (0: one launch per step) and tile height
     double *d_part = nullptr;
     int64_t tile_cap = 0;
     int grid = 0;
@@ -230,7 +231,7 @@ tc_status rebuild_tiles(tc_batch *b) {
                 }
         I.ntile = nt - I.tile0;
         if (I.ndim == 2) {
-            const int fx = (I.n + kFTX - 1) / kFTX, fy = (I.n + kFTY - 1) / kFTY;
+            const int fx = (I.n + kFTX - 1) / kFTX, fy = (I.n + b->fty - 1) / b->fty;
             for (int y = 0; y < fy; ++y)
                 for (int x = 0; x < fx; ++x) b->fused.h[nf++] = BTile{(int32_t)s, x, y, 0};
         }
@@ -258,7 +259,7 @@ tc_status capture(tc_batch *b) {
     if (hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed to start");
     const hipError_t e = batch_enqueue_iteration(b->d_inst, (int)b->slots.size(), b->all, b->three, b->fused,
-                                                 b->d_part, b->grid, b->o.cheb_steps, b->o.mixed != 0, b->use_fused,
+                                                 b->d_part, b->grid, b->o.cheb_steps, b->o.mixed != 0, b->fh, b->fty,
                                                  c.cap_stream);
     const hipError_t e2 = hipStreamEndCapture(c.cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed");
@@ -310,7 +311,15 @@ tc_status tc_batch_create(tc_ctx *ctx, const tc_batch_opts *opts, tc_batch **out
         return fail(c, TC_ERR_NOMEM, "tc_batch_create: cannot allocate the engine's arrays");
     }
     std::memset(b->h_inst, 0, ib);
-    if (const char *e = getenv("TC_BATCH_FUSED")) b->use_fused = atoi(e) != 0;
+    // TC_BATCH_FUSED=FH[,FTY]: Chebyshev steps per fused launch (0: none), tile height
+    if (const char *e = getenv("TC_BATCH_FUSED")) {
+        int fh = kFH, fty = kFTY;
+        if (std::sscanf(e, "%d,%d", &fh, &fty) < 1) fh = kFH;
+        const bool shape = (fh == 3 && (fty == 16 || fty == 32)) || (fh == 5 && (fty == 16 || fty == 32)) ||
+                           (fh == 9 && fty == 16);
+        b->fh = fh <= 0 ? 0 : (shape ? fh : kFH);
+        b->fty = shape ? fty : kFTY;
+    }
     if (rebuild_tiles(b) != TC_OK || capture(b) != TC_OK) {
         tc_batch_destroy(b);
         return TC_ERR_DEVICE;

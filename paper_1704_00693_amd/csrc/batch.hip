@@ -348,10 +348,10 @@ __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles,
 // owned cells.  At the domain boundary the mirrored neighbour is the cell
 // itself, as in bk_cheb.  Every cell's operations are bk_cheb's, in the same
 // order.
-template <typename T, int H>
+template <typename T, int H, int FTY>
 __global__ void __launch_bounds__(256) bk_cheb_fused(BInst *insts, const BTile *tiles, const int64_t *ntiles, int j0,
                                                      int j1, int rt_alt) {
-    constexpr int RW = kFTX + 2 * H, RH = kFTY + 2 * H, RC = RW * RH;
+    constexpr int RW = kFTX + 2 * H, RH = FTY + 2 * H, RC = RW * RH;
     constexpr int PER = (RC + 255) / 256;
     __shared__ T sdl[2][RC];
     const int64_t nt = *ntiles;
@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(256) bk_cheb_fused(BInst *insts, const BTile *
         if (!serves(I, mask) || I.ndim != 2 || j1 > K) continue;  // the same for the whole workgroup
         const T *rt_in = (const T *)(rt_alt ? I.rt2 : I.rt);
         T *rt_out = (T *)(rt_alt ? I.rt : I.rt2);
-        const int rx0 = tl.tx * kFTX - H, ry0 = tl.ty * kFTY - H;  // region origin
+        const int rx0 = tl.tx * kFTX - H, ry0 = tl.ty * FTY - H;  // region origin
         const T *kx = (const T *)I.kxi, *ky = (const T *)I.kyi;
         const T *sd = (const T *)((j0 & 1) ? I.sd0 : I.sd1);
         T ke[PER], kw[PER], kn[PER], ks[PER], rt[PER], z[PER];
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(256) bk_cheb_fused(BInst *insts, const BTile *
             const int lx = i % RW, ly = i / RW;
             const int x = rx0 + lx, y = ry0 + ly;
             act[k] = i < RC && x >= 0 && x < I.n && y >= 0 && y < I.n;
-            own[k] = act[k] && lx >= H && lx < H + kFTX && ly >= H && ly < H + kFTY;
+            own[k] = act[k] && lx >= H && lx < H + kFTX && ly >= H && ly < H + FTY;
             cc[k] = I.org + x + (int64_t)y * I.sy;
             oe[k] = (x + 1 < I.n && lx + 1 < RW) ? 1 : 0;
             ow[k] = (x > 0 && lx > 0) ? -1 : 0;
@@ -541,7 +541,8 @@ template <typename T>
 hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles,
                                const BTile *tiles3, const int64_t *ntiles3, const BTile *ftiles,
                                const int64_t *nftiles, double *part, int grid, int cheb_steps, bool mixed,
-                               bool fused, hipStream_t s) {
+                               int fh, int fty, hipStream_t s) {
+    const bool fused = fh > 0;
     const dim3 g(grid), b(256), f(ninst);
     // set-up of newly admitted instances
     hipLaunchKernelGGL(bk_init, g, b, 0, s, insts, tiles, ntiles, part);
@@ -558,14 +559,26 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
     hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 2);
     hipLaunchKernelGGL(bk_update_init<T>, g, b, 0, s, insts, tiles, ntiles);
     if (fused) {
-        // 2D instances: steps 1 .. cheb_steps-1 in launches of kFH steps (odd),
-        // the remainder one step at a time, on the fused tiles; 3D instances:
+        // 2D instances: steps 1 .. cheb_steps-1 in launches of at most fh
+        // steps (an odd number each), on the fused tiles; 3D instances:
         // one launch per step on their own tiles; then everybody's last step
         // (with the r.z and r.r partials)
         int launches = 0;
         for (int j0 = 1; j0 < cheb_steps;) {
-            const int j1 = cheb_steps - j0 >= kFH ? j0 + kFH : j0 + 1;
-            hipLaunchKernelGGL((bk_cheb_fused<T, kFH>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, launches & 1);
+            int len = cheb_steps - j0 < fh ? cheb_steps - j0 : fh;
+            len -= (len & 1) ^ 1;  // odd, so the direction lands in the other buffer
+            const int j1 = j0 + len;
+            const int alt = launches & 1;
+            if (fh == 3 && fty == 16)
+                hipLaunchKernelGGL((bk_cheb_fused<T, 3, 16>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
+            else if (fh == 3 && fty == 32)
+                hipLaunchKernelGGL((bk_cheb_fused<T, 3, 32>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
+            else if (fh == 5 && fty == 16)
+                hipLaunchKernelGGL((bk_cheb_fused<T, 5, 16>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
+            else if (fh == 5 && fty == 32)
+                hipLaunchKernelGGL((bk_cheb_fused<T, 5, 32>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
+            else
+                hipLaunchKernelGGL((bk_cheb_fused<T, 9, 16>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
             ++launches;
             j0 = j1;
         }
@@ -586,12 +599,12 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
 // (set-up, residual, one PPCG iteration); each instance advances according
 // to its own state.
 hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
-                                   const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed,
-                                   bool use_fused, hipStream_t s) {
+                                   const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed, int fh,
+                                   int fty, hipStream_t s) {
     return mixed ? enqueue_iteration_t<float>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
-                                              grid, cheb_steps, true, use_fused, s)
+                                              grid, cheb_steps, true, fh, fty, s)
                  : enqueue_iteration_t<double>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
-                                               grid, cheb_steps, false, use_fused, s);
+                                               grid, cheb_steps, false, fh, fty, s);
 }
 
 }  // namespace tc

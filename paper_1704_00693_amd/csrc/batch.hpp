@@ -33,8 +33,9 @@ enum BState : int {
 };
 
 constexpr int kBTX = 64, kBTY = 4;  // cells of one tile: one workgroup of 256 threads
-// 2D Chebyshev steps run kFH at a time on tiles of kFTX x kFTY owned cells
-// (plus kFH cells around them, recomputed), with the direction in LDS
+// 2D Chebyshev steps run up to FH at a time on tiles of kFTX x FTY owned
+// cells (plus FH cells around them, recomputed), with the direction in LDS;
+// (FH, FTY) is one of the compiled shapes below (default kFH, kFTY)
 constexpr int kFTX = 64, kFTY = 16, kFH = 3;
 constexpr int kBMaxCheb = 32;
 

@@ -186,3 +186,24 @@ def test_serving_trace_small(tc):
                 b.tc_batch_wait()
                 alone = b.tc_batch_read_x(tk)
             assert np.array_equal(alone, out["x"][i])
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fused_chebyshev_shapes_bit_identical(tc, monkeypatch, mixed):
+    """The 2D Chebyshev steps run several at a time on tiles with a
+    recomputed border (TC_BATCH_FUSED=steps,tile height; 0: one launch per
+    step): every shape gives the bits of the per-step kernels."""
+    cases = [(2, 20, 51), (2, 70, 52), (2, 129, 53), (3, 12, 54)]
+    results = {}
+    for shape in ("0", "3,16", "3,32", "5,16", "5,32", "9,16"):
+        monkeypatch.setenv("TC_BATCH_FUSED", shape)
+        say(f"batch mixed={mixed} fused={shape}")
+        with tc.Context() as c, tc.Batch(c, mixed=mixed, max_instances=4) as b:
+            ts = [b.tc_batch_submit(nd, n, seed, tol=1e-9, keep_x=True) for nd, n, seed in cases]
+            b.tc_batch_wait()
+            results[shape] = [(b.tc_batch_poll(t)["iterations"], b.tc_batch_read_x(t)) for t in ts]
+    base = results["0"]
+    for shape, res in results.items():
+        for (it0, x0), (it, x) in zip(base, res):
+            assert it == it0, shape
+            assert np.array_equal(x, x0), shape
