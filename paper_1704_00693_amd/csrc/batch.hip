@@ -268,9 +268,12 @@ __global__ void __launch_bounds__(256) bk_matvec(BInst *insts, const BTile *tile
 }
 
 // INNER: x += alpha p, r -= alpha w; then (INNER and INNER_START) the
-// preconditioner's start: rt = r, sd = rt / theta, z = 0.
+// preconditioner's start: rt = r, sd = rt / theta, z = 0 (skipped for 2D
+// instances when skip2d is set: the first fused Chebyshev launch starts from
+// r itself).
 template <typename T>
-__global__ void __launch_bounds__(256) bk_update_init(BInst *insts, const BTile *tiles, const int64_t *ntiles) {
+__global__ void __launch_bounds__(256) bk_update_init(BInst *insts, const BTile *tiles, const int64_t *ntiles,
+                                                      int skip2d) {
     const int64_t nt = *ntiles;
     const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
     for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
@@ -287,6 +290,7 @@ __global__ void __launch_bounds__(256) bk_update_init(BInst *insts, const BTile 
             rv = fmaB<T>(-al, ((const T *)I.w)[k.c], rv);
             r[k.c] = rv;
         }
+        if (skip2d && I.ndim == 2) continue;
         ((T *)I.rt)[k.c] = rv;
         ((T *)I.sd0)[k.c] = rv / (T)I.theta;
         ((T *)I.z)[k.c] = (T)0;
@@ -350,7 +354,7 @@ __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles,
 // order.
 template <typename T, int H, int FTY>
 __global__ void __launch_bounds__(256) bk_cheb_fused(BInst *insts, const BTile *tiles, const int64_t *ntiles, int j0,
-                                                     int j1, int rt_alt) {
+                                                     int j1, int rt_alt, int start) {
     constexpr int RW = kFTX + 2 * H, RH = FTY + 2 * H, RC = RW * RH;
     constexpr int PER = (RC + 255) / 256;
     __shared__ T sdl[2][RC];
@@ -388,9 +392,17 @@ __global__ void __launch_bounds__(256) bk_cheb_fused(BInst *insts, const BTile *
                 kw[k] = kx[c];
                 kn[k] = ky[c + I.sy];
                 ks[k] = ky[c];
-                rt[k] = rt_in[c];
-                if (own[k]) z[k] = ((const T *)I.z)[c];
-                sdl[0][i] = sd[c];
+                if (start) {
+                    // the preconditioner's start, as bk_update_init writes it
+                    const T rv = ((const T *)I.ri)[c];
+                    rt[k] = rv;
+                    z[k] = (T)0;
+                    sdl[0][i] = rv / (T)I.theta;
+                } else {
+                    rt[k] = rt_in[c];
+                    if (own[k]) z[k] = ((const T *)I.z)[c];
+                    sdl[0][i] = sd[c];
+                }
             }
         }
         __syncthreads();
@@ -557,7 +569,9 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
     hipLaunchKernelGGL(bk_cg_p<T>, g, b, 0, s, insts, tiles, ntiles);
     hipLaunchKernelGGL(bk_matvec<T>, g, b, 0, s, insts, tiles, ntiles, part);
     hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 2);
-    hipLaunchKernelGGL(bk_update_init<T>, g, b, 0, s, insts, tiles, ntiles);
+    // with fused Chebyshev launches the first one starts 2D instances from r
+    const int skip2d = fused && cheb_steps > 1 ? 1 : 0;
+    hipLaunchKernelGGL(bk_update_init<T>, g, b, 0, s, insts, tiles, ntiles, skip2d);
     if (fused) {
         // 2D instances: steps 1 .. cheb_steps-1 in launches of at most fh
         // steps (an odd number each), on the fused tiles; 3D instances:
@@ -568,17 +582,17 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
             int len = cheb_steps - j0 < fh ? cheb_steps - j0 : fh;
             len -= (len & 1) ^ 1;  // odd, so the direction lands in the other buffer
             const int j1 = j0 + len;
-            const int alt = launches & 1;
+            const int alt = launches & 1, first = launches == 0 ? 1 : 0;
             if (fh == 3 && fty == 16)
-                hipLaunchKernelGGL((bk_cheb_fused<T, 3, 16>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
+                hipLaunchKernelGGL((bk_cheb_fused<T, 3, 16>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt, first);
             else if (fh == 3 && fty == 32)
-                hipLaunchKernelGGL((bk_cheb_fused<T, 3, 32>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
+                hipLaunchKernelGGL((bk_cheb_fused<T, 3, 32>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt, first);
             else if (fh == 5 && fty == 16)
-                hipLaunchKernelGGL((bk_cheb_fused<T, 5, 16>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
+                hipLaunchKernelGGL((bk_cheb_fused<T, 5, 16>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt, first);
             else if (fh == 5 && fty == 32)
-                hipLaunchKernelGGL((bk_cheb_fused<T, 5, 32>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
+                hipLaunchKernelGGL((bk_cheb_fused<T, 5, 32>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt, first);
             else
-                hipLaunchKernelGGL((bk_cheb_fused<T, 9, 16>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt);
+                hipLaunchKernelGGL((bk_cheb_fused<T, 9, 16>), g, b, 0, s, insts, ftiles, nftiles, j0, j1, alt, first);
             ++launches;
             j0 = j1;
         }
