@@ -388,7 +388,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--warm-seconds", type=float, default=WARM_SECONDS,
                     help="least wall time each chain mode is warmed before timing (counter runs use 0)")
-    ap.add_argument("--cpu-sample", type=int, default=2048, help="grid edge of the oracle's timed sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=3072, help="grid edge of the oracle's timed sample (0: skip)")
     ap.add_argument("--fused-tile", default="0,0,0",
                     help="fused mode tile: rows per wavefront segment, window-register budget, most loops per group "
                          "(0: automatic)")
