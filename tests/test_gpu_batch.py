@@ -207,3 +207,26 @@ def test_fused_chebyshev_shapes_bit_identical(tc, monkeypatch, mixed):
         for (it0, x0), (it, x) in zip(base, res):
             assert it == it0, shape
             assert np.array_equal(x, x0), shape
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batch_full_size_instances(tc, mixed):
+    """Instances at the top of the batched workload's size range (1023^2,
+    the largest 2D size drawn) next to smaller 2D and 3D ones: every solve
+    converges and its true relative residual, recomputed by the oracle's
+    operator from the returned x, is within the tolerance and equal to the
+    one the engine reports."""
+    tol = 1e-8
+    cases = [(2, 1023, 61), (2, 700, 62), (2, 97, 63), (3, 64, 64)]
+    with tc.Context() as c, tc.Batch(c, mixed=mixed, max_instances=4) as b:
+        ts = [b.tc_batch_submit(nd, n, seed, tol=tol, keep_x=True) for nd, n, seed in cases]
+        b.tc_batch_wait()
+        for (nd, n, seed), t in zip(cases, ts):
+            r = b.tc_batch_poll(t)
+            x = b.tc_batch_read_x(t)
+            hp = heat_problem(n, seed=seed, ndim=nd)
+            res, _ = true_residual(hp, x)
+            say(f"  mixed={mixed} ndim={nd} n={n}: iterations {r['iterations']} residual {res:.3e}")
+            assert r["state"] == tc.TC_SOLVE_DONE and r["converged"] == 1
+            assert res <= tol * (1 + 1e-6)
+            assert abs(res - r["rel_residual"]) <= 1e-6 * res + 1e-15
