@@ -408,7 +408,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU design is described in DESIGN.md, not built)", file=sys.stderr)
+              "(several GPUs would split the grid into slabs with one deep-halo exchange per chain; "
+              "that path is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
