@@ -319,3 +319,44 @@ def test_full_size_3d_chain_sampled(tc):
     assert sums[0] == sums[1]
     for d in range(ch.ndat):
         assert np.array_equal(outs[0][d], outs[1][d])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fused_offset_ranges(tc, seed):
+    """Fused groups over a range that starts away from the origin (x start
+    not on a 16-column line) of a non-square grid with wide halos: the
+    interior grid sits inside the range with edge bands on all four sides.
+    Fused results equal the untiled ones bit for bit, which match the
+    oracle."""
+    from randchains import star_pts
+    rng = random.Random(900 + seed)
+    n = [203, 171]
+    ndat = 6
+    st = [rng.randint(3, 20), rng.randint(1, 20)]
+    en = [n[0] - rng.randint(0, 10), n[1] - rng.randint(0, 10)]
+    loops = []
+    for _ in range(rng.randint(10, 16)):
+        dats = list(range(ndat))
+        rng.shuffle(dats)
+        ins = []
+        for a in dats[1:1 + rng.randint(1, 3)]:
+            if rng.random() < 0.6:
+                sten = star_pts(2, rng.randint(1, 2))
+            else:
+                sten = [(0, 0)] + [tuple(rng.randint(-2, 2) for _ in range(2)) for _ in range(rng.randint(1, 4))]
+            ins.append({"dat": a, "stencil": sten, "access": "R"})
+        w = [rng.uniform(-0.3, 0.3) for a in ins for _ in a["stencil"]]
+        loops.append({"op": "WSUM", "start": st, "end": en, "params": w,
+                      "args": [{"dat": dats[0], "stencil": [(0, 0)], "access": "W"}] + ins})
+    ch = {"ndim": 2, "ndat": ndat, "n": n, "halo": 4, "loops": loops}
+    data = op_chain_data(ch, seed=seed)
+    ref = run_op_chain_oracle(ch, data)
+    base, _ = run_gpu_op_chain(tc, ch, data, tc.TC_TILING_NONE)
+    for g, r in zip(base, ref):
+        assert rel_err(g, r) <= TOL
+    for tile in [(0, 0, 0), (24, 0, 0), (0, 96, 4)]:
+        got, st_ = run_gpu_op_chain(tc, ch, data, tc.TC_TILING_FUSED, tile)
+        say(f"offset range {st}..{en} loops={len(loops)} fused tile={tile}: groups {st_['last_groups']}")
+        assert st_["last_groups"] >= 1
+        for g, gf in zip(base, got):
+            assert np.array_equal(g, gf)
