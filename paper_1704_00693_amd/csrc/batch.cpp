@@ -17,7 +17,7 @@
 namespace tc {
 hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
                                    const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed, int fh,
-                                   int fty, hipStream_t s);
+                                   int fty, bool with3d, hipStream_t s);
 }
 
 using namespace tc;
@@ -33,7 +33,10 @@ struct tc_batch {
     double *d_part = nullptr;
     int64_t tile_cap = 0;
     int grid = 0;
-    hipGraphExec_t gexec = nullptr;
+    // the captured iteration; gexec2d leaves out the 3D instances' per-step
+    // Chebyshev launches (replayed while no 3D solve is resident)
+    hipGraphExec_t gexec = nullptr, gexec2d = nullptr;
+    bool has3d = false;
     bool replayed = false;  // replays are in flight on the stream
 
     struct Slot {
@@ -238,6 +241,7 @@ tc_status rebuild_tiles(tc_batch *b) {
     }
     *b->all.hn = nt;
     *b->three.hn = n3;
+    b->has3d = n3 > 0;
     *b->fused.hn = nf;
     auto up = [&](BTileList &L) {
         return hipMemcpyAsync(L.d, L.h, (size_t)std::max<int64_t>(*L.hn, 1) * sizeof(BTile), hipMemcpyHostToDevice,
@@ -255,17 +259,19 @@ tc_status capture(tc_batch *b) {
     Ctx &c = C(b);
     if (!c.cap_stream && hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess)
         return fail(c, TC_ERR_DEVICE, "tc_batch: cannot create the capture stream");
-    hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed to start");
-    const hipError_t e = batch_enqueue_iteration(b->d_inst, (int)b->slots.size(), b->all, b->three, b->fused,
-                                                 b->d_part, b->grid, b->o.cheb_steps, b->o.mixed != 0, b->fh, b->fty,
-                                                 c.cap_stream);
-    const hipError_t e2 = hipStreamEndCapture(c.cap_stream, &g);
-    if (e != hipSuccess || e2 != hipSuccess || !g) return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed");
-    const hipError_t e3 = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e3 != hipSuccess) return fail(c, TC_ERR_DEVICE, "tc_batch: graph instantiation failed");
+    for (int with3d = 1; with3d >= 0; --with3d) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed to start");
+        const hipError_t e = batch_enqueue_iteration(b->d_inst, (int)b->slots.size(), b->all, b->three, b->fused,
+                                                     b->d_part, b->grid, b->o.cheb_steps, b->o.mixed != 0, b->fh,
+                                                     b->fty, with3d != 0, c.cap_stream);
+        const hipError_t e2 = hipStreamEndCapture(c.cap_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess || !g) return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed");
+        const hipError_t e3 = hipGraphInstantiate(with3d ? &b->gexec : &b->gexec2d, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(c, TC_ERR_DEVICE, "tc_batch: graph instantiation failed");
+    }
     return TC_OK;
 }
 
@@ -387,8 +393,9 @@ tc_status tc_batch_step(tc_batch *b, int32_t *unfinished) {
         if (st != TC_OK) return st;
     }
     if (!b->running.empty()) {
+        hipGraphExec_t ge = b->has3d || b->fh == 0 ? b->gexec : b->gexec2d;
         for (int k = 0; k < b->o.replays_per_step; ++k)
-            if (hipGraphLaunch(b->gexec, c.stream) != hipSuccess)
+            if (hipGraphLaunch(ge, c.stream) != hipSuccess)
                 return fail(c, TC_ERR_DEVICE, "tc_batch_step: graph launch failed");
         b->replayed = true;
     }
@@ -437,6 +444,7 @@ tc_status tc_batch_destroy(tc_batch *b) {
     for (auto &S : b->slots)
         if (S.mem) dev_free(c, S.mem);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->gexec2d) (void)hipGraphExecDestroy(b->gexec2d);
     if (b->d_inst) dev_free(c, b->d_inst);
     for (BTileList *L : {&b->all, &b->three, &b->fused}) {
         if (L->d) dev_free(c, L->d);

@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles,
             // after an odd number of fused launches a 2D instance's rt is in rt2
             T *rt = (T *)((rt_alt && I.ndim == 2) ? I.rt2 : I.rt), *z = (T *)I.z;
             const T rtv = rt[k.c] - av;
-            rt[k.c] = rtv;
+            if (!last) rt[k.c] = rtv;  // after the last step rt is not read again
             const T zv = z[k.c] + sd[k.c];
             z[k.c] = zv;
             if (!last) {
@@ -553,7 +553,7 @@ template <typename T>
 hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles,
                                const BTile *tiles3, const int64_t *ntiles3, const BTile *ftiles,
                                const int64_t *nftiles, double *part, int grid, int cheb_steps, bool mixed,
-                               int fh, int fty, hipStream_t s) {
+                               int fh, int fty, bool with3d, hipStream_t s) {
     const bool fused = fh > 0;
     const dim3 g(grid), b(256), f(ninst);
     // set-up of newly admitted instances
@@ -596,8 +596,9 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
             ++launches;
             j0 = j1;
         }
-        for (int j = 1; j < cheb_steps; ++j)
-            hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles3, ntiles3, part, j, 0);
+        if (with3d)
+            for (int j = 1; j < cheb_steps; ++j)
+                hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles3, ntiles3, part, j, 0);
         hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, cheb_steps, launches & 1);
     } else {
         for (int j = 1; j <= cheb_steps; ++j)
@@ -614,11 +615,11 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
 // to its own state.
 hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
                                    const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed, int fh,
-                                   int fty, hipStream_t s) {
+                                   int fty, bool with3d, hipStream_t s) {
     return mixed ? enqueue_iteration_t<float>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
-                                              grid, cheb_steps, true, fh, fty, s)
+                                              grid, cheb_steps, true, fh, fty, with3d, s)
                  : enqueue_iteration_t<double>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
-                                               grid, cheb_steps, false, fh, fty, s);
+                                               grid, cheb_steps, false, fh, fty, with3d, s);
 }
 
 }  // namespace tc
