@@ -314,17 +314,21 @@ __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles,
         DD rz = red_identity(TC_RED_SUM), rr = red_identity(TC_RED_SUM);
         if (k.ok) {
             const T *sd = (const T *)((j & 1) ? I.sd0 : I.sd1);
-            T *sdn = (T *)((j & 1) ? I.sd1 : I.sd0);
-            const T av = apply_A<T>(I, (const T *)I.kxi, (const T *)I.kyi, (const T *)I.kzi, sd, k);
-            // after an odd number of fused launches a 2D instance's rt is in rt2
-            T *rt = (T *)((rt_alt && I.ndim == 2) ? I.rt2 : I.rt), *z = (T *)I.z;
-            const T rtv = rt[k.c] - av;
-            if (!last) rt[k.c] = rtv;  // after the last step rt is not read again
-            const T zv = z[k.c] + sd[k.c];
-            z[k.c] = zv;
+            T *z = (T *)I.z;
             if (!last) {
+                T *sdn = (T *)((j & 1) ? I.sd1 : I.sd0);
+                const T av = apply_A<T>(I, (const T *)I.kxi, (const T *)I.kyi, (const T *)I.kzi, sd, k);
+                // after an odd number of fused launches a 2D instance's rt is in rt2
+                T *rt = (T *)((rt_alt && I.ndim == 2) ? I.rt2 : I.rt);
+                const T rtv = rt[k.c] - av;
+                rt[k.c] = rtv;
+                z[k.c] = z[k.c] + sd[k.c];
                 sdn[k.c] = fmaB<T>((T)I.al[j - 1], sd[k.c], (T)I.be[j - 1] * rtv);
             } else {
+                // the last step's rt and direction are never read: only z
+                // and the partials
+                const T zv = z[k.c] + sd[k.c];
+                z[k.c] = zv;
                 const T rv = ((const T *)I.ri)[k.c];
                 dd_add_prod(rz, (double)rv, (double)zv);
                 dd_add_prod(rr, (double)rv, (double)rv);
