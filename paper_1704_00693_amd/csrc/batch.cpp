@@ -17,7 +17,7 @@
 namespace tc {
 hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
                                    const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed, int fh,
-                                   int fty, bool with3d, hipStream_t s);
+                                   int fty, bool with3d, bool setup, hipStream_t s);
 }
 
 using namespace tc;
@@ -33,9 +33,10 @@ struct tc_batch {
     double *d_part = nullptr;
     int64_t tile_cap = 0;
     int grid = 0;
-    // the captured iteration; gexec2d leaves out the 3D instances' per-step
-    // Chebyshev launches (replayed while no 3D solve is resident)
-    hipGraphExec_t gexec = nullptr, gexec2d = nullptr;
+    // the captured iteration, gx[setup][with3d]: without set-up kernels
+    // (replayed except right after an admission), without the 3D instances'
+    // per-step Chebyshev launches (replayed while no 3D solve is resident)
+    hipGraphExec_t gx[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     bool has3d = false;
     bool replayed = false;  // replays are in flight on the stream
 
@@ -259,19 +260,21 @@ tc_status capture(tc_batch *b) {
     Ctx &c = C(b);
     if (!c.cap_stream && hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess)
         return fail(c, TC_ERR_DEVICE, "tc_batch: cannot create the capture stream");
-    for (int with3d = 1; with3d >= 0; --with3d) {
-        hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed to start");
-        const hipError_t e = batch_enqueue_iteration(b->d_inst, (int)b->slots.size(), b->all, b->three, b->fused,
-                                                     b->d_part, b->grid, b->o.cheb_steps, b->o.mixed != 0, b->fh,
-                                                     b->fty, with3d != 0, c.cap_stream);
-        const hipError_t e2 = hipStreamEndCapture(c.cap_stream, &g);
-        if (e != hipSuccess || e2 != hipSuccess || !g) return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed");
-        const hipError_t e3 = hipGraphInstantiate(with3d ? &b->gexec : &b->gexec2d, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e3 != hipSuccess) return fail(c, TC_ERR_DEVICE, "tc_batch: graph instantiation failed");
-    }
+    for (int setup = 0; setup < 2; ++setup)
+        for (int with3d = 0; with3d < 2; ++with3d) {
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed to start");
+            const hipError_t e = batch_enqueue_iteration(b->d_inst, (int)b->slots.size(), b->all, b->three, b->fused,
+                                                         b->d_part, b->grid, b->o.cheb_steps, b->o.mixed != 0, b->fh,
+                                                         b->fty, with3d != 0, setup != 0, c.cap_stream);
+            const hipError_t e2 = hipStreamEndCapture(c.cap_stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess || !g)
+                return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed");
+            const hipError_t e3 = hipGraphInstantiate(&b->gx[setup][with3d], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e3 != hipSuccess) return fail(c, TC_ERR_DEVICE, "tc_batch: graph instantiation failed");
+        }
     return TC_OK;
 }
 
@@ -358,7 +361,7 @@ tc_status tc_batch_step(tc_batch *b, int32_t *unfinished) {
             return fail(c, TC_ERR_DEVICE, "tc_batch_step: device sync failed");
         b->replayed = false;
     }
-    bool dirty = false;
+    bool dirty = false, admitted = false;
     for (size_t s = 0; s < b->slots.size(); ++s)
         if (b->slots[s].ticket >= 0 && b->h_inst[s].state == B_DONE) {
             retire(b, (int)s);
@@ -387,15 +390,18 @@ tc_status tc_batch_step(tc_batch *b, int32_t *unfinished) {
         if (st != TC_OK) return st;
         b->pending.pop_front();
         dirty = true;
+        admitted = true;
     }
     if (dirty) {
         const tc_status st = rebuild_tiles(b);
         if (st != TC_OK) return st;
     }
     if (!b->running.empty()) {
-        hipGraphExec_t ge = b->has3d || b->fh == 0 ? b->gexec : b->gexec2d;
+        // instances are in the set-up state only from their admission to the
+        // end of the next iteration
+        const int with3d = b->has3d || b->fh == 0 ? 1 : 0;
         for (int k = 0; k < b->o.replays_per_step; ++k)
-            if (hipGraphLaunch(ge, c.stream) != hipSuccess)
+            if (hipGraphLaunch(b->gx[admitted && k == 0 ? 1 : 0][with3d], c.stream) != hipSuccess)
                 return fail(c, TC_ERR_DEVICE, "tc_batch_step: graph launch failed");
         b->replayed = true;
     }
@@ -443,8 +449,9 @@ tc_status tc_batch_destroy(tc_batch *b) {
     (void)hipStreamSynchronize(c.stream);
     for (auto &S : b->slots)
         if (S.mem) dev_free(c, S.mem);
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    if (b->gexec2d) (void)hipGraphExecDestroy(b->gexec2d);
+    for (auto &row : b->gx)
+        for (hipGraphExec_t ge : row)
+            if (ge) (void)hipGraphExecDestroy(ge);
     if (b->d_inst) dev_free(c, b->d_inst);
     for (BTileList *L : {&b->all, &b->three, &b->fused}) {
         if (L->d) dev_free(c, L->d);

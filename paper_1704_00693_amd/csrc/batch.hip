@@ -557,14 +557,17 @@ template <typename T>
 hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles,
                                const BTile *tiles3, const int64_t *ntiles3, const BTile *ftiles,
                                const int64_t *nftiles, double *part, int grid, int cheb_steps, bool mixed,
-                               int fh, int fty, bool with3d, hipStream_t s) {
+                               int fh, int fty, bool with3d, bool setup, hipStream_t s) {
     const bool fused = fh > 0;
     const dim3 g(grid), b(256), f(ninst);
-    // set-up of newly admitted instances
-    hipLaunchKernelGGL(bk_init, g, b, 0, s, insts, tiles, ntiles, part);
-    hipLaunchKernelGGL(bk_faces<T>, g, b, 0, s, insts, tiles, ntiles);
-    hipLaunchKernelGGL(bk_gersh, g, b, 0, s, insts, tiles, ntiles, part);
-    hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 0);
+    // set-up of newly admitted instances (only the first iteration after an
+    // admission has any: left out of the other replays)
+    if (setup) {
+        hipLaunchKernelGGL(bk_init, g, b, 0, s, insts, tiles, ntiles, part);
+        hipLaunchKernelGGL(bk_faces<T>, g, b, 0, s, insts, tiles, ntiles);
+        hipLaunchKernelGGL(bk_gersh, g, b, 0, s, insts, tiles, ntiles, part);
+        hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 0);
+    }
     // refinement step (mixed) / first and verifying residuals
     if (mixed) hipLaunchKernelGGL(bk_apply_correction<T>, g, b, 0, s, insts, tiles, ntiles);
     hipLaunchKernelGGL(bk_resid<T>, g, b, 0, s, insts, tiles, ntiles, part);
@@ -619,11 +622,11 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
 // to its own state.
 hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
                                    const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed, int fh,
-                                   int fty, bool with3d, hipStream_t s) {
+                                   int fty, bool with3d, bool setup, hipStream_t s) {
     return mixed ? enqueue_iteration_t<float>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
-                                              grid, cheb_steps, true, fh, fty, with3d, s)
+                                              grid, cheb_steps, true, fh, fty, with3d, setup, s)
                  : enqueue_iteration_t<double>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
-                                               grid, cheb_steps, false, fh, fty, with3d, s);
+                                               grid, cheb_steps, false, fh, fty, with3d, setup, s);
 }
 
 }  // namespace tc
