@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(256) bk_update_init(BInst *insts, const BTile 
 // step adds the partials r . z (slot 0) and r . r (slot 1).
 template <typename T>
 __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part,
-                                               int j, int rt_alt) {
+                                               int j) {
     const int64_t nt = *ntiles;
     const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
     for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
@@ -318,8 +318,7 @@ __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles,
             if (!last) {
                 T *sdn = (T *)((j & 1) ? I.sd1 : I.sd0);
                 const T av = apply_A<T>(I, (const T *)I.kxi, (const T *)I.kyi, (const T *)I.kzi, sd, k);
-                // after an odd number of fused launches a 2D instance's rt is in rt2
-                T *rt = (T *)((rt_alt && I.ndim == 2) ? I.rt2 : I.rt);
+                T *rt = (T *)I.rt;
                 const T rtv = rt[k.c] - av;
                 rt[k.c] = rtv;
                 z[k.c] = z[k.c] + sd[k.c];
@@ -343,7 +342,7 @@ __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles,
 
 // Chebyshev steps j0 .. j1-1 (j1 - j0 <= H and odd) of 2D instances; the
 // last step, with its reductions, stays with bk_cheb.  A workgroup takes a
-// tile of kFTX x kFTY owned cells and the H cells around it (inside the
+// tile of kFTX x FTY owned cells and the H cells around it (inside the
 // domain): face coefficients, rt and the direction are loaded once (z for
 // the owned cells only: no neighbour needs it), each step exchanges the
 // direction through LDS, and rt, z and the last direction are stored for the
@@ -605,11 +604,11 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
         }
         if (with3d)
             for (int j = 1; j < cheb_steps; ++j)
-                hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles3, ntiles3, part, j, 0);
-        hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, cheb_steps, launches & 1);
+                hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles3, ntiles3, part, j);
+        hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, cheb_steps);
     } else {
         for (int j = 1; j <= cheb_steps; ++j)
-            hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, j, 0);
+            hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, j);
     }
     hipLaunchKernelGGL(bk_finalize, f, b, 0, s, insts, ninst, part, 3);
     return hipGetLastError();
