@@ -581,14 +581,7 @@ tc_status flush(Ctx &c) {
     tc_tiling mode = c.mode;
     int tile[3] = {c.tile[0], c.tile[1], c.tile[2]};
     const bool tuning_flush = mode == TC_TILING_AUTO;
-    if (tuning_flush) {
-        mode = autotune_choose(c, chain, tile);
-        if (c.tune_cand >= 0) {
-            for (auto &e : c.tune_ev)
-                if (!e) HIPCHK(c, hipEventCreate(&e));
-            HIPCHK(c, hipEventRecord(c.tune_ev[0], c.stream));
-        }
-    }
+    if (tuning_flush) mode = autotune_choose(c, chain, tile);
 
     tc_status st = TC_OK;
     int64_t bytes = 0, cells = 0;
@@ -624,6 +617,11 @@ tc_status flush(Ctx &c) {
         }
         st = ensure_partials(c, P->partials_total, (int)P->red_handles.size());
         if (st != TC_OK) return st;
+        if (tuning_flush && c.tune_cand >= 0) {  // the candidate's device time, plan work excluded
+            for (auto &e : c.tune_ev)
+                if (!e) HIPCHK(c, hipEventCreate(&e));
+            HIPCHK(c, hipEventRecord(c.tune_ev[0], c.stream));
+        }
         st = run_launches(c, chain, *P);
         if (st != TC_OK) return st;
         red_handles = P->red_handles;

@@ -1,15 +1,19 @@
-// AUTO mode: per chain structure, time each candidate schedule once and keep
-// the fastest.
+// AUTO mode: per chain structure, time each candidate schedule and keep the
+// fastest.
 #include "fused.hpp"
 
 namespace tc {
 
 // AUTO mode (Section 4.3 chooses a tile size from the cache size; here the
 // cache-based choice is one candidate and every candidate is measured): the
-// first flushes of a chain structure each run one candidate schedule while
-// its device time is measured; afterwards the fastest is used.  Every
-// candidate computes bit-identical results, so tuning never changes answers.
+// first flushes of a chain structure run the candidate schedules in turn,
+// three flushes each; the first two build the plan (and compile fused
+// kernels, capture the launch graph, allocate second buffers) and are not
+// timed, the device time of the third is recorded.  Afterwards the fastest
+// is used.  Every candidate computes bit-identical results, so tuning never
+// changes answers.
 namespace {
+constexpr int kTuneWarm = 2;  // untimed flushes of a candidate before the timed one
 struct Cand {
     tc_tiling mode;
     int tile[3];
@@ -45,8 +49,13 @@ tc_tiling autotune_choose(Ctx &c, const std::vector<LoopRec> &chain, int tile[3]
         c.tune_cand = -1;
     } else {
         pick = T.next;
-        c.tune_cand = pick;
         c.tune_key = key;
+        if (T.warm < kTuneWarm) {
+            ++T.warm;
+            c.tune_cand = -1;  // warming up: not timed
+        } else {
+            c.tune_cand = pick;
+        }
     }
     for (int d = 0; d < 3; ++d) tile[d] = cands[pick].tile[d];
     return cands[pick].mode;
@@ -57,6 +66,7 @@ void autotune_record(Ctx &c, double seconds) {
     Ctx::Tune &T = c.tuned[c.tune_key];
     T.seconds.push_back(seconds);
     T.next = c.tune_cand + 1;
+    T.warm = 0;
     // the candidate list depends only on the chain structure, so its length
     // is recovered from the number of candidates of any chain with this key
     c.tune_cand = -1;

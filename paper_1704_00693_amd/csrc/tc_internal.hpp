@@ -198,6 +198,7 @@ struct Ctx {
     // measured device times and the choice once every candidate has run
     struct Tune {
         int next = 0;
+        int warm = 0;  // untimed flushes of candidate `next` so far
         int best = -1;
         std::vector<double> seconds;
     };

@@ -189,8 +189,9 @@ def test_full_size_2d_chain_sampled(tc):
 
 
 def test_autotuner_results_identical(tc):
-    """AUTO mode measures every candidate schedule on successive flushes,
-    then keeps the fastest; each flush must give the untiled answer."""
+    """AUTO mode measures every candidate schedule on successive flushes
+    (three each: two untimed, one timed), then keeps the fastest; each flush
+    must give the untiled answer."""
     from paper_1704_00693_amd.apps import ChainRunner
     ch = make_chain(2, 200, 8, 12, seed=9)
     data = chain_data(ch)
@@ -200,7 +201,7 @@ def test_autotuner_results_identical(tc):
         c.tc_set_tiling(tc.TC_TILING_AUTO, (0, 0, 0))
         r = ChainRunner(c, ch, data)
         ru = ChainRunner(u, ch, data)
-        for k in range(8):
+        for k in range(3 * 5 + 4):  # five candidates for a 2D weighted-sum chain
             say(f"autotune flush {k}")
             r.run()
             ru.run()
@@ -208,8 +209,9 @@ def test_autotuner_results_identical(tc):
             for d in range(ch.ndat):
                 assert np.array_equal(r.read(d), ru.read(d))
     say(f"  modes used: {modes}")
-    assert len(set(modes[:5])) >= 2          # several candidates were tried
-    assert modes[-1] == modes[-2] == modes[-3]  # then one was kept
+    assert len(set(modes[:15])) >= 3  # untiled, skewed and fused were tried
+    assert modes[0] == modes[1] == modes[2]  # each candidate three flushes in a row
+    assert len(set(modes[15:])) == 1  # then one was kept
 
 
 def test_fused_weight_change(tc):
