@@ -25,7 +25,7 @@ struct SplitParams {
     int hseg = 0;      // rows per wavefront segment (0: automatic)
     int regs = 160;    // budget of window registers per lane
     int max_loops = 32;
-    int U = 4, PF = 2;
+    int U = 3, PF = 1;
     bool bake = false;
     int cpl = 1;       // columns per lane
     int wpe = 2;       // wavefronts per SIMD requested for the interior kernels (0: compiler's choice)

@@ -90,7 +90,7 @@ struct FusedGroup {
     bool sched_fence = false;  // scheduling barrier between the loops of a step
     int HL = 0, HR = 0, Wo = 0;
     int BMAX = 0, TMAX = 0;  // rows below / above the owned rows that are read
-    int Hseg = 0, U = 4, PF = 2;
+    int Hseg = 0, U = 3, PF = 1;
     int nstrips = 0, nsegs = 0;  // a plain grid of Wo-column strips and Hseg-row segments over the range
     // interior waves: in_ns strips by in_ng segments from (xlo + in_x, ylo + in_y)
     int in_x = 0, in_y = 0, in_ns = 0, in_ng = 0;

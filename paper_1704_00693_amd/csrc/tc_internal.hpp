@@ -227,8 +227,8 @@ struct Ctx {
 
     // fused groups: generated kernels compiled at plan time, cached by source
     std::unordered_map<uint64_t, hipModule_t> jit_modules;
-    int jit_unroll = 4;      // steps per iteration of the generated march loop (TC_JIT_UNROLL)
-    int jit_prefetch = 2;    // rows loaded ahead of their arrival step (TC_JIT_PREFETCH)
+    int jit_unroll = 3;      // steps per iteration of the generated march loop (TC_JIT_UNROLL)
+    int jit_prefetch = 1;    // rows loaded ahead of their arrival step (TC_JIT_PREFETCH)
     int jit_edge_div = 4;  // TC_JIT_EDGE_DIV: edge wavefronts march Hseg / this many rows
     int jit_wpe = 2;         // wavefronts per SIMD asked of the interior fused kernels (TC_JIT_WPE, 0: compiler's choice)
     int jit_max_window = 0;  // split the readers of a loaded dataset above this window (TC_JIT_MAXWIN, 0: never)
