@@ -266,3 +266,36 @@ def taylor_green(n: int, halo: int = 2, gamma: float = 1.4, mach: float = 0.1) -
     rho = np.ones_like(u)
     E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
     return [np.ascontiguousarray(a) for a in (rho, rho * u, rho * v, rho * w, E)]
+
+
+# --------------------------------------------------------------------------
+# Jacobi iteration of the 2D heat equation (the paper's baseline benchmark)
+# --------------------------------------------------------------------------
+
+# One explicit heat-equation step u' = u + nu (sum of the four neighbours - 4u)
+# with nu = 1/5: every one of the five points weighs 0.2 (the centre weight
+# 1 - 4 nu is 0.2 as well).  Points: centre, then -x, +x, -y, +y.
+JACOBI_POINTS = [(0, 0), (-1, 0), (1, 0), (0, -1), (0, 1)]
+JACOBI_WEIGHTS = [0.2] * 5
+
+
+def jacobi_field(n: int, seed: int = 5) -> np.ndarray:
+    """(n + 2)^2 values (y, x), the one-cell Dirichlet layer included: uniform
+    [0, 1) from the data stream (state seed ^ DATA_SALT), row-major with x
+    fastest.  The layer keeps these values for the whole run."""
+    state0 = (seed ^ DATA_SALT) & MASK
+    size = (n + 2) * (n + 2)
+    return np.ascontiguousarray(uniform_block(state0, 0, size, 0.0, 1.0).reshape(n + 2, n + 2))
+
+
+def jacobi_mode(n: int, k: int, l: int) -> np.ndarray:
+    """(n + 2)^2 values (y, x): sin(pi k (x+1)/(n+1)) sin(pi l (y+1)/(n+1))
+    on the interior x, y in [0, n), and exactly 0 on the Dirichlet layer
+    (x or y = -1 or n)."""
+    c = np.arange(-1, n + 1, dtype=np.float64) + 1.0
+    sx = np.sin(math.pi * k * c / (n + 1))
+    sy = np.sin(math.pi * l * c / (n + 1))
+    a = np.outer(sy, sx)
+    a[0, :] = a[-1, :] = 0.0
+    a[:, 0] = a[:, -1] = 0.0
+    return np.ascontiguousarray(a)

@@ -1,0 +1,90 @@
+"""Pins of the Jacobi heat-equation oracle (the paper's baseline benchmark,
+Sections 5 and 6.2): the closed-form decay of a discrete sine mode, a
+brute-force evaluation with exactly rounded fma on tiny grids, the fixed
+Dirichlet layer, equal copy and non-copy results, and the window oracle used
+for full-size checks."""
+import math
+import sys
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle.jacobi import jacobi
+from synthgen import JACOBI_POINTS, JACOBI_WEIGHTS, jacobi_field, jacobi_mode
+
+sys.path.insert(0, "tests")
+from windows import jacobi_window  # noqa: E402
+
+
+def _fma(a, b, c):
+    """fma(a, b, c) rounded once: exact rational arithmetic, then Python's
+    correctly rounded int / int division."""
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def _brute(u0, iters, points, weights):
+    """Jacobi iterations with pure-Python loops (non-copy order)."""
+    cur = [list(map(float, row)) for row in u0]
+    ny, nx = len(cur) - 2, len(cur[0]) - 2
+    for _ in range(iters):
+        nxt = [row[:] for row in cur]
+        for y in range(ny):
+            for x in range(nx):
+                acc = 0.0
+                for (dx, dy), w in zip(points, weights):
+                    acc = _fma(w, cur[y + 1 + dy][x + 1 + dx], acc)
+                nxt[y + 1][x + 1] = acc
+        cur = nxt
+    return np.array(cur)
+
+
+@pytest.mark.parametrize("n,k,l,iters", [(37, 3, 5, 40), (24, 1, 2, 31), (16, 7, 2, 9)])
+@pytest.mark.parametrize("copy", [False, True])
+def test_sine_mode_decays_by_the_eigenvalue(n, k, l, iters, copy):
+    """sin(a (x+1)) sin(b (y+1)), a = pi k/(n+1), b = pi l/(n+1), vanishes on
+    the layer and is an eigenvector of the stencil: one iteration scales it
+    by 0.2 (1 + 2 cos a + 2 cos b)."""
+    u0 = jacobi_mode(n, k, l)
+    lam = 0.2 * (1.0 + 2.0 * math.cos(math.pi * k / (n + 1)) + 2.0 * math.cos(math.pi * l / (n + 1)))
+    got = jacobi(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
+    exact = lam ** iters * u0
+    bound = 8 * iters * np.finfo(float).eps
+    assert np.abs(got - exact).max() <= bound, (np.abs(got - exact).max(), bound)
+    assert np.all(got[0, :] == 0) and np.all(got[-1, :] == 0)
+    assert np.all(got[:, 0] == 0) and np.all(got[:, -1] == 0)
+
+
+@pytest.mark.parametrize("shape,iters", [((7, 7), 3), ((6, 9), 4), ((9, 5), 2)])
+def test_brute_force_tiny(shape, iters):
+    """Bit-exact against pure-Python loops with exactly rounded fma, on
+    square and non-square fields, with asymmetric weights so that a swapped
+    axis or offset shows."""
+    u0 = jacobi_field(max(shape), seed=9)[:shape[0], :shape[1]].copy()
+    weights = [0.3, 0.11, 0.17, 0.13, 0.29]
+    for copy in (False, True):
+        got = jacobi(u0, iters, JACOBI_POINTS, weights, copy)
+        assert np.array_equal(got, _brute(u0, iters, JACOBI_POINTS, weights))
+
+
+@pytest.mark.parametrize("iters", [6, 7])
+def test_copy_and_non_copy_agree_and_layer_is_fixed(iters):
+    u0 = jacobi_field(30, seed=3)
+    a = jacobi(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, True)
+    b = jacobi(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, False)
+    assert np.array_equal(a, b)
+    for got in (a, b):
+        assert np.array_equal(got[0, :], u0[0, :]) and np.array_equal(got[-1, :], u0[-1, :])
+        assert np.array_equal(got[:, 0], u0[:, 0]) and np.array_equal(got[:, -1], u0[:, -1])
+    # weights sum to 1 and are positive: values stay within the initial range
+    assert a.min() >= u0.min() - 1e-15 and a.max() <= u0.max() + 1e-15
+
+
+@pytest.mark.parametrize("y0,x0,s", [(0, 0, 6), (20, 13, 5), (34, 34, 6), (0, 27, 9)])
+@pytest.mark.parametrize("copy", [False, True])
+def test_window_equals_full(y0, x0, s, copy):
+    n, iters = 40, 9
+    u0 = jacobi_field(n, seed=11)
+    full = jacobi(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
+    win = jacobi_window(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, copy, y0, x0, s)
+    assert np.array_equal(win, full[y0 + 1:y0 + 1 + s, x0 + 1:x0 + 1 + s])

@@ -81,3 +81,21 @@ def euler_window(q, n, h, zlo, zhi, dt, gamma=1.4, halo=2, margin=8):
                            ctypes.c_double(b), ctypes.c_double(dt))
     sl = slice(zlo - clo, zhi - clo)
     return [a[sl] for a in qs], [a[sl] for a in r]
+
+
+def jacobi_window(u0, iters, points, weights, copy, y0, x0, s):
+    """Oracle values of the Jacobi iteration on the s x s block of interior
+    cells [y0, y0 + s) x [x0, x0 + s) of a large field u0 ((n+2)^2, the
+    Dirichlet layer included).  A cell after T iterations depends only on
+    cells within distance T, so the oracle runs on the crop that extends the
+    block by T cells per side (clipped at the real layer), whose outer ring
+    stays fixed.  Where the ring is a cut through the interior its stale
+    values reach at most T cells inwards, never the block."""
+    from oracle.jacobi import jacobi
+    n = u0.shape[0] - 2
+    ya, yb = max(y0 - iters, 0), min(y0 + s + iters, n)
+    xa, xb = max(x0 - iters, 0), min(x0 + s + iters, n)
+    # interior coordinate c is array index c + 1; the crop keeps one ring
+    crop = np.ascontiguousarray(u0[ya:yb + 2, xa:xb + 2])
+    out = jacobi(crop, iters, points, weights, copy)
+    return out[y0 - ya + 1:y0 - ya + 1 + s, x0 - xa + 1:x0 - xa + 1 + s]
