@@ -242,7 +242,8 @@ def _timed(fn, steps, warm=0.5):
 def other_workloads(tc, which, steps):
     """The other configurations, each in the execution modes that apply:
     heat-conduction PPCG 256^2 (50 iterations of 10 Chebyshev steps), the
-    256^3 Taylor-Green RK3 step, and (optionally) the 384^3 synthetic chain."""
+    256^3 Taylor-Green RK3 step, the 8192^2 Jacobi iteration (250 iterations,
+    copy and non-copy) and (optionally) the 384^3 synthetic chain."""
     out = {}
     modes = [("none", tc.TC_TILING_NONE, (0, 0, 0)), ("skewed", tc.TC_TILING_SKEWED, (0, 0, 0))]
     if "tealeaf" in which:
@@ -277,6 +278,31 @@ def other_workloads(tc, which, steps):
         out["euler_rk3_256"] = {"workload": "Taylor-Green vortex 256^3 FP64, one SSP-RK3 step of 4th-order central "
                                             "differences (40 loops + energy sum)", "modes": res}
         log(f"euler 256^3: {res}")
+    if "jacobi" in which:
+        from paper_1704_00693_amd.apps import JacobiRunner
+        from synthgen import JACOBI_POINTS, JACOBI_WEIGHTS, jacobi_field
+        n, iters = 8192, 250
+        u0 = jacobi_field(n, seed=5)
+        res = {}
+        for variant, copy in (("non_copy", False), ("copy", True)):
+            per = {}
+            for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))]:
+                with tc.Context(0) as c:
+                    c.tc_set_tiling(m, tile)
+                    r = JacobiRunner(c, u0, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
+                    dt = _timed(lambda: r.run(iters), steps)
+                    st = c.tc_get_stats()
+                per[name] = {"seconds_per_run": dt, "cell_iterations_per_s": iters * n * n / dt,
+                             "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"],
+                             "groups": st["last_groups"]}
+            per["fused_speedup_vs_untiled"] = per["none"]["seconds_per_run"] / per["fused"]["seconds_per_run"]
+            res[variant] = per
+            log(f"jacobi 8192^2 {variant}: {per}")
+        out["jacobi_8192"] = {
+            "workload": "Jacobi heat equation 8192^2 FP64 with a one-cell Dirichlet layer, 250 iterations of the "
+                        "5-point stencil (all weights 0.2), copy and non-copy variants, uniform [0,1) field, seed 5",
+            "modes": res,
+            "context_paper_cpu_seconds_untiled_tiled": {"copy": [16.06, 5.11], "non_copy": [8.58, 3.69]}}
     if "chain3d" in which:
         from paper_1704_00693_amd.apps import ChainRunner
         from synthgen import chain_3d, chain_data
@@ -394,8 +420,8 @@ def main():
                          "(0: automatic)")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="batched heat-conduction solves to run after the chain (0: skip)")
-    ap.add_argument("--other", default="tealeaf,euler",
-                    help="other workloads to time: comma list of tealeaf, euler, chain3d ('' to skip)")
+    ap.add_argument("--other", default="tealeaf,euler,jacobi",
+                    help="other workloads to time: comma list of tealeaf, euler, jacobi, chain3d ('' to skip)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
                     help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
     ap.add_argument("--serve-rate", type=float, default=200.0)

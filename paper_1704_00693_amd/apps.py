@@ -1,6 +1,7 @@
 """Workload drivers written against the tilechain ABI (user code of the library,
 as the paper's applications are user code of OPS): the synthetic
-weighted-sum chains and the heat-conduction PPCG solve.
+weighted-sum chains, the Jacobi heat-equation iteration, the heat-conduction
+PPCG solve, the compressible-Euler step and the request-serving loop.
 
 Nothing here computes on the host beyond the scalar recurrences of the solver
 (CG's alpha and beta, the Chebyshev coefficients); every loop is recorded with
@@ -62,6 +63,71 @@ class ChainRunner:
 
     def read(self, d: int) -> np.ndarray:
         return self.ctx.tc_dat_read(self.dats[d])
+
+
+# ---------------------------------------------------------------------------
+# Jacobi iteration of the 2D heat equation
+# ---------------------------------------------------------------------------
+class JacobiRunner:
+    """The Jacobi benchmark of the paper (Section 5; measured in Section 6.2):
+    a five-point weighted stencil applied over the interior of an n^2 field
+    whose one-cell Dirichlet layer is never written.
+
+    Two datasets a and b, both holding the initial field (layer included).
+    ``record(iters)`` enqueues iterations without executing them:
+
+    * copy variant: b = stencil(a), then a second loop copies b into a;
+    * non-copy variant: a -> b and b -> a alternately, no copy.
+
+    The copy is recorded as a one-point weighted sum with weight 1, so that it
+    can share a fused group with the stencil loops: fma(1, v, 0) is v for
+    every value except -0, which becomes +0.
+
+    ``points`` are the stencil's (x, y) offsets, ``weights`` one weight per
+    point, applied in that order."""
+
+    def __init__(self, ctx: Context, u0: np.ndarray, points: Sequence[Sequence[int]], weights: Sequence[float],
+                 copy: bool, dtype: int = TC_F64):
+        self.ctx, self.copy = ctx, copy
+        self.n = n = u0.shape[0] - 2
+        if u0.shape != (n + 2, n + 2):
+            raise ValueError(f"u0 must be (n+2, n+2), got {u0.shape}")
+        self.blk = ctx.tc_decl_block(2, "jacobi")
+        self.a = ctx.tc_decl_dat(self.blk, [n, n], [1, 1], [1, 1], u0, dtype, "a")
+        self.b = ctx.tc_decl_dat(self.blk, [n, n], [1, 1], [1, 1], u0, dtype, "b")
+        self.S = ctx.tc_decl_stencil([tuple(p) for p in points])
+        self.S_c = ctx.tc_decl_stencil([(0, 0)])
+        self.w = [float(v) for v in weights]
+        self.range = [0, n, 0, n]
+        self.done = 0  # iterations recorded so far (the non-copy variant alternates across calls)
+
+    def record(self, iters: int):
+        c = self.ctx
+        for _ in range(iters):
+            t = self.done
+            if self.copy:
+                c.tc_par_loop("WSUM", self.blk, self.range, [(self.b, self.S_c, "W"), (self.a, self.S, "R")],
+                              self.w, name="jacobi")
+                c.tc_par_loop("WSUM", self.blk, self.range, [(self.a, self.S_c, "W"), (self.b, self.S_c, "R")],
+                              [1.0], name="copy")
+            else:
+                src, dst = (self.a, self.b) if t % 2 == 0 else (self.b, self.a)
+                c.tc_par_loop("WSUM", self.blk, self.range, [(dst, self.S_c, "W"), (src, self.S, "R")], self.w,
+                              name="jacobi")
+            self.done += 1
+
+    def run(self, iters: int):
+        """Record ``iters`` iterations and execute them as one chain."""
+        self.record(iters)
+        self.ctx.tc_flush()
+
+    def current(self) -> int:
+        """The dataset that holds the latest field."""
+        return self.a if self.copy or self.done % 2 == 0 else self.b
+
+    def result(self) -> np.ndarray:
+        """The latest field, (n + 2)^2 with the layer (flushes pending loops)."""
+        return self.ctx.tc_dat_read(self.current())
 
 
 # ---------------------------------------------------------------------------
