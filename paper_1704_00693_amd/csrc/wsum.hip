@@ -12,6 +12,10 @@
 //    takes its x neighbours from adjacent lanes with cross-lane shuffles, so
 //    global loads per output point drop from sum(stencil points) to about
 //    the number of inputs and no load is conditional.
+//  * point: 2D or 3D, every input read at its centre only (a scaled copy
+//    or a pointwise combination of up to four datasets).  Each lane computes
+//    kPointRows rows of one column and issues all their loads before the
+//    first fma chain, so four loads per input are in flight per lane.
 //  * generic: any stencils and dimensions; all loads of a point are issued
 //    before its fma chain so one memory latency covers the whole point.
 #include <hip/hip_runtime.h>
@@ -302,6 +306,62 @@ __global__ void __launch_bounds__(kBlockThreads) wsum_generic_kernel(LoopDesc d,
     o[(int64_t)x + (int64_t)y * d.arg[0].sy + (int64_t)z * d.arg[0].sz] = acc;
 }
 
+constexpr int kPointRows = 4;  // rows per lane of the point variant
+
+// b: the launch box with nby counting groups of bh * kPointRows rows.
+template <typename T, int K>
+__global__ void __launch_bounds__(kBlockThreads) wsum_point_kernel(LoopDesc d, Box b) {
+    const int lin = xcd_linear(blockIdx.x, b.nb);
+    const int bx = lin % b.nbx;
+    const int rest = lin / b.nbx;
+    const int by = rest % b.nby;
+    const int bz = rest / b.nby;
+    const int x = b.lo[0] + bx * b.bw + (int)(threadIdx.x % b.bw);
+    const int y0 = b.lo[1] + by * b.bh * kPointRows + (int)(threadIdx.x / b.bw);
+    const int z = b.lo[2] + bz;
+    if (x >= b.hi[0]) return;
+    T v[kPointRows][K];
+#pragma unroll
+    for (int r = 0; r < kPointRows; ++r) {
+        const int y = y0 + r * b.bh;
+        if (y < b.hi[1]) {
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const T *p = (const T *)d.arg[a + 1].ptr;
+                v[r][a] = p[(int64_t)x + (int64_t)y * d.arg[a + 1].sy + (int64_t)z * d.arg[a + 1].sz];
+            }
+        }
+    }
+    T *o = (T *)d.arg[0].ptr;
+#pragma unroll
+    for (int r = 0; r < kPointRows; ++r) {
+        const int y = y0 + r * b.bh;
+        if (y < b.hi[1]) {
+            T acc = (T)0;
+#pragma unroll
+            for (int a = 0; a < K; ++a) acc = fmaT<T>((T)d.prm[d.pt0[a + 1]], v[r][a], acc);
+            o[(int64_t)x + (int64_t)y * d.arg[0].sy + (int64_t)z * d.arg[0].sz] = acc;
+        }
+    }
+}
+
+// True if every input of the weighted sum is read at its centre only.
+bool centre_only_inputs(const LoopDesc &d) {
+    for (int a = 1; a < d.nargs; ++a)
+        if (d.npts[a] != 1 || d.off[d.pt0[a]] != 0) return false;
+    return d.nargs >= 2;
+}
+
+template <typename T, int K>
+hipError_t go_point(const LoopDesc &d, const Box &b, hipStream_t s) {
+    Box p = b;
+    const int ny = b.hi[1] - b.lo[1], nz = b.hi[2] - b.lo[2];
+    p.nby = (ny + b.bh * kPointRows - 1) / (b.bh * kPointRows);
+    p.nb = p.nbx * p.nby * nz;
+    hipLaunchKernelGGL((wsum_point_kernel<T, K>), dim3(p.nb), dim3(kBlockThreads), 0, s, d, p);
+    return hipGetLastError();
+}
+
 template <typename T, int K, int MASK>
 hipError_t go_march(const LoopDesc &d, const int lo[3], const int hi[3], int ty, hipStream_t s) {
     const int nbx = (hi[0] - lo[0] + kMarchOut - 1) / kMarchOut;
@@ -351,6 +411,15 @@ hipError_t wsum_t(const LoopDesc &d, const Box &b, int march_mask, int ty, hipSt
         case 2: return march_k<T, 2>(d, march_mask, b.lo, b.hi, ty, s);
         case 3: return march_k<T, 3>(d, march_mask, b.lo, b.hi, ty, s);
         case 4: return march_k<T, 4>(d, march_mask, b.lo, b.hi, ty, s);
+        default: break;
+        }
+    }
+    if (d.ndim >= 2 && b.hi[1] - b.lo[1] > 1 && b.bw * b.bh == kBlockThreads && centre_only_inputs(d)) {
+        switch (d.nargs - 1) {
+        case 1: return go_point<T, 1>(d, b, s);
+        case 2: return go_point<T, 2>(d, b, s);
+        case 3: return go_point<T, 3>(d, b, s);
+        case 4: return go_point<T, 4>(d, b, s);
         default: break;
         }
     }

@@ -72,6 +72,43 @@ def test_random_op_chains(tc, ndim):
             assert np.array_equal(g, gf)
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_centre_only_weighted_sums(tc, ndim):
+    """Weighted sums whose inputs are all read at their centre (1 to 4
+    inputs; the Jacobi copy loop is one of them) run in their own kernel,
+    four rows per lane: ragged ranges, ranges reaching into the halo, one-row
+    ranges (the generic kernel) and two-row ones, and boxes of the skewed
+    schedule, against the oracle."""
+    rng = random.Random(900 + ndim)
+    h = 2
+    n = [70, 37] if ndim == 2 else [45, 13, 9]
+    centre = [tuple([0] * ndim)]
+    loops = []
+    ranges = [([0] * ndim, list(n)),
+              ([-2] * ndim, [v + 2 for v in n]),
+              ([3] + [1] * (ndim - 1), [n[0] - 5, 2] + list(n[2:])),
+              ([0] + [5] * (ndim - 1), [n[0], 7] + [6] * (ndim - 2)),
+              ([1] * ndim, [v - 1 for v in n])]
+    for i in range(12):
+        k = 1 + i % 4
+        dats = list(range(6))
+        rng.shuffle(dats)
+        lo, hi = ranges[i % len(ranges)]
+        ins = [{"dat": a, "stencil": centre, "access": "R"} for a in dats[1:1 + k]]
+        loops.append({"op": "WSUM", "start": lo, "end": hi, "params": [rng.uniform(-1, 1) for _ in ins],
+                      "args": [{"dat": dats[0], "stencil": centre, "access": "W"}] + ins})
+    ch = {"ndim": ndim, "ndat": 6, "n": n, "halo": h, "loops": loops}
+    data = op_chain_data(ch, seed=77 + ndim)
+    ref = run_op_chain_oracle(ch, data)
+    for name, mode, tile in (("untiled", tc.TC_TILING_NONE, (0, 0, 0)),
+                             ("skewed", tc.TC_TILING_SKEWED, (0, 7, 4)[:ndim] + (0,) * (3 - ndim))):
+        say(f"centre-only weighted sums ndim={ndim} {name}")
+        got, _ = run_gpu_op_chain(tc, ch, data, mode, tile)
+        for g, r in zip(got, ref):
+            assert rel_err(g, r) <= TOL
+            assert np.array_equal(g, r)
+
+
 @pytest.mark.parametrize("ndim,n,ndat,nloops,tiles", [
     (2, 67, 12, 40, [(0, 16, 0), (24, 7, 0), (67, 67, 0)]),
     (2, 300, 12, 40, [(0, 0, 0)]),
