@@ -239,7 +239,7 @@ def _timed(fn, steps, warm=0.5):
     return (time.perf_counter() - t0) / steps
 
 
-def other_workloads(tc, which, steps):
+def other_workloads(tc, which, steps, jacobi_sizes=(8192,)):
     """The other configurations, each in the execution modes that apply:
     heat-conduction PPCG 256^2 (50 iterations of 10 Chebyshev steps), the
     256^3 Taylor-Green RK3 step, the 8192^2 Jacobi iteration (250 iterations,
@@ -281,28 +281,35 @@ def other_workloads(tc, which, steps):
     if "jacobi" in which:
         from paper_1704_00693_amd.apps import JacobiRunner
         from synthgen import JACOBI_POINTS, JACOBI_WEIGHTS, jacobi_field
-        n, iters = 8192, 250
-        u0 = jacobi_field(n, seed=5)
-        res = {}
-        for variant, copy in (("non_copy", False), ("copy", True)):
-            per = {}
-            for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))]:
-                with tc.Context(0) as c:
-                    c.tc_set_tiling(m, tile)
-                    r = JacobiRunner(c, u0, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
-                    dt = _timed(lambda: r.run(iters), steps)
-                    st = c.tc_get_stats()
-                per[name] = {"seconds_per_run": dt, "cell_iterations_per_s": iters * n * n / dt,
-                             "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"],
-                             "groups": st["last_groups"]}
-            per["fused_speedup_vs_untiled"] = per["none"]["seconds_per_run"] / per["fused"]["seconds_per_run"]
-            res[variant] = per
-            log(f"jacobi 8192^2 {variant}: {per}")
-        out["jacobi_8192"] = {
-            "workload": "Jacobi heat equation 8192^2 FP64 with a one-cell Dirichlet layer, 250 iterations of the "
-                        "5-point stencil (all weights 0.2), copy and non-copy variants, uniform [0,1) field, seed 5",
-            "modes": res,
-            "context_paper_cpu_seconds_untiled_tiled": {"copy": [16.06, 5.11], "non_copy": [8.58, 3.69]}}
+        iters = 250
+        for n in jacobi_sizes:
+            u0 = jacobi_field(n, seed=5)
+            res = {}
+            for variant, copy in (("non_copy", False), ("copy", True)):
+                per = {}
+                for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))]:
+                    with tc.Context(0) as c:
+                        c.tc_set_tiling(m, tile)
+                        r = JacobiRunner(c, u0, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
+                        dt = _timed(lambda: r.run(iters), steps)
+                        st = c.tc_get_stats()
+                    per[name] = {"seconds_per_run": dt, "cell_iterations_per_s": iters * n * n / dt,
+                                 "ps_per_point_iteration": dt / (iters * n * n) * 1e12,
+                                 "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"],
+                                 "groups": st["last_groups"]}
+                per["fused_speedup_vs_untiled"] = per["none"]["seconds_per_run"] / per["fused"]["seconds_per_run"]
+                res[variant] = per
+                log(f"jacobi {n}^2 {variant}: {per}")
+            out[f"jacobi_{n}"] = {
+                "workload": f"Jacobi heat equation {n}^2 FP64 with a one-cell Dirichlet layer, 250 iterations of "
+                            "the 5-point stencil (all weights 0.2), copy and non-copy variants, uniform [0,1) field, "
+                            "seed 5",
+                "footprint_MB": 2 * (n + 2) ** 2 * 8 / 1e6,
+                "modes": res}
+            if n == 8192:
+                out[f"jacobi_{n}"]["context_paper_cpu_seconds_untiled_tiled"] = {"copy": [16.06, 5.11],
+                                                                                  "non_copy": [8.58, 3.69]}
+            del u0
     if "chain3d" in which:
         from paper_1704_00693_amd.apps import ChainRunner
         from synthgen import chain_3d, chain_data
@@ -422,6 +429,8 @@ def main():
                     help="batched heat-conduction solves to run after the chain (0: skip)")
     ap.add_argument("--other", default="tealeaf,euler,jacobi",
                     help="other workloads to time: comma list of tealeaf, euler, jacobi, chain3d ('' to skip)")
+    ap.add_argument("--jacobi-n", default="8192",
+                    help="grid edges of the Jacobi workload, comma list (a cache-capacity sweep)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
                     help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -495,7 +504,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": None if tr is None else tr["hbm_bytes_per_flush"] / launches,
                 "kernel": kname, "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": alg}
-    others = other_workloads(tc, args.other.split(","), 10) if args.other else None
+    others = (other_workloads(tc, args.other.split(","), 10, [int(v) for v in args.jacobi_n.split(",")])
+              if args.other else None)
     batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
     served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None
     cpu = cpu_baseline(ch, args.cpu_sample) if args.cpu_sample > 0 else None
