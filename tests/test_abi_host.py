@@ -152,3 +152,39 @@ def test_fused_layout_covers_range_once(n, hseg):
         r = ChainRunner(c, ch, None)
         r.record()
         assert c.tc_fused_groups((hseg, 0, 0))
+
+
+@pytest.mark.parametrize("copy", [False, True])
+def test_jacobi_plans_host_only(copy):
+    """The Jacobi chain (halo-1 datasets, a one-cell Dirichlet layer) through
+    the library's analysers: its Algorithm 1 plan equals the oracle's, with a
+    skew of one row per later loop (each stencil loop reads its input one row
+    out; each copy overwrites the array the stencil loop before it read one
+    row out, a write-after-read dependency), and the fused mode puts every
+    loop into a group whose kernels compile."""
+    from oracle.skewed import Arg, Loop
+    from paper_1704_00693_amd.apps import JacobiRunner
+    from synthgen import JACOBI_POINTS, JACOBI_WEIGHTS
+    n, iters = 300, 30
+    pts = [tuple(p) for p in JACOBI_POINTS]
+    loops = []
+    for t in range(iters):
+        if copy:
+            loops.append(Loop([0, 0], [n, n], [Arg(1, [(0, 0)], "W"), Arg(0, pts, "R")]))
+            loops.append(Loop([0, 0], [n, n], [Arg(0, [(0, 0)], "W"), Arg(1, [(0, 0)], "R")]))
+        else:
+            src, dst = (0, 1) if t % 2 == 0 else (1, 0)
+            loops.append(Loop([0, 0], [n, n], [Arg(dst, [(0, 0)], "W"), Arg(src, pts, "R")]))
+    tile = [n, 40]
+    with tc.Context(host_only=True) as c:
+        r = JacobiRunner(c, np.zeros((n + 2, n + 2)), JACOBI_POINTS, JACOBI_WEIGHTS, copy)
+        r.record(iters)
+        num, start, end = c.tc_chain_plan(tile, len(loops), 2)
+        groups = c.tc_fused_groups()
+    ref = skewed_plan(loops, 2, tile)
+    assert num == ref.num_tiles
+    assert start == ref.start and end == ref.end
+    # the first tile's first loop ends one row per later loop above its last loop
+    assert end[1][0][0] - end[1][0][len(loops) - 1] == len(loops) - 1
+    assert groups[0][0] == 0 and groups[-1][1] == len(loops)
+    assert all(a[1] == b[0] for a, b in zip(groups, groups[1:]))
