@@ -239,7 +239,7 @@ def _timed(fn, steps, warm=0.5):
     return (time.perf_counter() - t0) / steps
 
 
-def other_workloads(tc, which, steps, jacobi_sizes=(8192,)):
+def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=()):
     """The other configurations, each in the execution modes that apply:
     heat-conduction PPCG 256^2 (50 iterations of 10 Chebyshev steps), the
     256^3 Taylor-Green RK3 step, the 8192^2 Jacobi iteration (250 iterations,
@@ -287,7 +287,8 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,)):
             res = {}
             for variant, copy in (("non_copy", False), ("copy", True)):
                 per = {}
-                for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))]:
+                extra = [(f"skewed_rows{t}", tc.TC_TILING_SKEWED, (0, t, 0)) for t in jacobi_skew_rows]
+                for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))] + extra:
                     with tc.Context(0) as c:
                         c.tc_set_tiling(m, tile)
                         r = JacobiRunner(c, u0, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
@@ -431,6 +432,8 @@ def main():
                     help="other workloads to time: comma list of tealeaf, euler, jacobi, chain3d ('' to skip)")
     ap.add_argument("--jacobi-n", default="8192",
                     help="grid edges of the Jacobi workload, comma list (a cache-capacity sweep)")
+    ap.add_argument("--jacobi-skew-rows", default="",
+                    help="extra skewed Jacobi runs with these tile heights in rows, comma list (a tile-height study)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
                     help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -504,7 +507,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": None if tr is None else tr["hbm_bytes_per_flush"] / launches,
                 "kernel": kname, "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": alg}
-    others = (other_workloads(tc, args.other.split(","), 10, [int(v) for v in args.jacobi_n.split(",")])
+    others = (other_workloads(tc, args.other.split(","), 10, [int(v) for v in args.jacobi_n.split(",")],
+                              [int(v) for v in args.jacobi_skew_rows.split(",") if v])
               if args.other else None)
     batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
     served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None
