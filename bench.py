@@ -239,7 +239,7 @@ def _timed(fn, steps, warm=0.5):
     return (time.perf_counter() - t0) / steps
 
 
-def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=()):
+def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(), jacobi_two_columns=False):
     """The other configurations, each in the execution modes that apply:
     heat-conduction PPCG 256^2 (50 iterations of 10 Chebyshev steps), the
     256^3 Taylor-Green RK3 step, the 8192^2 Jacobi iteration (250 iterations,
@@ -288,12 +288,25 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=())
             for variant, copy in (("non_copy", False), ("copy", True)):
                 per = {}
                 extra = [(f"skewed_rows{t}", tc.TC_TILING_SKEWED, (0, t, 0)) for t in jacobi_skew_rows]
+                if jacobi_two_columns:
+                    # fused kernels with two columns per lane and a 240-register budget
+                    # (generator knob TC_JIT_CPL, read when a context starts)
+                    extra.append(("fused_2col_regs240", tc.TC_TILING_FUSED, (0, 240, 0)))
                 for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))] + extra:
-                    with tc.Context(0) as c:
-                        c.tc_set_tiling(m, tile)
-                        r = JacobiRunner(c, u0, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
-                        dt = _timed(lambda: r.run(iters), steps)
-                        st = c.tc_get_stats()
+                    saved = os.environ.get("TC_JIT_CPL")
+                    if name == "fused_2col_regs240":
+                        os.environ["TC_JIT_CPL"] = "2"
+                    try:
+                        with tc.Context(0) as c:
+                            c.tc_set_tiling(m, tile)
+                            r = JacobiRunner(c, u0, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
+                            dt = _timed(lambda: r.run(iters), steps)
+                            st = c.tc_get_stats()
+                    finally:
+                        if saved is None:
+                            os.environ.pop("TC_JIT_CPL", None)
+                        else:
+                            os.environ["TC_JIT_CPL"] = saved
                     per[name] = {"seconds_per_run": dt, "cell_iterations_per_s": iters * n * n / dt,
                                  "ps_per_point_iteration": dt / (iters * n * n) * 1e12,
                                  "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"],
@@ -434,6 +447,8 @@ def main():
                     help="grid edges of the Jacobi workload, comma list (a cache-capacity sweep)")
     ap.add_argument("--jacobi-skew-rows", default="",
                     help="extra skewed Jacobi runs with these tile heights in rows, comma list (a tile-height study)")
+    ap.add_argument("--jacobi-two-columns", action="store_true",
+                    help="also time the fused Jacobi with two columns per lane and a 240-register budget")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
                     help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -508,7 +523,7 @@ def main():
                 "traffic": None if tr is None else tr["hbm_bytes_per_flush"] / launches,
                 "kernel": kname, "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": alg}
     others = (other_workloads(tc, args.other.split(","), 10, [int(v) for v in args.jacobi_n.split(",")],
-                              [int(v) for v in args.jacobi_skew_rows.split(",") if v])
+                              [int(v) for v in args.jacobi_skew_rows.split(",") if v], args.jacobi_two_columns)
               if args.other else None)
     batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
     served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None
