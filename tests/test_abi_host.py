@@ -188,3 +188,24 @@ def test_jacobi_plans_host_only(copy):
     assert end[1][0][0] - end[1][0][len(loops) - 1] == len(loops) - 1
     assert groups[0][0] == 0 and groups[-1][1] == len(loops)
     assert all(a[1] == b[0] for a, b in zip(groups, groups[1:]))
+
+
+@pytest.mark.parametrize("cpl,tile", [("1", (0, 0, 0)), ("2", (0, 0, 0)), ("2", (0, 240, 0))])
+def test_jacobi_fused_layouts_host_only(monkeypatch, cpl, tile):
+    """The fused layouts of the 8192^2 Jacobi chain, with one or two columns
+    per lane (generator knob TC_JIT_CPL, read when a context starts): every
+    loop in a group, groups in order, and each group's interior and edge
+    wavefronts own its range exactly once (checked by the library before it
+    generates and compiles the kernels)."""
+    from paper_1704_00693_amd.apps import JacobiRunner
+    from synthgen import JACOBI_POINTS, JACOBI_WEIGHTS
+    monkeypatch.setenv("TC_JIT_CPL", cpl)
+    n, iters = 8192, 48
+    for copy in (False, True):
+        with tc.Context(host_only=True) as c:
+            r = JacobiRunner(c, np.zeros((n + 2, n + 2)), JACOBI_POINTS, JACOBI_WEIGHTS, copy)
+            r.record(iters)
+            groups = c.tc_fused_groups(tile)
+        L = iters * (2 if copy else 1)
+        assert groups[0][0] == 0 and groups[-1][1] == L
+        assert all(a[1] == b[0] for a, b in zip(groups, groups[1:]))
