@@ -88,3 +88,42 @@ def test_window_equals_full(y0, x0, s, copy):
     full = jacobi(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
     win = jacobi_window(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, copy, y0, x0, s)
     assert np.array_equal(win, full[y0 + 1:y0 + 1 + s, x0 + 1:x0 + 1 + s])
+
+
+@pytest.mark.parametrize("copy", [False, True])
+@pytest.mark.parametrize("tile", [[8, 5], [30, 3], [4, 11]])
+def test_skewed_tiles_reproduce_program_order(copy, tile):
+    """The skewed tiling of Algorithms 1 and 2 applied to the Jacobi chain on
+    the CPU (every tile in order, every loop over its skewed range) gives the
+    program-order values bit for bit: the copy variant's write-after-read
+    dependencies included."""
+    from oracle import Grid, wsum
+    from oracle.jacobi import _copy_interior
+    from oracle.skewed import Arg, Loop, execute_tiled, skewed_plan
+    n, iters = 23, 9
+    u0 = jacobi_field(n, seed=21)
+    pts = [tuple(p) for p in JACOBI_POINTS]
+    loops, ops = [], []
+    for t in range(iters):
+        if copy:
+            loops += [Loop([0, 0], [n, n], [Arg(1, [(0, 0)], "W"), Arg(0, pts, "R")]),
+                      Loop([0, 0], [n, n], [Arg(0, [(0, 0)], "W"), Arg(1, [(0, 0)], "R")])]
+            ops += [("stencil", 0, 1), ("copy", 1, 0)]
+        else:
+            src, dst = (0, 1) if t % 2 == 0 else (1, 0)
+            loops.append(Loop([0, 0], [n, n], [Arg(dst, [(0, 0)], "W"), Arg(src, pts, "R")]))
+            ops.append(("stencil", src, dst))
+    arrs = [u0.copy(), u0.copy()]
+    grid = Grid(2, n, 1)
+
+    def run_loop(l, lo, hi):
+        kind, src, dst = ops[l]
+        if kind == "stencil":
+            wsum(grid, lo, hi, arrs[dst], [arrs[src]], [pts], JACOBI_WEIGHTS)
+        else:
+            _copy_interior(grid, lo, hi, arrs[dst], arrs[src])
+
+    execute_tiled(skewed_plan(loops, 2, tile), len(loops), run_loop)
+    ref = jacobi(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
+    got = arrs[0] if copy or iters % 2 == 0 else arrs[1]
+    assert np.array_equal(got, ref)
