@@ -127,3 +127,70 @@ def test_skewed_tiles_reproduce_program_order(copy, tile):
     ref = jacobi(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
     got = arrs[0] if copy or iters % 2 == 0 else arrs[1]
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("mutation", ["moved point", "dropped term", "swapped weight"])
+def test_closed_form_catches_a_planted_stencil_mistake(mutation):
+    """Negative control of the eigenmode pin: the oracle run with a wrong
+    stencil (a point moved one cell further, a point left out, or two weights
+    exchanged on an asymmetric stencil) misses the closed-form decay by far
+    more than the rounding bound."""
+    n, k, l, iters = 37, 3, 5, 40
+    u0 = jacobi_mode(n, k, l)
+    lam = 0.2 * (1.0 + 2.0 * math.cos(math.pi * k / (n + 1)) + 2.0 * math.cos(math.pi * l / (n + 1)))
+    pts = [tuple(p) for p in JACOBI_POINTS]
+    w = list(JACOBI_WEIGHTS)
+    if mutation == "moved point":
+        i = pts.index((1, 0))
+        pts[i] = (2, 0)
+    elif mutation == "dropped term":
+        i = pts.index((0, 1))
+        del pts[i], w[i]
+    else:
+        # an x/y-asymmetric mode, so exchanging an x weight with a y weight shows
+        k, l = 2, 7
+        u0 = jacobi_mode(n, k, l)
+        w = [0.2, 0.25, 0.25, 0.15, 0.15]
+        lam = 0.2 + 0.5 * math.cos(math.pi * k / (n + 1)) + 0.3 * math.cos(math.pi * l / (n + 1))
+        ix, iy = pts.index((1, 0)), pts.index((0, 1))
+        w[ix], w[iy] = w[iy], w[ix]
+    got = jacobi(u0, iters, pts, w, False)
+    err = np.abs(got - lam ** iters * u0).max()
+    assert err > 1e4 * 8 * iters * np.finfo(float).eps, err
+
+
+def test_skewed_plan_without_skew_breaks_program_order():
+    """Negative control of the skewed-schedule pin: the same tiles with every
+    loop cut at the same rows (the skew of Algorithm 1 removed) let a later
+    iteration read rows of the next tile that an earlier iteration has not
+    produced yet, and the result differs from program order."""
+    from oracle import Grid, wsum
+    from oracle.skewed import Arg, Loop, Plan, execute_tiled, skewed_plan
+    n, iters, rows = 23, 9, 5
+    u0 = jacobi_field(n, seed=21)
+    pts = [tuple(p) for p in JACOBI_POINTS]
+    loops = []
+    for t in range(iters):
+        src, dst = (0, 1) if t % 2 == 0 else (1, 0)
+        loops.append(Loop([0, 0], [n, n], [Arg(dst, [(0, 0)], "W"), Arg(src, pts, "R")]))
+    good = skewed_plan(loops, 2, [0, rows])
+    T = good.num_tiles[1]
+    flat_end = [[[min(n, (t + 1) * rows) for _ in loops] for t in range(T)]]
+    flat_start = [[[t * rows for _ in loops] for t in range(T)]]
+    flat = Plan(2, good.num_tiles, [good.start[0], flat_start[0]], [good.end[0], flat_end[0]])
+    assert flat.num_tiles == [1, T] and T > 2
+
+    def run(plan):
+        arrs = [u0.copy(), u0.copy()]
+        grid = Grid(2, n, 1)
+
+        def run_loop(l, lo, hi):
+            src, dst = (0, 1) if l % 2 == 0 else (1, 0)
+            wsum(grid, lo, hi, arrs[dst], [arrs[src]], [pts], JACOBI_WEIGHTS)
+
+        execute_tiled(plan, len(loops), run_loop)
+        return arrs[1] if iters % 2 else arrs[0]
+
+    ref = jacobi(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, False)
+    assert np.array_equal(run(good), ref)
+    assert not np.array_equal(run(flat), ref)
