@@ -239,7 +239,17 @@ def _timed(fn, steps, warm=0.5):
     return (time.perf_counter() - t0) / steps
 
 
-def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(), jacobi_two_columns=False):
+def _tune(ctx, fn, limit=80):
+    """Flush until the autotuner has measured its candidates for the chain
+    structures fn records (tc_stats.tuning drops to 0), at most `limit` times."""
+    for _ in range(limit):
+        fn()
+        if not ctx.tc_get_stats()["tuning"]:
+            return True
+    return False
+
+
+def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(), jacobi_two_columns=True):
     """The other configurations, each in the execution modes that apply:
     heat-conduction PPCG 256^2 (50 iterations of 10 Chebyshev steps), the
     256^3 Taylor-Green RK3 step, the 8192^2 Jacobi iteration (250 iterations,
@@ -290,8 +300,10 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
                 extra = [(f"skewed_rows{t}", tc.TC_TILING_SKEWED, (0, t, 0)) for t in jacobi_skew_rows]
                 if jacobi_two_columns:
                     # fused kernels with two columns per lane and a 240-register budget
-                    # (generator knob TC_JIT_CPL, read when a context starts)
+                    # (generator knob TC_JIT_CPL, read when a context starts), and the
+                    # autotuner, which has this layout among its candidates
                     extra.append(("fused_2col_regs240", tc.TC_TILING_FUSED, (0, 240, 0)))
+                    extra.append(("auto", tc.TC_TILING_AUTO, (0, 0, 0)))
                 for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))] + extra:
                     saved = os.environ.get("TC_JIT_CPL")
                     if name == "fused_2col_regs240":
@@ -300,6 +312,9 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
                         with tc.Context(0) as c:
                             c.tc_set_tiling(m, tile)
                             r = JacobiRunner(c, u0, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
+                            settled = True
+                            if m == tc.TC_TILING_AUTO:
+                                settled = _tune(c, lambda: r.run(iters))
                             dt = _timed(lambda: r.run(iters), steps)
                             st = c.tc_get_stats()
                     finally:
@@ -311,7 +326,14 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
                                  "ps_per_point_iteration": dt / (iters * n * n) * 1e12,
                                  "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"],
                                  "groups": st["last_groups"]}
-                per["fused_speedup_vs_untiled"] = per["none"]["seconds_per_run"] / per["fused"]["seconds_per_run"]
+                    if m == tc.TC_TILING_AUTO:
+                        per[name].update({"tuned": settled, "chosen_mode": st["last_mode"],
+                                          "chosen_tile": st["last_tile"], "chosen_columns_per_lane": st["last_cpl"]})
+                fused_names = [k for k in per if k.startswith("fused")]
+                best_fused = min(fused_names, key=lambda k: per[k]["seconds_per_run"])
+                per["fused_best_layout"] = best_fused
+                per["fused_speedup_vs_untiled"] = (per["none"]["seconds_per_run"] /
+                                                   per[best_fused]["seconds_per_run"])
                 res[variant] = per
                 log(f"jacobi {n}^2 {variant}: {per}")
             out[f"jacobi_{n}"] = {
@@ -345,18 +367,49 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
     return out
 
 
-def cpu_baseline(ch_full, n_sample: int):
+_CPU_WORKER = """
+import sys, time
+sys.path.insert(0, {root!r})
+import oracle
+from synthgen import make_chain, chain_data
+ch = make_chain(2, {n}, {ndat}, {nloops}, {seed})
+data = chain_data(ch)
+print("ready", flush=True)
+sys.stdin.readline()
+t0 = time.perf_counter()
+oracle.run_chain(ch, data)
+print(ch.cell_updates(), time.perf_counter() - t0, flush=True)
+"""
+
+
+def cpu_baseline(ch_full, n_sample: int, procs: int = 0):
     """The oracle (single-threaded C, FP64) on the same chain over an
-    n_sample^2 grid (a bounded sample of the workload)."""
-    import oracle
-    from synthgen import make_chain, chain_data
-    ch = make_chain(2, n_sample, ch_full.ndat, len(ch_full.loops), ch_full.seed)
-    data = chain_data(ch)
+    n_sample^2 grid (a bounded sample of the workload), run as one process
+    per host core at once (at most 16, the host share of one GPU); the
+    throughput is the sum of the processes' cell-updates over the wall time
+    of the slowest.  The processes only import the oracle; none touches the
+    GPU."""
+    import subprocess
+    if procs <= 0:
+        procs = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    code = _CPU_WORKER.format(root=ROOT, n=n_sample, ndat=ch_full.ndat, nloops=len(ch_full.loops), seed=ch_full.seed)
+    ps = [subprocess.Popen([sys.executable, "-c", code], stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
+          for _ in range(procs)]
+    for p in ps:
+        assert p.stdout.readline().strip() == "ready"
     t0 = time.perf_counter()
-    oracle.run_chain(ch, data)
-    dt = time.perf_counter() - t0
-    return {"value": ch.cell_updates() / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"same 40-loop chain on a {n_sample}^2 grid ({ch.cell_updates()} cell-updates, {dt:.1f} s)",
+    for p in ps:  # inputs are generated: start the timed runs together
+        p.stdin.write("go\n")
+        p.stdin.flush()
+    cells = 0
+    for p in ps:
+        c, _ = p.stdout.readline().split()
+        cells += int(c)
+        p.wait()
+    wall = time.perf_counter() - t0
+    return {"value": cells / wall, "unit": "cell-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"same 40-loop chain on a {n_sample}^2 grid, {procs} single-threaded oracle processes at once "
+                      f"({cells} cell-updates in {wall:.1f} s wall)",
             "cpu": _cpu_model()}
 
 
@@ -435,24 +488,26 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--warm-seconds", type=float, default=WARM_SECONDS,
                     help="least wall time each chain mode is warmed before timing (counter runs use 0)")
-    ap.add_argument("--cpu-sample", type=int, default=3072, help="grid edge of the oracle's timed sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="grid edge of the oracle's timed sample (0: skip)")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle processes run at once for the CPU baseline (0: one per host core, at most 16)")
     ap.add_argument("--fused-tile", default="0,0,0",
                     help="fused mode tile: rows per wavefront segment, window-register budget, most loops per group "
                          "(0: automatic)")
     ap.add_argument("--batch-count", type=int, default=512,
                     help="batched heat-conduction solves to run after the chain (0: skip)")
-    ap.add_argument("--other", default="tealeaf,euler,jacobi",
+    ap.add_argument("--other", default="tealeaf,euler,jacobi,chain3d",
                     help="other workloads to time: comma list of tealeaf, euler, jacobi, chain3d ('' to skip)")
     ap.add_argument("--jacobi-n", default="8192",
                     help="grid edges of the Jacobi workload, comma list (a cache-capacity sweep)")
     ap.add_argument("--jacobi-skew-rows", default="",
                     help="extra skewed Jacobi runs with these tile heights in rows, comma list (a tile-height study)")
-    ap.add_argument("--jacobi-two-columns", action="store_true",
-                    help="also time the fused Jacobi with two columns per lane and a 240-register budget")
-    ap.add_argument("--serve-seconds", type=float, default=0.0,
+    ap.add_argument("--jacobi-one-layout", action="store_true",
+                    help="time the fused Jacobi in its default layout only (no two-column layout, no autotuner)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-drain", type=float, default=60.0)
+    ap.add_argument("--serve-drain", type=float, default=15.0)
     ap.add_argument("--ingest-counters", nargs="*", default=None,
                     help="host only: MODE:COUNTER:DIR:FLUSHES entries from rocprofv3 --pmc runs")
     args = ap.parse_args()
@@ -523,11 +578,11 @@ def main():
                 "traffic": None if tr is None else tr["hbm_bytes_per_flush"] / launches,
                 "kernel": kname, "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": alg}
     others = (other_workloads(tc, args.other.split(","), 10, [int(v) for v in args.jacobi_n.split(",")],
-                              [int(v) for v in args.jacobi_skew_rows.split(",") if v], args.jacobi_two_columns)
+                              [int(v) for v in args.jacobi_skew_rows.split(",") if v], not args.jacobi_one_layout)
               if args.other else None)
     batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
     served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None
-    cpu = cpu_baseline(ch, args.cpu_sample) if args.cpu_sample > 0 else None
+    cpu = cpu_baseline(ch, args.cpu_sample, args.cpu_procs) if args.cpu_sample > 0 else None
     untiled = results.get("none")
     tr_none = traffic_entry("none")
     line = {

@@ -263,6 +263,11 @@ typedef struct {
     int64_t fused_bytes;
     double prof_fused_seconds;
     double jit_compile_seconds; /* total host time spent compiling fused kernels */
+    int32_t last_tile[3];       /* tile used by the last flush (the autotuner's pick under AUTO) */
+    int32_t last_cpl;           /* columns per lane of the last flush's fused kernels (1 or 2) */
+    int32_t tuning;             /* 1 if the last flush was one of the autotuner's measurement
+                                   flushes (its chain structure has no choice yet), else 0 */
+    int32_t pad;
 } tc_stats;
 
 tc_status tc_get_stats(tc_ctx *ctx, tc_stats *out);
@@ -273,11 +278,27 @@ tc_status tc_get_stats(tc_ctx *ctx, tc_stats *out);
 tc_status tc_set_profiling(tc_ctx *ctx, int on);
 
 /* Analyse the pending chain without running it (works on host-only
- * contexts).  Skewed mode: writes num_tiles[3] and, into ranges, for every
- * tile index t_d of every dimension d and every loop l, the pair (start, end):
- * ranges[((d * max_tiles + t_d) * nloops + l) * 2 + {0,1}] with max_tiles the
- * largest num_tiles[d]; cap is the number of int32 slots available.  Returns
- * TC_ERR_ARG if cap is too small (num_tiles is still written). */
+ * contexts); the chain stays pending.  cap is the number of int32 slots of
+ * ranges.  Returns TC_ERR_ARG if cap is too small (num_tiles is still
+ * written, so a first call with ranges = NULL sizes the buffer).
+ *
+ * TC_TILING_SKEWED (Algorithm 1): num_tiles[d] tiles per dimension and, for
+ * every tile index t_d of every dimension d and every loop l, the pair
+ * (start, end) at ranges[((d * max_tiles + t_d) * nloops + l) * 2 + {0,1}],
+ * max_tiles the largest num_tiles[d].
+ *
+ * TC_TILING_FUSED (Section 4.4, overlapped tiles fused per group):
+ * num_tiles[0] = G fusion groups, num_tiles[1] = L loops in the chain,
+ * num_tiles[2] = 0; needs 2 G + 5 L slots.  ranges[2 g], ranges[2 g + 1] are
+ * the first and one-past-last chain loop of group g.  Then five ints per
+ * chain loop l at ranges[2 G + 5 l + k]: k = 0 is 1 if a group computes the
+ * loop, 0 if the loop is in a group but never computed (its result is
+ * neither read later in the group nor the final value of its dataset), -1
+ * if it runs on its own; k = 1..4 are the columns to the left and right and
+ * the rows below and above that the loop computes beyond a wavefront's owned
+ * block (the recomputed overlap; 0 unless computed in a group).  The groups'
+ * kernels are generated and compiled (hipRTC) by this call; generation
+ * errors are returned as TC_ERR_STATE. */
 tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_t *num_tiles,
                         int32_t *ranges, int64_t cap);
 

@@ -72,13 +72,15 @@ class Stats(ctypes.Structure):
                 ("modelled_bytes", ctypes.c_int64), ("cell_updates", ctypes.c_int64),
                 ("last_flush_seconds", ctypes.c_double), ("prof_kernel_seconds", ctypes.c_double),
                 ("prof_launches", ctypes.c_int64), ("fused_bytes", ctypes.c_int64),
-                ("prof_fused_seconds", ctypes.c_double), ("jit_compile_seconds", ctypes.c_double)]
+                ("prof_fused_seconds", ctypes.c_double), ("jit_compile_seconds", ctypes.c_double),
+                ("last_tile", ctypes.c_int32 * 3), ("last_cpl", ctypes.c_int32), ("tuning", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
     def as_dict(self):
         out = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            out[name] = list(v) if name == "max_skew" else v
+            out[name] = list(v) if name in ("max_skew", "last_tile") else v
         return out
 
 
@@ -346,13 +348,24 @@ class Context:
         """Fusion groups the fused mode would form for the pending chain, as
         (first, last + 1) loop indices; their kernels are generated and
         compiled (also on host-only contexts), nothing runs."""
+        return self.tc_fused_plan(tile)[0]
+
+    def tc_fused_plan(self, tile: Sequence[int] = (0, 0, 0)):
+        """Fused-mode analysis of the pending chain: the groups as (first,
+        last + 1) loop indices and, per chain loop, (computed, left, right,
+        below, above): computed is 1 / 0 / -1 (in a group and computed, in a
+        group but dead, on its own), the others the columns and rows the loop
+        computes beyond a wavefront's owned block."""
         t = list(tile) + [0] * (3 - len(tile))
         nt = (ctypes.c_int32 * 3)()
         lib().tc_chain_plan(self.ptr, TC_TILING_FUSED, _i32(t), nt, None, 0)
-        cap = max(2 * nt[0], 1)
+        G, L = nt[0], nt[1]
+        cap = max(2 * G + 5 * L, 1)
         buf = (ctypes.c_int32 * cap)()
         self._ck(lib().tc_chain_plan(self.ptr, TC_TILING_FUSED, _i32(t), nt, buf, cap), "tc_chain_plan")
-        return [(int(buf[2 * g]), int(buf[2 * g + 1])) for g in range(nt[0])]
+        groups = [(int(buf[2 * g]), int(buf[2 * g + 1])) for g in range(G)]
+        per = [tuple(int(buf[2 * G + 5 * l + k]) for k in range(5)) for l in range(L)]
+        return groups, per
 
 
 class Batch:

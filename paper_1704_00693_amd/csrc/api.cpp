@@ -347,7 +347,7 @@ void finish_partials(const Ctx &c, const std::vector<LoopRec> &chain, std::share
 }
 
 std::shared_ptr<CachedPlan> build_plan(Ctx &c, const std::vector<LoopRec> &chain, tc_tiling mode,
-                                       const int tile[3]) {
+                                       const int tile[3], int cpl) {
     auto P = std::make_shared<CachedPlan>();
     P->mode = mode;
     for (const auto &lp : chain)
@@ -387,7 +387,7 @@ std::shared_ptr<CachedPlan> build_plan(Ctx &c, const std::vector<LoopRec> &chain
                         add_launch(c, chain[l], l, lo, hi, P, used);
                     }
     } else if (mode == TC_TILING_FUSED) {
-        P->groups = fused_split(c, chain, tile);
+        P->groups = fused_split(c, chain, tile, cpl);
         size_t gi = 0;
         for (int l = 0; l < (int)chain.size();) {
             if (gi < P->groups.size() && P->groups[gi]->g0 == l) {
@@ -580,8 +580,14 @@ tc_status flush(Ctx &c) {
 
     tc_tiling mode = c.mode;
     int tile[3] = {c.tile[0], c.tile[1], c.tile[2]};
+    int cpl = c.jit_cpl;
     const bool tuning_flush = mode == TC_TILING_AUTO;
-    if (tuning_flush) mode = autotune_choose(c, chain, tile);
+    if (tuning_flush) {
+        const TuneCand k = autotune_choose(c, chain);
+        mode = k.mode;
+        for (int d = 0; d < 3; ++d) tile[d] = k.tile[d];
+        cpl = k.cpl;
+    }
 
     tc_status st = TC_OK;
     int64_t bytes = 0, cells = 0;
@@ -597,7 +603,7 @@ tc_status flush(Ctx &c) {
     std::vector<int64_t> red_base, red_count;
     int launches = 0, tiles = 0, groups = 0;
     {
-        const uint64_t key = chain_key(c, chain, mode, tile);
+        const uint64_t key = chain_key(c, chain, mode, tile, cpl);
         std::shared_ptr<CachedPlan> P;
         auto it = c.plans.find(key);
         if (it != c.plans.end()) {
@@ -605,7 +611,7 @@ tc_status flush(Ctx &c) {
             c.stats.plan_hits++;
         } else {
             const double pb = now_s();
-            P = build_plan(c, chain, mode, tile);
+            P = build_plan(c, chain, mode, tile, cpl);
             if (mode == TC_TILING_FUSED) {
                 st = fused_compile(c, P->groups);
                 if (st != TC_OK) return st;
@@ -673,13 +679,16 @@ tc_status flush(Ctx &c) {
         float ms = 0.f;
         HIPCHK(c, hipEventElapsedTime(&ms, c.tune_ev[0], c.tune_ev[1]));
         autotune_record(c, ms * 1e-3);
-        autotune_finish(c, autotune_candidates(chain));
+        autotune_finish(c, chain);
     }
     c.stats.flushes++;
     c.stats.last_launches = launches;
     c.stats.last_tiles = tiles;
     c.stats.last_groups = groups;
     c.stats.last_mode = mode;
+    for (int d = 0; d < 3; ++d) c.stats.last_tile[d] = tile[d];
+    c.stats.last_cpl = cpl;
+    c.stats.tuning = tuning_flush && c.tuned[autotune_key(c, chain)].best < 0 ? 1 : 0;
     c.stats.modelled_bytes = bytes;
     c.stats.cell_updates = cells;
     c.stats.last_flush_seconds = now_s() - t0;
@@ -711,9 +720,10 @@ tc_status copy_host(Ctx &c, Dataset &ds, void *host, const void *src, int which,
 // ===========================================================================
 // C ABI
 // ===========================================================================
-extern "C" {
+// Bodies of the C ABI calls; the exported wrappers below turn any C++
+// exception into a status code.
 
-tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
+static tc_status impl_tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (!out) return TC_ERR_ARG;
     *out = nullptr;
     tc_ctx *ctx = new (std::nothrow) tc_ctx();
@@ -738,6 +748,7 @@ tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (const char *e = getenv("TC_JIT_UNROLL")) c.jit_unroll = std::min(16, std::max(1, atoi(e)));
     if (const char *e = getenv("TC_JIT_PREFETCH")) c.jit_prefetch = std::min(8, std::max(1, atoi(e)));
     if (const char *e = getenv("TC_JIT_BAKE")) c.jit_bake = atoi(e) != 0;
+    if (const char *e = getenv("TC_JIT_TEST_SHORT_WINDOWS")) c.jit_test_short_windows = atoi(e) != 0;
     if (const char *e = getenv("TC_JIT_CPL")) c.jit_cpl = atoi(e) == 2 ? 2 : 1;
     if (const char *e = getenv("TC_JIT_EDGE_DIV")) c.jit_edge_div = std::min(16, std::max(1, atoi(e)));
     if (const char *e = getenv("TC_JIT_WPE")) c.jit_wpe = std::min(8, std::max(0, atoi(e)));
@@ -767,7 +778,7 @@ tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
     return TC_OK;
 }
 
-tc_status tc_finalize(tc_ctx *ctx) {
+static tc_status impl_tc_finalize(tc_ctx *ctx) {
     if (!ctx) return TC_OK;
     Ctx &c = ctx->c;
     tc_status st = TC_OK;
@@ -796,7 +807,7 @@ tc_status tc_finalize(tc_ctx *ctx) {
     return st;
 }
 
-tc_status tc_decl_block(tc_ctx *ctx, int ndim, const char *name, tc_block *out) {
+static tc_status impl_tc_decl_block(tc_ctx *ctx, int ndim, const char *name, tc_block *out) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
     if (ndim < 1 || ndim > 3 || !out) return fail(c, TC_ERR_ARG, "block dimension must be 1..3");
@@ -805,7 +816,7 @@ tc_status tc_decl_block(tc_ctx *ctx, int ndim, const char *name, tc_block *out) 
     return TC_OK;
 }
 
-tc_status tc_decl_dat(tc_ctx *ctx, tc_block blk, tc_dtype dtype, const int32_t *size, const int32_t *halo_neg,
+static tc_status impl_tc_decl_dat(tc_ctx *ctx, tc_block blk, tc_dtype dtype, const int32_t *size, const int32_t *halo_neg,
                       const int32_t *halo_pos, const void *host_init, const char *name, tc_dat *out) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
@@ -854,7 +865,7 @@ tc_status tc_decl_dat(tc_ctx *ctx, tc_block blk, tc_dtype dtype, const int32_t *
     return TC_OK;
 }
 
-tc_status tc_decl_stencil(tc_ctx *ctx, int ndim, int npoints, const int32_t *offsets, const char *name,
+static tc_status impl_tc_decl_stencil(tc_ctx *ctx, int ndim, int npoints, const int32_t *offsets, const char *name,
                           tc_stencil *out) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
@@ -886,7 +897,7 @@ tc_status tc_decl_stencil(tc_ctx *ctx, int ndim, int npoints, const int32_t *off
     return TC_OK;
 }
 
-tc_status tc_decl_reduction(tc_ctx *ctx, tc_redop op, const char *name, tc_red *out) {
+static tc_status impl_tc_decl_reduction(tc_ctx *ctx, tc_redop op, const char *name, tc_red *out) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
     if ((op != TC_RED_SUM && op != TC_RED_MIN && op != TC_RED_MAX) || !out)
@@ -901,7 +912,7 @@ tc_status tc_decl_reduction(tc_ctx *ctx, tc_redop op, const char *name, tc_red *
     return TC_OK;
 }
 
-tc_status tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_block blk, const int32_t *range, const tc_arg *args,
+static tc_status impl_tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_block blk, const int32_t *range, const tc_arg *args,
                       int nargs, const double *params, int nparams) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
@@ -1013,12 +1024,12 @@ tc_status tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_block blk, con
     return TC_OK;
 }
 
-tc_status tc_flush(tc_ctx *ctx) {
+static tc_status impl_tc_flush(tc_ctx *ctx) {
     CHECK_CTX(ctx);
     return flush(ctx->c);
 }
 
-tc_status tc_reduction_result(tc_ctx *ctx, tc_red red, double *out) {
+static tc_status impl_tc_reduction_result(tc_ctx *ctx, tc_red red, double *out) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
     if (red < 0 || red >= (int)c.reds.size() || !out) return fail(c, TC_ERR_ARG, "bad reduction handle");
@@ -1032,7 +1043,7 @@ tc_status tc_reduction_result(tc_ctx *ctx, tc_red red, double *out) {
     return TC_OK;
 }
 
-tc_status tc_dat_read(tc_ctx *ctx, tc_dat dat, void *host) {
+static tc_status impl_tc_dat_read(tc_ctx *ctx, tc_dat dat, void *host) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
     if (dat < 0 || dat >= (int)c.dats.size() || !host) return fail(c, TC_ERR_ARG, "bad dataset handle");
@@ -1043,7 +1054,7 @@ tc_status tc_dat_read(tc_ctx *ctx, tc_dat dat, void *host) {
     return copy_host(c, ds, host, nullptr, ds.cur, false);
 }
 
-tc_status tc_dat_write(tc_ctx *ctx, tc_dat dat, const void *host) {
+static tc_status impl_tc_dat_write(tc_ctx *ctx, tc_dat dat, const void *host) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
     if (dat < 0 || dat >= (int)c.dats.size() || !host) return fail(c, TC_ERR_ARG, "bad dataset handle");
@@ -1055,7 +1066,7 @@ tc_status tc_dat_write(tc_ctx *ctx, tc_dat dat, const void *host) {
     return copy_host(c, ds, nullptr, host, ds.cur, true);
 }
 
-tc_status tc_dat_device_view(tc_ctx *ctx, tc_dat dat, void **origin, int64_t strides[3]) {
+static tc_status impl_tc_dat_device_view(tc_ctx *ctx, tc_dat dat, void **origin, int64_t strides[3]) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
     if (dat < 0 || dat >= (int)c.dats.size() || !origin || !strides) return fail(c, TC_ERR_ARG, "bad argument");
@@ -1071,7 +1082,7 @@ tc_status tc_dat_device_view(tc_ctx *ctx, tc_dat dat, void **origin, int64_t str
     return TC_OK;
 }
 
-tc_status tc_set_tiling(tc_ctx *ctx, tc_tiling mode, const int32_t *tile) {
+static tc_status impl_tc_set_tiling(tc_ctx *ctx, tc_tiling mode, const int32_t *tile) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
     if (mode < TC_TILING_NONE || mode > TC_TILING_AUTO) return fail(c, TC_ERR_ARG, "bad tiling mode");
@@ -1082,14 +1093,14 @@ tc_status tc_set_tiling(tc_ctx *ctx, tc_tiling mode, const int32_t *tile) {
     return TC_OK;
 }
 
-tc_status tc_set_profiling(tc_ctx *ctx, int on) {
+static tc_status impl_tc_set_profiling(tc_ctx *ctx, int on) {
     CHECK_CTX(ctx);
     if (ctx->c.host_only && on) return fail(ctx->c, TC_ERR_STATE, "host-only context cannot time kernels");
     ctx->c.profiling = on != 0;
     return TC_OK;
 }
 
-tc_status tc_get_stats(tc_ctx *ctx, tc_stats *out) {
+static tc_status impl_tc_get_stats(tc_ctx *ctx, tc_stats *out) {
     CHECK_CTX(ctx);
     if (!out) return TC_ERR_ARG;
     *out = ctx->c.stats;
@@ -1097,7 +1108,7 @@ tc_status tc_get_stats(tc_ctx *ctx, tc_stats *out) {
     return TC_OK;
 }
 
-tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_t *num_tiles, int32_t *ranges,
+static tc_status impl_tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_t *num_tiles, int32_t *ranges,
                         int64_t cap) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
@@ -1105,15 +1116,32 @@ tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_
         return fail(c, TC_ERR_UNSUPPORTED, "tc_chain_plan: skewed or fused mode only");
     int t3[3] = {tile ? tile[0] : 0, tile ? tile[1] : 0, tile ? tile[2] : 0};
     if (mode == TC_TILING_FUSED) {
-        auto groups = fused_split(c, c.chain, t3);
+        auto groups = fused_split(c, c.chain, t3, c.jit_cpl);
+        const int L = (int)c.chain.size();
         num_tiles[0] = (int32_t)groups.size();
-        num_tiles[1] = num_tiles[2] = 1;
-        if (!ranges || cap < 2 * (int64_t)groups.size())
-            return fail(c, TC_ERR_ARG, "tc_chain_plan: need %lld slots", (long long)(2 * groups.size()));
+        num_tiles[1] = L;
+        num_tiles[2] = 0;
+        const int64_t need = 2 * (int64_t)groups.size() + 5 * (int64_t)L;
+        if (!ranges || cap < need) return fail(c, TC_ERR_ARG, "tc_chain_plan: need %lld slots", (long long)need);
         for (size_t g = 0; g < groups.size(); ++g) {
             ranges[2 * g] = groups[g]->g0;
             ranges[2 * g + 1] = groups[g]->g1;
         }
+        int32_t *per = ranges + 2 * groups.size();
+        for (int l = 0; l < L; ++l) {
+            per[5 * l] = -1;
+            for (int k = 1; k < 5; ++k) per[5 * l + k] = 0;
+        }
+        for (const auto &g : groups)
+            for (const auto &J : g->loops) {
+                int32_t *e = per + 5 * J.loop;
+                e[0] = J.needed ? 1 : 0;
+                if (!J.needed) continue;
+                e[1] = J.extL;
+                e[2] = J.extR;
+                e[3] = J.extB;
+                e[4] = J.extT;
+            }
         return fused_compile(c, groups);
     }
     SkewedPlan P = build_skewed_plan(c, c.chain, t3);
@@ -1134,11 +1162,93 @@ tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_
     return TC_OK;
 }
 
-tc_status tc_pending(tc_ctx *ctx, int32_t *nloops) {
+static tc_status impl_tc_pending(tc_ctx *ctx, int32_t *nloops) {
     CHECK_CTX(ctx);
     if (!nloops) return TC_ERR_ARG;
     *nloops = (int32_t)ctx->c.chain.size();
     return TC_OK;
+}
+
+extern "C" {
+
+tc_status tc_init(const tc_init_opts *opts, tc_ctx **out) {
+    return tc::guard_abi(nullptr, [&] { return impl_tc_init(opts, out); });
+}
+
+tc_status tc_finalize(tc_ctx *ctx) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_finalize(ctx); });
+}
+
+tc_status tc_decl_block(tc_ctx *ctx, int ndim, const char *name, tc_block *out) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_decl_block(ctx, ndim, name, out); });
+}
+
+tc_status tc_decl_dat(tc_ctx *ctx, tc_block blk, tc_dtype dtype, const int32_t *size, const int32_t *halo_neg,
+                      const int32_t *halo_pos, const void *host_init, const char *name, tc_dat *out) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] {
+        return impl_tc_decl_dat(ctx, blk, dtype, size, halo_neg, halo_pos, host_init, name, out);
+    });
+}
+
+tc_status tc_decl_stencil(tc_ctx *ctx, int ndim, int npoints, const int32_t *offsets, const char *name,
+                          tc_stencil *out) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] {
+        return impl_tc_decl_stencil(ctx, ndim, npoints, offsets, name, out);
+    });
+}
+
+tc_status tc_decl_reduction(tc_ctx *ctx, tc_redop op, const char *name, tc_red *out) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_decl_reduction(ctx, op, name, out); });
+}
+
+tc_status tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_block blk, const int32_t *range, const tc_arg *args,
+                      int nargs, const double *params, int nparams) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] {
+        return impl_tc_par_loop(ctx, name, op, blk, range, args, nargs, params, nparams);
+    });
+}
+
+tc_status tc_flush(tc_ctx *ctx) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_flush(ctx); });
+}
+
+tc_status tc_reduction_result(tc_ctx *ctx, tc_red red, double *out) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_reduction_result(ctx, red, out); });
+}
+
+tc_status tc_dat_read(tc_ctx *ctx, tc_dat dat, void *host) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_dat_read(ctx, dat, host); });
+}
+
+tc_status tc_dat_write(tc_ctx *ctx, tc_dat dat, const void *host) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_dat_write(ctx, dat, host); });
+}
+
+tc_status tc_dat_device_view(tc_ctx *ctx, tc_dat dat, void **origin, int64_t strides[3]) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_dat_device_view(ctx, dat, origin, strides); });
+}
+
+tc_status tc_set_tiling(tc_ctx *ctx, tc_tiling mode, const int32_t *tile) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_set_tiling(ctx, mode, tile); });
+}
+
+tc_status tc_set_profiling(tc_ctx *ctx, int on) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_set_profiling(ctx, on); });
+}
+
+tc_status tc_get_stats(tc_ctx *ctx, tc_stats *out) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_get_stats(ctx, out); });
+}
+
+tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_t *num_tiles, int32_t *ranges,
+                        int64_t cap) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] {
+        return impl_tc_chain_plan(ctx, mode, tile, num_tiles, ranges, cap);
+    });
+}
+
+tc_status tc_pending(tc_ctx *ctx, int32_t *nloops) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_pending(ctx, nloops); });
 }
 
 const char *tc_status_string(tc_status s) {

@@ -69,6 +69,8 @@ namespace {
 
 Ctx &C(tc_batch *b) { return b->ctx->c; }
 
+Ctx *batch_ctx(tc_batch *b) { return b && b->ctx ? &b->ctx->c : nullptr; }
+
 int64_t padded_cells(const tc_solve_desc &d) {
     const int64_t p = d.n + 2;
     return d.ndim == 3 ? p * p * p : p * p;
@@ -280,9 +282,10 @@ tc_status capture(tc_batch *b) {
 
 }  // namespace
 
-extern "C" {
+// Bodies of the C ABI calls; the exported wrappers below turn any C++
+// exception into a status code.
 
-tc_status tc_batch_create(tc_ctx *ctx, const tc_batch_opts *opts, tc_batch **out) {
+static tc_status impl_tc_batch_create(tc_ctx *ctx, const tc_batch_opts *opts, tc_batch **out) {
     if (!ctx || !opts || !out) return TC_ERR_ARG;
     Ctx &c = ctx->c;
     if (c.poisoned) return TC_ERR_DEVICE;
@@ -337,7 +340,7 @@ tc_status tc_batch_create(tc_ctx *ctx, const tc_batch_opts *opts, tc_batch **out
     return TC_OK;
 }
 
-tc_status tc_batch_submit(tc_batch *b, const tc_solve_desc *d, int64_t *ticket) {
+static tc_status impl_tc_batch_submit(tc_batch *b, const tc_solve_desc *d, int64_t *ticket) {
     if (!b || !d || !ticket) return TC_ERR_ARG;
     Ctx &c = C(b);
     if (c.poisoned) return TC_ERR_DEVICE;
@@ -349,7 +352,7 @@ tc_status tc_batch_submit(tc_batch *b, const tc_solve_desc *d, int64_t *ticket) 
     return TC_OK;
 }
 
-tc_status tc_batch_step(tc_batch *b, int32_t *unfinished) {
+static tc_status impl_tc_batch_step(tc_batch *b, int32_t *unfinished) {
     if (!b) return TC_ERR_ARG;
     Ctx &c = C(b);
     if (c.poisoned) return TC_ERR_DEVICE;
@@ -409,7 +412,7 @@ tc_status tc_batch_step(tc_batch *b, int32_t *unfinished) {
     return TC_OK;
 }
 
-tc_status tc_batch_poll(tc_batch *b, int64_t ticket, tc_solve_result *out) {
+static tc_status impl_tc_batch_poll(tc_batch *b, int64_t ticket, tc_solve_result *out) {
     if (!b || !out) return TC_ERR_ARG;
     auto it = b->done.find(ticket);
     std::memset(out, 0, sizeof *out);
@@ -422,7 +425,7 @@ tc_status tc_batch_poll(tc_batch *b, int64_t ticket, tc_solve_result *out) {
     return TC_OK;
 }
 
-tc_status tc_batch_wait(tc_batch *b) {
+static tc_status impl_tc_batch_wait(tc_batch *b) {
     if (!b) return TC_ERR_ARG;
     int32_t left = 1;
     while (left > 0) {
@@ -433,7 +436,7 @@ tc_status tc_batch_wait(tc_batch *b) {
     return tc_batch_step(b, &left);
 }
 
-tc_status tc_batch_read_x(tc_batch *b, int64_t ticket, double *host, int64_t cap) {
+static tc_status impl_tc_batch_read_x(tc_batch *b, int64_t ticket, double *host, int64_t cap) {
     if (!b || !host) return TC_ERR_ARG;
     auto it = b->done.find(ticket);
     if (it == b->done.end() || it->second.x.empty())
@@ -443,7 +446,7 @@ tc_status tc_batch_read_x(tc_batch *b, int64_t ticket, double *host, int64_t cap
     return TC_OK;
 }
 
-tc_status tc_batch_destroy(tc_batch *b) {
+static tc_status impl_tc_batch_destroy(tc_batch *b) {
     if (!b) return TC_OK;
     Ctx &c = C(b);
     (void)hipStreamSynchronize(c.stream);
@@ -463,6 +466,36 @@ tc_status tc_batch_destroy(tc_batch *b) {
     if (b->h_inst) (void)hipHostFree(b->h_inst);
     delete b;
     return TC_OK;
+}
+
+extern "C" {
+
+tc_status tc_batch_create(tc_ctx *ctx, const tc_batch_opts *opts, tc_batch **out) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_batch_create(ctx, opts, out); });
+}
+
+tc_status tc_batch_submit(tc_batch *b, const tc_solve_desc *d, int64_t *ticket) {
+    return tc::guard_abi(batch_ctx(b), [&] { return impl_tc_batch_submit(b, d, ticket); });
+}
+
+tc_status tc_batch_step(tc_batch *b, int32_t *unfinished) {
+    return tc::guard_abi(batch_ctx(b), [&] { return impl_tc_batch_step(b, unfinished); });
+}
+
+tc_status tc_batch_poll(tc_batch *b, int64_t ticket, tc_solve_result *out) {
+    return tc::guard_abi(batch_ctx(b), [&] { return impl_tc_batch_poll(b, ticket, out); });
+}
+
+tc_status tc_batch_wait(tc_batch *b) {
+    return tc::guard_abi(batch_ctx(b), [&] { return impl_tc_batch_wait(b); });
+}
+
+tc_status tc_batch_read_x(tc_batch *b, int64_t ticket, double *host, int64_t cap) {
+    return tc::guard_abi(batch_ctx(b), [&] { return impl_tc_batch_read_x(b, ticket, host, cap); });
+}
+
+tc_status tc_batch_destroy(tc_batch *b) {
+    return tc::guard_abi(batch_ctx(b), [&] { return impl_tc_batch_destroy(b); });
 }
 
 }  // extern "C"

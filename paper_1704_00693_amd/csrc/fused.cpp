@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <sstream>
+#include <stdexcept>
 #include <tuple>
 #include <unordered_map>
 
@@ -483,8 +484,10 @@ struct Gen {
     int slot(int v, int lag, int dy) const {
         const int m = lag - dy - lag_of(v);
         if (m < 0 || m >= V.win[v]) {
-            std::fprintf(stderr, "tilechain: fused window error (version %d, m %d, window %d)\n", v, m, V.win[v]);
-            std::abort();
+            char msg[160];
+            std::snprintf(msg, sizeof msg, "fused group [%d,%d): register window of version %d too short (row %d, window %d)",
+                          G.g0, G.g1, v, m, V.win[v]);
+            throw std::logic_error(msg);
         }
         return V.win[v] - 1 - m;
     }
@@ -804,7 +807,10 @@ uint64_t fnv1a(const std::string &s) {
 
 }  // namespace
 
-std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3]) {
+bool fused_op_supported(const LoopRec &lp) { return lp.op == TC_OP_WSUM && lp.ndim == 2; }
+
+std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3],
+                                                     int cpl) {
     SplitParams sp;
     sp.bake = c.jit_bake;
     sp.hseg = tile[0] > 0 ? tile[0] : 0;
@@ -812,7 +818,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
     sp.max_loops = tile[2] > 0 ? tile[2] : 32;
     sp.U = std::max(1, c.jit_unroll);
     sp.PF = std::max(1, c.jit_prefetch);
-    sp.cpl = c.jit_cpl;
+    sp.cpl = cpl == 2 ? 2 : 1;
     sp.wpe = c.jit_wpe;
     sp.max_window = c.jit_max_window;
     sp.cse_steps = c.jit_cse_steps;
@@ -833,7 +839,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
             piece[j] = nullptr;
         }
         for (int i = j - 2; i >= 0 && j - i <= sp.max_loops; --i) {
-            if (chain[i].op != TC_OP_WSUM || chain[i].ndim != 2) break;
+            if (!fused_op_supported(chain[i])) break;
             auto G = std::make_shared<FusedGroup>();
             if (!analyse(c, chain, i, j, sp, *G)) continue;
             if (best[i] + G->cost < best[j]) {
@@ -870,7 +876,18 @@ tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups
                         g->g1);
     std::ostringstream src;
     src << kPrelude;
-    for (size_t gi = 0; gi < groups.size(); ++gi) gen_group(c, *groups[gi], (int)gi, src);
+    try {
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            // testing aid: every register window one row short, so that the
+            // generator's window check fails and the error reaches the caller
+            if (c.jit_test_short_windows)
+                for (auto &V : groups[gi]->var)
+                    for (int &w : V.win) w = std::max(0, w - 1);
+            gen_group(c, *groups[gi], (int)gi, src);
+        }
+    } catch (const std::logic_error &e) {
+        return fail(c, TC_ERR_STATE, "%s", e.what());
+    }
     const std::string s = src.str();
     if (const char *dump = getenv("TC_JIT_DUMP")) {
         if (FILE *fp = std::fopen(dump, "w")) {

@@ -119,7 +119,11 @@ struct FusedGroup {
 
 // Split a chain into fusion groups (loops outside any group run one kernel
 // each) and generate their kernels; returns the groups in chain order.
-std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3]);
+std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3],
+                                                     int cpl);
+
+// Whether a loop can be part of a fusion group at all (its op and dimension).
+bool fused_op_supported(const LoopRec &lp);
 
 // Compile (and, on a device context, load) the kernels of a plan's groups.
 tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups);
@@ -131,13 +135,13 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &g);
 // Release modules held for fused execution.
 void fused_release(Ctx &c);
 
-// AUTO mode: the execution mode (and tile, written back) to use for this
-// chain; while candidates are being measured, autotune_record receives the
-// flush's device time and autotune_finish picks the fastest when all ran.
-tc_tiling autotune_choose(Ctx &c, const std::vector<LoopRec> &chain, int tile[3]);
+// AUTO mode: the schedule to use for this chain; while candidates are being
+// measured, autotune_record receives the flush's device time and
+// autotune_finish picks the fastest when all ran.
+TuneCand autotune_choose(Ctx &c, const std::vector<LoopRec> &chain);
 void autotune_record(Ctx &c, double seconds);
-void autotune_finish(Ctx &c, size_t ncand);
-size_t autotune_candidates(const std::vector<LoopRec> &chain);
+void autotune_finish(Ctx &c, const std::vector<LoopRec> &chain);
+uint64_t autotune_key(const Ctx &c, const std::vector<LoopRec> &chain);
 
 // shared helpers (api.cpp)
 int canonical_star2(const Stencil &st);

@@ -142,7 +142,7 @@ SkewedPlan build_skewed_plan(const Ctx &c, const std::vector<LoopRec> &chain, co
 // FNV-1a over the structure of the chain: ops, blocks, ranges, dataset ids,
 // stencil ids, access modes, reduction ids and the tiling request.  Scalar
 // parameters are not part of the key.
-uint64_t chain_key(const Ctx &c, const std::vector<LoopRec> &chain, int mode, const int tile[3]) {
+uint64_t chain_key(const Ctx &c, const std::vector<LoopRec> &chain, int mode, const int tile[3], int cpl) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](int64_t v) {
         for (int i = 0; i < 8; ++i) {
@@ -152,6 +152,7 @@ uint64_t chain_key(const Ctx &c, const std::vector<LoopRec> &chain, int mode, co
     };
     mix(mode);
     for (int d = 0; d < 3; ++d) mix(tile[d]);
+    mix(mode == TC_TILING_FUSED ? cpl : 0);
     mix((int64_t)chain.size());
     for (const auto &lp : chain) {
         mix(lp.op);

@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -173,6 +175,14 @@ struct CachedPlan {
     uint64_t ghash = 0, ghash_prev = 0;
 };
 
+// One schedule the autotuner can pick: mode, tile (as for tc_set_tiling) and,
+// for fused groups, the columns each lane holds (1 or 2).
+struct TuneCand {
+    tc_tiling mode;
+    int tile[3];
+    int cpl;
+};
+
 struct Ctx {
     int device = 0;
     bool host_only = false;
@@ -200,9 +210,12 @@ struct Ctx {
         int next = 0;
         int warm = 0;  // untimed flushes of candidate `next` so far
         int best = -1;
-        std::vector<double> seconds;
+        std::vector<std::vector<double>> samples;  // timed flushes per candidate
+        std::vector<double> seconds;               // median per finished candidate
     };
     std::unordered_map<uint64_t, Tune> tuned;
+    std::unordered_map<uint64_t, TuneCand> tune_saved;  // choices read from / written to TC_TUNE_CACHE
+    bool tune_cache_loaded = false;
     int tune_cand = -1;          // candidate being timed by the current flush
     uint64_t tune_key = 0;
     hipEvent_t tune_ev[2] = {nullptr, nullptr};
@@ -236,6 +249,7 @@ struct Ctx {
     bool jit_sched_fence = false;  // TC_JIT_FENCE=1: scheduling barrier between loops
     bool jit_align_store = true;   // TC_JIT_ALIGN=0: owned strips of any width (else whole 128-byte lines)
     int jit_cpl = 1;         // consecutive columns per lane in fused kernels (TC_JIT_CPL: 1 or 2)
+    bool jit_test_short_windows = false;  // TC_JIT_TEST_SHORT_WINDOWS=1: fault injection for error-path tests
     bool jit_bake = true;    // compile the weights into the kernels (TC_JIT_BAKE=0: read them from arguments)
     double jit_compile_seconds = 0.0;
 
@@ -244,9 +258,37 @@ struct Ctx {
     std::vector<hipEvent_t> events;
 };
 
+// No C++ exception crosses the C ABI: every exported call runs its body
+// through this guard, which turns std::bad_alloc into TC_ERR_NOMEM and any
+// other exception into TC_ERR_STATE, keeping the text as the context's last
+// error (when there is a context).
+inline void note_abi_error(Ctx *c, const char *msg) noexcept {
+    if (!c) return;
+    try {
+        c->last_error = msg;
+    } catch (...) {
+    }
+}
+
+template <class F>
+tc_status guard_abi(Ctx *c, F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        note_abi_error(c, "host memory allocation failed");
+        return TC_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        note_abi_error(c, e.what());
+        return TC_ERR_STATE;
+    } catch (...) {
+        note_abi_error(c, "internal error");
+        return TC_ERR_STATE;
+    }
+}
+
 // plan.cpp
 SkewedPlan build_skewed_plan(const Ctx &c, const std::vector<LoopRec> &chain, const int tile[3]);
-uint64_t chain_key(const Ctx &c, const std::vector<LoopRec> &chain, int mode, const int tile[3]);
+uint64_t chain_key(const Ctx &c, const std::vector<LoopRec> &chain, int mode, const int tile[3], int cpl);
 
 }  // namespace tc
 

@@ -209,3 +209,40 @@ def test_jacobi_fused_layouts_host_only(monkeypatch, cpl, tile):
         L = iters * (2 if copy else 1)
         assert groups[0][0] == 0 and groups[-1][1] == L
         assert all(a[1] == b[0] for a, b in zip(groups, groups[1:]))
+
+
+def test_generator_error_returns_a_status(monkeypatch):
+    """A failure inside the fused kernel generator reaches the caller as
+    TC_ERR_STATE with its text (fault injection: every register window one
+    row short), the process survives, and the context stays usable."""
+    from paper_1704_00693_amd.apps import JacobiRunner
+    from synthgen import JACOBI_POINTS, JACOBI_WEIGHTS
+    monkeypatch.setenv("TC_JIT_TEST_SHORT_WINDOWS", "1")
+    with tc.Context(host_only=True) as c:
+        r = JacobiRunner(c, np.zeros((130, 130)), JACOBI_POINTS, JACOBI_WEIGHTS, False)
+        r.record(6)
+        with pytest.raises(tc.TcError) as e:
+            c.tc_fused_groups()
+        assert e.value.status == tc.TC_ERR_STATE
+        assert "register window" in str(e.value)
+        assert c.tc_pending() == 6
+        num, start, end = c.tc_chain_plan([0, 16], 6, 2)
+        assert num == [1, 8]
+
+
+def test_fused_plan_reports_recomputed_extents():
+    """A run of Jacobi steps (radius 1, one dataset pair) fused into one
+    group: loop l of an L-loop group computes L - 1 - l extra columns and
+    rows on every side of a wavefront's owned block (Section 4.4: each loop
+    computes what the later loops of the group read from it)."""
+    from paper_1704_00693_amd.apps import JacobiRunner
+    from synthgen import JACOBI_POINTS, JACOBI_WEIGHTS
+    L = 5
+    with tc.Context(host_only=True) as c:
+        r = JacobiRunner(c, np.zeros((258, 258)), JACOBI_POINTS, JACOBI_WEIGHTS, False)
+        r.record(L)
+        groups, per = c.tc_fused_plan((0, 0, L))
+    assert groups == [(0, L)]
+    for l, (computed, left, right, below, above) in enumerate(per):
+        assert computed == 1
+        assert (left, right, below, above) == (L - 1 - l,) * 4

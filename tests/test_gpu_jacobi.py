@@ -40,9 +40,21 @@ def rel_err(got, ref):
     return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
 
 
-def run_gpu(tc, u0, iters, copy, mode, tile=(0, 0, 0), chunks=1):
+def run_gpu(tc, u0, iters, copy, mode, tile=(0, 0, 0), chunks=1, cpl=1):
+    """cpl: columns per lane of the fused kernels (generator knob
+    TC_JIT_CPL, read when the context starts; restored afterwards)."""
+    import os
     from paper_1704_00693_amd.apps import JacobiRunner
-    with tc.Context() as c:
+    old = os.environ.get("TC_JIT_CPL")
+    os.environ["TC_JIT_CPL"] = str(cpl)
+    try:
+        c = tc.Context()
+    finally:
+        if old is None:
+            del os.environ["TC_JIT_CPL"]
+        else:
+            os.environ["TC_JIT_CPL"] = old
+    with c:
         c.tc_set_tiling(mode, tile)
         r = JacobiRunner(c, u0, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
         left = iters
@@ -56,11 +68,13 @@ def run_gpu(tc, u0, iters, copy, mode, tile=(0, 0, 0), chunks=1):
 
 
 def modes(tc):
-    return [("untiled", tc.TC_TILING_NONE, (0, 0, 0)),
-            ("skewed", tc.TC_TILING_SKEWED, (0, 0, 0)),
-            ("skewed 0x23", tc.TC_TILING_SKEWED, (0, 23, 0)),
-            ("fused", tc.TC_TILING_FUSED, (0, 0, 0)),
-            ("fused hseg 16", tc.TC_TILING_FUSED, (16, 0, 0))]
+    return [("untiled", tc.TC_TILING_NONE, (0, 0, 0), 1),
+            ("skewed", tc.TC_TILING_SKEWED, (0, 0, 0), 1),
+            ("skewed 0x23", tc.TC_TILING_SKEWED, (0, 23, 0), 1),
+            ("fused", tc.TC_TILING_FUSED, (0, 0, 0), 1),
+            ("fused hseg 16", tc.TC_TILING_FUSED, (16, 0, 0), 1),
+            ("fused 2 columns per lane", tc.TC_TILING_FUSED, (0, 0, 0), 2),
+            ("fused 2 columns per lane, 240 registers", tc.TC_TILING_FUSED, (0, 240, 0), 2)]
 
 
 @pytest.mark.parametrize("n,iters", [(203, 21), (130, 40), (64, 7)])
@@ -69,9 +83,9 @@ def test_jacobi_small_all_modes(tc, n, iters, copy):
     u0 = jacobi_field(n, seed=n)
     ref = jacobi(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, copy)
     base = None
-    for name, mode, tile in modes(tc):
+    for name, mode, tile, cpl in modes(tc):
         say(f"jacobi n={n} iters={iters} copy={copy} {name}")
-        got, st = run_gpu(tc, u0, iters, copy, mode, tile)
+        got, st = run_gpu(tc, u0, iters, copy, mode, tile, cpl=cpl)
         err = rel_err(got, ref)
         say(f"  error {err:.2e}, identical to the oracle: {np.array_equal(got, ref)}, "
             f"launches {st['last_launches']}, groups {st['last_groups']}")
@@ -106,17 +120,19 @@ def field8192():
 
 @pytest.mark.parametrize("copy", [False, True])
 def test_jacobi_benchmark_size_sampled(tc, field8192, copy):
-    """8192^2, 250 iterations, untiled and fused: sampled 32 x 32 blocks
-    against the window oracle, the Dirichlet layer unchanged, the two modes
-    identical."""
+    """8192^2, 250 iterations, untiled and fused (both fused layouts the
+    benchmark times): sampled 32 x 32 blocks against the window oracle, the
+    Dirichlet layer unchanged, the modes identical."""
     n, iters, s = 8192, 250, 32
     u0 = field8192
     blocks = [(0, 0), (0, n - s), (n - s, 0), (n - s, n - s), (4093, 2050), (17, 6000), (7000, 300)]
     refs = [jacobi_window(u0, iters, JACOBI_POINTS, JACOBI_WEIGHTS, copy, y, x, s) for y, x in blocks]
     outs = []
-    for name, mode in (("fused", tc.TC_TILING_FUSED), ("untiled", tc.TC_TILING_NONE)):
+    for name, mode, tile, cpl in (("fused", tc.TC_TILING_FUSED, (0, 0, 0), 1),
+                                  ("fused 2 columns, 240 registers", tc.TC_TILING_FUSED, (0, 240, 0), 2),
+                                  ("untiled", tc.TC_TILING_NONE, (0, 0, 0), 1)):
         say(f"jacobi 8192^2 x 250 copy={copy} {name}")
-        got, st = run_gpu(tc, u0, iters, copy, mode)
+        got, st = run_gpu(tc, u0, iters, copy, mode, tile, cpl=cpl)
         say(f"  launches {st['last_launches']}, groups {st['last_groups']}")
         for (y, x), ref in zip(blocks, refs):
             blk = got[y + 1:y + 1 + s, x + 1:x + 1 + s]
@@ -125,18 +141,20 @@ def test_jacobi_benchmark_size_sampled(tc, field8192, copy):
         assert np.array_equal(got[:, 0], u0[:, 0]) and np.array_equal(got[:, -1], u0[:, -1])
         outs.append(got)
         del got
-    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("cpl,tile", [(1, (0, 0, 0)), (2, (0, 240, 0))])
 @pytest.mark.parametrize("copy", [False, True])
-def test_jacobi_benchmark_size_sine_mode(tc, copy):
+def test_jacobi_benchmark_size_sine_mode(tc, copy, cpl, tile):
     """Every cell of the 8192^2 field after 250 fused iterations against the
     closed form: a discrete sine mode decays by its eigenvalue per iteration."""
     n, iters, k, l = 8192, 250, 64, 100
     u0 = jacobi_mode(n, k, l)
     lam = 0.2 * (1.0 + 2.0 * math.cos(math.pi * k / (n + 1)) + 2.0 * math.cos(math.pi * l / (n + 1)))
-    say(f"jacobi 8192^2 sine mode ({k},{l}) copy={copy} fused")
-    got, _ = run_gpu(tc, u0, iters, copy, tc.TC_TILING_FUSED)
+    say(f"jacobi 8192^2 sine mode ({k},{l}) copy={copy} fused, {cpl} column(s) per lane, tile {tile}")
+    got, st = run_gpu(tc, u0, iters, copy, tc.TC_TILING_FUSED, tile, cpl=cpl)
+    assert st["last_groups"] >= 1
     err = float(np.abs(got - lam ** iters * u0).max())
     say(f"  max error against the closed form {err:.2e}")
     assert err <= 16 * iters * np.finfo(float).eps
