@@ -225,30 +225,51 @@ def test_full_size_2d_chain_sampled(tc):
         assert np.array_equal(outs[0][d], outs[2][d])
 
 
-def test_autotuner_results_identical(tc):
+def test_autotuner_results_identical(tc, tmp_path, monkeypatch):
     """AUTO mode measures every candidate schedule on successive flushes
-    (three each: two untimed, one timed), then keeps the fastest; each flush
-    must give the untiled answer."""
+    (five each: two untimed, then three timed, the median kept), then keeps
+    the fastest; each flush must give the untiled answer.  The choice is
+    written to the TC_TUNE_CACHE file, and a new context that reads it starts
+    with the chosen schedule."""
     from paper_1704_00693_amd.apps import ChainRunner
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("TC_TUNE_CACHE", str(cache))
     ch = make_chain(2, 200, 8, 12, seed=9)
     data = chain_data(ch)
-    ref = data
-    modes = []
+    ncand, per = 7, 5  # untiled, two skewed, four fused layouts for a 2D weighted-sum chain
+    scheds, tuning = [], []
     with tc.Context() as c, tc.Context() as u:
         c.tc_set_tiling(tc.TC_TILING_AUTO, (0, 0, 0))
         r = ChainRunner(c, ch, data)
         ru = ChainRunner(u, ch, data)
-        for k in range(3 * 5 + 4):  # five candidates for a 2D weighted-sum chain
+        for k in range(ncand * per + 4):
             say(f"autotune flush {k}")
             r.run()
             ru.run()
-            modes.append(c.tc_get_stats()["last_mode"])
+            st = c.tc_get_stats()
+            scheds.append((st["last_mode"], tuple(st["last_tile"]), st["last_cpl"]))
+            tuning.append(st["tuning"])
             for d in range(ch.ndat):
                 assert np.array_equal(r.read(d), ru.read(d))
-    say(f"  modes used: {modes}")
-    assert len(set(modes[:15])) >= 3  # untiled, skewed and fused were tried
-    assert modes[0] == modes[1] == modes[2]  # each candidate three flushes in a row
-    assert len(set(modes[15:])) == 1  # then one was kept
+    say(f"  schedules used: {scheds}")
+    T = ncand * per
+    assert len(set(m for m, _, _ in scheds[:T])) == 3  # untiled, skewed and fused were tried
+    assert any(cpl == 2 for _, _, cpl in scheds[:T])  # two columns per lane among them
+    assert len(set(scheds[:T])) == ncand
+    for i in range(0, T, per):
+        assert len(set(scheds[i:i + per])) == 1  # each candidate five flushes in a row
+    assert all(tuning[:T - 1]) and not any(tuning[T - 1:])
+    assert len(set(scheds[T - 1:])) == 1 or len(set(scheds[T:])) == 1  # then one was kept
+    chosen = scheds[-1]
+    lines = cache.read_text().split()
+    assert len(lines) == 7 and (int(lines[1]), int(lines[5])) == (chosen[0], chosen[2])
+    with tc.Context() as c2:
+        c2.tc_set_tiling(tc.TC_TILING_AUTO, (0, 0, 0))
+        r2 = ChainRunner(c2, ch, data)
+        r2.run()
+        st = c2.tc_get_stats()
+        assert st["tuning"] == 0
+        assert (st["last_mode"], tuple(st["last_tile"]), st["last_cpl"]) == chosen
 
 
 def test_fused_weight_change(tc):
