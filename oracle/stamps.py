@@ -76,3 +76,45 @@ def tiled_schedule(plan, n_loops: int):
             if all(h > o for o, h in zip(lo, hi)):
                 out.append((l, lo, hi))
     return out
+
+
+def check_overlapped(loops: List[Loop], tiles, compute_boxes) -> None:
+    """Version-stamp check of overlapped tiles (Section 4.4).  Every tile
+    starts from the chain-start state (all stamps -1) and runs every loop over
+    ``compute_boxes(own)[l]`` (a (lo, hi) box or None).  Every read it makes
+    must see the writer program order gives that read, and on the owned box
+    every dataset's last writer must be program order's.  Raise
+    AssertionError otherwise, or if the owned boxes do not cover the union of
+    the loops' ranges exactly once."""
+    ref_seen, ref_stamp, _ = _run(loops, program_order(loops))
+    nd = len(loops[0].start)
+    lo = [min(lp.start[d] for lp in loops) for d in range(nd)]
+    hi = [max(lp.end[d] for lp in loops) for d in range(nd)]
+    owner: Dict[Tuple[int, ...], int] = {}
+    for i, (olo, ohi) in enumerate(tiles):
+        for x in _points(olo, ohi):
+            if x in owner:
+                raise AssertionError(f"point {x} owned by tiles {owner[x]} and {i}")
+            owner[x] = i
+    if set(owner) != set(_points(lo, hi)):
+        raise AssertionError("owned boxes do not cover the union of the loop ranges")
+    dats = {a.dat for lp in loops for a in lp.args}
+    for i, own in enumerate(tiles):
+        boxes = compute_boxes(own)
+        sched = []
+        for l, b in enumerate(boxes):
+            if b is None:
+                continue
+            blo, bhi = b
+            if any(bl < s or bh > e for bl, bh, s, e in zip(blo, bhi, loops[l].start, loops[l].end)):
+                raise AssertionError(f"tile {i}: loop {l} box {b} leaves the loop's range")
+            sched.append((l, blo, bhi))
+        seen, stamp, _ = _run(loops, sched)
+        for k, v in seen.items():
+            if ref_seen[k] != v:
+                raise AssertionError(f"tile {i}: read {k} saw writer {v}, program order saw {ref_seen[k]}")
+        for x in _points(*own):
+            for d in dats:
+                if stamp.get((d, x), -1) != ref_stamp.get((d, x), -1):
+                    raise AssertionError(f"tile {i}: dataset {d} at {x} last written by "
+                                         f"{stamp.get((d, x), -1)}, program order {ref_stamp.get((d, x), -1)}")
