@@ -214,6 +214,25 @@ tc_status tc_reduction_result(tc_ctx *ctx, tc_red red, double *out);
 /* Execute the pending chain now. */
 tc_status tc_flush(tc_ctx *ctx);
 
+/* tc_reduction_result for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same flush and result as tc_reduction_result, but the call
+ * allocates nothing: its reduction partials and finalised results live in a
+ * static device array of the library (1 MiB, 131072 doubles per device, held
+ * until the process ends), no graph is captured or replayed, no kernel is
+ * compiled or loaded and profiling is off for the call.
+ *   - The chain's reductions may need at most 131072 doubles: two per
+ *     workgroup of every reduction loop plus two per reduction handle;
+ *     otherwise TC_ERR_ARG (nothing runs, the chain stays pending).
+ *   - A chain structure whose schedule needs a compiled fused plan, an
+ *     undecided autotuner choice or a not yet allocated second buffer must
+ *     first be flushed once with tc_flush or tc_reduction_result; otherwise
+ *     TC_ERR_STATE (nothing runs, the chain stays pending).
+ *   - Every call on one device shares that device's array and leaves the last
+ *     call's values in it: calls that overlap on one device (from any context
+ *     or thread) race. */
+tc_status tc_reduction_result_static(tc_ctx *ctx, tc_red red, double *out);
+
 /* Flush, then copy a dataset to / from host memory.  The host layout is the
  * padded array with halos, packed, x fastest (as in tc_decl_dat). */
 tc_status tc_dat_read(tc_ctx *ctx, tc_dat dat, void *host);

@@ -37,7 +37,7 @@ OPS = {
 }
 ACCESS = {"R": TC_READ, "W": TC_WRITE, "RW": TC_RW, "INC": TC_INC}
 EXPORTS = ["tc_init", "tc_finalize", "tc_decl_block", "tc_decl_dat", "tc_decl_stencil", "tc_decl_reduction",
-           "tc_par_loop", "tc_reduction_result", "tc_flush", "tc_dat_read", "tc_dat_write", "tc_dat_device_view",
+           "tc_par_loop", "tc_reduction_result", "tc_reduction_result_static", "tc_flush", "tc_dat_read", "tc_dat_write", "tc_dat_device_view",
            "tc_set_tiling", "tc_set_profiling", "tc_get_stats", "tc_chain_plan", "tc_pending", "tc_status_string",
            "tc_last_error", "tc_batch_create", "tc_batch_submit", "tc_batch_step", "tc_batch_poll", "tc_batch_wait",
            "tc_batch_read_x", "tc_batch_destroy"]
@@ -129,6 +129,7 @@ def lib() -> ctypes.CDLL:
         "tc_par_loop": [P, ctypes.c_char_p, i32, i32, i32p, ctypes.POINTER(Arg), ctypes.c_int,
                         ctypes.POINTER(ctypes.c_double), ctypes.c_int],
         "tc_reduction_result": [P, i32, ctypes.POINTER(ctypes.c_double)],
+        "tc_reduction_result_static": [P, i32, ctypes.POINTER(ctypes.c_double)],
         "tc_flush": [P],
         "tc_dat_read": [P, i32, P],
         "tc_dat_write": [P, i32, P],
@@ -290,6 +291,12 @@ class Context:
     def tc_reduction_result(self, red: int) -> float:
         out = ctypes.c_double()
         self._ck(lib().tc_reduction_result(self.ptr, red, ctypes.byref(out)), "tc_reduction_result")
+        return out.value
+
+    def tc_reduction_result_static(self, red: int) -> float:
+        """tc_reduction_result that allocates no device memory (static scratch)."""
+        out = ctypes.c_double()
+        self._ck(lib().tc_reduction_result_static(self.ptr, red, ctypes.byref(out)), "tc_reduction_result_static")
         return out.value
 
     def tc_dat_read(self, dat: int) -> np.ndarray:

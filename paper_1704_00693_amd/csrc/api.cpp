@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "fused.hpp"
@@ -17,6 +18,31 @@
 using namespace tc;
 
 namespace tc {
+
+// Device scratch of the calls that allocate nothing (tc_reduction_result_static):
+// reduction partials followed by the finalised (hi, lo) pairs.  One copy per
+// device, held until the process ends; its device address is looked up once
+// per device (hipGetSymbolAddress) when a context is created on that device.
+constexpr int64_t kScratchDoubles = 1 << 17;  // 1 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double *g_scratch_ptr[kMaxDevices];
+
+// Called with the context's device current.
+tc_status bind_scratch(Ctx &c) {
+    if (c.device < 0 || c.device >= kMaxDevices) return fail(c, TC_ERR_UNSUPPORTED, "device ordinal above %d", kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[c.device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(c, TC_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[c.device] = (double *)ptr;
+    }
+    c.scratch = g_scratch_ptr[c.device];
+    return TC_OK;
+}
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -172,6 +198,23 @@ bool access_ok(int want, int got) {
 // device resources for reductions
 // ---------------------------------------------------------------------------
 tc_status ensure_partials(Ctx &c, int64_t pairs, int nslots) {
+    if (c.noalloc) {
+        // partials at the start of the scratch array, the outputs after them;
+        // laid out by the flush's first call (its plan's partial count), kept
+        // by later calls that only ask for the outputs
+        if (pairs == 0 && c.red_out && c.red_out_cap >= 2 * (int64_t)nslots) return TC_OK;
+        const int64_t need = 2 * pairs + 2 * (int64_t)nslots;
+        if (need > kScratchDoubles)
+            return fail(c, TC_ERR_ARG,
+                        "this chain's reductions need %lld doubles of scratch (%lld partials, %d results); the static "
+                        "scratch holds %lld",
+                        (long long)need, (long long)pairs, nslots, (long long)kScratchDoubles);
+        c.partials = c.scratch;
+        c.partials_cap = 2 * pairs;
+        c.red_out = c.scratch + 2 * pairs;
+        c.red_out_cap = 2 * (int64_t)nslots;
+        return TC_OK;
+    }
     if (pairs * 2 > c.partials_cap) {
         dev_free(c, c.partials);
         int64_t cap = std::max<int64_t>(pairs * 2, 1 << 16);
@@ -581,7 +624,19 @@ tc_status flush(Ctx &c) {
     tc_tiling mode = c.mode;
     int tile[3] = {c.tile[0], c.tile[1], c.tile[2]};
     int cpl = c.jit_cpl;
-    const bool tuning_flush = mode == TC_TILING_AUTO;
+    const bool tuning_flush = mode == TC_TILING_AUTO && !c.noalloc;
+    if (mode == TC_TILING_AUTO && c.noalloc) {
+        TuneCand k;
+        if (!autotune_lookup(c, chain, k)) {
+            c.chain.swap(chain);
+            return fail(c, TC_ERR_STATE,
+                        "the autotuner has not chosen a schedule for this chain yet (its measurement flushes "
+                        "allocate); flush it with tc_flush until it has");
+        }
+        mode = k.mode;
+        for (int d = 0; d < 3; ++d) tile[d] = k.tile[d];
+        cpl = k.cpl;
+    }
     if (tuning_flush) {
         const TuneCand k = autotune_choose(c, chain);
         mode = k.mode;
@@ -609,6 +664,11 @@ tc_status flush(Ctx &c) {
         if (it != c.plans.end()) {
             P = it->second;
             c.stats.plan_hits++;
+        } else if (c.noalloc && mode == TC_TILING_FUSED) {
+            c.chain.swap(chain);
+            return fail(c, TC_ERR_STATE,
+                        "no cached fused plan for this chain: its kernels must be compiled and loaded, which a call "
+                        "that allocates nothing cannot do; flush it once with tc_flush first");
         } else {
             const double pb = now_s();
             P = build_plan(c, chain, mode, tile, cpl);
@@ -622,7 +682,13 @@ tc_status flush(Ctx &c) {
             c.plans[key] = P;
         }
         st = ensure_partials(c, P->partials_total, (int)P->red_handles.size());
-        if (st != TC_OK) return st;
+        if (st == TC_OK && c.noalloc)
+            for (const auto &g : P->groups)
+                if ((st = fused_check_noalloc(c, chain, *g)) != TC_OK) break;
+        if (st != TC_OK) {
+            if (c.noalloc) c.chain.swap(chain);  // nothing ran: the chain stays pending
+            return st;
+        }
         if (tuning_flush && c.tune_cand >= 0) {  // the candidate's device time, plan work excluded
             for (auto &e : c.tune_ev)
                 if (!e) HIPCHK(c, hipEventCreate(&e));
@@ -653,12 +719,14 @@ tc_status flush(Ctx &c) {
         for (size_t s = 0; s < red_handles.size(); ++s)
             HIPCHK(c, launch_finalize(c.partials + 2 * red_base[s], red_count[s], c.reds[red_handles[s]].op,
                                       c.red_out + 2 * s, c.stream));
-        HIPCHK(c, hipMemcpyAsync(c.red_host, c.red_out, red_handles.size() * 2 * sizeof(double),
-                                 hipMemcpyDeviceToHost, c.stream));
+        std::vector<double> host_out(c.noalloc ? 2 * red_handles.size() : 0);
+        double *dst = c.noalloc ? host_out.data() : c.red_host;
+        HIPCHK(c, hipMemcpyAsync(dst, c.red_out, red_handles.size() * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                 c.stream));
         HIPCHK(c, hipStreamSynchronize(c.stream));
         for (size_t s = 0; s < red_handles.size(); ++s) {
             Reduction &r = c.reds[red_handles[s]];
-            const double hi = c.red_host[2 * s], lo = c.red_host[2 * s + 1];
+            const double hi = dst[2 * s], lo = dst[2 * s + 1];
             if (r.op == TC_RED_SUM) {
                 double sum = r.hi + hi;
                 double bb = sum - r.hi;
@@ -763,6 +831,10 @@ static tc_status impl_tc_init(const tc_init_opts *opts, tc_ctx **out) {
             return TC_ERR_DEVICE;
         }
         if (hipSetDevice(c.device) != hipSuccess) {
+            delete ctx;
+            return TC_ERR_DEVICE;
+        }
+        if (bind_scratch(c) != TC_OK) {
             delete ctx;
             return TC_ERR_DEVICE;
         }
@@ -1043,6 +1115,48 @@ static tc_status impl_tc_reduction_result(tc_ctx *ctx, tc_red red, double *out) 
     return TC_OK;
 }
 
+// tc_reduction_result without any device allocation: the context's
+// partials, outputs, graph use and profiling are swapped out for the call.
+static tc_status impl_tc_reduction_result_static(tc_ctx *ctx, tc_red red, double *out) {
+    CHECK_CTX(ctx);
+    Ctx &c = ctx->c;
+    if (red < 0 || red >= (int)c.reds.size() || !out) return fail(c, TC_ERR_ARG, "bad reduction handle");
+    if (c.host_only) return fail(c, TC_ERR_STATE, "host-only context cannot execute loops");
+    if (!c.scratch) return fail(c, TC_ERR_STATE, "no static scratch on this context's device");
+    struct Saved {
+        Ctx &c;
+        double *partials, *red_out;
+        int64_t partials_cap, red_out_cap;
+        bool graphs, profiling;
+        explicit Saved(Ctx &cc)
+            : c(cc), partials(cc.partials), red_out(cc.red_out), partials_cap(cc.partials_cap),
+              red_out_cap(cc.red_out_cap), graphs(cc.use_graphs), profiling(cc.profiling) {
+            c.noalloc = true;
+            c.use_graphs = false;
+            c.profiling = false;
+            c.partials = c.red_out = nullptr;  // laid out in the scratch by the flush
+            c.partials_cap = c.red_out_cap = 0;
+        }
+        ~Saved() {
+            c.partials = partials;
+            c.red_out = red_out;
+            c.partials_cap = partials_cap;
+            c.red_out_cap = red_out_cap;
+            c.use_graphs = graphs;
+            c.profiling = profiling;
+            c.noalloc = false;
+        }
+    } saved(c);
+    tc_status st = flush(c);
+    if (st != TC_OK) return st;
+    Reduction &r = c.reds[red];
+    *out = r.op == TC_RED_SUM ? r.hi + r.lo : r.hi;
+    r.hi = r.op == TC_RED_SUM ? 0.0 : (r.op == TC_RED_MIN ? INFINITY : -INFINITY);
+    r.lo = 0.0;
+    r.touched = false;
+    return TC_OK;
+}
+
 static tc_status impl_tc_dat_read(tc_ctx *ctx, tc_dat dat, void *host) {
     CHECK_CTX(ctx);
     Ctx &c = ctx->c;
@@ -1214,6 +1328,10 @@ tc_status tc_flush(tc_ctx *ctx) {
 
 tc_status tc_reduction_result(tc_ctx *ctx, tc_red red, double *out) {
     return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_reduction_result(ctx, red, out); });
+}
+
+tc_status tc_reduction_result_static(tc_ctx *ctx, tc_red red, double *out) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_reduction_result_static(ctx, red, out); });
 }
 
 tc_status tc_dat_read(tc_ctx *ctx, tc_dat dat, void *host) {

@@ -117,6 +117,25 @@ TuneCand autotune_choose(Ctx &c, const std::vector<LoopRec> &chain) {
     return cands[T.next];
 }
 
+bool autotune_lookup(Ctx &c, const std::vector<LoopRec> &chain, TuneCand &out) {
+    const uint64_t key = autotune_key(c, chain);
+    const auto cands = candidates(chain);
+    load_cache(c);
+    auto t = c.tuned.find(key);
+    if (t != c.tuned.end() && t->second.best >= 0) {
+        out = cands[t->second.best];
+        return true;
+    }
+    auto it = c.tune_saved.find(key);
+    if (it == c.tune_saved.end()) return false;
+    for (const auto &k : cands)
+        if (same(k, it->second)) {
+            out = k;
+            return true;
+        }
+    return false;
+}
+
 void autotune_record(Ctx &c, double seconds) {
     if (c.tune_cand < 0) return;
     Ctx::Tune &T = c.tuned[c.tune_key];

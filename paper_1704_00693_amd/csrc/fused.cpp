@@ -952,6 +952,10 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
         for (int l = G.g0; l < G.g1 && same; ++l)
             for (double w : chain[l].params) same = same && k < G.wvals.size() && G.wvals[k++] == w;
         if (!same) {
+            if (c.noalloc)
+                return fail(c, TC_ERR_STATE,
+                            "fused group [%d,%d): new weights need kernels compiled and loaded, which a call that "
+                            "allocates nothing cannot do; flush once with tc_flush first", G.g0, G.g1);
             if (getenv("TC_JIT_VERBOSE"))
                 std::fprintf(stderr, "fused group [%d,%d): weights changed, switching to argument weights\n", G.g0,
                              G.g1);
@@ -978,6 +982,10 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
             continue;
         }
         const int tw = 1 - ds.cur;
+        if (!ds.raw[tw] && c.noalloc)
+            return fail(c, TC_ERR_STATE,
+                        "the second buffer of %s does not exist yet and a call that allocates nothing cannot create "
+                        "it; flush this chain once with tc_flush first", ds.name.c_str());
         if (!ds.raw[tw]) {
             ds.raw[tw] = dev_alloc(c, (size_t)(ds.bytes + ds.stagger));
             if (!ds.raw[tw]) return fail(c, TC_ERR_NOMEM, "cannot allocate the second buffer of %s", ds.name.c_str());
@@ -1018,6 +1026,24 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
             Dataset &ds = c.dats[G.dst_dat[i]];
             ds.cur = 1 - ds.cur;
         }
+    return TC_OK;
+}
+
+tc_status fused_check_noalloc(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &G) {
+    if (G.baked) {
+        size_t k = 0;
+        for (int l = G.g0; l < G.g1; ++l)
+            for (double w : chain[l].params)
+                if (k >= G.wvals.size() || G.wvals[k++] != w)
+                    return fail(c, TC_ERR_STATE,
+                                "fused group [%d,%d): new weights need kernels compiled and loaded, which a call that "
+                                "allocates nothing cannot do; flush once with tc_flush first", G.g0, G.g1);
+    }
+    for (size_t i = 0; i < G.dst_dat.size(); ++i)
+        if (G.dst_twin[i] && (!c.dats[G.dst_dat[i]].raw[0] || !c.dats[G.dst_dat[i]].raw[1]))
+            return fail(c, TC_ERR_STATE,
+                        "the second buffer of %s does not exist yet and a call that allocates nothing cannot create "
+                        "it; flush this chain once with tc_flush first", c.dats[G.dst_dat[i]].name.c_str());
     return TC_OK;
 }
 

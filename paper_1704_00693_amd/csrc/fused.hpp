@@ -132,6 +132,10 @@ tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups
 // prepared and swapped here).
 tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &g);
 
+// For a call that allocates nothing: TC_ERR_STATE if running the group would
+// compile kernels or allocate its second buffers (checked before anything runs).
+tc_status fused_check_noalloc(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &G);
+
 // Release modules held for fused execution.
 void fused_release(Ctx &c);
 
@@ -142,6 +146,9 @@ TuneCand autotune_choose(Ctx &c, const std::vector<LoopRec> &chain);
 void autotune_record(Ctx &c, double seconds);
 void autotune_finish(Ctx &c, const std::vector<LoopRec> &chain);
 uint64_t autotune_key(const Ctx &c, const std::vector<LoopRec> &chain);
+// The autotuner's choice for this chain structure if it has one (measured in
+// this context or read from the choice cache); no measurement state changes.
+bool autotune_lookup(Ctx &c, const std::vector<LoopRec> &chain, TuneCand &out);
 
 // shared helpers (api.cpp)
 int canonical_star2(const Stencil &st);

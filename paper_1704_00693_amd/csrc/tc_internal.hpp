@@ -253,6 +253,13 @@ struct Ctx {
     bool jit_bake = true;    // compile the weights into the kernels (TC_JIT_BAKE=0: read them from arguments)
     double jit_compile_seconds = 0.0;
 
+    // calls that must not allocate device memory (tc_reduction_result_static):
+    // while set, reduction partials and outputs live in the library's static
+    // device scratch array, graphs and profiling are off, and any path that
+    // would allocate, compile or load code fails with TC_ERR_STATE instead
+    bool noalloc = false;
+    double *scratch = nullptr;  // device address of this device's scratch array
+
     // per-launch kernel timing (tc_set_profiling)
     bool profiling = false;
     std::vector<hipEvent_t> events;
