@@ -261,15 +261,19 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
         from synthgen import heat_problem
         hp = heat_problem(256, seed=0)
         res = {}
-        for name, m, tile in modes:
+        for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))]:
             with tc.Context(0) as c:
                 c.tc_set_tiling(m, tile)
                 s = HeatSolver(c, hp.density, hp.energy)
                 dt = _timed(lambda: s.solve(outer=50, inner=10), max(1, steps // 10))
                 st = c.tc_get_stats()
-            res[name] = {"seconds_per_solve": dt, "loops_recorded": st["loops_recorded"]}
+            res[name] = {"seconds_per_solve": dt, "loops_recorded": st["loops_recorded"],
+                         "launches_last_flush": st["last_launches"], "groups_last_flush": st["last_groups"]}
         out["tealeaf_256"] = {"workload": "heat conduction 256^2 FP64, PPCG 50 x 10 Chebyshev steps, seed 0",
-                              "modes": res}
+                              "modes": res,
+                              "fused_speedup_vs_untiled": res["none"]["seconds_per_solve"] /
+                              res["fused"]["seconds_per_solve"],
+                              "context_paper_speedup": 3.56}
         log(f"tealeaf 256^2: {res}")
     if "euler" in which:
         from paper_1704_00693_amd.apps import EulerRunner
@@ -277,14 +281,15 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
         n = 256
         q = taylor_green(n)
         res = {}
-        for name, m, tile in modes:
+        for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))]:
             with tc.Context(0) as c:
                 c.tc_set_tiling(m, tile)
                 r = EulerRunner(c, q, n, 2 * math.pi / n)
                 dt = _timed(lambda: r.step(1e-3), steps)
                 st = c.tc_get_stats()
             res[name] = {"ms_per_step": dt * 1e3, "cell_updates_per_s": st["cell_updates"] / dt,
-                         "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"]}
+                         "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"],
+                         "groups": st["last_groups"]}
         out["euler_rk3_256"] = {"workload": "Taylor-Green vortex 256^3 FP64, one SSP-RK3 step of 4th-order central "
                                             "differences (40 loops + energy sum)", "modes": res}
         log(f"euler 256^3: {res}")

@@ -308,18 +308,32 @@ tc_status tc_set_profiling(tc_ctx *ctx, int on);
  *
  * TC_TILING_FUSED (Section 4.4, overlapped tiles fused per group):
  * num_tiles[0] = G fusion groups, num_tiles[1] = L loops in the chain,
- * num_tiles[2] = 0; needs 2 G + 5 L slots.  ranges[2 g], ranges[2 g + 1] are
- * the first and one-past-last chain loop of group g.  Then five ints per
- * chain loop l at ranges[2 G + 5 l + k]: k = 0 is 1 if a group computes the
- * loop, 0 if the loop is in a group but never computed (its result is
- * neither read later in the group nor the final value of its dataset), -1
- * if it runs on its own; k = 1..4 are the columns to the left and right and
- * the rows below and above that the loop computes beyond a wavefront's owned
- * block (the recomputed overlap; 0 unless computed in a group).  The groups'
- * kernels are generated and compiled (hipRTC) by this call; generation
- * errors are returned as TC_ERR_STATE. */
+ * num_tiles[2] = 0; needs 2 G + 7 L slots.  ranges[2 g], ranges[2 g + 1] are
+ * the first and one-past-last chain loop of group g.  Then seven ints per
+ * chain loop l at ranges[2 G + 7 l + k]: k = 0 is 1 if a register-window
+ * group computes the loop, 2 if a staged group does (LDS-staged tiles, any
+ * op and range), 0 if the loop is in a group but never computed (its result
+ * is neither read later in the group nor the final value of its dataset),
+ * -1 if it runs on its own; k = 1..6 are the points below and above the
+ * owned block along x, y and z that the loop computes (the recomputed
+ * overlap; register-window groups: a wavefront's owned block, z entries 0;
+ * staged groups: the most interior tile's owned box; 0 unless computed).
+ * Register-window kernels are generated and compiled (hipRTC) by this call;
+ * generation errors are returned as TC_ERR_STATE. */
 tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_t *num_tiles,
                         int32_t *ranges, int64_t cap);
+
+/* Staged tiles of one fusion group of the pending chain, as TC_TILING_FUSED
+ * with `tile` would plan them (Section 4.4: every tile's owned box and the
+ * box each loop of the group computes for it; works on host-only contexts;
+ * the chain stays pending).  info (6 ints): first and one-past-last chain
+ * loop of the group, the number of tiles T (0 if the group is a
+ * register-window group, which has no tiles), and the owned box extents.
+ * boxes (may be NULL to query info only): per tile, 6 + 6 L ints (L loops of
+ * the group): the owned box lo[3], hi[3], then per loop its computed box
+ * lo[3], hi[3] (empty when some hi <= lo); TC_ERR_ARG if cap is below
+ * T (6 + 6 L) or group is not a group index. */
+tc_status tc_staged_tiles(tc_ctx *ctx, const int32_t *tile, int32_t group, int32_t *info, int32_t *boxes, int64_t cap);
 
 /* Number of loops currently recorded and not yet executed. */
 tc_status tc_pending(tc_ctx *ctx, int32_t *nloops);

@@ -103,9 +103,12 @@ def owned_partition(lo: Sequence[int], hi: Sequence[int], tile: Sequence[int]) -
 
 
 def union_range(loops: List[Loop]) -> Box:
-    nd = len(loops[0].start)
-    return ([min(lp.start[d] for lp in loops) for d in range(nd)],
-            [max(lp.end[d] for lp in loops) for d in range(nd)])
+    """Bounding box of the loops' iteration spaces (loops with an empty range
+    have no points and do not count)."""
+    live = [lp for lp in loops if all(e > s for s, e in zip(lp.start, lp.end))] or loops
+    nd = len(live[0].start)
+    return ([min(lp.start[d] for lp in live) for d in range(nd)],
+            [max(lp.end[d] for lp in live) for d in range(nd)])
 
 
 def execute_overlapped(loops: List[Loop], tiles: List[Box], state,

@@ -88,8 +88,9 @@ def check_overlapped(loops: List[Loop], tiles, compute_boxes) -> None:
     the loops' ranges exactly once."""
     ref_seen, ref_stamp, _ = _run(loops, program_order(loops))
     nd = len(loops[0].start)
-    lo = [min(lp.start[d] for lp in loops) for d in range(nd)]
-    hi = [max(lp.end[d] for lp in loops) for d in range(nd)]
+    live = [lp for lp in loops if all(e > s for s, e in zip(lp.start, lp.end))] or loops
+    lo = [min(lp.start[d] for lp in live) for d in range(nd)]
+    hi = [max(lp.end[d] for lp in live) for d in range(nd)]
     owner: Dict[Tuple[int, ...], int] = {}
     for i, (olo, ohi) in enumerate(tiles):
         for x in _points(olo, ohi):

@@ -38,7 +38,7 @@ OPS = {
 ACCESS = {"R": TC_READ, "W": TC_WRITE, "RW": TC_RW, "INC": TC_INC}
 EXPORTS = ["tc_init", "tc_finalize", "tc_decl_block", "tc_decl_dat", "tc_decl_stencil", "tc_decl_reduction",
            "tc_par_loop", "tc_reduction_result", "tc_reduction_result_static", "tc_flush", "tc_dat_read", "tc_dat_write", "tc_dat_device_view",
-           "tc_set_tiling", "tc_set_profiling", "tc_get_stats", "tc_chain_plan", "tc_pending", "tc_status_string",
+           "tc_set_tiling", "tc_set_profiling", "tc_get_stats", "tc_chain_plan", "tc_staged_tiles", "tc_pending", "tc_status_string",
            "tc_last_error", "tc_batch_create", "tc_batch_submit", "tc_batch_step", "tc_batch_poll", "tc_batch_wait",
            "tc_batch_read_x", "tc_batch_destroy"]
 TC_SOLVE_PENDING, TC_SOLVE_RUNNING, TC_SOLVE_DONE, TC_SOLVE_REJECTED = 0, 1, 2, -1
@@ -130,6 +130,7 @@ def lib() -> ctypes.CDLL:
                         ctypes.POINTER(ctypes.c_double), ctypes.c_int],
         "tc_reduction_result": [P, i32, ctypes.POINTER(ctypes.c_double)],
         "tc_reduction_result_static": [P, i32, ctypes.POINTER(ctypes.c_double)],
+        "tc_staged_tiles": [P, i32p, i32, i32p, i32p, i64],
         "tc_flush": [P],
         "tc_dat_read": [P, i32, P],
         "tc_dat_write": [P, i32, P],
@@ -359,20 +360,47 @@ class Context:
 
     def tc_fused_plan(self, tile: Sequence[int] = (0, 0, 0)):
         """Fused-mode analysis of the pending chain: the groups as (first,
-        last + 1) loop indices and, per chain loop, (computed, left, right,
-        below, above): computed is 1 / 0 / -1 (in a group and computed, in a
-        group but dead, on its own), the others the columns and rows the loop
-        computes beyond a wavefront's owned block."""
+        last + 1) loop indices and, per chain loop, (computed, x below, x
+        above, y below, y above, z below, z above): computed is 1 / 2 / 0 / -1
+        (computed in a register-window group, in a staged group, in a group
+        but dead, on its own), the others the points the loop computes beyond
+        an owned block."""
         t = list(tile) + [0] * (3 - len(tile))
         nt = (ctypes.c_int32 * 3)()
         lib().tc_chain_plan(self.ptr, TC_TILING_FUSED, _i32(t), nt, None, 0)
         G, L = nt[0], nt[1]
-        cap = max(2 * G + 5 * L, 1)
+        cap = max(2 * G + 7 * L, 1)
         buf = (ctypes.c_int32 * cap)()
         self._ck(lib().tc_chain_plan(self.ptr, TC_TILING_FUSED, _i32(t), nt, buf, cap), "tc_chain_plan")
         groups = [(int(buf[2 * g]), int(buf[2 * g + 1])) for g in range(G)]
-        per = [tuple(int(buf[2 * G + 5 * l + k]) for k in range(5)) for l in range(L)]
+        per = [tuple(int(buf[2 * G + 7 * l + k]) for k in range(7)) for l in range(L)]
         return groups, per
+
+    def tc_staged_tiles(self, group: int, tile: Sequence[int] = (0, 0, 0)):
+        """Staged tiles of fusion group ``group`` of the pending chain: (g0, g1,
+        owned extents, [(owned lo, owned hi, [computed (lo, hi) or None per
+        loop]) per tile]); no tiles for a register-window group."""
+        t = list(tile) + [0] * (3 - len(tile))
+        info = (ctypes.c_int32 * 6)()
+        self._ck(lib().tc_staged_tiles(self.ptr, _i32(t), group, info, None, 0), "tc_staged_tiles")
+        g0, g1, T = int(info[0]), int(info[1]), int(info[2])
+        ext = tuple(int(info[3 + d]) for d in range(3))
+        if T == 0:
+            return g0, g1, ext, []
+        L = g1 - g0
+        per = 6 + 6 * L
+        buf = (ctypes.c_int32 * (per * T))()
+        self._ck(lib().tc_staged_tiles(self.ptr, _i32(t), group, info, buf, per * T), "tc_staged_tiles")
+        tiles = []
+        for k in range(T):
+            r = buf[per * k: per * (k + 1)]
+            own = (list(r[0:3]), list(r[3:6]))
+            boxes = []
+            for l in range(L):
+                lo, hi = list(r[6 + 6 * l: 9 + 6 * l]), list(r[9 + 6 * l: 12 + 6 * l])
+                boxes.append(None if any(h <= o for o, h in zip(lo, hi)) else (lo, hi))
+            tiles.append((own, boxes))
+        return g0, g1, ext, tiles
 
 
 class Batch:

@@ -374,15 +374,28 @@ void finish_partials(const Ctx &c, const std::vector<LoopRec> &chain, std::share
     }
     P->partials_total = tot;
     std::vector<int64_t> fill(ns, 0);
-    for (auto &L : P->launches) {
-        const LoopRec &lp = chain[L.loop];
-        int j = 0;
-        for (const auto &a : lp.args) {
-            if (a.kind != TC_ARG_RED) continue;
-            int slot = (int)L.part_off[j];
-            L.part_off[j] = P->red_base[slot] + fill[slot];
-            fill[slot] += L.nb;
-            ++j;
+    for (const Step &st : P->steps) {
+        if (st.kind == 0) {
+            Launch &L = P->launches[st.index];
+            const LoopRec &lp = chain[L.loop];
+            int j = 0;
+            for (const auto &a : lp.args) {
+                if (a.kind != TC_ARG_RED) continue;
+                int slot = (int)L.part_off[j];
+                L.part_off[j] = P->red_base[slot] + fill[slot];
+                fill[slot] += L.nb;
+                ++j;
+            }
+        } else if (auto S = P->groups[st.index]->staged) {
+            for (int k = S->g0; k < S->g1; ++k) {
+                int j = 0;
+                for (const auto &a : chain[k].args) {
+                    if (a.kind != TC_ARG_RED) continue;
+                    const int slot = (int)S->loops[k - S->g0].part[j];
+                    S->loops[k - S->g0].part[j++] = P->red_base[slot] + fill[slot];
+                    fill[slot] += S->ntot;
+                }
+            }
         }
     }
     for (size_t s = 0; s < ns; ++s) P->red_count[s] = fill[s];
@@ -435,6 +448,20 @@ std::shared_ptr<CachedPlan> build_plan(Ctx &c, const std::vector<LoopRec> &chain
         for (int l = 0; l < (int)chain.size();) {
             if (gi < P->groups.size() && P->groups[gi]->g0 == l) {
                 P->steps.push_back({1, (int)gi});
+                if (auto S = P->groups[gi]->staged) {
+                    // one partial per tile for every reduction argument (the
+                    // slot for now; finish_partials turns it into an offset)
+                    for (int k = S->g0; k < S->g1; ++k) {
+                        int j = 0;
+                        for (const auto &a : chain[k].args) {
+                            if (a.kind != TC_ARG_RED) continue;
+                            const int slot = (int)(std::find(P->red_handles.begin(), P->red_handles.end(), a.handle) -
+                                                   P->red_handles.begin());
+                            S->loops[k - S->g0].part[j++] = slot;
+                            used[slot] += S->ntot;
+                        }
+                    }
+                }
                 l = P->groups[gi]->g1;
                 ++gi;
             } else {
@@ -673,7 +700,7 @@ tc_status flush(Ctx &c) {
             const double pb = now_s();
             P = build_plan(c, chain, mode, tile, cpl);
             if (mode == TC_TILING_FUSED) {
-                st = fused_compile(c, P->groups);
+                st = fused_compile(c, chain, P->groups);
                 if (st != TC_OK) return st;
             }
             P->build_seconds = now_s() - pb;
@@ -824,6 +851,12 @@ static tc_status impl_tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (const char *e = getenv("TC_JIT_CSE")) c.jit_cse_steps = atoi(e) != 0;
     if (const char *e = getenv("TC_JIT_FENCE")) c.jit_sched_fence = atoi(e) != 0;
     if (const char *e = getenv("TC_JIT_ALIGN")) c.jit_align_store = atoi(e) != 0;
+    if (const char *e = getenv("TC_STAGED")) c.staged_enabled = atoi(e) != 0;
+    if (const char *e = getenv("TC_STAGED_TILE")) {
+        int v[3] = {0, 0, 0};
+        if (std::sscanf(e, "%d,%d,%d", &v[0], &v[1], &v[2]) >= 1)
+            for (int d = 0; d < 3; ++d) c.staged_tile[d] = std::max(0, v[d]);
+    }
     if (!c.host_only) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || n <= 0 || c.device < 0 || c.device >= n) {
@@ -870,6 +903,7 @@ static tc_status impl_tc_finalize(tc_ctx *ctx) {
         for (auto e : c.events) (void)hipEventDestroy(e);
         for (auto e : c.tune_ev)
             if (e) (void)hipEventDestroy(e);
+        for (void *p : c.staged_allocs) dev_free(c, p);
         dev_free(c, c.partials);
         dev_free(c, c.red_out);
         if (c.red_host) (void)hipHostFree(c.red_host);
@@ -1235,7 +1269,7 @@ static tc_status impl_tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *
         num_tiles[0] = (int32_t)groups.size();
         num_tiles[1] = L;
         num_tiles[2] = 0;
-        const int64_t need = 2 * (int64_t)groups.size() + 5 * (int64_t)L;
+        const int64_t need = 2 * (int64_t)groups.size() + 7 * (int64_t)L;
         if (!ranges || cap < need) return fail(c, TC_ERR_ARG, "tc_chain_plan: need %lld slots", (long long)need);
         for (size_t g = 0; g < groups.size(); ++g) {
             ranges[2 * g] = groups[g]->g0;
@@ -1243,12 +1277,23 @@ static tc_status impl_tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *
         }
         int32_t *per = ranges + 2 * groups.size();
         for (int l = 0; l < L; ++l) {
-            per[5 * l] = -1;
-            for (int k = 1; k < 5; ++k) per[5 * l + k] = 0;
+            per[7 * l] = -1;
+            for (int k = 1; k < 7; ++k) per[7 * l + k] = 0;
         }
-        for (const auto &g : groups)
+        for (const auto &g : groups) {
+            if (g->staged) {
+                const StagedGroup &S = *g->staged;
+                for (int l = S.g0; l < S.g1; ++l) {
+                    int32_t *e = per + 7 * l;
+                    const auto &x = S.ext[l - S.g0];
+                    e[0] = S.computed[l - S.g0] ? 2 : 0;
+                    if (x[0] < 0) continue;
+                    for (int k = 0; k < 6; ++k) e[1 + k] = x[k];
+                }
+                continue;
+            }
             for (const auto &J : g->loops) {
-                int32_t *e = per + 5 * J.loop;
+                int32_t *e = per + 7 * J.loop;
                 e[0] = J.needed ? 1 : 0;
                 if (!J.needed) continue;
                 e[1] = J.extL;
@@ -1256,7 +1301,8 @@ static tc_status impl_tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *
                 e[3] = J.extB;
                 e[4] = J.extT;
             }
-        return fused_compile(c, groups);
+        }
+        return fused_compile(c, c.chain, groups);
     }
     SkewedPlan P = build_skewed_plan(c, c.chain, t3);
     int maxT = 1;
@@ -1273,6 +1319,38 @@ static tc_status impl_tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *
                 ranges[((int64_t)(d * maxT + t) * L + l) * 2] = P.s(d, t, l);
                 ranges[((int64_t)(d * maxT + t) * L + l) * 2 + 1] = P.e(d, t, l);
             }
+    return TC_OK;
+}
+
+static tc_status impl_tc_staged_tiles(tc_ctx *ctx, const int32_t *tile, int32_t group, int32_t *info, int32_t *boxes,
+                                      int64_t cap) {
+    CHECK_CTX(ctx);
+    Ctx &c = ctx->c;
+    if (!info) return fail(c, TC_ERR_ARG, "tc_staged_tiles: info is NULL");
+    int t3[3] = {tile ? tile[0] : 0, tile ? tile[1] : 0, tile ? tile[2] : 0};
+    auto groups = fused_split(c, c.chain, t3, c.jit_cpl);
+    if (group < 0 || group >= (int)groups.size()) return fail(c, TC_ERR_ARG, "tc_staged_tiles: no group %d", group);
+    const FusedGroup &g = *groups[group];
+    info[0] = g.g0;
+    info[1] = g.g1;
+    if (!g.staged) {
+        info[2] = 0;
+        return TC_OK;
+    }
+    const StagedGroup &S = *g.staged;
+    info[2] = S.ntot;
+    for (int d = 0; d < 3; ++d) info[3 + d] = S.tile[d];
+    const int L = S.g1 - S.g0, ns = (int)S.slots.size();
+    const int64_t per = 6 + 6 * (int64_t)L, need = per * S.ntot;
+    if (!boxes) return TC_OK;
+    if (cap < need) return fail(c, TC_ERR_ARG, "tc_staged_tiles: need %lld slots", (long long)need);
+    for (int t = 0; t < S.ntot; ++t) {
+        const int *r = &S.table[(size_t)t * S.rec];
+        int32_t *o = boxes + per * t;
+        for (int k = 0; k < 6; ++k) o[k] = r[k];
+        for (int l = 0; l < L; ++l)
+            for (int k = 0; k < 6; ++k) o[6 + 6 * l + k] = r[6 + 9 * ns + 6 * l + k];
+    }
     return TC_OK;
 }
 
@@ -1363,6 +1441,10 @@ tc_status tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *tile, int32_
     return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] {
         return impl_tc_chain_plan(ctx, mode, tile, num_tiles, ranges, cap);
     });
+}
+
+tc_status tc_staged_tiles(tc_ctx *ctx, const int32_t *tile, int32_t group, int32_t *info, int32_t *boxes, int64_t cap) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_staged_tiles(ctx, tile, group, info, boxes, cap); });
 }
 
 tc_status tc_pending(tc_ctx *ctx, int32_t *nloops) {

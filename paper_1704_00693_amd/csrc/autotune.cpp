@@ -37,7 +37,11 @@ std::vector<TuneCand> candidates(const std::vector<LoopRec> &chain) {
     }
     bool fusable = false;
     for (const auto &lp : chain) fusable = fusable || fused_op_supported(lp);
-    if (fusable) {
+    if (!fusable && chain.size() >= 2) {
+        // no weighted sums for register windows: the fused mode's staged
+        // groups (any ops and ranges) are the one fused candidate
+        v.push_back({TC_TILING_FUSED, {0, 0, 0}, 1});
+    } else if (fusable) {
         // fused layouts: one or two columns per lane, and register budgets
         // that trade group depth (fewer, deeper groups) against the
         // recomputed overlap and occupancy

@@ -826,35 +826,95 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
     sp.align_store = c.jit_align_store;
     sp.edge_div = c.jit_edge_div;
     const int L = (int)chain.size();
-    // best[j]: least modelled time of loops [0, j); from[j]: start of the last piece
-    std::vector<double> best(L + 1, 1e300);
-    std::vector<int> from(L + 1, -1);
-    std::vector<std::shared_ptr<FusedGroup>> piece(L + 1);
-    best[0] = 0.0;
-    for (int j = 1; j <= L; ++j) {
-        const double s = best[j - 1] + single_loop_cost(c, chain[j - 1]);
-        if (s < best[j]) {
-            best[j] = s;
-            from[j] = j - 1;
-            piece[j] = nullptr;
-        }
-        for (int i = j - 2; i >= 0 && j - i <= sp.max_loops; --i) {
-            if (!fused_op_supported(chain[i])) break;
-            auto G = std::make_shared<FusedGroup>();
-            if (!analyse(c, chain, i, j, sp, *G)) continue;
-            if (best[i] + G->cost < best[j]) {
-                best[j] = best[i] + G->cost;
-                from[j] = i;
-                piece[j] = G;
+    // staged candidates [i, j) whose full analysis failed (some tile needs
+    // more LDS than the representative ones)
+    std::vector<std::pair<int, int>> bad;
+    std::vector<std::shared_ptr<FusedGroup>> out;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        // best[j]: least modelled time of loops [0, j); from[j]: start of the last piece
+        std::vector<double> best(L + 1, 1e300);
+        std::vector<int> from(L + 1, -1);
+        std::vector<std::shared_ptr<FusedGroup>> piece(L + 1);
+        best[0] = 0.0;
+        for (int j = 1; j <= L; ++j) {
+            const double s = best[j - 1] + single_loop_cost(c, chain[j - 1]);
+            if (s < best[j]) {
+                best[j] = s;
+                from[j] = j - 1;
+                piece[j] = nullptr;
+            }
+            // register-window groups: runs of 2D weighted sums; staged groups:
+            // runs that register windows cannot take (any op, dimension, range)
+            bool reg_ok = true, stg_ok = c.staged_enabled, all_wsum = true;
+            for (int i = j - 1; i >= 0; --i) {
+                if (!fused_op_supported(chain[i])) {
+                    reg_ok = false;
+                    all_wsum = false;
+                }
+                if (j - i < 2) continue;
+                if (reg_ok && j - i <= sp.max_loops) {
+                    auto G = std::make_shared<FusedGroup>();
+                    if (analyse(c, chain, i, j, sp, *G) && best[i] + G->cost < best[j]) {
+                        best[j] = best[i] + G->cost;
+                        from[j] = i;
+                        piece[j] = G;
+                    }
+                }
+                if (stg_ok && !all_wsum) {
+                    if (j - i > kSMaxLoops) {
+                        stg_ok = false;
+                    } else if (std::find(bad.begin(), bad.end(), std::make_pair(i, j)) == bad.end()) {
+                        auto S = std::make_shared<StagedGroup>();
+                        if (!staged_analyse(c, chain, i, j, c.staged_tile, false, *S)) {
+                            stg_ok = false;  // prepending loops only adds datasets, parameters and LDS
+                        } else if (best[i] + S->cost < best[j]) {
+                            auto G = std::make_shared<FusedGroup>();
+                            G->g0 = i;
+                            G->g1 = j;
+                            G->cost = S->cost;
+                            G->staged = S;
+                            best[j] = best[i] + S->cost;
+                            from[j] = i;
+                            piece[j] = G;
+                        }
+                    }
+                }
+                if (!reg_ok && !stg_ok) break;
             }
         }
+        out.clear();
+        for (int j = L; j > 0; j = from[j])
+            if (piece[j]) out.push_back(piece[j]);
+        std::reverse(out.begin(), out.end());
+        // staged groups: every tile walked, tables built
+        bool ok = true;
+        for (auto &g : out) {
+            if (!g->staged) continue;
+            auto full = std::make_shared<StagedGroup>();
+            if (!staged_analyse(c, chain, g->g0, g->g1, c.staged_tile, true, *full)) {
+                bad.push_back({g->g0, g->g1});
+                ok = false;
+                continue;
+            }
+            g->staged = full;
+            g->nblocks = full->ntot;
+            g->alg_bytes = full->alg_bytes;
+        }
+        if (ok) break;
+        if (attempt == 7)  // give up on the failing groups: their loops run one kernel each
+            out.erase(std::remove_if(out.begin(), out.end(),
+                                     [](const std::shared_ptr<FusedGroup> &g) { return g->staged && g->staged->rec == 0; }),
+                      out.end());
     }
-    std::vector<std::shared_ptr<FusedGroup>> out;
-    for (int j = L; j > 0; j = from[j])
-        if (piece[j]) out.push_back(piece[j]);
-    std::reverse(out.begin(), out.end());
     if (getenv("TC_JIT_VERBOSE"))
         for (const auto &g : out) {
+            if (g->staged) {
+                const StagedGroup &S = *g->staged;
+                std::fprintf(stderr, "staged group [%d,%d): tile %dx%dx%d, %d tiles, %d slots, LDS %lld B, cost %.1f us\n",
+                             g->g0, g->g1, S.tile[0], S.tile[1], S.tile[2], S.ntot, (int)S.slots.size(),
+                             (long long)(S.desc_off + (int64_t)sizeof(LoopDesc)), S.cost * 1e6);
+                continue;
+            }
             int nl = 0, nld = 0;
             for (const auto &J : g->loops) nl += J.needed;
             for (char x : g->var[0].loaded) nld += x;
@@ -868,7 +928,18 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
     return out;
 }
 
-tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups) {
+tc_status fused_compile(Ctx &c, const std::vector<LoopRec> &chain, std::vector<std::shared_ptr<FusedGroup>> &all) {
+    std::vector<std::shared_ptr<FusedGroup>> groups;
+    for (auto &g : all) {
+        if (!g->staged) {
+            groups.push_back(g);
+            continue;
+        }
+        if (!g->staged->dev) {
+            const tc_status st = staged_upload(c, chain, *g->staged);
+            if (st != TC_OK) return st;
+        }
+    }
     if (groups.empty()) return TC_OK;
     for (const auto &g : groups)
         if (!layout_covers_once(*g))
@@ -943,6 +1014,7 @@ tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups
 }
 
 tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
+    if (G.staged) return staged_run(c, chain, *G.staged);
     if (G.baked) {
         // kernels with the weights compiled in serve only the weights they
         // were generated for; on a change the group falls back for good to
@@ -961,7 +1033,7 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
                              G.g1);
             G.baked = false;
             std::vector<std::shared_ptr<FusedGroup>> one{std::shared_ptr<FusedGroup>(&G, [](FusedGroup *) {})};
-            const tc_status st = fused_compile(c, one);
+            const tc_status st = fused_compile(c, chain, one);
             if (st != TC_OK) return st;
         }
     }
@@ -1030,6 +1102,7 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
 }
 
 tc_status fused_check_noalloc(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &G) {
+    if (G.staged) return staged_check_noalloc(c, *G.staged);
     if (G.baked) {
         size_t k = 0;
         for (int l = G.g0; l < G.g1; ++l)

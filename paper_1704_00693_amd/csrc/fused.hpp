@@ -26,6 +26,7 @@
 #include <string>
 #include <vector>
 
+#include "staged.hpp"
 #include "tc_internal.hpp"
 
 namespace tc {
@@ -115,6 +116,9 @@ struct FusedGroup {
     std::string source;         // generated kernels
     std::string kname_in, kname_edge;
     hipFunction_t fin = nullptr, fedge = nullptr;
+    // set for a staged group (any ops, dimensions and ranges; staged.hpp):
+    // the loops run as staged tiles instead of generated register windows
+    std::shared_ptr<StagedGroup> staged;
 };
 
 // Split a chain into fusion groups (loops outside any group run one kernel
@@ -125,8 +129,9 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
 // Whether a loop can be part of a fusion group at all (its op and dimension).
 bool fused_op_supported(const LoopRec &lp);
 
-// Compile (and, on a device context, load) the kernels of a plan's groups.
-tc_status fused_compile(Ctx &c, std::vector<std::shared_ptr<FusedGroup>> &groups);
+// Compile (and, on a device context, load) the kernels of a plan's groups;
+// staged groups get their device tables uploaded.
+tc_status fused_compile(Ctx &c, const std::vector<LoopRec> &chain, std::vector<std::shared_ptr<FusedGroup>> &groups);
 
 // Run one fusion group on the context's stream (ping-pong buffers are
 // prepared and swapped here).
@@ -151,6 +156,7 @@ uint64_t autotune_key(const Ctx &c, const std::vector<LoopRec> &chain);
 bool autotune_lookup(Ctx &c, const std::vector<LoopRec> &chain, TuneCand &out);
 
 // shared helpers (api.cpp)
+void build_desc(const Ctx &c, const LoopRec &lp, LoopDesc &d);
 int canonical_star2(const Stencil &st);
 double now_s();
 tc_status fail(Ctx &c, tc_status s, const char *fmt, ...);

@@ -251,6 +251,11 @@ struct Ctx {
     int jit_cpl = 1;         // consecutive columns per lane in fused kernels (TC_JIT_CPL: 1 or 2)
     bool jit_test_short_windows = false;  // TC_JIT_TEST_SHORT_WINDOWS=1: fault injection for error-path tests
     bool jit_bake = true;    // compile the weights into the kernels (TC_JIT_BAKE=0: read them from arguments)
+    // staged groups (overlapped tiles in LDS for loops of any op and range):
+    // TC_STAGED=0 disables them, TC_STAGED_TILE=x,y,z fixes the owned box
+    bool staged_enabled = true;
+    int staged_tile[3] = {0, 0, 0};
+    std::vector<void *> staged_allocs;  // device tables of staged groups (freed at finalize)
     double jit_compile_seconds = 0.0;
 
     // calls that must not allocate device memory (tc_reduction_result_static):

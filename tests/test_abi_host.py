@@ -243,6 +243,7 @@ def test_fused_plan_reports_recomputed_extents():
         r.record(L)
         groups, per = c.tc_fused_plan((0, 0, L))
     assert groups == [(0, L)]
-    for l, (computed, left, right, below, above) in enumerate(per):
+    for l, (computed, left, right, below, above, zlo, zhi) in enumerate(per):
         assert computed == 1
         assert (left, right, below, above) == (L - 1 - l,) * 4
+        assert (zlo, zhi) == (0, 0)

@@ -179,7 +179,7 @@ def test_library_fused_extents_pass_stamps():
             def lib_boxes(own, g0=g0, g1=g1, sub=sub):
                 out = []
                 for l in range(g0, g1):
-                    computed, left, right, below, above = per[l]
+                    computed, left, right, below, above = per[l][:5]
                     if computed != 1:
                         out.append(None)
                         continue
