@@ -165,6 +165,15 @@ def reference_copy_GBps(nbytes: int = 1 << 31, reps: int = 20) -> float:
     return gbps
 
 
+# Algorithmic bytes of one FP64 PPCG iteration per cell, loop by loop (8 B
+# per R or W access, 16 B per RW): matvec (p, Kx, Ky read, w written) 32,
+# x and r update (x, r RW, p, w read) 48, preconditioner set-up (r read; rt,
+# sd, z written) 32, ten Chebyshev steps (P1: Kx, Ky, sd read, rt, z RW, 56
+# B; P2: sd RW, rt read, 24 B; nine P2) 776, the two dot products 24 and
+# the p update 24.
+BATCH_BYTES_PER_CELL_ITERATION = 32 + 48 + 32 + 10 * 56 + 9 * 24 + 24 + 24
+
+
 def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8):
     """Batched heat-conduction solves: `count` instances of log-uniform size
     64^2..1024^2 (synthgen.batch_sizes), all submitted at once, to `tol`
@@ -186,11 +195,21 @@ def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8):
             dt = time.perf_counter() - t0
             rs = [b.tc_batch_poll(t) for t in tickets]
         lat = np.array([r["seconds"] for r in rs])
+        cell_iters = float(sum(n * n * r["iterations"] for (n, _), r in zip(sizes, rs)))
         out[mode] = {"solves_per_s": count / dt, "makespan_s": dt, "p50_latency_s": float(np.percentile(lat, 50)),
                      "p99_latency_s": float(np.percentile(lat, 99)),
                      "iterations": int(sum(r["iterations"] for r in rs)),
                      "converged": int(sum(r["converged"] for r in rs)),
-                     "max_rel_residual": float(max(r["rel_residual"] for r in rs))}
+                     "max_rel_residual": float(max(r["rel_residual"] for r in rs)),
+                     "cell_iterations": cell_iters}
+        if mode != "mixed":
+            # the per-loop byte model of one FP64 PPCG iteration per cell
+            # (BATCH_BYTES_PER_CELL_ITERATION) over the makespan
+            eff = cell_iters * BATCH_BYTES_PER_CELL_ITERATION / dt / 1e9
+            out[mode]["roofline"] = {"bound": "hbm", "achieved": eff, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": eff / HBM_PEAK_GBS, "traffic": None,
+                                     "bytes_per_cell_iteration": BATCH_BYTES_PER_CELL_ITERATION,
+                                     "model": "per-loop algorithmic bytes of one PPCG iteration, makespan time"}
         log(f"batch {mode}: {out[mode]['solves_per_s']:.1f} solves/s, makespan {dt:.2f} s, "
             f"converged {out[mode]['converged']}/{count}")
     out["mixed_over_sequential_fp64"] = out["mixed"]["solves_per_s"] / out["fp64_sequential"]["solves_per_s"]
@@ -249,7 +268,8 @@ def _tune(ctx, fn, limit=80):
     return False
 
 
-def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(), jacobi_two_columns=True):
+def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(), jacobi_two_columns=True,
+                    tealeaf_sizes=(256,)):
     """The other configurations, each in the execution modes that apply:
     heat-conduction PPCG 256^2 (50 iterations of 10 Chebyshev steps), the
     256^3 Taylor-Green RK3 step, the 8192^2 Jacobi iteration (250 iterations,
@@ -259,22 +279,24 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
     if "tealeaf" in which:
         from paper_1704_00693_amd.apps import HeatSolver
         from synthgen import heat_problem
-        hp = heat_problem(256, seed=0)
-        res = {}
-        for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))]:
-            with tc.Context(0) as c:
-                c.tc_set_tiling(m, tile)
-                s = HeatSolver(c, hp.density, hp.energy)
-                dt = _timed(lambda: s.solve(outer=50, inner=10), max(1, steps // 10))
-                st = c.tc_get_stats()
-            res[name] = {"seconds_per_solve": dt, "loops_recorded": st["loops_recorded"],
-                         "launches_last_flush": st["last_launches"], "groups_last_flush": st["last_groups"]}
-        out["tealeaf_256"] = {"workload": "heat conduction 256^2 FP64, PPCG 50 x 10 Chebyshev steps, seed 0",
-                              "modes": res,
-                              "fused_speedup_vs_untiled": res["none"]["seconds_per_solve"] /
-                              res["fused"]["seconds_per_solve"],
-                              "context_paper_speedup": 3.56}
-        log(f"tealeaf 256^2: {res}")
+        for n in tealeaf_sizes:
+            hp = heat_problem(n, seed=0)
+            res = {}
+            for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))]:
+                with tc.Context(0) as c:
+                    c.tc_set_tiling(m, tile)
+                    s = HeatSolver(c, hp.density, hp.energy)
+                    dt = _timed(lambda: s.solve(outer=50, inner=10), max(1, steps // 10))
+                    st = c.tc_get_stats()
+                res[name] = {"seconds_per_solve": dt, "loops_recorded": st["loops_recorded"],
+                             "cell_updates_per_s": 50 * 63 * n * n / dt}
+            out[f"tealeaf_{n}"] = {"workload": f"heat conduction {n}^2 FP64, PPCG 50 x 10 Chebyshev steps, seed 0",
+                                   "modes": res,
+                                   "fused_speedup_vs_untiled": res["none"]["seconds_per_solve"] /
+                                   res["fused"]["seconds_per_solve"],
+                                   "context_paper_speedup": {"2000^2": 3.56, "700^2": 1.07}}
+            log(f"tealeaf {n}^2: {res}")
+            del hp
     if "euler" in which:
         from paper_1704_00693_amd.apps import EulerRunner
         from synthgen import taylor_green
@@ -505,6 +527,8 @@ def main():
                     help="other workloads to time: comma list of tealeaf, euler, jacobi, chain3d ('' to skip)")
     ap.add_argument("--jacobi-n", default="8192",
                     help="grid edges of the Jacobi workload, comma list (a cache-capacity sweep)")
+    ap.add_argument("--tealeaf-n", default="256",
+                    help="grid edges of the heat-conduction PPCG workload, comma list (a problem-size sweep)")
     ap.add_argument("--jacobi-skew-rows", default="",
                     help="extra skewed Jacobi runs with these tile heights in rows, comma list (a tile-height study)")
     ap.add_argument("--jacobi-one-layout", action="store_true",
@@ -583,7 +607,8 @@ def main():
                 "traffic": None if tr is None else tr["hbm_bytes_per_flush"] / launches,
                 "kernel": kname, "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": alg}
     others = (other_workloads(tc, args.other.split(","), 10, [int(v) for v in args.jacobi_n.split(",")],
-                              [int(v) for v in args.jacobi_skew_rows.split(",") if v], not args.jacobi_one_layout)
+                              [int(v) for v in args.jacobi_skew_rows.split(",") if v], not args.jacobi_one_layout,
+                              [int(v) for v in args.tealeaf_n.split(",")])
               if args.other else None)
     batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
     served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None

@@ -206,6 +206,23 @@ tc_status tc_decl_reduction(tc_ctx *ctx, tc_redop op, const char *name, tc_red *
 tc_status tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_block blk, const int32_t *range,
                       const tc_arg *args, int nargs, const double *params, int nparams);
 
+/* Record n loops in one call: the same as n calls of tc_par_loop in order
+ * (each validated and copied; nothing runs).  Loop i takes its arguments
+ * from args[loops[i].first_arg ..] and its parameters from
+ * params[loops[i].first_param ..]; loops get empty names.  Stops at the first
+ * loop rejected and returns its status: the loops before it stay recorded and
+ * *recorded (may be NULL) gives their number.  For callers that record the
+ * same loops every iteration (one call per chain instead of one per loop). */
+typedef struct {
+    int32_t op;      /* tc_op */
+    int32_t block;
+    int32_t range[6];  /* as tc_par_loop: lo[0], hi[0], lo[1], hi[1], ... (first 2*ndim used) */
+    int32_t first_arg, nargs;
+    int32_t first_param, nparams;
+} tc_loop;
+tc_status tc_par_loops(tc_ctx *ctx, int32_t n, const tc_loop *loops, const tc_arg *args, const double *params,
+                       int32_t *recorded);
+
 /* Flush the chain (Section 4.1), then return the reduction's value (as
  * double) and reset it to its identity.  A reduction accumulates over every
  * loop that used it since its previous fetch. */

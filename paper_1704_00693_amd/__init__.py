@@ -37,7 +37,7 @@ OPS = {
 }
 ACCESS = {"R": TC_READ, "W": TC_WRITE, "RW": TC_RW, "INC": TC_INC}
 EXPORTS = ["tc_init", "tc_finalize", "tc_decl_block", "tc_decl_dat", "tc_decl_stencil", "tc_decl_reduction",
-           "tc_par_loop", "tc_reduction_result", "tc_reduction_result_static", "tc_flush", "tc_dat_read", "tc_dat_write", "tc_dat_device_view",
+           "tc_par_loop", "tc_par_loops", "tc_reduction_result", "tc_reduction_result_static", "tc_flush", "tc_dat_read", "tc_dat_write", "tc_dat_device_view",
            "tc_set_tiling", "tc_set_profiling", "tc_get_stats", "tc_chain_plan", "tc_staged_tiles", "tc_pending", "tc_status_string",
            "tc_last_error", "tc_batch_create", "tc_batch_submit", "tc_batch_step", "tc_batch_poll", "tc_batch_wait",
            "tc_batch_read_x", "tc_batch_destroy"]
@@ -62,6 +62,13 @@ class InitOpts(ctypes.Structure):
 class Arg(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("handle", ctypes.c_int32), ("stencil", ctypes.c_int32),
                 ("access", ctypes.c_int32)]
+
+
+class LoopSpec(ctypes.Structure):
+    """tc_loop: one loop of a tc_par_loops call."""
+    _fields_ = [("op", ctypes.c_int32), ("block", ctypes.c_int32), ("range", ctypes.c_int32 * 6),
+                ("first_arg", ctypes.c_int32), ("nargs", ctypes.c_int32), ("first_param", ctypes.c_int32),
+                ("nparams", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -128,6 +135,8 @@ def lib() -> ctypes.CDLL:
         "tc_decl_reduction": [P, i32, ctypes.c_char_p, i32p],
         "tc_par_loop": [P, ctypes.c_char_p, i32, i32, i32p, ctypes.POINTER(Arg), ctypes.c_int,
                         ctypes.POINTER(ctypes.c_double), ctypes.c_int],
+        "tc_par_loops": [P, i32, ctypes.POINTER(LoopSpec), ctypes.POINTER(Arg), ctypes.POINTER(ctypes.c_double),
+                         i32p],
         "tc_reduction_result": [P, i32, ctypes.POINTER(ctypes.c_double)],
         "tc_reduction_result_static": [P, i32, ctypes.POINTER(ctypes.c_double)],
         "tc_staged_tiles": [P, i32p, i32, i32p, i32p, i64],
@@ -171,6 +180,9 @@ class Context:
                  stream: Optional[int] = None):
         L = lib()
         self._tensors: Dict[int, object] = {}
+        self._loop_arrays: Dict[tuple, tuple] = {}
+        self._capture: Optional[list] = None
+        self._no_params = (ctypes.c_double * 1)()
         opts = InitOpts()
         opts.device = device
         opts.flags = TC_INIT_HOST_ONLY if host_only else 0
@@ -274,17 +286,47 @@ class Context:
     def tc_par_loop(self, op, blk: int, rng: Sequence[int], args, params: Sequence[float] = (), name: str = ""):
         """args: tuples (dat, stencil, access) for datasets, ("red", handle)
         for reductions; access as "R"/"W"/"RW"/"INC" or the TC_ constant."""
-        opc = OPS[op] if isinstance(op, str) else int(op)
-        arr = (Arg * max(len(args), 1))()
-        for i, a in enumerate(args):
-            if a[0] == "red":
-                arr[i] = Arg(TC_ARG_RED, int(a[1]), 0, 0)
-            else:
-                acc = ACCESS[a[2]] if isinstance(a[2], str) else int(a[2])
-                arr[i] = Arg(TC_ARG_DAT, int(a[0]), int(a[1]), acc)
-        prm = (ctypes.c_double * max(len(params), 1))(*[float(p) for p in params])
-        self._ck(lib().tc_par_loop(self.ptr, name.encode(), opc, blk, _i32(rng), arr, len(args), prm, len(params)),
-                 f"tc_par_loop({name})")
+        if self._capture is not None:  # building a LoopBatch: keep the loop instead
+            self._capture.append((op, blk, tuple(rng), tuple(args), tuple(float(p) for p in params)))
+            return
+        # the marshalled op, range and argument arrays of a loop shape are
+        # kept (applications record the same shapes every iteration)
+        key = (op, blk, tuple(rng), tuple(args), name)
+        m = self._loop_arrays.get(key)
+        if m is None:
+            opc = OPS[op] if isinstance(op, str) else int(op)
+            arr = (Arg * max(len(args), 1))()
+            for i, a in enumerate(args):
+                if a[0] == "red":
+                    arr[i] = Arg(TC_ARG_RED, int(a[1]), 0, 0)
+                else:
+                    acc = ACCESS[a[2]] if isinstance(a[2], str) else int(a[2])
+                    arr[i] = Arg(TC_ARG_DAT, int(a[0]), int(a[1]), acc)
+            if len(self._loop_arrays) > 4096:
+                self._loop_arrays.clear()
+            m = self._loop_arrays[key] = (opc, arr, len(args), _i32(rng), name.encode())
+        opc, arr, nargs, rarr, bname = m
+        n = len(params)
+        prm = (ctypes.c_double * n)(*params) if n else self._no_params
+        st = lib().tc_par_loop(self.ptr, bname, opc, blk, rarr, arr, nargs, prm, n)
+        if st != TC_OK:
+            self._ck(st, f"tc_par_loop({name})")
+
+    def capture(self):
+        """Context manager: tc_par_loop calls inside it are collected (not
+        recorded) into the list it yields, for a LoopBatch."""
+        ctx = self
+
+        class _Cap:
+            def __enter__(self_):
+                ctx._capture = []
+                return ctx._capture
+
+            def __exit__(self_, *exc):
+                ctx._capture = None
+                return False
+
+        return _Cap()
 
     def tc_flush(self):
         self._ck(lib().tc_flush(self.ptr), "tc_flush")
@@ -401,6 +443,50 @@ class Context:
                 boxes.append(None if any(h <= o for o, h in zip(lo, hi)) else (lo, hi))
             tiles.append((own, boxes))
         return g0, g1, ext, tiles
+
+
+class LoopBatch:
+    """A fixed list of loops recorded with one tc_par_loops call.  Built from
+    (op, block, range, args, params) entries (as Context.capture collects
+    them); ``params`` is a writable view of all loops' parameters, so a
+    caller can change scalars between recordings."""
+
+    def __init__(self, ctx: "Context", loops):
+        self.ctx = ctx
+        n = len(loops)
+        nargs = sum(len(l[3]) for l in loops)
+        nprm = sum(len(l[4]) for l in loops)
+        self.specs = (LoopSpec * max(n, 1))()
+        self.args = (Arg * max(nargs, 1))()
+        self.cparams = (ctypes.c_double * max(nprm, 1))()
+        self.first_param = []
+        ka = kp = 0
+        for i, (op, blk, rng, args, params) in enumerate(loops):
+            sp = self.specs[i]
+            sp.op = OPS[op] if isinstance(op, str) else int(op)
+            sp.block = int(blk)
+            for k, v in enumerate(rng):
+                sp.range[k] = int(v)
+            sp.first_arg, sp.nargs = ka, len(args)
+            for a in args:
+                if a[0] == "red":
+                    self.args[ka] = Arg(TC_ARG_RED, int(a[1]), 0, 0)
+                else:
+                    acc = ACCESS[a[2]] if isinstance(a[2], str) else int(a[2])
+                    self.args[ka] = Arg(TC_ARG_DAT, int(a[0]), int(a[1]), acc)
+                ka += 1
+            sp.first_param, sp.nparams = kp, len(params)
+            self.first_param.append(kp)
+            for v in params:
+                self.cparams[kp] = float(v)
+                kp += 1
+        self.n = n
+        self.params = np.ctypeslib.as_array(self.cparams)
+
+    def record(self):
+        done = ctypes.c_int32()
+        self.ctx._ck(lib().tc_par_loops(self.ctx.ptr, self.n, self.specs, self.args, self.cparams,
+                                        ctypes.byref(done)), "tc_par_loops")
 
 
 class Batch:

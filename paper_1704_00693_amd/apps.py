@@ -5,7 +5,8 @@ PPCG solve, the compressible-Euler step and the request-serving loop.
 
 Nothing here computes on the host beyond the scalar recurrences of the solver
 (CG's alpha and beta, the Chebyshev coefficients); every loop is recorded with
-``tc_par_loop`` and runs in the library's HIP kernels.
+``tc_par_loop`` (or several at once with ``tc_par_loops``) and runs in the
+library's HIP kernels.
 """
 from __future__ import annotations
 
@@ -14,7 +15,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from . import (TC_F32, TC_F64, TC_RED_MAX, TC_RED_SUM, Context)
+from . import (TC_F32, TC_F64, TC_RED_MAX, TC_RED_SUM, Context, LoopBatch)
 
 
 # ---------------------------------------------------------------------------
@@ -201,6 +202,7 @@ class HeatSolver:
         self.r_sum = [ctx.tc_decl_reduction(TC_RED_SUM, f"s{i}") for i in range(3)]
         self.r_max = ctx.tc_decl_reduction(TC_RED_MAX, "lmax")
         self.interior = [v for _ in range(D) for v in (0, n)]
+        self._batches: Dict[tuple, LoopBatch] = {}
 
     # -- loop helpers --------------------------------------------------------
     def K(self):
@@ -270,16 +272,38 @@ class HeatSolver:
         hist = {"rr": [], "rz": [], "pw": []}
         it = 0
         limit = outer if tol is None else max_iter
-        while it < limit:
+
+        def cg_p():
+            self.loop("TEA_CG_P", [self.F("p", "RW"), self.F("z", "R")], [0.0])
+
+        def matvec():
             self.halo_fill("p")
             self.loop("TEA_MATVEC_DOT", self.K() + [self.F("p", "R", self.S_star), self.F("w", "W"), ("red", s0)])
-            pw = ctx.tc_reduction_result(s0)
-            alpha = rz / pw
+
+        def update():
             self.loop("TEA_CG_UPDATE", [self.F("u", "RW"), self.F("r", "RW"), self.F("p", "R"), self.F("w", "R")],
-                      [alpha])
+                      [0.0])
             self.precondition(theta, al, be, inner)
             self.dot("r", "z", s1)
             self.dot("r", "r", s2)
+
+        # the loops between two reduction fetches are the same every
+        # iteration: each chain is recorded with one call, only the CG scalar
+        # (beta of the p update, alpha of the x, r update) changing
+        chain_a0 = self._batch(("a0",), matvec)
+        chain_a = self._batch(("a",), lambda: (cg_p(), matvec()))
+        chain_b = self._batch(("b", inner, theta, tuple(al), tuple(be)), update)
+        beta = None
+        while it < limit:
+            if beta is None:
+                chain_a0.record()
+            else:
+                chain_a.params[chain_a.first_param[0]] = beta
+                chain_a.record()
+            pw = ctx.tc_reduction_result(s0)
+            alpha = rz / pw
+            chain_b.params[chain_b.first_param[0]] = alpha
+            chain_b.record()
             rz_new = ctx.tc_reduction_result(s1)
             rr = ctx.tc_reduction_result(s2)
             it += 1
@@ -287,12 +311,24 @@ class HeatSolver:
             hist["rz"].append(rz_new)
             hist["pw"].append(pw)
             if tol is not None and math.sqrt(rr) <= tol * bnorm:
+                beta = None
                 break
             beta = rz_new / rz
             rz = rz_new
+        if beta is not None:  # the last p update, as the plain iteration makes it
             self.loop("TEA_CG_P", [self.F("p", "RW"), self.F("z", "R")], [beta])
         ctx.tc_flush()
         return {"iterations": it, "lmax": lmax, "bnorm": bnorm, **hist}
+
+    def _batch(self, key, record) -> LoopBatch:
+        """The loops ``record`` enqueues, captured once per key and then
+        recorded with one tc_par_loops call each time."""
+        b = self._batches.get(key)
+        if b is None:
+            with self.ctx.capture() as loops:
+                record()
+            b = self._batches[key] = LoopBatch(self.ctx, loops)
+        return b
 
     def field(self, name: str) -> np.ndarray:
         a = self.ctx.tc_dat_read(self.f[name])

@@ -1130,6 +1130,25 @@ static tc_status impl_tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_bl
     return TC_OK;
 }
 
+static tc_status impl_tc_par_loops(tc_ctx *ctx, int32_t n, const tc_loop *loops, const tc_arg *args,
+                                   const double *params, int32_t *recorded) {
+    CHECK_CTX(ctx);
+    Ctx &c = ctx->c;
+    if (recorded) *recorded = 0;
+    if (n < 0 || (n > 0 && !loops)) return fail(c, TC_ERR_ARG, "tc_par_loops: bad loop list");
+    for (int32_t i = 0; i < n; ++i) {
+        const tc_loop &L = loops[i];
+        if (L.nargs < 0 || L.nparams < 0 || L.first_arg < 0 || L.first_param < 0 || (L.nargs > 0 && !args) ||
+            (L.nparams > 0 && !params))
+            return fail(c, TC_ERR_ARG, "tc_par_loops: loop %d has a bad argument or parameter slice", (int)i);
+        const tc_status st = impl_tc_par_loop(ctx, "", (tc_op)L.op, L.block, L.range, args + L.first_arg, L.nargs,
+                                              params + L.first_param, L.nparams);
+        if (st != TC_OK) return st;
+        if (recorded) *recorded = i + 1;
+    }
+    return TC_OK;
+}
+
 static tc_status impl_tc_flush(tc_ctx *ctx) {
     CHECK_CTX(ctx);
     return flush(ctx->c);
@@ -1398,6 +1417,11 @@ tc_status tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_block blk, con
     return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] {
         return impl_tc_par_loop(ctx, name, op, blk, range, args, nargs, params, nparams);
     });
+}
+
+tc_status tc_par_loops(tc_ctx *ctx, int32_t n, const tc_loop *loops, const tc_arg *args, const double *params,
+                       int32_t *recorded) {
+    return tc::guard_abi(ctx ? &ctx->c : nullptr, [&] { return impl_tc_par_loops(ctx, n, loops, args, params, recorded); });
 }
 
 tc_status tc_flush(tc_ctx *ctx) {

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
 
 #include "fused.hpp"
@@ -90,17 +91,28 @@ bool has_red(const LoopRec &lp) {
     return false;
 }
 
-// rough VALU cycles of one point of a loop, per lane (cost model only)
-double op_cycles(const Ctx &c, const LoopRec &lp) {
-    int pts = 0;
-    for (const auto &a : lp.args)
-        if (a.kind == TC_ARG_DAT) pts += c.stencils[a.stencil].npoints();
-    switch (lp.op) {
-    case TC_OP_EULER_RHS: return 500.0;
-    case TC_OP_EULER_PRIM: return 120.0;
-    case TC_OP_TEA_K: return 150.0;
-    default: return 40.0 + 12.0 * pts;
+// Modelled cycles of one point of a loop on one lane (cost model only).  A
+// staged tile reaches its data through generic (flat) addresses, and a
+// point's loads cannot move above the previous point's stores, so every
+// access costs about its latency: about 60 cycles for a dataset staged in
+// LDS, about 500 for one read from device memory (an L2 or Infinity Cache
+// hit).  Measured on MI355X with every read-only dataset in device memory:
+// a PPCG chain of 63 loops took about 1.6 us per loop per tile, and a 3D
+// Euler stage (primitives and five fourth-order right-hand sides) about
+// 80 us per 16 x 8 x 8 tile with one workgroup per CU.
+double op_cycles(const Ctx &c, const LoopRec &lp, const std::vector<int> &slot_of_arg, int base,
+                 const std::vector<char> &staged) {
+    double cyc = 20.0;
+    if (lp.op == TC_OP_EULER_RHS) cyc = 400.0;
+    if (lp.op == TC_OP_EULER_PRIM || lp.op == TC_OP_TEA_K) cyc = 120.0;
+    int k = 0;
+    for (const auto &a : lp.args) {
+        if (a.kind != TC_ARG_DAT) continue;
+        const int s = slot_of_arg[base + k++];
+        const double n = c.stencils[a.stencil].npoints() + (a.writes() ? 1.0 : 0.0);
+        cyc += n * (staged[s] ? 60.0 : 500.0);
     }
+    return cyc;
 }
 
 // One tile's backward walk.
@@ -178,39 +190,77 @@ B3 tile_box(const StagedGroup &G, const int t[3]) {
     return O;
 }
 
-// Sizes the LDS boxes from the walks of `tiles` and fills the cost model;
-// false if the staged datasets do not fit.
+// Sizes the LDS boxes from the walks of `tiles`, decides which datasets the
+// group only reads are staged in LDS too (the most accessed first, while
+// they fit), and fills the cost model; false if the written datasets do
+// not fit.
 bool layout(const Ctx &c, const Ana &A, StagedGroup &G, const std::vector<std::array<int, 3>> &tiles,
             std::vector<Walk> &walks) {
     const size_t ns = A.dats.size();
     const int L = A.g1 - A.g0;
+    const int es = G.dtype == TC_F64 ? 8 : 4;
     std::vector<int> dim(3 * ns, 0);
     std::vector<char> twin(ns, 0);
     walks.resize(tiles.size());
-    double cyc_sum = 0.0, bytes_sum = 0.0;
-    const int es = G.dtype == TC_F64 ? 8 : 4;
     G.computed.assign(L, 0);
     for (size_t i = 0; i < tiles.size(); ++i) {
         const B3 O = tile_box(G, tiles[i].data());
         Walk &w = walks[i];
         A.walk(O, w);
+        for (int l = 0; l < L; ++l)
+            if (vol(w.C[l]) > 0) G.computed[l] = 1;
+        for (size_t s = 0; s < ns; ++s) {
+            for (int d = 0; d < 3; ++d)
+                if (!empty(w.box[s])) dim[3 * s + d] = std::max(dim[3 * s + d], w.box[s].hi[d] - w.box[s].lo[d]);
+            if (A.resident[s] && !contains(isect(O, A.wr[s]), w.load[s])) twin[s] = 1;
+        }
+    }
+    auto elems = [&](size_t s) {
+        return ((int64_t)std::max(1, dim[3 * s]) * std::max(1, dim[3 * s + 1]) * std::max(1, dim[3 * s + 2]) + 3) / 4 * 4;
+    };
+    // written datasets are always staged; read-only ones by access count
+    std::vector<char> staged(ns, 0);
+    int64_t used = 0;
+    for (size_t s = 0; s < ns; ++s)
+        if (A.resident[s]) {
+            staged[s] = 1;
+            used += elems(s);
+        }
+    if ((used * es + 15) / 16 * 16 + (int64_t)sizeof(LoopDesc) > kSLdsBudget) return false;
+    {
+        std::vector<std::pair<int, size_t>> order;
+        std::vector<int> count(ns, 0);
+        for (int l = A.g0; l < A.g1; ++l) {
+            int k = 0;
+            for (const auto &a : A.chain[l].args)
+                if (a.kind == TC_ARG_DAT) count[A.slot_of_arg[(l - A.g0) * kMaxArgs + k++]] += c.stencils[a.stencil].npoints();
+        }
+        for (size_t s = 0; s < ns; ++s)
+            if (!A.resident[s]) order.push_back({-count[s], s});
+        std::sort(order.begin(), order.end());
+        for (const auto &o : order)
+            if ((((used + elems(o.second)) * es + 15) / 16 * 16) + (int64_t)sizeof(LoopDesc) <= kSLdsBudget) {
+                staged[o.second] = 1;
+                used += elems(o.second);
+            }
+    }
+    double cyc_sum = 0.0, bytes_sum = 0.0;
+    for (size_t i = 0; i < tiles.size(); ++i) {
+        const B3 O = tile_box(G, tiles[i].data());
+        const Walk &w = walks[i];
         double cyc = 0.0, bytes = 0.0;
         for (int l = 0; l < L; ++l) {
             const int64_t n = vol(w.C[l]);
             if (n == 0) continue;
-            G.computed[l] = 1;
-            cyc += (double)((n + kSThreads - 1) / kSThreads) * op_cycles(c, A.chain[A.g0 + l]) + 400.0;
+            cyc += (double)((n + kSThreads - 1) / kSThreads) *
+                       op_cycles(c, A.chain[A.g0 + l], A.slot_of_arg, l * kMaxArgs, staged) + 1500.0;
         }
         for (size_t s = 0; s < ns; ++s) {
-            if (A.resident[s]) {
-                for (int d = 0; d < 3; ++d)
-                    if (!empty(w.box[s])) dim[3 * s + d] = std::max(dim[3 * s + d], w.box[s].hi[d] - w.box[s].lo[d]);
-                if (!contains(isect(O, A.wr[s]), w.load[s])) twin[s] = 1;
-                bytes += (double)(vol(w.load[s]) + vol(isect(O, A.wr[s]))) * es;
-                cyc += (double)(vol(w.load[s]) + vol(isect(O, A.wr[s]))) / kSThreads * 20.0;
-            } else {
-                bytes += (double)vol(w.box[s]) * es;
-            }
+            const double moved = A.resident[s] ? (double)(vol(w.load[s]) + vol(isect(O, A.wr[s]))) : (double)vol(w.box[s]);
+            bytes += moved * es;
+            // staging and write-back: rounds of eight loads in flight per
+            // lane, each about a device-memory latency
+            if (staged[s]) cyc += std::ceil(moved / (kSThreads * 8.0)) * 2000.0;
         }
         cyc_sum += cyc;
         bytes_sum += bytes;
@@ -221,26 +271,29 @@ bool layout(const Ctx &c, const Ana &A, StagedGroup &G, const std::vector<std::a
         SSlot &S = G.slots[s];
         std::memset(&S, 0, sizeof S);
         S.resident = A.resident[s];
+        S.staged = staged[s];
         for (int d = 0; d < 3; ++d) {
             S.wlo[d] = A.wr[s].lo[d];
             S.whi[d] = A.wr[s].hi[d];
         }
-        if (!S.resident) continue;
+        if (!S.staged) continue;
         S.twin = twin[s];
-        const int64_t bx = std::max(1, dim[3 * s]), by = std::max(1, dim[3 * s + 1]), bz = std::max(1, dim[3 * s + 2]);
+        const int64_t bx = std::max(1, dim[3 * s]), by = std::max(1, dim[3 * s + 1]);
         S.lds_off = off;
         S.lsy = bx;
         S.lsz = bx * by;
-        off += (bx * by * bz + 3) / 4 * 4;
+        off += elems(s);
     }
     G.lds_bytes = off * es;
     G.desc_off = (G.lds_bytes + 15) / 16 * 16;
-    if (G.desc_off + (int64_t)sizeof(LoopDesc) > kSLdsBudget) return false;
-    // cost: latency-bound tiles (workgroups per CU by LDS) or bytes moved
+    // latency-bound tiles: rounds of one tile per CU; a second resident
+    // workgroup per CU (if LDS allows) overlaps about half of the latency
     const double per_tile = cyc_sum / (double)tiles.size();
     const double lds = (double)(G.desc_off + sizeof(LoopDesc) + 1024);
     const double wg_per_cu = std::max(1.0, std::min(4.0, std::floor(160.0 * 1024.0 / lds)));
-    const double t_lat = (double)G.ntot * per_tile / (256.0 * std::min(wg_per_cu, 2.0) * 2.4e9);
+    const double per_cu = std::max(1.0, (double)G.ntot / 256.0);
+    const double overlap = std::min(per_cu, std::min(wg_per_cu, 2.0));
+    const double t_lat = per_cu * per_tile / ((1.0 + 0.5 * (overlap - 1.0)) * 2.4e9);
     const double t_bw = (double)G.ntot * (bytes_sum / (double)tiles.size()) / 4.0e12;
     G.cost = std::max(t_lat, t_bw) + 5e-6;
     return true;
@@ -407,6 +460,7 @@ bool staged_analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int
         build_desc(c, chain[l], d);
         S.prm_off = po;
         S.nprm = chain[l].op == TC_OP_WSUM ? d.pt0[d.nargs - 1] + d.npts[d.nargs - 1] : (int)chain[l].params.size();
+        S.prm_skip = chain[l].op == TC_OP_WSUM ? d.npts[0] : 0;
         po += S.nprm;
         if (has_red(chain[l])) ++G.nred_loops;
     }
@@ -429,7 +483,7 @@ bool staged_analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int
             for (size_t s = 0; s < ns; ++s) {
                 int *q = r + 6 + 9 * s;
                 const B3 b = empty(w.box[s]) ? O : w.box[s];
-                const B3 ld = A.resident[s] ? w.load[s] : none();
+                const B3 ld = A.resident[s] ? w.load[s] : (G.slots[s].staged ? w.box[s] : none());
                 for (int d = 0; d < 3; ++d) {
                     q[d] = b.lo[d];
                     q[3 + d] = empty(ld) ? 0 : ld.lo[d];
@@ -463,7 +517,7 @@ tc_status staged_upload(Ctx &c, const std::vector<LoopRec> &chain, StagedGroup &
             for (const auto &x : chain[G.g0 + l].args)
                 if (x.kind == TC_ARG_DAT && k++ == a) st = &c.stencils[x.stencil];
             d.arg[a].ptr = nullptr;
-            if (!G.slots[s].resident) continue;
+            if (!G.slots[s].staged) continue;
             d.arg[a].sy = G.slots[s].lsy;
             d.arg[a].sz = G.slots[s].lsz;
             for (int p = 0; p < d.npts[a]; ++p)
@@ -552,11 +606,12 @@ tc_status staged_run(Ctx &c, const std::vector<LoopRec> &chain, StagedGroup &G) 
         }
         a.dst[s] = ds.origin(tw);
     }
+    // this flush's parameters in each loop's descriptor layout (a weighted
+    // sum's weights follow its output stencil points, as build_desc places them)
     for (int l = G.g0; l < G.g1; ++l) {
-        LoopDesc d;
-        build_desc(c, chain[l], d);
         const SLoop &S = G.loops[l - G.g0];
-        for (int i = 0; i < S.nprm; ++i) a.prm[S.prm_off + i] = d.prm[i];
+        const std::vector<double> &p = chain[l].params;
+        for (size_t i = 0; i < p.size() && S.prm_skip + (int)i < S.nprm; ++i) a.prm[S.prm_off + S.prm_skip + i] = p[i];
     }
     const hipError_t e = launch_staged(a, G.dtype, (size_t)G.desc_off + sizeof(LoopDesc), c.stream);
     if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "staged group launch failed: %s", hipGetErrorString(e));

@@ -6,15 +6,20 @@
 // points only and write one double-double partial per tile.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "ops.hpp"
 #include "staged.hpp"
 
 namespace tc {
 
 static_assert(sizeof(LoopDesc) % 8 == 0, "descriptors are copied to LDS in 8-byte words");
+static_assert(sizeof(LoopDesc) <= 2 * 8 * kSThreads, "a descriptor is at most two words per thread");
 static_assert(sizeof(SArgs) <= 4096, "staged kernel arguments stay within 4 KiB");
 
 namespace {
+
+constexpr int kBatch = 8;  // values per lane loaded before they are stored (staging and write-back)
 
 __device__ __forceinline__ int tile_order(int i, int nb) {
     // XCD-aware order: hardware block i runs on XCD i % 8; XCD k gets a
@@ -116,9 +121,11 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
     const int ns = a.nslots;
 
     // chain-start values of the staged datasets where the tile needs them
+    // (written ones: where their chain-start values are read; read-only
+    // ones: their read hull)
     for (int s = 0; s < ns; ++s) {
         const SSlot &S = a.slots[s];
-        if (!S.resident) continue;
+        if (!S.staged) continue;
         const int *q = r + 6 + 9 * s;
         const int *L = q + 3;
         const int wx = q[6] - L[0], wy = q[7] - L[1], wz = q[8] - L[2];
@@ -127,19 +134,43 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
         const int64_t gsy = a.gsy[s], gsz = a.gsz[s];
         T *box = lds + S.lds_off;
         const int n = wx * wy * wz;
-        for (int i = threadIdx.x; i < n; i += kSThreads) {
-            const Pt p = box_point(L, wx, wy, i);
-            box[(p.x - q[0]) + (p.y - q[1]) * S.lsy + (p.z - q[2]) * S.lsz] =
-                src[(int64_t)p.x + (int64_t)p.y * gsy + (int64_t)p.z * gsz];
+        // kBatch loads in flight per lane before their stores
+        for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * kSThreads) {
+            T v[kBatch];
+            int o[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int i = i0 + k * kSThreads;
+                o[k] = -1;
+                if (i < n) {
+                    const Pt p = box_point(L, wx, wy, i);
+                    o[k] = (p.x - q[0]) + (p.y - q[1]) * S.lsy + (p.z - q[2]) * S.lsz;
+                    v[k] = src[(int64_t)p.x + (int64_t)p.y * gsy + (int64_t)p.z * gsz];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                if (o[k] >= 0) box[o[k]] = v[k];
         }
     }
     __syncthreads();
 
-    for (int l = 0; l < a.nloops; ++l) {
-        const int *C = r + 6 + 9 * ns + 6 * l;
-        if (C[3] <= C[0] || C[4] <= C[1] || C[5] <= C[2]) {
-            // nothing to compute here; a reduction still gets this tile's
-            // partial (the identity), since the finalize pass reads one per tile
+    // Loops in order.  A loop's descriptor is read from device memory while
+    // the previous loop computes and written to LDS after it, with the
+    // tile's pointers, the flush's parameters and the partial addresses
+    // substituted as the words are stored; loops the tile does not compute
+    // are skipped (their reductions get an identity partial).
+    constexpr int kWords = (int)(sizeof(LoopDesc) / 8);
+    constexpr int kArg0 = (int)(offsetof(LoopDesc, arg) / 8);
+    constexpr int kPrm0 = (int)(offsetof(LoopDesc, prm) / 8);
+    constexpr int kPart0 = (int)(offsetof(LoopDesc, partials) / 8);
+    static_assert(sizeof(DArg) == 24 && offsetof(DArg, ptr) == 0, "descriptor argument layout");
+    static_assert(offsetof(LoopDesc, arg) % 8 == 0 && offsetof(LoopDesc, prm) % 8 == 0 &&
+                      offsetof(LoopDesc, partials) % 8 == 0, "descriptor word layout");
+    auto next_loop = [&](int l) {
+        for (++l; l < a.nloops; ++l) {
+            const int *C = r + 6 + 9 * ns + 6 * l;
+            if (C[3] > C[0] && C[4] > C[1] && C[5] > C[2]) break;
             const LoopDesc &tmpl = a.loops[l];
             if (threadIdx.x < (unsigned)tmpl.nred) {
                 const int j = threadIdx.x;
@@ -148,38 +179,51 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
                 part[0] = e.hi;
                 part[1] = e.lo;
             }
-            continue;
         }
-        // this loop's descriptor into LDS, re-pointed at the tile's boxes
-        {
-            const uint64_t *from = (const uint64_t *)(a.loops + l);
-            uint64_t *to = (uint64_t *)&d;
-            for (int i = threadIdx.x; i < (int)(sizeof(LoopDesc) / 8); i += kSThreads) to[i] = from[i];
-        }
-        __syncthreads();
+        return l;
+    };
+    // the word of loop l's descriptor at index wi, with this tile's substitutions
+    auto word = [&](int l, int wi, uint64_t v) -> uint64_t {
         const SLoop &SL = a.sl[l];
-        if (threadIdx.x < (unsigned)d.nargs) {
-            const int k = threadIdx.x;
-            const int s = SL.slot[k];
-            const SSlot &S = a.slots[s];
-            if (S.resident) {
+        if (wi >= kArg0 && wi < kArg0 + 3 * kMaxArgs && (wi - kArg0) % 3 == 0) {
+            const int k = (wi - kArg0) / 3;
+            if (k < a.loops[l].nargs) {
+                const int s = SL.slot[k];
+                const SSlot &S = a.slots[s];
+                if (!S.staged) return (uint64_t)a.src[s];
                 const int *q = r + 6 + 9 * s;
-                d.arg[k].ptr = (void *)(lds + S.lds_off - ((int64_t)q[0] + (int64_t)q[1] * S.lsy + (int64_t)q[2] * S.lsz));
-            } else {
-                d.arg[k].ptr = a.src[s];
+                return (uint64_t)(lds + S.lds_off - ((int64_t)q[0] + (int64_t)q[1] * S.lsy + (int64_t)q[2] * S.lsz));
             }
+        } else if (wi >= kPrm0 && wi < kPrm0 + SL.nprm) {
+            return __builtin_bit_cast(uint64_t, a.prm[SL.prm_off + (wi - kPrm0)]);
+        } else if (wi >= kPart0 && wi < kPart0 + 2) {
+            return (uint64_t)(a.partials + 2 * SL.part[wi - kPart0]);
         }
-        if (threadIdx.x >= 64 && threadIdx.x < 64u + (unsigned)SL.nprm) {
-            const int k = threadIdx.x - 64;
-            d.prm[k] = a.prm[SL.prm_off + k];
+        return v;
+    };
+    uint64_t *dw = (uint64_t *)&d;
+    int l = next_loop(-1);
+    if (l < a.nloops) {
+        const uint64_t *from = (const uint64_t *)(a.loops + l);
+        for (int i = threadIdx.x; i < kWords; i += kSThreads) dw[i] = word(l, i, from[i]);
+    }
+    __syncthreads();
+    while (l < a.nloops) {
+        const int ln = next_loop(l);
+        uint64_t w0 = 0, w1 = 0;
+        if (ln < a.nloops) {  // in flight while this loop computes
+            const uint64_t *from = (const uint64_t *)(a.loops + ln);
+            if (threadIdx.x < (unsigned)kWords) w0 = from[threadIdx.x];
+            if (threadIdx.x + kSThreads < (unsigned)kWords) w1 = from[threadIdx.x + kSThreads];
         }
-        if (threadIdx.x >= 192 && threadIdx.x < 194) {
-            const int j = threadIdx.x - 192;
-            d.partials[j] = a.partials + 2 * SL.part[j];
+        dispatch<T>(d, r + 6 + 9 * ns + 6 * l, O, tile);
+        __syncthreads();
+        if (ln < a.nloops) {
+            if (threadIdx.x < (unsigned)kWords) dw[threadIdx.x] = word(ln, threadIdx.x, w0);
+            if (threadIdx.x + kSThreads < (unsigned)kWords) dw[threadIdx.x + kSThreads] = word(ln, threadIdx.x + kSThreads, w1);
         }
         __syncthreads();
-        dispatch<T>(d, C, O, tile);
-        __syncthreads();
+        l = ln;
     }
 
     // owned values of the staged datasets
@@ -198,10 +242,22 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
         const int64_t gsy = a.gsy[s], gsz = a.gsz[s];
         const T *box = lds + S.lds_off;
         const int n = wx * wy * wz;
-        for (int i = threadIdx.x; i < n; i += kSThreads) {
-            const Pt p = box_point(lo, wx, wy, i);
-            dst[(int64_t)p.x + (int64_t)p.y * gsy + (int64_t)p.z * gsz] =
-                box[(p.x - q[0]) + (p.y - q[1]) * S.lsy + (p.z - q[2]) * S.lsz];
+        for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * kSThreads) {
+            T v[kBatch];
+            int64_t o[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int i = i0 + k * kSThreads;
+                o[k] = 0;
+                if (i < n) {  // logical offsets may be negative (halo points)
+                    const Pt p = box_point(lo, wx, wy, i);
+                    o[k] = (int64_t)p.x + (int64_t)p.y * gsy + (int64_t)p.z * gsz;
+                    v[k] = box[(p.x - q[0]) + (p.y - q[1]) * S.lsy + (p.z - q[2]) * S.lsz];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                if (i0 + k * kSThreads < n) dst[o[k]] = v[k];
         }
     }
 }

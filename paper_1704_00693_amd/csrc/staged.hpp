@@ -15,8 +15,9 @@
 // the hull of everything the tile reads or writes of it; its chain-start
 // values are loaded where they are needed, the loops run one after the
 // other (one barrier between loops) in place, and the owned box is written
-// back.  Datasets the group only reads are read from device memory
-// directly.  A written dataset whose chain-start values a tile loads beyond
+// back.  Datasets the group only reads are staged in LDS over their read
+// hull too while they fit (the most accessed first), else read from device
+// memory directly.  A written dataset whose chain-start values a tile loads beyond
 // its own owned box is written to the dataset's second buffer (ping-pong),
 // so no tile overwrites a value another still loads.  The point arithmetic
 // is the per-loop kernels' own functors (ops.hpp), so results are
@@ -39,8 +40,10 @@ constexpr int64_t kSLdsBudget = 150 * 1024;  // bytes of LDS for the staged data
 
 // Per dataset slot of a group (device copy in the group's table).
 struct SSlot {
-    int resident;    // written by the group: staged in LDS
+    int resident;    // written by the group: staged in LDS and written back
+    int staged;      // held in LDS (every written dataset; read-only ones while they fit)
     int twin;        // write back to the second buffer
+    int pad;
     int64_t lds_off;  // element offset of the slot's LDS box
     int64_t lsy, lsz;  // element strides of the LDS box
     int wlo[3], whi[3];  // hull of the ranges of the loops writing it (write-back region within a tile)
@@ -50,6 +53,9 @@ struct SSlot {
 struct SLoop {
     int slot[kMaxArgs];  // slot of every dataset argument
     int prm_off, nprm;   // parameters in the kernel-argument array (LoopDesc prm layout)
+    int prm_skip;        // leading entries of that layout the loop's parameters skip (a weighted
+                         // sum's output stencil points)
+    int pad;
     int64_t part[2];     // first partial of each reduction argument (one per tile follows)
 };
 

@@ -247,3 +247,43 @@ def test_fused_plan_reports_recomputed_extents():
         assert computed == 1
         assert (left, right, below, above) == (L - 1 - l,) * 4
         assert (zlo, zhi) == (0, 0)
+
+
+def test_par_loops_records_like_par_loop():
+    """tc_par_loops records the same loops as tc_par_loop one by one (same
+    plans), stops at the first rejected loop keeping the ones before it, and
+    its parameters can change between recordings."""
+    from paper_1704_00693_amd.apps import HeatSolver, chebyshev_coefs
+    n = 32
+    theta, delta, al, be = chebyshev_coefs(1.0, 50.0, 4)
+    plans = []
+    for batched in (False, True):
+        with tc.Context(host_only=True) as c:
+            hs = HeatSolver(c, np.full((n, n), 0.5), np.full((n, n), 1.5))
+            if batched:
+                b = hs._batch(("p",), lambda: hs.precondition(theta, al, be, 4))
+                assert c.tc_pending() == 0
+                b.record()
+            else:
+                hs.precondition(theta, al, be, 4)
+            assert c.tc_pending() == 1 + 4 * 4 + 4 + 3
+            L = c.tc_pending()
+            plans.append((c.tc_chain_plan((0, 8, 0), L, 2), c.tc_fused_plan()))
+    assert plans[0] == plans[1]
+    with tc.Context(host_only=True) as c:
+        hs = HeatSolver(c, np.full((n, n), 0.5), np.full((n, n), 1.5))
+        with c.capture() as loops:
+            hs.precondition(theta, al, be, 2)
+        bad = list(loops)
+        op, blk, rng, args, params = bad[3]
+        bad[3] = (op, blk, rng, args, params + (1.0,))  # one parameter too many
+        b = tc.LoopBatch(c, bad)
+        with pytest.raises(tc.TcError) as e:
+            b.record()
+        assert e.value.status == tc.TC_ERR_ARG
+        assert c.tc_pending() == 3
+        good = tc.LoopBatch(c, loops)
+        p2 = [i for i, l in enumerate(loops) if l[0] == "TEA_P2"][0]
+        good.params[good.first_param[p2]:good.first_param[p2] + 2] = (0.25, -0.5)
+        good.record()
+        assert c.tc_pending() == 3 + len(loops)
