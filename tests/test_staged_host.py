@@ -119,10 +119,14 @@ def test_ppcg_chain_is_one_staged_group():
         L = c.tc_pending()
         groups, per = c.tc_fused_plan()
         g0, g1, ext, tiles = c.tc_staged_tiles(0)
-    assert groups == [(0, L)]
-    assert all(p[0] == 2 for p in per)
-    # update and preconditioner set-up: one point per Chebyshev step on every side
-    assert per[0][1:5] == (10, 10, 10, 10) and per[1][1:5] == (10, 10, 10, 10)
+    # one staged group holds the preconditioner and the dot products (the
+    # x, r update before it joins or runs alone, as the cost model prefers)
+    assert len(groups) == 1 and groups[0][0] <= 1 and groups[0][1] == L
+    assert all(p[0] == 2 for p in per[1:])
+    # preconditioner set-up: one point per Chebyshev step on every side
+    assert per[1][1:5] == (10, 10, 10, 10)
+    if groups[0][0] == 0:
+        assert per[0][1:5] == (10, 10, 10, 10)
     # the last preconditioner step and the dot products: the owned box only
     assert per[-1][1:5] == (0, 0, 0, 0) and per[-3][1:5] == (0, 0, 0, 0)
-    assert tiles and (g0, g1) == (0, L)
+    assert tiles and (g0, g1) == groups[0]
