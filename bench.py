@@ -203,13 +203,15 @@ def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8):
                      "max_rel_residual": float(max(r["rel_residual"] for r in rs)),
                      "cell_iterations": cell_iters}
         if mode != "mixed":
-            # the per-loop byte model of one FP64 PPCG iteration per cell
-            # (BATCH_BYTES_PER_CELL_ITERATION) over the makespan
+            # the paper's effective bandwidth: the per-loop byte model of one
+            # FP64 PPCG iteration per cell (BATCH_BYTES_PER_CELL_ITERATION)
+            # over the makespan; fused Chebyshev launches and cache-resident
+            # small instances move fewer bytes than the model counts, so it
+            # can exceed the HBM peak (a model figure, not a roofline fraction)
             eff = cell_iters * BATCH_BYTES_PER_CELL_ITERATION / dt / 1e9
-            out[mode]["roofline"] = {"bound": "hbm", "achieved": eff, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                     "frac": eff / HBM_PEAK_GBS, "traffic": None,
-                                     "bytes_per_cell_iteration": BATCH_BYTES_PER_CELL_ITERATION,
-                                     "model": "per-loop algorithmic bytes of one PPCG iteration, makespan time"}
+            out[mode]["effective_bandwidth"] = {"GBps": eff, "of_hbm_peak": eff / HBM_PEAK_GBS,
+                                                "bytes_per_cell_iteration": BATCH_BYTES_PER_CELL_ITERATION,
+                                                "model": "per-loop bytes of one PPCG iteration, makespan time"}
         log(f"batch {mode}: {out[mode]['solves_per_s']:.1f} solves/s, makespan {dt:.2f} s, "
             f"converged {out[mode]['converged']}/{count}")
     out["mixed_over_sequential_fp64"] = out["mixed"]["solves_per_s"] / out["fp64_sequential"]["solves_per_s"]

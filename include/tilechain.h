@@ -329,7 +329,9 @@ tc_status tc_set_profiling(tc_ctx *ctx, int on);
  * the first and one-past-last chain loop of group g.  Then seven ints per
  * chain loop l at ranges[2 G + 7 l + k]: k = 0 is 1 if a register-window
  * group computes the loop, 2 if a staged group does (LDS-staged tiles, any
- * op and range), 0 if the loop is in a group but never computed (its result
+ * op and range), 3 if a fused 3D Runge-Kutta stage does (the five
+ * EULER_RHS loops and the five RK_STAGE loops of a stage in one z-marching
+ * kernel; no recomputed overlap), 0 if the loop is in a group but never computed (its result
  * is neither read later in the group nor the final value of its dataset),
  * -1 if it runs on its own; k = 1..6 are the points below and above the
  * owned block along x, y and z that the loop computes (the recomputed

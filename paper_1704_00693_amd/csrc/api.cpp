@@ -1300,6 +1300,10 @@ static tc_status impl_tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *
             for (int k = 1; k < 7; ++k) per[7 * l + k] = 0;
         }
         for (const auto &g : groups) {
+            if (g->estage) {
+                for (int l = g->g0; l < g->g1; ++l) per[7 * l] = 3;
+                continue;
+            }
             if (g->staged) {
                 const StagedGroup &S = *g->staged;
                 for (int l = S.g0; l < S.g1; ++l) {

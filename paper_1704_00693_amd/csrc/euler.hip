@@ -55,6 +55,16 @@ __device__ __forceinline__ T flux(T q, T ud, T p) {
     return f;
 }
 
+// the same flux with the component chosen at run time (a switch the
+// compiler resolves when the caller's loop over components is unrolled)
+template <typename T, int AX>
+__device__ __forceinline__ T flux_c(int c, T q, T ud, T p) {
+    T f = q * ud;
+    if (c == AX + 1) f = f + p;
+    if (c == 4) f = fma_t<T>(p, ud, f);
+    return f;
+}
+
 template <typename T>
 __device__ __forceinline__ T diff4(T fm2, T fm1, T fp1, T fp2) {
     const T t1 = fp1 - fm1;
@@ -184,7 +194,180 @@ hipError_t rhs3_t(const LoopDesc &d, const Box &b, hipStream_t s) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// One Runge-Kutta stage after the primitive variables: the five right-hand
+// sides and the five updates in one z march.  Per plane a lane forms the x,
+// y and z fluxes of all five components from Q, u, v, w, p (x neighbours
+// from adjacent lanes, y neighbours through LDS as above, z neighbours from
+// a five-plane window), then R_c = -(g_x + g_y + g_z) s and
+// Q_c = fma(a, Q0_c, b fma(dt, R_c, Q_c)) -- the arithmetic of the RHS and
+// RK_STAGE loops, in their order, so the results are their bits.  Q is read
+// at stencil offsets by neighbouring workgroups, so the new Q goes to the
+// datasets' second buffers; R is written only if a later loop reads it.
+// ---------------------------------------------------------------------------
+constexpr int kStageThreads = 256;  // four wavefronts, one per y row
+constexpr int kStageOut = 60;
+constexpr int kStageRows = 4;
+constexpr int kStageTz = 32;
+
+template <typename T>
+__global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageArgs a) {
+    __shared__ T fy_lds[2][kStageRows + 4][5][64];
+    const int lin = xcd_block(blockIdx.x, a.nb);
+    const int bx = lin % a.nbx, rest = lin / a.nbx, by = rest % a.nby, bz = rest / a.nby;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = a.lo[0] + bx * kStageOut - 2 + lane;
+    const int y0 = a.lo[1] + by * kStageRows;
+    const int y = y0 + wave;
+    const bool active = lane >= 2 && lane < 2 + kStageOut && x < a.hi[0] && y < a.hi[1];
+    const int z0 = a.lo[2] + bz * a.tz;
+    const int z1 = min(z0 + a.tz, a.hi[2]);
+    // every position read lies in [lo - 2, hi + 1] per axis (inside the
+    // allocation); lanes and rows beyond that are clamped and feed no output
+    const int xc = min(max(x, a.lo[0] - 2), a.hi[0] + 1);
+    const int yr = min(y, a.hi[1] + 1);
+    const int hslot = wave < 2 ? wave : wave + kStageRows;
+    const int yh = min(y0 - 2 + hslot, a.hi[1] + 1);
+    // row bases: own row (yr) and outside row (yh), column xc
+    auto at = [&](int k, int row) { return (const T *)a.ptr[k] + xc + (int64_t)row * a.sy[k]; };
+    const T *q[5], *hq[5], *q0[5];
+    for (int c = 0; c < 5; ++c) {
+        q[c] = at(kQ + c, yr);
+        hq[c] = at(kQ + c, yh);
+        q0[c] = at(kQ0 + c, yr);
+    }
+    const T *u = at(kU, yr), *v = at(kU + 1, yr), *w = at(kU + 2, yr), *p = at(kP, yr);
+    const T *hv = at(kU + 1, yh), *hp = at(kP, yh);
+    auto ld = [&](const T *base, int k, int z) { return base[(int64_t)z * a.sz[k]]; };
+    const T s = (T)a.s, ra = (T)a.a, rb = (T)a.b, dt = (T)a.dt;
+
+    // z fluxes of planes z0-2 .. z0+1
+    T fz[5][5];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int pl = z0 - 2 + k;
+        const T wk = ld(w, kU + 2, pl), pk = ld(p, kP, pl);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) fz[c][k] = flux_c<T, 2>(c, ld(q[c], kQ + c, pl), wk, pk);
+    }
+    // own row at planes z (current) and z+1: Q, u, v, p; the leading plane
+    // z+2: Q, u, v, w, p; the outside row at plane z: Q, v, p; Q0 at plane z
+    T cq[5], nq[5], lq[5], oq[5], cq0[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        cq[c] = ld(q[c], kQ + c, z0);
+        nq[c] = ld(q[c], kQ + c, z0 + 1);
+        lq[c] = ld(q[c], kQ + c, z0 + 2);
+        oq[c] = ld(hq[c], kQ + c, z0);
+        cq0[c] = ld(q0[c], kQ0 + c, z0);
+    }
+    T cu = ld(u, kU, z0), cv = ld(v, kU + 1, z0), cp = ld(p, kP, z0);
+    T nu = ld(u, kU, z0 + 1), nv = ld(v, kU + 1, z0 + 1), np_ = ld(p, kP, z0 + 1);
+    T lu = ld(u, kU, z0 + 2), lv = ld(v, kU + 1, z0 + 2), lw = ld(w, kU + 2, z0 + 2), lp = ld(p, kP, z0 + 2);
+    T ov = ld(hv, kU + 1, z0), op = ld(hp, kP, z0);
+
+    T *qn[5], *rr[5];
+    for (int c = 0; c < 5; ++c) {
+        qn[c] = (T *)a.out[c] + xc + (int64_t)yr * a.osy[c];
+        rr[c] = a.rout[c] ? (T *)a.rout[c] + xc + (int64_t)yr * a.rsy[c] : nullptr;
+    }
+    int buf = 0;
+    for (int z = z0; z < z1; ++z) {
+        // y fluxes of this plane: own row and outside row into LDS
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            fy_lds[buf][wave + 2][c][lane] = flux_c<T, 1>(c, cq[c], cv, cp);
+            fy_lds[buf][hslot][c][lane] = flux_c<T, 1>(c, oq[c], ov, op);
+        }
+        // the leading plane completes the z windows
+#pragma unroll
+        for (int c = 0; c < 5; ++c) fz[c][4] = flux_c<T, 2>(c, lq[c], lw, lp);
+        // x fluxes of this lane's column, neighbours from adjacent lanes
+        T gx[5], gz[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const T fx = flux_c<T, 0>(c, cq[c], cu, cp);
+            const T fxm1 = __shfl_up(fx, 1, 64), fxp1 = __shfl_down(fx, 1, 64);
+            const T fxm2 = __shfl_up(fx, 2, 64), fxp2 = __shfl_down(fx, 2, 64);
+            gx[c] = diff4<T>(fxm2, fxm1, fxp1, fxp2);
+            gz[c] = diff4<T>(fz[c][0], fz[c][1], fz[c][3], fz[c][4]);
+        }
+        // loads for the next plane (the leading plane z+3, the outside row
+        // and Q0 at z+1)
+        T iq[5], ioq[5], iq0[5];
+        T iu = (T)0, iv = (T)0, iw = (T)0, ip = (T)0, iov = (T)0, iop = (T)0;
+        const bool more = z + 1 < z1;
+        if (more) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                iq[c] = ld(q[c], kQ + c, z + 3);
+                ioq[c] = ld(hq[c], kQ + c, z + 1);
+                iq0[c] = ld(q0[c], kQ0 + c, z + 1);
+            }
+            iu = ld(u, kU, z + 3);
+            iv = ld(v, kU + 1, z + 3);
+            iw = ld(w, kU + 2, z + 3);
+            ip = ld(p, kP, z + 3);
+            iov = ld(hv, kU + 1, z + 1);
+            iop = ld(hp, kP, z + 1);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const T gy = diff4<T>(fy_lds[buf][wave][c][lane], fy_lds[buf][wave + 1][c][lane],
+                                  fy_lds[buf][wave + 3][c][lane], fy_lds[buf][wave + 4][c][lane]);
+            T acc = gx[c];
+            acc = acc + gy;
+            acc = acc + gz[c];
+            const T r = -acc * s;
+            const T t = fma_t<T>(dt, r, cq[c]);
+            const T qnew = fma_t<T>(ra, cq0[c], rb * t);
+            if (active) {
+                qn[c][(int64_t)z * a.osz[c]] = qnew;
+                if (rr[c]) rr[c][(int64_t)z * a.rsz[c]] = r;
+            }
+        }
+        // advance the windows
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) fz[c][k] = fz[c][k + 1];
+            cq[c] = nq[c];
+            nq[c] = lq[c];
+            if (more) {
+                lq[c] = iq[c];
+                oq[c] = ioq[c];
+                cq0[c] = iq0[c];
+            }
+        }
+        cu = nu; cv = nv; cp = np_;
+        nu = lu; nv = lv; np_ = lp;
+        if (more) {
+            lu = iu; lv = iv; lw = iw; lp = ip;
+            ov = iov; op = iop;
+        }
+        buf ^= 1;
+    }
+}
+
+template <typename T>
+hipError_t go_stage3(const EulerStageArgs &in, hipStream_t s) {
+    EulerStageArgs a = in;
+    a.nbx = (a.hi[0] - a.lo[0] + kStageOut - 1) / kStageOut;
+    a.nby = (a.hi[1] - a.lo[1] + kStageRows - 1) / kStageRows;
+    const int nbz = (a.hi[2] - a.lo[2] + kStageTz - 1) / kStageTz;
+    a.tz = kStageTz;
+    a.nb = a.nbx * a.nby * nbz;
+    if (a.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(euler_stage3_kernel<T>, dim3(a.nb), dim3(kStageThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_euler_stage3(const EulerStageArgs &a, int dtype, hipStream_t s) {
+    return dtype == TC_F64 ? go_stage3<double>(a, s) : go_stage3<float>(a, s);
+}
 
 hipError_t launch_euler_rhs3(const LoopDesc &d, const Box &b, int dtype, hipStream_t s) {
     if (b.nb <= 0) return hipSuccess;

@@ -1,6 +1,7 @@
 // Fusion groups: analysis, split, kernel generation, hipRTC compilation and
 // launch (the scheme is described in fused.hpp).
 #include "fused.hpp"
+#include "kernels.hpp"
 
 #include <hip/hiprtc.h>
 
@@ -805,7 +806,86 @@ uint64_t fnv1a(const std::string &s) {
     return h;
 }
 
+// Whether dataset d, written over box [lo, hi) by loop `after` - 1, is read
+// by a later loop of the chain before some later loop overwrites all of
+// that box (or the chain ends with the value as its final state).
+bool live_after(const std::vector<LoopRec> &chain, int after, int d, const int lo[3], const int hi[3]) {
+    for (size_t l = after; l < chain.size(); ++l) {
+        const LoopRec &lp = chain[l];
+        bool reads = false, covers = false;
+        for (const auto &a : lp.args) {
+            if (a.kind != TC_ARG_DAT || a.handle != d) continue;
+            if (a.reads()) reads = true;
+            if (a.access == TC_WRITE) {
+                covers = true;
+                for (int k = 0; k < 3; ++k) covers = covers && lp.lo[k] <= lo[k] && lp.hi[k] >= hi[k];
+            }
+        }
+        if (reads) return true;
+        if (covers) return false;
+    }
+    return true;
+}
+
 }  // namespace
+
+bool euler_stage_match(const Ctx &c, const std::vector<LoopRec> &chain, int i, EulerStage &E) {
+    if (i + 10 > (int)chain.size()) return false;
+    const LoopRec &f = chain[i];
+    if (f.ndim != 3) return false;
+    int dtype = -1;
+    double s = 0.0;
+    for (int k = 0; k < 10; ++k) {
+        const LoopRec &lp = chain[i + k];
+        if (lp.ndim != 3 || lp.block != f.block || lp.op != (k < 5 ? TC_OP_EULER_RHS : TC_OP_RK_STAGE)) return false;
+        for (int d = 0; d < 3; ++d)
+            if (lp.lo[d] != f.lo[d] || lp.hi[d] != f.hi[d]) return false;
+        for (const auto &a : lp.args) {
+            if (a.kind != TC_ARG_DAT) return false;
+            if (dtype < 0) dtype = c.dats[a.handle].dtype;
+            if (c.dats[a.handle].dtype != dtype) return false;
+        }
+        if (k < 5) {
+            // R_c(W), Q_c, u, v, w, p; params (c, s)
+            if (lp.args.size() != 6 || (int)lp.params[0] != k || lp.params[0] != (double)k) return false;
+            if (k == 0) s = lp.params[1];
+            if (lp.params[1] != s) return false;
+            E.r[k] = lp.args[0].handle;
+            E.q[k] = lp.args[1].handle;
+            for (int d = 0; d < 3; ++d) {
+                if (k == 0) E.u[d] = lp.args[2 + d].handle;
+                if (lp.args[2 + d].handle != E.u[d]) return false;
+            }
+            if (k == 0) E.p = lp.args[5].handle;
+            if (lp.args[5].handle != E.p) return false;
+        } else {
+            // Q0_c, Q_c(RW), R_c; params (a, b, dt) shared by the five
+            const int cc = k - 5;
+            if (lp.args.size() != 3 || lp.args[1].handle != E.q[cc] || lp.args[2].handle != E.r[cc]) return false;
+            E.q0[cc] = lp.args[0].handle;
+            for (int j = 0; j < 3; ++j)
+                if (lp.params[j] != chain[i + 5].params[j]) return false;
+        }
+    }
+    // every role a different dataset
+    std::vector<int> all;
+    for (int k = 0; k < 5; ++k) {
+        all.push_back(E.q[k]);
+        all.push_back(E.q0[k]);
+        all.push_back(E.r[k]);
+    }
+    for (int d = 0; d < 3; ++d) all.push_back(E.u[d]);
+    all.push_back(E.p);
+    std::vector<int> sorted = all;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return false;
+    for (int d = 0; d < 3; ++d) {
+        E.lo[d] = f.lo[d];
+        E.hi[d] = f.hi[d];
+    }
+    for (int k = 0; k < 5; ++k) E.r_live[k] = live_after(chain, i + 10, E.r[k], E.lo, E.hi);
+    return true;
+}
 
 bool fused_op_supported(const LoopRec &lp) { return lp.op == TC_OP_WSUM && lp.ndim == 2; }
 
@@ -842,6 +922,27 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                 best[j] = s;
                 from[j] = j - 1;
                 piece[j] = nullptr;
+            }
+            // a 3D Runge-Kutta stage ending here: one z-marching kernel
+            if (j >= 10) {
+                EulerStage E;
+                if (euler_stage_match(c, chain, j - 10, E)) {
+                    const LoopRec &f = chain[j - 10];
+                    int nlive = 0;
+                    for (bool b : E.r_live) nlive += b;
+                    const double cost = (double)f.points() * c.dats[E.q[0]].esize() * (19 + nlive) / 4.5e12 + 5e-6;
+                    if (best[j - 10] + cost < best[j]) {
+                        auto G = std::make_shared<FusedGroup>();
+                        G->g0 = j - 10;
+                        G->g1 = j;
+                        G->cost = cost;
+                        G->estage = std::make_shared<EulerStage>(E);
+                        G->alg_bytes = f.points() * (int64_t)c.dats[E.q[0]].esize() * (19 + nlive);
+                        best[j] = best[j - 10] + cost;
+                        from[j] = j - 10;
+                        piece[j] = G;
+                    }
+                }
             }
             // register-window groups: runs of 2D weighted sums; staged groups:
             // runs that register windows cannot take (any op, dimension, range)
@@ -908,6 +1009,10 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
     }
     if (getenv("TC_JIT_VERBOSE"))
         for (const auto &g : out) {
+            if (g->estage) {
+                std::fprintf(stderr, "Runge-Kutta stage group [%d,%d): cost %.1f us\n", g->g0, g->g1, g->cost * 1e6);
+                continue;
+            }
             if (g->staged) {
                 const StagedGroup &S = *g->staged;
                 std::fprintf(stderr, "staged group [%d,%d): tile %dx%dx%d, %d tiles, %d slots, LDS %lld B, cost %.1f us\n",
@@ -931,6 +1036,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
 tc_status fused_compile(Ctx &c, const std::vector<LoopRec> &chain, std::vector<std::shared_ptr<FusedGroup>> &all) {
     std::vector<std::shared_ptr<FusedGroup>> groups;
     for (auto &g : all) {
+        if (g->estage) continue;  // a precompiled kernel
         if (!g->staged) {
             groups.push_back(g);
             continue;
@@ -1013,8 +1119,81 @@ tc_status fused_compile(Ctx &c, const std::vector<LoopRec> &chain, std::vector<s
     return TC_OK;
 }
 
+// Second buffer of a dataset the group reads at offsets and writes over
+// [lo, hi): allocated on first use and made equal to the current buffer
+// outside that box.  Returns its logical origin through *origin.
+tc_status second_buffer(Ctx &c, Dataset &ds, const int lo[3], const int hi[3], void **origin) {
+    const int tw = 1 - ds.cur;
+    if (!ds.raw[tw] && c.noalloc)
+        return fail(c, TC_ERR_STATE,
+                    "the second buffer of %s does not exist yet and a call that allocates nothing cannot create "
+                    "it; flush this chain once with tc_flush first", ds.name.c_str());
+    if (!ds.raw[tw]) {
+        ds.raw[tw] = dev_alloc(c, (size_t)(ds.bytes + ds.stagger));
+        if (!ds.raw[tw]) return fail(c, TC_ERR_NOMEM, "cannot allocate the second buffer of %s", ds.name.c_str());
+        ds.buf[tw] = (char *)ds.raw[tw] + ds.stagger;
+        ds.twin_synced = false;
+    }
+    bool inside = true;
+    if (ds.ever_written)
+        for (int d = 0; d < 3; ++d) inside = inside && ds.wlo[d] >= lo[d] && ds.whi[d] <= hi[d];
+    if (!ds.twin_synced || !inside) {
+        if (hipMemcpyAsync(ds.buf[tw], ds.buf[ds.cur], (size_t)ds.bytes, hipMemcpyDeviceToDevice, c.stream) !=
+            hipSuccess)
+            return fail(c, TC_ERR_DEVICE, "hipMemcpyAsync (second buffer) failed");
+        ds.twin_synced = true;
+    }
+    *origin = ds.origin(tw);
+    return TC_OK;
+}
+
+tc_status euler_stage_run(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &G) {
+    const EulerStage &E = *G.estage;
+    EulerStageArgs a;
+    std::memset(&a, 0, sizeof a);
+    auto put = [&](int k, int d) {
+        const Dataset &ds = c.dats[d];
+        a.ptr[k] = ds.origin(ds.cur);
+        a.sy[k] = ds.sy();
+        a.sz[k] = ds.sz();
+    };
+    for (int k = 0; k < 5; ++k) {
+        put(kQ + k, E.q[k]);
+        put(kQ0 + k, E.q0[k]);
+    }
+    for (int d = 0; d < 3; ++d) put(kU + d, E.u[d]);
+    put(kP, E.p);
+    for (int k = 0; k < 5; ++k) {
+        Dataset &dq = c.dats[E.q[k]];
+        const tc_status st = second_buffer(c, dq, E.lo, E.hi, &a.out[k]);
+        if (st != TC_OK) return st;
+        a.osy[k] = dq.sy();
+        a.osz[k] = dq.sz();
+        if (E.r_live[k]) {
+            const Dataset &dr = c.dats[E.r[k]];
+            a.rout[k] = dr.origin(dr.cur);
+            a.rsy[k] = dr.sy();
+            a.rsz[k] = dr.sz();
+        }
+    }
+    const LoopRec &rhs = chain[G.g0], &rk = chain[G.g0 + 5];
+    a.s = rhs.params[1];
+    a.a = rk.params[0];
+    a.b = rk.params[1];
+    a.dt = rk.params[2];
+    for (int d = 0; d < 3; ++d) {
+        a.lo[d] = E.lo[d];
+        a.hi[d] = E.hi[d];
+    }
+    const hipError_t e = launch_euler_stage3(a, c.dats[E.q[0]].dtype, c.stream);
+    if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "Runge-Kutta stage launch failed: %s", hipGetErrorString(e));
+    for (int k = 0; k < 5; ++k) c.dats[E.q[k]].cur ^= 1;
+    return TC_OK;
+}
+
 tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
     if (G.staged) return staged_run(c, chain, *G.staged);
+    if (G.estage) return euler_stage_run(c, chain, G);
     if (G.baked) {
         // kernels with the weights compiled in serve only the weights they
         // were generated for; on a change the group falls back for good to
@@ -1103,6 +1282,16 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
 
 tc_status fused_check_noalloc(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &G) {
     if (G.staged) return staged_check_noalloc(c, *G.staged);
+    if (G.estage) {
+        for (int k = 0; k < 5; ++k) {
+            const Dataset &ds = c.dats[G.estage->q[k]];
+            if (!ds.raw[0] || !ds.raw[1])
+                return fail(c, TC_ERR_STATE,
+                            "the second buffer of %s does not exist yet and a call that allocates nothing cannot "
+                            "create it; flush this chain once with tc_flush first", ds.name.c_str());
+        }
+        return TC_OK;
+    }
     if (G.baked) {
         size_t k = 0;
         for (int l = G.g0; l < G.g1; ++l)

@@ -119,7 +119,21 @@ struct FusedGroup {
     // set for a staged group (any ops, dimensions and ranges; staged.hpp):
     // the loops run as staged tiles instead of generated register windows
     std::shared_ptr<StagedGroup> staged;
+    // set for a 3D Runge-Kutta stage (EULER_RHS for the five components,
+    // then RK_STAGE for the five): one z-marching kernel (euler.hip)
+    std::shared_ptr<struct EulerStage> estage;
 };
+
+struct EulerStage {
+    int q[5], q0[5], r[5], u[3], p;  // datasets
+    bool r_live[5];                  // R_c read by a later loop before it is overwritten
+    int lo[3], hi[3];
+};
+
+// Loops [i, i + 10) as a 3D Runge-Kutta stage (the five right-hand sides,
+// then the five updates over one range, sharing Q, the velocities and the
+// pressure): fills E and returns true, else false.
+bool euler_stage_match(const Ctx &c, const std::vector<LoopRec> &chain, int i, EulerStage &E);
 
 // Split a chain into fusion groups (loops outside any group run one kernel
 // each) and generate their kernels; returns the groups in chain order.

@@ -29,6 +29,25 @@ hipError_t launch_wsum(const LoopDesc &d, const Box &b, int dtype, int march_mas
 // 3D EULER_RHS marching up z (same arithmetic as the per-point kernel)
 hipError_t launch_euler_rhs3(const LoopDesc &d, const Box &b, int dtype, hipStream_t s);
 
+// One 3D Runge-Kutta stage after the primitives: EULER_RHS for the five
+// components and RK_STAGE for the five components, fused (euler.hip).
+// Arrays (logical origins and strides): kQ + c the stage's Q_c (read at
+// +-2 along every axis), kQ0 + c the step's Q0_c, kU + d the velocities, kP
+// the pressure; out[c] receives the new Q_c, rout[c] (may be NULL) R_c.
+enum { kQ = 0, kQ0 = 5, kU = 10, kP = 13, kEulerArrays = 14 };
+struct EulerStageArgs {
+    const void *ptr[kEulerArrays];
+    int64_t sy[kEulerArrays], sz[kEulerArrays];
+    void *out[5];
+    int64_t osy[5], osz[5];
+    void *rout[5];
+    int64_t rsy[5], rsz[5];
+    double s, a, b, dt;
+    int lo[3], hi[3];
+    int nbx, nby, nb, tz;  // set by the launcher
+};
+hipError_t launch_euler_stage3(const EulerStageArgs &a, int dtype, hipStream_t s);
+
 // Combine `count` (hi, lo) partials into out[0..1] with one workgroup.
 hipError_t launch_finalize(const double *part, int64_t count, int op, double *out, hipStream_t s);
 

@@ -1,5 +1,7 @@
 """GPU parity of the compressible-Euler RK3 chain (EULER_PRIM, EULER_RHS,
-RK_STAGE loops through the chain API, untiled and skewed-tiled) with the
+RK_STAGE loops through the chain API, untiled, skewed-tiled and fused: in 3D
+each stage's five right-hand sides and five updates run as one z-marching
+kernel) with the
 oracle's step: small grids element by element (1e-12 relative; the same fma
 sequences make it bit-exact in practice) and the 256^3 Taylor-Green workload
 on two z-slabs against the window oracle, with the energy sum checked against
@@ -56,13 +58,15 @@ def test_rk3_step_small(tc, ndim, n):
     ref = EulerOracle(q, n, h)
     ref.step(1e-3)
     outs = {}
-    for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0)), (tc.TC_TILING_SKEWED, (0, 0, 5) if ndim == 3 else (0, 7, 0))]:
+    for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0)), (tc.TC_TILING_SKEWED, (0, 0, 5) if ndim == 3 else (0, 7, 0)),
+                       (tc.TC_TILING_FUSED, (0, 0, 0))]:
         say(f"euler ndim={ndim} n={n} mode={mode}")
         with tc.Context() as c:
             c.tc_set_tiling(mode, tile)
             r = EulerRunner(c, q, n, h)
             esum = r.step(1e-3)
             got = [c.tc_dat_read(d) for d in r.Q + r.R + r.vel + [r.p]]
+            groups = c.tc_get_stats()["last_groups"]
         want = ref.q + ref.r + ref.vel + [ref.p]
         hh = 2
         for g, w in zip(got, want):
@@ -71,8 +75,12 @@ def test_rk3_step_small(tc, ndim, n):
         e = ref.interior(ref.q[ndim + 1])
         assert abs(esum - math.fsum(e.ravel().tolist())) <= 1e-15 * float(np.abs(e).sum())
         outs[mode] = got
-    for a, b in zip(outs[0], outs[1]):
-        assert np.array_equal(a, b)
+        if mode == tc.TC_TILING_FUSED and ndim == 3:
+            # the three stages ran as fused Runge-Kutta stage kernels
+            assert groups == 3
+    for m in (1, 2):
+        for a, b in zip(outs[0], outs[m]):
+            assert np.array_equal(a, b)
 
 
 def test_rhs_march_kernel_equals_per_point_kernel(tc, monkeypatch):
@@ -104,7 +112,8 @@ def test_rk3_taylor_green_256_sampled(tc):
     slabs = [(0, 3), (126, 130), (253, 256)]
     refs = [euler_window(q, n, h, a, b, 1e-3) for a, b in slabs]
     res = {}
-    for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0)), (tc.TC_TILING_SKEWED, (0, 0, 0))]:
+    for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0)), (tc.TC_TILING_SKEWED, (0, 0, 0)),
+                       (tc.TC_TILING_FUSED, (0, 0, 0))]:
         say(f"taylor-green 256^3 mode={mode}")
         with tc.Context() as c:
             c.tc_set_tiling(mode, tile)
@@ -124,6 +133,30 @@ def test_rk3_taylor_green_256_sampled(tc):
         say(f"  energy sum {esum!r} exact {exact!r}")
         assert abs(esum - exact) <= 1e-15 * float(np.abs(e).sum())
         res[mode] = (esum, [a[::5, ::3, ::7].copy() for a in qs])
-    assert res[0][0] == res[1][0]
-    for a, b in zip(res[0][1], res[1][1]):
+    for m in (1, 2):
+        assert res[0][0] == res[m][0]
+        for a, b in zip(res[0][1], res[m][1]):
+            assert np.array_equal(a, b)
+
+
+def test_rk3_two_steps_fused(tc):
+    """Two steps in one chain (the first step's last-stage R is overwritten
+    by the second step before any read, so the fused stage skips writing it):
+    the fused mode gives the untiled bits for Q, R and the primitives."""
+    from paper_1704_00693_amd.apps import EulerRunner
+    n = 37
+    h = 2 * math.pi / n
+    q = taylor_green(n)
+    outs = []
+    for mode in (tc.TC_TILING_NONE, tc.TC_TILING_FUSED):
+        say(f"euler two steps n={n} mode={mode}")
+        with tc.Context() as c:
+            c.tc_set_tiling(mode, (0, 0, 0))
+            r = EulerRunner(c, q, n, h)
+            r.record_step(1e-3)
+            r.step(1e-3)
+            if mode == tc.TC_TILING_FUSED:
+                assert c.tc_get_stats()["last_groups"] >= 6
+            outs.append([c.tc_dat_read(d) for d in r.Q + r.R + r.vel + [r.p]])
+    for a, b in zip(*outs):
         assert np.array_equal(a, b)
