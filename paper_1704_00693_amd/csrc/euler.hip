@@ -210,7 +210,23 @@ constexpr int kStageOut = 60;
 constexpr int kStageRows = 4;
 constexpr int kStageTz = 32;
 
+// Primitive variables of one point, as TC_OP_EULER_PRIM computes them.
 template <typename T>
+__device__ __forceinline__ void prims3(const T q[5], T gm1, T &u, T &v, T &w, T &p) {
+    const T ri = (T)1 / q[0];
+    const T u0 = q[1] * ri, u1 = q[2] * ri, u2 = q[3] * ri;
+    T ke = q[3] * u2;
+    ke = fma_t<T>(q[2], u1, ke);
+    ke = fma_t<T>(q[1], u0, ke);
+    u = u0;
+    v = u1;
+    w = u2;
+    p = gm1 * fma_t<T>((T)-0.5, ke, q[4]);
+}
+
+// PRIM: the stage's primitive variables are computed here from Q (its
+// primitive-variable loop is fused in) instead of being loaded.
+template <typename T, bool PRIM>
 __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageArgs a) {
     __shared__ T fy_lds[2][kStageRows + 4][5][64];
     const int lin = xcd_block(blockIdx.x, a.nb);
@@ -236,19 +252,30 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
         hq[c] = at(kQ + c, yh);
         q0[c] = at(kQ0 + c, yr);
     }
-    const T *u = at(kU, yr), *v = at(kU + 1, yr), *w = at(kU + 2, yr), *p = at(kP, yr);
-    const T *hv = at(kU + 1, yh), *hp = at(kP, yh);
+    const T *u = PRIM ? nullptr : at(kU, yr), *v = PRIM ? nullptr : at(kU + 1, yr);
+    const T *w = PRIM ? nullptr : at(kU + 2, yr), *p = PRIM ? nullptr : at(kP, yr);
+    const T *hv = PRIM ? nullptr : at(kU + 1, yh), *hp = PRIM ? nullptr : at(kP, yh);
     auto ld = [&](const T *base, int k, int z) { return base[(int64_t)z * a.sz[k]]; };
-    const T s = (T)a.s, ra = (T)a.a, rb = (T)a.b, dt = (T)a.dt;
+    const T s = (T)a.s, ra = (T)a.a, rb = (T)a.b, dt = (T)a.dt, gm1 = (T)a.gm1;
 
     // z fluxes of planes z0-2 .. z0+1
     T fz[5][5];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int pl = z0 - 2 + k;
-        const T wk = ld(w, kU + 2, pl), pk = ld(p, kP, pl);
+        T qk[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) fz[c][k] = flux_c<T, 2>(c, ld(q[c], kQ + c, pl), wk, pk);
+        for (int c = 0; c < 5; ++c) qk[c] = ld(q[c], kQ + c, pl);
+        T wk, pk;
+        if constexpr (PRIM) {
+            T uk, vk;
+            prims3<T>(qk, gm1, uk, vk, wk, pk);
+        } else {
+            wk = ld(w, kU + 2, pl);
+            pk = ld(p, kP, pl);
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) fz[c][k] = flux_c<T, 2>(c, qk[c], wk, pk);
     }
     // own row at planes z (current) and z+1: Q, u, v, p; the leading plane
     // z+2: Q, u, v, w, p; the outside row at plane z: Q, v, p; Q0 at plane z
@@ -261,10 +288,19 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
         oq[c] = ld(hq[c], kQ + c, z0);
         cq0[c] = ld(q0[c], kQ0 + c, z0);
     }
-    T cu = ld(u, kU, z0), cv = ld(v, kU + 1, z0), cp = ld(p, kP, z0);
-    T nu = ld(u, kU, z0 + 1), nv = ld(v, kU + 1, z0 + 1), np_ = ld(p, kP, z0 + 1);
-    T lu = ld(u, kU, z0 + 2), lv = ld(v, kU + 1, z0 + 2), lw = ld(w, kU + 2, z0 + 2), lp = ld(p, kP, z0 + 2);
-    T ov = ld(hv, kU + 1, z0), op = ld(hp, kP, z0);
+    T cu, cv, cp, nu, nv, np_, lu, lv, lw, lp, ov, op;
+    if constexpr (PRIM) {
+        T t0, t1;
+        prims3<T>(cq, gm1, cu, cv, t0, cp);
+        prims3<T>(nq, gm1, nu, nv, t1, np_);
+        prims3<T>(lq, gm1, lu, lv, lw, lp);
+        prims3<T>(oq, gm1, t0, ov, t1, op);
+    } else {
+        cu = ld(u, kU, z0), cv = ld(v, kU + 1, z0), cp = ld(p, kP, z0);
+        nu = ld(u, kU, z0 + 1), nv = ld(v, kU + 1, z0 + 1), np_ = ld(p, kP, z0 + 1);
+        lu = ld(u, kU, z0 + 2), lv = ld(v, kU + 1, z0 + 2), lw = ld(w, kU + 2, z0 + 2), lp = ld(p, kP, z0 + 2);
+        ov = ld(hv, kU + 1, z0), op = ld(hp, kP, z0);
+    }
 
     T *qn[5], *rr[5];
     for (int c = 0; c < 5; ++c) {
@@ -304,12 +340,18 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
                 ioq[c] = ld(hq[c], kQ + c, z + 1);
                 iq0[c] = ld(q0[c], kQ0 + c, z + 1);
             }
-            iu = ld(u, kU, z + 3);
-            iv = ld(v, kU + 1, z + 3);
-            iw = ld(w, kU + 2, z + 3);
-            ip = ld(p, kP, z + 3);
-            iov = ld(hv, kU + 1, z + 1);
-            iop = ld(hp, kP, z + 1);
+            if constexpr (PRIM) {
+                T t0, t1;
+                prims3<T>(iq, gm1, iu, iv, iw, ip);
+                prims3<T>(ioq, gm1, t0, iov, t1, iop);
+            } else {
+                iu = ld(u, kU, z + 3);
+                iv = ld(v, kU + 1, z + 3);
+                iw = ld(w, kU + 2, z + 3);
+                ip = ld(p, kP, z + 3);
+                iov = ld(hv, kU + 1, z + 1);
+                iop = ld(hp, kP, z + 1);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -359,7 +401,10 @@ hipError_t go_stage3(const EulerStageArgs &in, hipStream_t s) {
     a.tz = kStageTz;
     a.nb = a.nbx * a.nby * nbz;
     if (a.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(euler_stage3_kernel<T>, dim3(a.nb), dim3(kStageThreads), 0, s, a);
+    if (a.prim)
+        hipLaunchKernelGGL((euler_stage3_kernel<T, true>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((euler_stage3_kernel<T, false>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -887,6 +887,26 @@ bool euler_stage_match(const Ctx &c, const std::vector<LoopRec> &chain, int i, E
     return true;
 }
 
+bool euler_stage_match_prim(const Ctx &c, const std::vector<LoopRec> &chain, int i, EulerStage &E) {
+    if (i + 11 > (int)chain.size()) return false;
+    const LoopRec &pr = chain[i];
+    if (pr.op != TC_OP_EULER_PRIM || pr.ndim != 3 || pr.args.size() != 9) return false;
+    if (!euler_stage_match(c, chain, i + 1, E)) return false;
+    for (int k = 0; k < 5; ++k)
+        if (pr.args[k].kind != TC_ARG_DAT || pr.args[k].handle != E.q[k]) return false;
+    for (int d = 0; d < 3; ++d)
+        if (pr.args[5 + d].handle != E.u[d]) return false;
+    if (pr.args[8].handle != E.p || c.dats[pr.args[0].handle].dtype != c.dats[E.q[0]].dtype) return false;
+    // the right-hand sides read the primitives up to 2 points beyond their range
+    for (int d = 0; d < 3; ++d)
+        if (pr.lo[d] > E.lo[d] - 2 || pr.hi[d] < E.hi[d] + 2) return false;
+    const int prims[4] = {E.u[0], E.u[1], E.u[2], E.p};
+    for (int v : prims)
+        if (live_after(chain, i + 11, v, pr.lo, pr.hi)) return false;
+    E.prim = true;
+    return true;
+}
+
 bool fused_op_supported(const LoopRec &lp) { return lp.op == TC_OP_WSUM && lp.ndim == 2; }
 
 std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3],
@@ -923,25 +943,29 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                 from[j] = j - 1;
                 piece[j] = nullptr;
             }
-            // a 3D Runge-Kutta stage ending here: one z-marching kernel
-            if (j >= 10) {
+            // a 3D Runge-Kutta stage ending here (with its primitive-variable
+            // loop when their values die in the chain): one z-marching kernel
+            for (int len : {11, 10}) {
+                if (j < len) continue;
                 EulerStage E;
-                if (euler_stage_match(c, chain, j - 10, E)) {
-                    const LoopRec &f = chain[j - 10];
-                    int nlive = 0;
-                    for (bool b : E.r_live) nlive += b;
-                    const double cost = (double)f.points() * c.dats[E.q[0]].esize() * (19 + nlive) / 4.5e12 + 5e-6;
-                    if (best[j - 10] + cost < best[j]) {
-                        auto G = std::make_shared<FusedGroup>();
-                        G->g0 = j - 10;
-                        G->g1 = j;
-                        G->cost = cost;
-                        G->estage = std::make_shared<EulerStage>(E);
-                        G->alg_bytes = f.points() * (int64_t)c.dats[E.q[0]].esize() * (19 + nlive);
-                        best[j] = best[j - 10] + cost;
-                        from[j] = j - 10;
-                        piece[j] = G;
-                    }
+                const bool ok = len == 11 ? euler_stage_match_prim(c, chain, j - 11, E)
+                                          : euler_stage_match(c, chain, j - 10, E);
+                if (!ok) continue;
+                const LoopRec &f = chain[j - 10];
+                int nlive = 0;
+                for (bool b : E.r_live) nlive += b;
+                const int arrays = (E.prim ? 15 : 19) + nlive;
+                const double cost = (double)f.points() * c.dats[E.q[0]].esize() * arrays / 4.5e12 + 5e-6;
+                if (best[j - len] + cost < best[j]) {
+                    auto G = std::make_shared<FusedGroup>();
+                    G->g0 = j - len;
+                    G->g1 = j;
+                    G->cost = cost;
+                    G->estage = std::make_shared<EulerStage>(E);
+                    G->alg_bytes = f.points() * (int64_t)c.dats[E.q[0]].esize() * arrays;
+                    best[j] = best[j - len] + cost;
+                    from[j] = j - len;
+                    piece[j] = G;
                 }
             }
             // register-window groups: runs of 2D weighted sums; staged groups:
@@ -1176,7 +1200,10 @@ tc_status euler_stage_run(Ctx &c, const std::vector<LoopRec> &chain, const Fused
             a.rsz[k] = dr.sz();
         }
     }
-    const LoopRec &rhs = chain[G.g0], &rk = chain[G.g0 + 5];
+    const int off = E.prim ? 1 : 0;
+    const LoopRec &rhs = chain[G.g0 + off], &rk = chain[G.g0 + off + 5];
+    a.prim = E.prim ? 1 : 0;
+    a.gm1 = E.prim ? chain[G.g0].params[0] : 0.0;
     a.s = rhs.params[1];
     a.a = rk.params[0];
     a.b = rk.params[1];

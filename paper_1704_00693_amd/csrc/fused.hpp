@@ -127,6 +127,7 @@ struct FusedGroup {
 struct EulerStage {
     int q[5], q0[5], r[5], u[3], p;  // datasets
     bool r_live[5];                  // R_c read by a later loop before it is overwritten
+    bool prim = false;               // the stage's EULER_PRIM loop is the group's first loop
     int lo[3], hi[3];
 };
 
@@ -134,6 +135,10 @@ struct EulerStage {
 // then the five updates over one range, sharing Q, the velocities and the
 // pressure): fills E and returns true, else false.
 bool euler_stage_match(const Ctx &c, const std::vector<LoopRec> &chain, int i, EulerStage &E);
+// Loops [i, i + 11): the stage's EULER_PRIM loop (over a range that covers
+// the right-hand sides' reads) and the stage, with every primitive variable
+// overwritten by a later loop before any read (so none reaches memory).
+bool euler_stage_match_prim(const Ctx &c, const std::vector<LoopRec> &chain, int i, EulerStage &E);
 
 // Split a chain into fusion groups (loops outside any group run one kernel
 // each) and generate their kernels; returns the groups in chain order.

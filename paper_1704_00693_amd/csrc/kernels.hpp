@@ -29,8 +29,9 @@ hipError_t launch_wsum(const LoopDesc &d, const Box &b, int dtype, int march_mas
 // 3D EULER_RHS marching up z (same arithmetic as the per-point kernel)
 hipError_t launch_euler_rhs3(const LoopDesc &d, const Box &b, int dtype, hipStream_t s);
 
-// One 3D Runge-Kutta stage after the primitives: EULER_RHS for the five
-// components and RK_STAGE for the five components, fused (euler.hip).
+// One 3D Runge-Kutta stage: EULER_RHS for the five components and RK_STAGE
+// for the five components, fused (euler.hip), optionally with the stage's
+// EULER_PRIM loop before them (its results then never reach memory).
 // Arrays (logical origins and strides): kQ + c the stage's Q_c (read at
 // +-2 along every axis), kQ0 + c the step's Q0_c, kU + d the velocities, kP
 // the pressure; out[c] receives the new Q_c, rout[c] (may be NULL) R_c.
@@ -43,6 +44,8 @@ struct EulerStageArgs {
     void *rout[5];
     int64_t rsy[5], rsz[5];
     double s, a, b, dt;
+    double gm1;            // prim: gamma - 1
+    int prim;              // 1: the primitives are computed from Q (their loop is fused in)
     int lo[3], hi[3];
     int nbx, nby, nb, tz;  // set by the launcher
 };
