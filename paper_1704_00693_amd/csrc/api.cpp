@@ -851,7 +851,7 @@ static tc_status impl_tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (const char *e = getenv("TC_JIT_CSE")) c.jit_cse_steps = atoi(e) != 0;
     if (const char *e = getenv("TC_JIT_FENCE")) c.jit_sched_fence = atoi(e) != 0;
     if (const char *e = getenv("TC_JIT_ALIGN")) c.jit_align_store = atoi(e) != 0;
-    if (const char *e = getenv("TC_STAGED")) c.staged_enabled = atoi(e) != 0;
+    if (const char *e = getenv("TC_STAGED")) c.staged_mode = std::min(2, std::max(0, atoi(e)));
     if (const char *e = getenv("TC_STAGED_TILE")) {
         int v[3] = {0, 0, 0};
         if (std::sscanf(e, "%d,%d,%d", &v[0], &v[1], &v[2]) >= 1)

@@ -395,11 +395,20 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
     return true;
 }
 
+// Modelled time of one loop run on its own: its bytes at the HBM rate, or
+// at the Infinity Cache's when its datasets together fit well inside the
+// 256 MB cache (consecutive loops then mostly hit it), and at least a
+// launch.  Measured per-loop PPCG kernels: 3-4 us at 256^2 and 700^2, a
+// matrix-vector step over 2000^2 (224 MB moved, 160 MB of datasets) 32 us.
 double single_loop_cost(const Ctx &c, const LoopRec &lp) {
-    double b = 0.0;
+    double b = 0.0, footprint = 0.0;
     for (const auto &a : lp.args)
-        if (a.kind == TC_ARG_DAT) b += (a.access == TC_RW || a.access == TC_INC ? 2.0 : 1.0) * c.dats[a.handle].esize();
-    return (double)lp.points() * b / 4.2e12 + 3e-6;
+        if (a.kind == TC_ARG_DAT) {
+            b += (a.access == TC_RW || a.access == TC_INC ? 2.0 : 1.0) * c.dats[a.handle].esize();
+            footprint += (double)c.dats[a.handle].bytes;
+        }
+    const double bw = footprint < 192e6 ? 7.0e12 : 4.2e12;
+    return std::max(3e-6, (double)lp.points() * b / bw) + 1e-6;
 }
 
 // ---------------------------------------------------------------------------
@@ -970,7 +979,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
             }
             // register-window groups: runs of 2D weighted sums; staged groups:
             // runs that register windows cannot take (any op, dimension, range)
-            bool reg_ok = true, stg_ok = c.staged_enabled, all_wsum = true;
+            bool reg_ok = true, stg_ok = c.staged_mode != 0, all_wsum = true;
             for (int i = j - 1; i >= 0; --i) {
                 if (!fused_op_supported(chain[i])) {
                     reg_ok = false;
@@ -992,7 +1001,9 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                         auto S = std::make_shared<StagedGroup>();
                         if (!staged_analyse(c, chain, i, j, c.staged_tile, false, *S)) {
                             stg_ok = false;  // prepending loops only adds datasets, parameters and LDS
-                        } else if (best[i] + S->cost < best[j]) {
+                        } else if (c.staged_mode == 2 ? S->cost * 1e-6 < best[j] - best[i]
+                                                      : best[i] + S->cost < best[j]) {
+                            if (c.staged_mode == 2) S->cost *= 1e-6;
                             auto G = std::make_shared<FusedGroup>();
                             G->g0 = i;
                             G->g1 = j;

@@ -22,6 +22,17 @@ __device__ __forceinline__ T *P(const LoopDesc &d, int a) {
     return (T *)d.arg[a].ptr;
 }
 
+// A descriptor whose dataset pointers all address workgroup-local memory
+// (LDS): the same layout, but P<T>() returns LDS-qualified pointers, so the
+// functors' accesses compile to LDS instructions instead of generic ones.
+struct LdsDesc : LoopDesc {};
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T *;
+template <typename T>
+__device__ __forceinline__ lds_ptr<T> P(const LdsDesc &d, int a) {
+    return (lds_ptr<T>)(T *)d.arg[a].ptr;
+}
+
 __device__ __forceinline__ int64_t IX(const LoopDesc &d, int a, int x, int y, int z) {
     return (int64_t)x + (int64_t)y * d.arg[a].sy + (int64_t)z * d.arg[a].sz;
 }
@@ -38,8 +49,8 @@ __device__ __forceinline__ float fmaT<float>(float a, float b, float c) {
 // Weighted sum: acc = fma(w, in[x+q], acc) over inputs and stencil points in
 // order.  Common stencil sizes are unrolled so the loads issue together; the
 // fma chain keeps its order.
-template <typename T, int NP>
-__device__ __forceinline__ T wsum_input(const LoopDesc &d, const T *p, int q0, T acc) {
+template <typename T, int NP, class Desc, class Ptr>
+__device__ __forceinline__ T wsum_input(const Desc &d, Ptr p, int q0, T acc) {
     T v[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) v[k] = p[d.off[q0 + k]];
@@ -50,10 +61,11 @@ __device__ __forceinline__ T wsum_input(const LoopDesc &d, const T *p, int q0, T
 
 template <typename T>
 struct OpWsum {
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         T acc = (T)0;
         for (int a = 1; a < d.nargs; ++a) {
-            const T *p = P<T>(d, a) + IX(d, a, x, y, z);
+            const auto p = P<T>(d, a) + IX(d, a, x, y, z);
             const int q0 = d.pt0[a];
             switch (d.npts[a]) {
             case 5: acc = wsum_input<T, 5>(d, p, q0, acc); break;
@@ -71,15 +83,17 @@ struct OpWsum {
 // COPY with possible conversion: arg0 type TO, arg1 type FROM
 template <typename TO, typename FROM>
 struct OpCopy {
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         P<TO>(d, 0)[IX(d, 0, x, y, z)] = (TO)P<FROM>(d, 1)[IX(d, 1, x, y, z)];
     }
 };
 
 template <typename T>
 struct OpAxpby {
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
-        T *yp = P<T>(d, 0) + IX(d, 0, x, y, z);
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
+        auto yp = P<T>(d, 0) + IX(d, 0, x, y, z);
         T xv = P<T>(d, 1)[IX(d, 1, x, y, z)];
         *yp = fmaT<T>((T)d.prm[0], xv, (T)d.prm[1] * *yp);
     }
@@ -87,7 +101,8 @@ struct OpAxpby {
 
 template <typename T>
 struct OpDot {
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *r) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *r) {
         double a = (double)P<T>(d, 0)[IX(d, 0, x, y, z)];
         double b = (double)P<T>(d, 1)[IX(d, 1, x, y, z)];
         dd_add_prod(r[0], a, b);
@@ -96,31 +111,34 @@ struct OpDot {
 
 template <typename T>
 struct OpSum {
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *r) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *r) {
         dd_add(r[0], (double)P<T>(d, 0)[IX(d, 0, x, y, z)]);
     }
 };
 
 template <typename T>
 struct OpHaloReflect {
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         const int axis = (int)d.prm[0], side = (int)d.prm[1], n = (int)d.prm[2];
         int c[3] = {x, y, z};
         int s[3] = {x, y, z};
         s[axis] = side == 0 ? -1 - c[axis] : 2 * n - 1 - c[axis];
-        T *v = P<T>(d, 0);
+        auto v = P<T>(d, 0);
         v[IX(d, 0, x, y, z)] = v[IX(d, 0, s[0], s[1], s[2])];
     }
 };
 
 // ---- heat conduction ------------------------------------------------------
 // K arguments are the first ndim dataset arguments.
-template <typename T>
-__device__ __forceinline__ T tea_apply(const LoopDesc &d, int vi, int x, int y, int z) {
-    const T *kx = P<T>(d, 0), *ky = P<T>(d, 1);
+template <typename T, class Desc>
+__device__ __forceinline__ T tea_apply(const Desc &d, int vi, int x, int y, int z) {
+    const auto kx = P<T>(d, 0);
+        const auto ky = P<T>(d, 1);
     const T ke = kx[IX(d, 0, x + 1, y, z)], kw = kx[IX(d, 0, x, y, z)];
     const T kn = ky[IX(d, 1, x, y + 1, z)], ks = ky[IX(d, 1, x, y, z)];
-    const T *v = P<T>(d, vi);
+    const auto v = P<T>(d, vi);
     const int64_t c = IX(d, vi, x, y, z);
     const int64_t sy = d.arg[vi].sy;
     T diag = (T)1 + ke;
@@ -130,7 +148,7 @@ __device__ __forceinline__ T tea_apply(const LoopDesc &d, int vi, int x, int y, 
     T kt = 0, kb = 0;
     const bool three = d.ndim == 3;
     if (three) {
-        const T *kz = P<T>(d, 2);
+        const auto kz = P<T>(d, 2);
         kt = kz[IX(d, 2, x, y, z + 1)];
         kb = kz[IX(d, 2, x, y, z)];
         diag = diag + kt;
@@ -151,7 +169,8 @@ __device__ __forceinline__ T tea_apply(const LoopDesc &d, int vi, int x, int y, 
 
 template <typename T>
 struct OpTeaInit {  // rho, e, u0, u
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         T t = P<T>(d, 1)[IX(d, 1, x, y, z)] * P<T>(d, 0)[IX(d, 0, x, y, z)];
         P<T>(d, 2)[IX(d, 2, x, y, z)] = t;
         P<T>(d, 3)[IX(d, 3, x, y, z)] = t;
@@ -160,8 +179,9 @@ struct OpTeaInit {  // rho, e, u0, u
 
 template <typename T>
 struct OpTeaK {  // rho, Kx, Ky[, Kz]; prm r
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
-        const T *rho = P<T>(d, 0);
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
+        const auto rho = P<T>(d, 0);
         const int64_t c = IX(d, 0, x, y, z);
         const T rc = rho[c];
         const T two_r = (T)2 * (T)d.prm[0];
@@ -173,7 +193,8 @@ struct OpTeaK {  // rho, Kx, Ky[, Kz]; prm r
 
 template <typename T>
 struct OpTeaResid {  // K.., x, b, r
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         const int nd = d.ndim;
         T av = tea_apply<T>(d, nd, x, y, z);
         P<T>(d, nd + 2)[IX(d, nd + 2, x, y, z)] = P<T>(d, nd + 1)[IX(d, nd + 1, x, y, z)] - av;
@@ -182,7 +203,8 @@ struct OpTeaResid {  // K.., x, b, r
 
 template <typename T>
 struct OpTeaMatvecDot {  // K.., p, w, red
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *r) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *r) {
         const int nd = d.ndim;
         T av = tea_apply<T>(d, nd, x, y, z);
         P<T>(d, nd + 1)[IX(d, nd + 1, x, y, z)] = av;
@@ -192,20 +214,22 @@ struct OpTeaMatvecDot {  // K.., p, w, red
 
 template <typename T>
 struct OpTeaP1 {  // K.., sd, rt, z
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         const int nd = d.ndim;
         T av = tea_apply<T>(d, nd, x, y, z);
-        T *rt = P<T>(d, nd + 1) + IX(d, nd + 1, x, y, z);
+        auto rt = P<T>(d, nd + 1) + IX(d, nd + 1, x, y, z);
         *rt = *rt - av;
-        T *zz = P<T>(d, nd + 2) + IX(d, nd + 2, x, y, z);
+        auto zz = P<T>(d, nd + 2) + IX(d, nd + 2, x, y, z);
         *zz = *zz + P<T>(d, nd)[IX(d, nd, x, y, z)];
     }
 };
 
 template <typename T>
 struct OpTeaP2 {  // sd, rt; alpha, beta
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
-        T *sd = P<T>(d, 0) + IX(d, 0, x, y, z);
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
+        auto sd = P<T>(d, 0) + IX(d, 0, x, y, z);
         T rt = P<T>(d, 1)[IX(d, 1, x, y, z)];
         *sd = fmaT<T>((T)d.prm[0], *sd, (T)d.prm[1] * rt);
     }
@@ -213,7 +237,8 @@ struct OpTeaP2 {  // sd, rt; alpha, beta
 
 template <typename T>
 struct OpTeaPreconInit {  // r, rt, sd, z; theta
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         T v = P<T>(d, 0)[IX(d, 0, x, y, z)];
         P<T>(d, 1)[IX(d, 1, x, y, z)] = v;
         P<T>(d, 2)[IX(d, 2, x, y, z)] = v / (T)d.prm[0];
@@ -223,10 +248,11 @@ struct OpTeaPreconInit {  // r, rt, sd, z; theta
 
 template <typename T>
 struct OpTeaCgUpdate {  // x, r, p, w; alpha
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         const T al = (T)d.prm[0];
-        T *xp = P<T>(d, 0) + IX(d, 0, x, y, z);
-        T *rp = P<T>(d, 1) + IX(d, 1, x, y, z);
+        auto xp = P<T>(d, 0) + IX(d, 0, x, y, z);
+        auto rp = P<T>(d, 1) + IX(d, 1, x, y, z);
         *xp = fmaT<T>(al, P<T>(d, 2)[IX(d, 2, x, y, z)], *xp);
         *rp = fmaT<T>(-al, P<T>(d, 3)[IX(d, 3, x, y, z)], *rp);
     }
@@ -234,21 +260,24 @@ struct OpTeaCgUpdate {  // x, r, p, w; alpha
 
 template <typename T>
 struct OpTeaCgP {  // p, z; beta
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
-        T *pp = P<T>(d, 0) + IX(d, 0, x, y, z);
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
+        auto pp = P<T>(d, 0) + IX(d, 0, x, y, z);
         *pp = fmaT<T>((T)d.prm[0], *pp, P<T>(d, 1)[IX(d, 1, x, y, z)]);
     }
 };
 
 template <typename T>
 struct OpTeaGersh {  // K.., red(max)
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *r) {
-        const T *kx = P<T>(d, 0), *ky = P<T>(d, 1);
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *r) {
+        const auto kx = P<T>(d, 0);
+        const auto ky = P<T>(d, 1);
         T s = kx[IX(d, 0, x + 1, y, z)] + kx[IX(d, 0, x, y, z)];
         s = s + ky[IX(d, 1, x, y + 1, z)];
         s = s + ky[IX(d, 1, x, y, z)];
         if (d.ndim == 3) {
-            const T *kz = P<T>(d, 2);
+            const auto kz = P<T>(d, 2);
             s = s + kz[IX(d, 2, x, y, z + 1)];
             s = s + kz[IX(d, 2, x, y, z)];
         }
@@ -260,7 +289,8 @@ struct OpTeaGersh {  // K.., red(max)
 // ---- compressible Euler ----------------------------------------------------
 template <typename T>
 struct OpEulerPrim {  // Q_0..Q_{D+1}, u_1..u_D, p; gm1
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         const int D = d.ndim;
         const T ri = (T)1 / P<T>(d, 0)[IX(d, 0, x, y, z)];
         T u[3], m[3];
@@ -278,7 +308,8 @@ struct OpEulerPrim {  // Q_0..Q_{D+1}, u_1..u_D, p; gm1
 
 template <typename T>
 struct OpEulerRhs {  // R, Q_c, u_1..u_D, p; c, s
-    static __device__ __forceinline__ T flux(const LoopDesc &d, int c, int ax, int x, int y, int z) {
+    template <class Desc>
+    static __device__ __forceinline__ T flux(const Desc &d, int c, int ax, int x, int y, int z) {
         const int D = d.ndim;
         const T ud = P<T>(d, 2 + ax)[IX(d, 2 + ax, x, y, z)];
         T f = P<T>(d, 1)[IX(d, 1, x, y, z)] * ud;
@@ -286,7 +317,8 @@ struct OpEulerRhs {  // R, Q_c, u_1..u_D, p; c, s
         if (c == D + 1) f = fmaT<T>(P<T>(d, 2 + D)[IX(d, 2 + D, x, y, z)], ud, f);
         return f;
     }
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
         const int D = d.ndim;
         const int c = (int)d.prm[0];
         T acc = (T)0;
@@ -307,8 +339,9 @@ struct OpEulerRhs {  // R, Q_c, u_1..u_D, p; c, s
 
 template <typename T>
 struct OpRkStage {  // Q0, Q, R; a, b, dt
-    static __device__ __forceinline__ void run(const LoopDesc &d, int x, int y, int z, DD *) {
-        T *q = P<T>(d, 1) + IX(d, 1, x, y, z);
+    template <class Desc>
+    static __device__ __forceinline__ void run(const Desc &d, int x, int y, int z, DD *) {
+        auto q = P<T>(d, 1) + IX(d, 1, x, y, z);
         const T t = fmaT<T>((T)d.prm[2], P<T>(d, 2)[IX(d, 2, x, y, z)], *q);
         *q = fmaT<T>((T)d.prm[0], P<T>(d, 0)[IX(d, 0, x, y, z)], (T)d.prm[1] * t);
     }

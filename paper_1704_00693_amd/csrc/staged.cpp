@@ -293,7 +293,9 @@ bool layout(const Ctx &c, const Ana &A, StagedGroup &G, const std::vector<std::a
     const double wg_per_cu = std::max(1.0, std::min(4.0, std::floor(160.0 * 1024.0 / lds)));
     const double per_cu = std::max(1.0, (double)G.ntot / 256.0);
     const double overlap = std::min(per_cu, std::min(wg_per_cu, 2.0));
-    const double t_lat = per_cu * per_tile / ((1.0 + 0.5 * (overlap - 1.0)) * 2.4e9);
+    // calibration: measured staged launches took 2.4x (PPCG 256^2, 153 tiles)
+    // to 3.6x (PPCG 2000^2, 2016 tiles) the cycles modelled above
+    const double t_lat = 3.0 * per_cu * per_tile / ((1.0 + 0.5 * (overlap - 1.0)) * 2.4e9);
     const double t_bw = (double)G.ntot * (bytes_sum / (double)tiles.size()) / 4.0e12;
     G.cost = std::max(t_lat, t_bw) + 5e-6;
     return true;
@@ -461,6 +463,8 @@ bool staged_analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int
         S.prm_off = po;
         S.nprm = chain[l].op == TC_OP_WSUM ? d.pt0[d.nargs - 1] + d.npts[d.nargs - 1] : (int)chain[l].params.size();
         S.prm_skip = chain[l].op == TC_OP_WSUM ? d.npts[0] : 0;
+        S.all_lds = 1;
+        for (int a = 0; a < d.nargs; ++a) S.all_lds = S.all_lds && G.slots[S.slot[a]].staged;
         po += S.nprm;
         if (has_red(chain[l])) ++G.nred_loops;
     }

@@ -1,4 +1,4 @@
-// Staged tiles on gfx950: one workgroup (256 threads) per tile.  The datasets
+// Staged tiles on gfx950: one workgroup (1024 threads) per tile.  The datasets
 // the group writes are staged in LDS over the tile's boxes; the loops run in
 // order over their computed boxes with the per-loop kernels' functors,
 // re-pointed at the LDS copies (the descriptor itself is copied to LDS and
@@ -32,34 +32,85 @@ struct Pt {
     int x, y, z;
 };
 
-// i-th point of the box [lo, hi) with x fastest
-__device__ __forceinline__ Pt box_point(const int *lo, int wx, int wy, int i) {
-    Pt p;
-    const int q = i / wx;
-    p.x = lo[0] + (i - q * wx);
-    const int r = q / wy;
-    p.y = lo[1] + (q - r * wy);
-    p.z = lo[2] + r;
-    return p;
+// Workgroup-wide combine of one DD value per thread (kSThreads threads):
+// within each wavefront by butterfly shuffles, then the wavefronts' values
+// in wavefront order by thread 0.
+__device__ DD tile_reduce(int op, DD v) {
+    constexpr int kWaves = kSThreads / 64;
+    __shared__ double sh_hi[kWaves], sh_lo[kWaves];
+    for (int o = 32; o > 0; o >>= 1) {
+        DD w;
+        w.hi = __shfl_xor(v.hi, o);
+        w.lo = __shfl_xor(v.lo, o);
+        v = red_combine(op, v, w);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh_hi[wv] = v.hi;
+        sh_lo[wv] = v.lo;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DD a;
+        a.hi = sh_hi[0];
+        a.lo = sh_lo[0];
+        for (int i = 1; i < kWaves; ++i) {
+            DD b;
+            b.hi = sh_hi[i];
+            b.lo = sh_lo[i];
+            a = red_combine(op, a, b);
+        }
+        v = a;
+    }
+    __syncthreads();
+    return v;
 }
 
-template <class Op>
-__device__ void run_loop_box(const LoopDesc &d, const int *C, const int *O, int nred, double *partials0,
+// Quotient of 0 <= i < 2^24 by w > 0 through a float reciprocal (inv =
+// 1.0f / w): the product is off by at most one, and one correction step
+// makes it exact.
+__device__ __forceinline__ int quot(int i, int w, float inv) {
+    int q = (int)((float)i * inv);
+    const int r = i - q * w;
+    q += r < 0 ? -1 : (r >= w ? 1 : 0);
+    return q;
+}
+
+// The box [lo, lo + (wx, wy, *)) walked with x fastest.
+struct BoxWalk {
+    int lo0, lo1, lo2, wx, wy;
+    float ix, iy;
+    __device__ BoxWalk(const int *lo, int wx_, int wy_)
+        : lo0(lo[0]), lo1(lo[1]), lo2(lo[2]), wx(wx_), wy(wy_), ix(1.0f / (float)wx_), iy(1.0f / (float)wy_) {}
+    __device__ __forceinline__ Pt operator()(int i) const {
+        Pt p;
+        const int q = quot(i, wx, ix);
+        p.x = lo0 + (i - q * wx);
+        const int r = quot(q, wy, iy);
+        p.y = lo1 + (q - r * wy);
+        p.z = lo2 + r;
+        return p;
+    }
+};
+
+template <class Op, class D>
+__device__ void run_loop_box(const D &d, const int *C, const int *O, int nred, double *partials0,
                              double *partials1, int tile) {
     const int wx = C[3] - C[0], wy = C[4] - C[1], wz = C[5] - C[2];
     const int n = wx * wy * wz;
+    const BoxWalk box_point(C, wx, wy);
     DD red[2];
     red[0] = red_identity(d.red_op[0]);
     red[1] = red_identity(d.red_op[1]);
     if (nred == 0) {
         for (int i = threadIdx.x; i < n; i += kSThreads) {
-            const Pt p = box_point(C, wx, wy, i);
+            const Pt p = box_point(i);
             Op::run(d, p.x, p.y, p.z, red);
         }
         return;
     }
     for (int i = threadIdx.x; i < n; i += kSThreads) {
-        const Pt p = box_point(C, wx, wy, i);
+        const Pt p = box_point(i);
         const bool own = p.x >= O[0] && p.x < O[3] && p.y >= O[1] && p.y < O[4] && p.z >= O[2] && p.z < O[5];
         if (own) {
             Op::run(d, p.x, p.y, p.z, red);
@@ -72,7 +123,7 @@ __device__ void run_loop_box(const LoopDesc &d, const int *C, const int *O, int 
     }
     for (int j = 0; j < 2; ++j) {
         if (j >= nred) break;
-        const DD v = block_reduce(d.red_op[j], red[j]);
+        const DD v = tile_reduce(d.red_op[j], red[j]);
         double *part = j == 0 ? partials0 : partials1;
         if (threadIdx.x == 0) {
             part[2 * (int64_t)tile] = v.hi;
@@ -81,8 +132,8 @@ __device__ void run_loop_box(const LoopDesc &d, const int *C, const int *O, int 
     }
 }
 
-template <typename T>
-__device__ void dispatch(const LoopDesc &d, const int *C, const int *O, int tile) {
+template <typename T, class D>
+__device__ void dispatch(const D &d, const int *C, const int *O, int tile) {
     const int nred = d.nred;
     double *p0 = d.partials[0], *p1 = d.partials[1];
     switch (d.op) {
@@ -134,6 +185,7 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
         const int64_t gsy = a.gsy[s], gsz = a.gsz[s];
         T *box = lds + S.lds_off;
         const int n = wx * wy * wz;
+        const BoxWalk box_point(L, wx, wy);
         // kBatch loads in flight per lane before their stores
         for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * kSThreads) {
             T v[kBatch];
@@ -143,7 +195,7 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
                 const int i = i0 + k * kSThreads;
                 o[k] = -1;
                 if (i < n) {
-                    const Pt p = box_point(L, wx, wy, i);
+                    const Pt p = box_point(i);
                     o[k] = (p.x - q[0]) + (p.y - q[1]) * S.lsy + (p.z - q[2]) * S.lsz;
                     v[k] = src[(int64_t)p.x + (int64_t)p.y * gsy + (int64_t)p.z * gsz];
                 }
@@ -216,7 +268,10 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
             if (threadIdx.x < (unsigned)kWords) w0 = from[threadIdx.x];
             if (threadIdx.x + kSThreads < (unsigned)kWords) w1 = from[threadIdx.x + kSThreads];
         }
-        dispatch<T>(d, r + 6 + 9 * ns + 6 * l, O, tile);
+        if (a.sl[l].all_lds)  // every dataset in LDS: LDS-addressed loads and stores
+            dispatch<T>(static_cast<const LdsDesc &>(d), r + 6 + 9 * ns + 6 * l, O, tile);
+        else
+            dispatch<T>(d, r + 6 + 9 * ns + 6 * l, O, tile);
         __syncthreads();
         if (ln < a.nloops) {
             if (threadIdx.x < (unsigned)kWords) dw[threadIdx.x] = word(ln, threadIdx.x, w0);
@@ -242,6 +297,7 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
         const int64_t gsy = a.gsy[s], gsz = a.gsz[s];
         const T *box = lds + S.lds_off;
         const int n = wx * wy * wz;
+        const BoxWalk box_point(lo, wx, wy);
         for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * kSThreads) {
             T v[kBatch];
             int64_t o[kBatch];
@@ -250,7 +306,7 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
                 const int i = i0 + k * kSThreads;
                 o[k] = 0;
                 if (i < n) {  // logical offsets may be negative (halo points)
-                    const Pt p = box_point(lo, wx, wy, i);
+                    const Pt p = box_point(i);
                     o[k] = (int64_t)p.x + (int64_t)p.y * gsy + (int64_t)p.z * gsz;
                     v[k] = box[(p.x - q[0]) + (p.y - q[1]) * S.lsy + (p.z - q[2]) * S.lsz];
                 }

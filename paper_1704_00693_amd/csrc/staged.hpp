@@ -35,7 +35,8 @@ namespace tc {
 constexpr int kSMaxDat = 24;        // datasets one staged group names
 constexpr int kSMaxLoops = 128;     // loops of one staged group
 constexpr int kSMaxPrm = 256;       // scalar parameters of one group (kernel arguments)
-constexpr int kSThreads = 256;      // threads per tile workgroup
+constexpr int kSThreads = 1024;     // threads per tile workgroup (16 wavefronts: a tile's LDS
+                                    // allows few workgroups per CU, so each brings many waves)
 constexpr int64_t kSLdsBudget = 150 * 1024;  // bytes of LDS for the staged datasets and one descriptor
 
 // Per dataset slot of a group (device copy in the group's table).
@@ -55,7 +56,7 @@ struct SLoop {
     int prm_off, nprm;   // parameters in the kernel-argument array (LoopDesc prm layout)
     int prm_skip;        // leading entries of that layout the loop's parameters skip (a weighted
                          // sum's output stencil points)
-    int pad;
+    int all_lds;         // every dataset argument is staged: LDS-addressed accesses
     int64_t part[2];     // first partial of each reduction argument (one per tile follows)
 };
 

@@ -252,8 +252,10 @@ struct Ctx {
     bool jit_test_short_windows = false;  // TC_JIT_TEST_SHORT_WINDOWS=1: fault injection for error-path tests
     bool jit_bake = true;    // compile the weights into the kernels (TC_JIT_BAKE=0: read them from arguments)
     // staged groups (overlapped tiles in LDS for loops of any op and range):
-    // TC_STAGED=0 disables them, TC_STAGED_TILE=x,y,z fixes the owned box
-    bool staged_enabled = true;
+    // TC_STAGED=0 disables them, TC_STAGED=2 takes every one the analysis
+    // accepts whatever the cost model says, TC_STAGED_TILE=x,y,z fixes the
+    // owned box
+    int staged_mode = 1;
     int staged_tile[3] = {0, 0, 0};
     std::vector<void *> staged_allocs;  // device tables of staged groups (freed at finalize)
     double jit_compile_seconds = 0.0;
