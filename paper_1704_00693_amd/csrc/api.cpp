@@ -542,7 +542,7 @@ tc_status run_per_loop_graph(Ctx &c, const std::vector<LoopRec> &chain, CachedPl
         h = fnv(h, &it.t0, 3 * sizeof(int));
         items.push_back(it);
     }
-    h = fnv(h, &c.march_ty, sizeof(int));
+    h = fnv(h, &c.march, sizeof(MarchShape));
     if (P.gexec && P.ghash == h) {
         HIPCHK(c, hipGraphLaunch(P.gexec, c.stream));
         done = true;
@@ -558,7 +558,7 @@ tc_status run_per_loop_graph(Ctx &c, const std::vector<LoopRec> &chain, CachedPl
     }
     hipError_t err = hipSuccess;
     for (const auto &it : items) {
-        err = launch_loop(it.d, it.b, it.t0, it.t1, it.mm, c.march_ty, s);
+        err = launch_loop(it.d, it.b, it.t0, it.t1, it.mm, c.march, s);
         if (err != hipSuccess) break;
     }
     if (capture) {
@@ -612,7 +612,7 @@ tc_status run_launches(Ctx &c, const std::vector<LoopRec> &chain, CachedPlan &P)
             for (int j = 0; j < d.nred; ++j) d.partials[j] = c.partials + 2 * L.part_off[j];
             Box b = make_box(chain[L.loop].ndim, L.lo, L.hi);
             HIPCHK(c, launch_loop(d, b, dat_dtype(c, chain[L.loop], 0), dat_dtype(c, chain[L.loop], 1),
-                                  march[L.loop], c.march_ty, c.stream));
+                                  march[L.loop], c.march, c.stream));
             note_loop_writes(c, chain[L.loop]);
         } else {
             const FusedGroup &G = *P.groups[S.index];
@@ -837,7 +837,12 @@ static tc_status impl_tc_init(const tc_init_opts *opts, tc_ctx **out) {
         }
     }
     if (const char *e = getenv("TC_WSUM_MARCH")) c.march_enabled = atoi(e) != 0;
-    if (const char *e = getenv("TC_MARCH_TY")) c.march_ty = std::max(1, atoi(e));
+    if (const char *e = getenv("TC_MARCH_TY")) c.march.ty = std::max(1, atoi(e));
+    if (const char *e = getenv("TC_MARCH3_ROWS")) {
+        const int v = atoi(e);
+        if (v == 4 || v == 8) c.march.rows3 = v;
+    }
+    if (const char *e = getenv("TC_MARCH3_TZ")) c.march.tz3 = std::min(512, std::max(0, atoi(e) / 4 * 4));
     if (const char *e = getenv("TC_GRAPHS")) c.use_graphs = atoi(e) != 0;
     if (const char *e = getenv("TC_STAGGER")) c.stagger_unit = std::max(0ll, atoll(e)) / 256 * 256;
     if (const char *e = getenv("TC_JIT_UNROLL")) c.jit_unroll = std::min(16, std::max(1, atoi(e)));

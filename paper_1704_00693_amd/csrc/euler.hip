@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "lanes.hpp"
 
 namespace tc {
 
@@ -148,8 +149,8 @@ __global__ void __launch_bounds__(kRhsThreads) euler_rhs3_kernel(LoopDesc d, int
         }
         // x: fluxes of this lane's column, neighbours from adjacent lanes
         const T fx = flux<T, C, 0>(q0, u0, PX ? p0 : (T)0);
-        const T fxm1 = __shfl_up(fx, 1, 64), fxp1 = __shfl_down(fx, 1, 64);
-        const T fxm2 = __shfl_up(fx, 2, 64), fxp2 = __shfl_down(fx, 2, 64);
+        const T fxm1 = lane_prev(fx), fxp1 = lane_next(fx);
+        const T fxm2 = lane_prev(fxm1), fxp2 = lane_next(fxp1);
         const T gx = diff4<T>(fxm2, fxm1, fxp1, fxp2);
         const T gz = diff4<T>(fz[0], fz[1], fz[3], fz[4]);
         __syncthreads();
@@ -323,8 +324,8 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             const T fx = flux_c<T, 0>(c, cq[c], cu, cp);
-            const T fxm1 = __shfl_up(fx, 1, 64), fxp1 = __shfl_down(fx, 1, 64);
-            const T fxm2 = __shfl_up(fx, 2, 64), fxp2 = __shfl_down(fx, 2, 64);
+            const T fxm1 = lane_prev(fx), fxp1 = lane_next(fx);
+            const T fxm2 = lane_prev(fxm1), fxp2 = lane_next(fxp1);
             gx[c] = diff4<T>(fxm2, fxm1, fxp1, fxp2);
             gz[c] = diff4<T>(fz[c][0], fz[c][1], fz[c][3], fz[c][4]);
         }

@@ -289,6 +289,10 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
         V.post = post + 1;
         V.regs = regs;
     }
+    // The budget bounds the interior variant, which runs on almost every
+    // strip.  The edge variant holds extra windows for chain-start versions
+    // and may exceed it (it runs on the two edge strips of a row of tiles,
+    // where a spill costs little); group length is not cut for it.
     if (G.var[0].regs > sp.regs) return false;
     // datasets loaded / stored, in kernel argument order
     for (size_t v = 0; v < G.vers.size(); ++v)

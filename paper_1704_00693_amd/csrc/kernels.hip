@@ -131,10 +131,10 @@ static hipError_t dispatch_t(const LoopDesc &d, const Box &b, hipStream_t s) {
     }
 }
 
-hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, int march_mask, int march_ty,
+hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, int march_mask, const MarchShape &ms,
                        hipStream_t s) {
     if (b.nb <= 0) return hipSuccess;
-    if (d.op == TC_OP_WSUM) return launch_wsum(d, b, dtype0, march_mask, march_ty, s);
+    if (d.op == TC_OP_WSUM) return launch_wsum(d, b, dtype0, march_mask, ms, s);
     if (d.op == TC_OP_EULER_RHS && d.ndim == 3 && march_mask >= 0) return launch_euler_rhs3(d, b, dtype0, s);
     if (d.op == TC_OP_COPY) {
         if (dtype0 == TC_F64 && dtype1 == TC_F64) return go<OpCopy<double, double>>(d, b, s);

@@ -20,12 +20,12 @@ Box make_box(int ndim, const int lo[3], const int hi[3]);
 // arguments 0 and 1 (they differ only for a converting TC_OP_COPY).
 // march_mask: for TC_OP_WSUM, -1 or the radius mask of the register-window
 // variant (bit a set: input a uses the radius-2 canonical star, else radius 1).
-// march_ty: rows per workgroup of that variant.
-hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, int march_mask, int march_ty,
+// ms: workgroup shapes of that variant.
+hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, int march_mask, const MarchShape &ms,
                        hipStream_t s);
 
 // Weighted-sum kernels (wsum.hip).
-hipError_t launch_wsum(const LoopDesc &d, const Box &b, int dtype, int march_mask, int march_ty, hipStream_t s);
+hipError_t launch_wsum(const LoopDesc &d, const Box &b, int dtype, int march_mask, const MarchShape &ms, hipStream_t s);
 // 3D EULER_RHS marching up z (same arithmetic as the per-point kernel)
 hipError_t launch_euler_rhs3(const LoopDesc &d, const Box &b, int dtype, hipStream_t s);
 

@@ -183,6 +183,16 @@ struct TuneCand {
     int cpl;
 };
 
+// Workgroup shapes of the register-window (marching) kernels: in 2D, rows
+// per workgroup (TC_MARCH_TY); in 3D, rows per workgroup, one wavefront each
+// (TC_MARCH3_ROWS: 4 or 8), and planes each workgroup marches
+// (TC_MARCH3_TZ); 0: chosen by the launcher from the box.
+struct MarchShape {
+    int ty = 8;
+    int rows3 = 0;
+    int tz3 = 0;
+};
+
 struct Ctx {
     int device = 0;
     bool host_only = false;
@@ -232,7 +242,7 @@ struct Ctx {
     // weighted-sum loops on canonical 2D star stencils use the register-window
     // kernel (TC_WSUM_MARCH=0 in the environment selects the generic kernel)
     bool march_enabled = true;
-    int march_ty = 8;             // rows per workgroup of the register-window kernel
+    MarchShape march;             // workgroup shapes of the register-window kernels
     int64_t stagger_unit = 0;     // dataset i's base is offset by (i % 16) * stagger_unit bytes
 
     bool use_graphs = true;              // TC_GRAPHS=0 disables graph replay

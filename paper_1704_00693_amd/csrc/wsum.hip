@@ -9,7 +9,7 @@
 //    60 output columns plus two halo columns per side) and marches TY rows
 //    up y; each lane keeps the vertical window of every input in registers
 //    (one new row load per input per output row, issued one row ahead) and
-//    takes its x neighbours from adjacent lanes with cross-lane shuffles, so
+//    takes its x neighbours from adjacent lanes with DPP lane moves, so
 //    global loads per output point drop from sum(stencil points) to about
 //    the number of inputs and no load is conditional.
 //  * point: 2D or 3D, every input read at its centre only (a scaled copy
@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "lanes.hpp"
 
 namespace tc {
 
@@ -40,14 +41,6 @@ __device__ __forceinline__ float fmaT<float>(float a, float b, float c) {
     return __builtin_fmaf(a, b, c);
 }
 
-template <typename T>
-__device__ __forceinline__ T shfl_up(T v, int d) {
-    return __shfl_up(v, d, 64);
-}
-template <typename T>
-__device__ __forceinline__ T shfl_down(T v, int d) {
-    return __shfl_down(v, d, 64);
-}
 
 // XCD-aware workgroup order: hardware block i runs on XCD i % 8; XCD k gets
 // the contiguous logical block range starting at k*q + min(k, r).
@@ -111,7 +104,7 @@ __global__ void __launch_bounds__(kMarchW) wsum_march_kernel(LoopDesc d, int lo0
             for (int a = 0; a < K; ++a) {
                 const int r = (MASK >> a) & 1 ? 2 : 1;
                 const T c = win[a][2 + t];
-                const T xm1 = shfl_up(c, 1), xp1 = shfl_down(c, 1);
+                const T xm1 = lane_prev(c), xp1 = lane_next(c);
                 const int q = d.pt0[a + 1];
                 if (r == 1) {
                     acc = fmaT<T>((T)d.prm[q + 0], c, acc);
@@ -120,7 +113,7 @@ __global__ void __launch_bounds__(kMarchW) wsum_march_kernel(LoopDesc d, int lo0
                     acc = fmaT<T>((T)d.prm[q + 3], win[a][1 + t], acc);
                     acc = fmaT<T>((T)d.prm[q + 4], win[a][3 + t], acc);
                 } else {
-                    const T xm2 = shfl_up(c, 2), xp2 = shfl_down(c, 2);
+                    const T xm2 = lane_prev(xm1), xp2 = lane_next(xp1);
                     acc = fmaT<T>((T)d.prm[q + 0], c, acc);
                     acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
                     acc = fmaT<T>((T)d.prm[q + 2], xp1, acc);
@@ -141,29 +134,34 @@ __global__ void __launch_bounds__(kMarchW) wsum_march_kernel(LoopDesc d, int lo0
     }
 }
 
-// 3D: a workgroup covers 60 columns x 4 rows (one wavefront per row, lanes
+// 3D: a workgroup covers 60 columns x NW rows (one wavefront per row, lanes
 // as in the 2D march) and marches up z over `tz` planes.  Each lane keeps the
 // z window of its own column for every input in registers; x neighbours come
-// from adjacent lanes.  For the y neighbours each wavefront puts the centre
-// value of its own row, and of one of the four rows just outside the
-// workgroup (y0-2, y0-1, y0+4, y0+5; loaded one batch ahead), into LDS, where
-// the workgroup's rows read them (one barrier per plane, two LDS buffers).
-template <typename T, int K, int MASK>
-__global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo0, int hi0, int lo1, int hi1, int lo2,
+// from adjacent lanes.  For the y neighbours every wavefront puts the centre
+// value of its own row into LDS, and wavefronts 0-3 also that of one of the
+// four rows just outside the workgroup (y0-2, y0-1, y0+NW, y0+NW+1; loaded
+// one batch ahead), where the workgroup's rows read them (one barrier per
+// plane, two LDS buffers).  Taller workgroups load fewer outside rows per
+// output row (4 per NW).
+template <typename T, int K, int MASK, int NW>
+__global__ void __launch_bounds__(64 * NW) wsum_march3_kernel(LoopDesc d, int lo0, int hi0, int lo1, int hi1, int lo2,
                                                               int hi2, int nbx, int nby, int nb, int tz) {
     constexpr int TB = kMarchBatch;
     static_assert(TB % 2 == 0, "the LDS buffer of a plane alternates with its parity");
-    __shared__ T yl[2][K][8][64];
+    static_assert(NW >= 4, "wavefronts 0-3 carry the four outside rows");
+    __shared__ T yl[2][K][NW + 4][64];
     const int lin = xcd_linear(blockIdx.x, nb);
     const int bx = lin % nbx, rest = lin / nbx, by = rest % nby, bz = rest / nby;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: branches on it stay scalar
     const int x = lo0 + bx * kWaveOut - 2 + lane;
-    const int y0 = lo1 + by * 4;
+    const int y0 = lo1 + by * NW;
     const int y = y0 + wave;
     const bool active = lane >= 2 && lane < 62 && x < hi0 && y < hi1;
     const int z0 = lo2 + bz * tz;
     const int z1 = min(z0 + tz, hi2);
-    const int hslot = wave < 2 ? wave : wave + 4;  // LDS row of this wave's outside row
+    const bool outer = wave < 4;                    // this wavefront also carries an outside row
+    const int hslot = wave < 2 ? wave : NW + wave;  // its LDS row (rows y0-2, y0-1, y0+NW, y0+NW+1)
 
     const T *ptr[K];
     const T *optr[K];
@@ -174,6 +172,8 @@ __global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo
 #pragma unroll
     for (int a = 0; a < K; ++a) {
         const int r = (MASK >> a) & 1 ? 2 : 1;
+        // rows y0-2 and y0+NW+1 are read through radius-2 stencils only
+        const bool oa = outer && (r == 2 || (hslot != 0 && hslot != NW + 3));
         // Positions are clamped to the input's reach [lo - r, hi - 1 + r]:
         // whenever an output reads a position, it lies in that reach and is
         // not moved; clamped ones feed no output.
@@ -187,19 +187,17 @@ __global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (j >= 2 - r && j < 2 + r) win[a][j] = ptr[a][(int64_t)(z0 - 2 + j) * sz[a]];
+        // planes past the input's reach are clamped onto its last plane: no
+        // output reads them, and no load is conditional on the plane
+#pragma unroll
+        for (int t = 0; t < TB; ++t) pf[a][t] = ptr[a][(int64_t)min(z0 + r + t, z1 - 1 + r) * sz[a]];
 #pragma unroll
         for (int t = 0; t < TB; ++t)
-            if (z0 + r + t <= z1 - 1 + r) pf[a][t] = ptr[a][(int64_t)(z0 + r + t) * sz[a]];
-        // rows y0-2 and y0+5 are read through radius-2 stencils only
-#pragma unroll
-        for (int t = 0; t < TB; ++t)
-            if ((r == 2 || (hslot != 0 && hslot != 7)) && z0 + t < z1)
-                ob[a][t] = optr[a][(int64_t)(z0 + t) * sz[a]];
+            if (oa) ob[a][t] = optr[a][(int64_t)min(z0 + t, z1 - 1) * sz[a]];
     }
     T *out = (T *)d.arg[0].ptr + x + (int64_t)min(y, hi1 - 1) * d.arg[0].sy;
     const int64_t osz = d.arg[0].sz;
     for (int z = z0; z < z1; z += TB) {
-        T cur_ob[K][TB];
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             const int r = (MASK >> a) & 1 ? 2 : 1;
@@ -207,11 +205,7 @@ __global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo
             for (int t = 0; t < TB; ++t) win[a][2 + r + t] = pf[a][t];
 #pragma unroll
             for (int t = 0; t < TB; ++t) {
-                cur_ob[a][t] = ob[a][t];
-                const int pl = z + TB + r + t;
-                if (pl <= z1 - 1 + r) pf[a][t] = ptr[a][(int64_t)pl * sz[a]];
-                const int po = z + TB + t;
-                if ((r == 2 || (hslot != 0 && hslot != 7)) && po < z1) ob[a][t] = optr[a][(int64_t)po * sz[a]];
+                pf[a][t] = ptr[a][(int64_t)min(z + TB + r + t, z1 - 1 + r) * sz[a]];
             }
         }
 #pragma unroll
@@ -219,8 +213,12 @@ __global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo
             const int buf = t & 1;
 #pragma unroll
             for (int a = 0; a < K; ++a) {
+                const int r = (MASK >> a) & 1 ? 2 : 1;
+                const bool oa = outer && (r == 2 || (hslot != 0 && hslot != NW + 3));
                 yl[buf][a][wave + 2][lane] = win[a][2 + t];
-                yl[buf][a][hslot][lane] = cur_ob[a][t];
+                if (outer) yl[buf][a][hslot][lane] = ob[a][t];
+                // the outside row of plane z + t is in LDS: load the one TB planes on
+                if (oa) ob[a][t] = optr[a][(int64_t)min(z + TB + t, z1 - 1) * sz[a]];
             }
             __syncthreads();
             T acc = (T)0;
@@ -228,7 +226,7 @@ __global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo
             for (int a = 0; a < K; ++a) {
                 const int r = (MASK >> a) & 1 ? 2 : 1;
                 const T c = win[a][2 + t];
-                const T xm1 = shfl_up(c, 1), xp1 = shfl_down(c, 1);
+                const T xm1 = lane_prev(c), xp1 = lane_next(c);
                 const T ym1 = yl[buf][a][wave + 1][lane], yp1 = yl[buf][a][wave + 3][lane];
                 const int q = d.pt0[a + 1];
                 if (r == 1) {
@@ -240,7 +238,7 @@ __global__ void __launch_bounds__(kMarchW) wsum_march3_kernel(LoopDesc d, int lo
                     acc = fmaT<T>((T)d.prm[q + 5], win[a][1 + t], acc);
                     acc = fmaT<T>((T)d.prm[q + 6], win[a][3 + t], acc);
                 } else {
-                    const T xm2 = shfl_up(c, 2), xp2 = shfl_down(c, 2);
+                    const T xm2 = lane_prev(xm1), xp2 = lane_next(xp1);
                     const T ym2 = yl[buf][a][wave][lane], yp2 = yl[buf][a][wave + 4][lane];
                     acc = fmaT<T>((T)d.prm[q + 0], c, acc);
                     acc = fmaT<T>((T)d.prm[q + 1], xm1, acc);
@@ -372,29 +370,51 @@ hipError_t go_march(const LoopDesc &d, const int lo[3], const int hi[3], int ty,
     return hipGetLastError();
 }
 
-template <typename T, int K, int MASK>
-hipError_t go_march3(const LoopDesc &d, const int lo[3], const int hi[3], hipStream_t s) {
-    constexpr int tz = 32;
+// Planes per workgroup: the given count, or (0) the largest of 128, 64, 32
+// that still makes about 1000 workgroups (four per CU).  Longer marches
+// re-read fewer z-halo planes; measured on a 384^3 chain: 128 planes 27.9 ms,
+// 64 28.2, 32 28.7, 192 29.8 (too few workgroups to balance).
+template <typename T, int K, int MASK, int NW>
+hipError_t go_march3_nw(const LoopDesc &d, const int lo[3], const int hi[3], int tz, hipStream_t s) {
     const int nbx = (hi[0] - lo[0] + kWaveOut - 1) / kWaveOut;
-    const int nby = (hi[1] - lo[1] + 3) / 4;
-    const int nbz = (hi[2] - lo[2] + tz - 1) / tz;
+    const int nby = (hi[1] - lo[1] + NW - 1) / NW;
+    const int nz = hi[2] - lo[2];
+    if (tz <= 0) {
+        tz = 128;
+        while (tz > 32 && (int64_t)nbx * nby * ((nz + tz - 1) / tz) < 1000) tz /= 2;
+    }
+    const int nbz = (nz + tz - 1) / tz;
     const int nb = nbx * nby * nbz;
-    hipLaunchKernelGGL((wsum_march3_kernel<T, K, MASK>), dim3(nb), dim3(kMarchW), 0, s, d, lo[0], hi[0], lo[1], hi[1],
-                       lo[2], hi[2], nbx, nby, nb, tz);
+    hipLaunchKernelGGL((wsum_march3_kernel<T, K, MASK, NW>), dim3(nb), dim3(64 * NW), 0, s, d, lo[0], hi[0], lo[1],
+                       hi[1], lo[2], hi[2], nbx, nby, nb, tz);
     return hipGetLastError();
 }
 
 template <typename T, int K, int MASK>
-hipError_t go_march_nd(const LoopDesc &d, const int lo[3], const int hi[3], int ty, hipStream_t s) {
-    return d.ndim == 3 ? go_march3<T, K, MASK>(d, lo, hi, s) : go_march<T, K, MASK>(d, lo, hi, ty, s);
+hipError_t go_march3(const LoopDesc &d, const int lo[3], const int hi[3], const MarchShape &ms, hipStream_t s) {
+    // rows: the given 4 or 8, or (0) 8 unless that leaves fewer than about
+    // 1000 workgroups of 32 planes (thin boxes, as skewed tiles launch)
+    int rows = ms.rows3;
+    if (rows != 4 && rows != 8) {
+        const int64_t nb8 = (int64_t)((hi[0] - lo[0] + kWaveOut - 1) / kWaveOut) * ((hi[1] - lo[1] + 7) / 8) *
+                            ((hi[2] - lo[2] + 31) / 32);
+        rows = nb8 >= 1000 ? 8 : 4;
+    }
+    return rows == 4 ? go_march3_nw<T, K, MASK, 4>(d, lo, hi, ms.tz3, s)
+                     : go_march3_nw<T, K, MASK, 8>(d, lo, hi, ms.tz3, s);
+}
+
+template <typename T, int K, int MASK>
+hipError_t go_march_nd(const LoopDesc &d, const int lo[3], const int hi[3], const MarchShape &ms, hipStream_t s) {
+    return d.ndim == 3 ? go_march3<T, K, MASK>(d, lo, hi, ms, s) : go_march<T, K, MASK>(d, lo, hi, ms.ty, s);
 }
 
 template <typename T, int K>
-hipError_t march_k(const LoopDesc &d, int mask, const int lo[3], const int hi[3], int ty, hipStream_t s) {
+hipError_t march_k(const LoopDesc &d, int mask, const int lo[3], const int hi[3], const MarchShape &ms, hipStream_t s) {
     switch (mask) {
 #define M(m)                                                                        \
     case m:                                                                         \
-        if constexpr ((m >> K) == 0) return go_march_nd<T, K, m>(d, lo, hi, ty, s);  \
+        if constexpr ((m >> K) == 0) return go_march_nd<T, K, m>(d, lo, hi, ms, s);  \
         break;
         M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15)
 #undef M
@@ -403,14 +423,14 @@ hipError_t march_k(const LoopDesc &d, int mask, const int lo[3], const int hi[3]
 }
 
 template <typename T>
-hipError_t wsum_t(const LoopDesc &d, const Box &b, int march_mask, int ty, hipStream_t s) {
+hipError_t wsum_t(const LoopDesc &d, const Box &b, int march_mask, const MarchShape &ms, hipStream_t s) {
     const int k = d.nargs - 1;
     if (march_mask >= 0 && ((d.ndim == 2 && b.hi[2] - b.lo[2] == 1) || d.ndim == 3)) {
         switch (k) {
-        case 1: return march_k<T, 1>(d, march_mask, b.lo, b.hi, ty, s);
-        case 2: return march_k<T, 2>(d, march_mask, b.lo, b.hi, ty, s);
-        case 3: return march_k<T, 3>(d, march_mask, b.lo, b.hi, ty, s);
-        case 4: return march_k<T, 4>(d, march_mask, b.lo, b.hi, ty, s);
+        case 1: return march_k<T, 1>(d, march_mask, b.lo, b.hi, ms, s);
+        case 2: return march_k<T, 2>(d, march_mask, b.lo, b.hi, ms, s);
+        case 3: return march_k<T, 3>(d, march_mask, b.lo, b.hi, ms, s);
+        case 4: return march_k<T, 4>(d, march_mask, b.lo, b.hi, ms, s);
         default: break;
         }
     }
@@ -429,9 +449,9 @@ hipError_t wsum_t(const LoopDesc &d, const Box &b, int march_mask, int ty, hipSt
 
 }  // namespace
 
-hipError_t launch_wsum(const LoopDesc &d, const Box &b, int dtype, int march_mask, int ty, hipStream_t s) {
+hipError_t launch_wsum(const LoopDesc &d, const Box &b, int dtype, int march_mask, const MarchShape &ms, hipStream_t s) {
     if (b.nb <= 0) return hipSuccess;
-    return dtype == TC_F64 ? wsum_t<double>(d, b, march_mask, ty, s) : wsum_t<float>(d, b, march_mask, ty, s);
+    return dtype == TC_F64 ? wsum_t<double>(d, b, march_mask, ms, s) : wsum_t<float>(d, b, march_mask, ms, s);
 }
 
 }  // namespace tc

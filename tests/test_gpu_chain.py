@@ -135,18 +135,28 @@ def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
             if mode == tc.TC_TILING_FUSED:
                 say(f"  fused groups={st['last_groups']} blocks={st['last_tiles']} steps={st['last_launches']}")
                 assert st["last_groups"] >= 1
-    # the generic weighted-sum kernel instead of the register-window one
+    # the generic weighted-sum kernel instead of the register-window one, and
+    # in 3D the register-window kernel's other workgroup shapes (rows of
+    # wavefronts, planes per workgroup; ragged in y and z here)
     import os
-    os.environ["TC_WSUM_MARCH"] = "0"
-    try:
-        with tc.Context() as c:
-            r = ChainRunner(c, ch, data)
-            r.run()
-            r.run()
-            r.run()
-            results["generic"] = [r.read(d) for d in range(ndat)]
-    finally:
-        del os.environ["TC_WSUM_MARCH"]
+    variants = [("generic", {"TC_WSUM_MARCH": "0"})]
+    if ndim == 3:
+        variants += [("rows 4", {"TC_MARCH3_ROWS": "4"}), ("rows 8", {"TC_MARCH3_ROWS": "8"}),
+                     ("rows 8, 8 planes", {"TC_MARCH3_ROWS": "8", "TC_MARCH3_TZ": "8"}),
+                     ("rows 4, 12 planes", {"TC_MARCH3_ROWS": "4", "TC_MARCH3_TZ": "12"})]
+    for name, env in variants:
+        say(f"synthetic chain ndim={ndim} n={n} {name}")
+        os.environ.update(env)
+        try:
+            with tc.Context() as c:
+                r = ChainRunner(c, ch, data)
+                r.run()
+                r.run()
+                r.run()
+                results[name] = [r.read(d) for d in range(ndat)]
+        finally:
+            for k in env:
+                del os.environ[k]
     base = results[(tc.TC_TILING_NONE, (0, 0, 0))]
     exact = 0
     for d in range(ndat):
