@@ -226,8 +226,10 @@ __device__ __forceinline__ void prims3(const T q[5], T gm1, T &u, T &v, T &w, T 
 }
 
 // PRIM: the stage's primitive variables are computed here from Q (its
-// primitive-variable loop is fused in) instead of being loaded.
-template <typename T, bool PRIM>
+// primitive-variable loop is fused in) instead of being loaded.  COPY0: the
+// step's copies Q0 = Q are fused in: the update takes Q0 from the stage's Q
+// (the copy's value) and Q0 is stored at the owned points.
+template <typename T, bool PRIM, bool COPY0>
 __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageArgs a) {
     __shared__ T fy_lds[2][kStageRows + 4][5][64];
     const int lin = xcd_block(blockIdx.x, a.nb);
@@ -251,7 +253,7 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
     for (int c = 0; c < 5; ++c) {
         q[c] = at(kQ + c, yr);
         hq[c] = at(kQ + c, yh);
-        q0[c] = at(kQ0 + c, yr);
+        q0[c] = COPY0 ? nullptr : at(kQ0 + c, yr);
     }
     const T *u = PRIM ? nullptr : at(kU, yr), *v = PRIM ? nullptr : at(kU + 1, yr);
     const T *w = PRIM ? nullptr : at(kU + 2, yr), *p = PRIM ? nullptr : at(kP, yr);
@@ -287,7 +289,7 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
         nq[c] = ld(q[c], kQ + c, z0 + 1);
         lq[c] = ld(q[c], kQ + c, z0 + 2);
         oq[c] = ld(hq[c], kQ + c, z0);
-        cq0[c] = ld(q0[c], kQ0 + c, z0);
+        cq0[c] = COPY0 ? cq[c] : ld(q0[c], kQ0 + c, z0);
     }
     T cu, cv, cp, nu, nv, np_, lu, lv, lw, lp, ov, op;
     if constexpr (PRIM) {
@@ -303,10 +305,11 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
         ov = ld(hv, kU + 1, z0), op = ld(hp, kP, z0);
     }
 
-    T *qn[5], *rr[5];
+    T *qn[5], *rr[5], *q0o[5];
     for (int c = 0; c < 5; ++c) {
         qn[c] = (T *)a.out[c] + xc + (int64_t)yr * a.osy[c];
         rr[c] = a.rout[c] ? (T *)a.rout[c] + xc + (int64_t)yr * a.rsy[c] : nullptr;
+        q0o[c] = COPY0 ? (T *)a.q0out[c] + xc + (int64_t)yr * a.q0sy[c] : nullptr;
     }
     int buf = 0;
     for (int z = z0; z < z1; ++z) {
@@ -339,7 +342,7 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
             for (int c = 0; c < 5; ++c) {
                 iq[c] = ld(q[c], kQ + c, z + 3);
                 ioq[c] = ld(hq[c], kQ + c, z + 1);
-                iq0[c] = ld(q0[c], kQ0 + c, z + 1);
+                if constexpr (!COPY0) iq0[c] = ld(q0[c], kQ0 + c, z + 1);
             }
             if constexpr (PRIM) {
                 T t0, t1;
@@ -368,6 +371,7 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
             if (active) {
                 qn[c][(int64_t)z * a.osz[c]] = qnew;
                 if (rr[c]) rr[c][(int64_t)z * a.rsz[c]] = r;
+                if constexpr (COPY0) q0o[c][(int64_t)z * a.q0sz[c]] = cq0[c];
             }
         }
         // advance the windows
@@ -380,8 +384,8 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
             if (more) {
                 lq[c] = iq[c];
                 oq[c] = ioq[c];
-                cq0[c] = iq0[c];
             }
+            cq0[c] = COPY0 ? cq[c] : (more ? iq0[c] : cq0[c]);  // cq: already the next plane's
         }
         cu = nu; cv = nv; cp = np_;
         nu = lu; nv = lv; np_ = lp;
@@ -402,10 +406,14 @@ hipError_t go_stage3(const EulerStageArgs &in, hipStream_t s) {
     a.tz = kStageTz;
     a.nb = a.nbx * a.nby * nbz;
     if (a.nb <= 0) return hipSuccess;
-    if (a.prim)
-        hipLaunchKernelGGL((euler_stage3_kernel<T, true>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
+    if (a.prim && a.copy0)
+        hipLaunchKernelGGL((euler_stage3_kernel<T, true, true>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
+    else if (a.prim)
+        hipLaunchKernelGGL((euler_stage3_kernel<T, true, false>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
+    else if (a.copy0)
+        hipLaunchKernelGGL((euler_stage3_kernel<T, false, true>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((euler_stage3_kernel<T, false>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
+        hipLaunchKernelGGL((euler_stage3_kernel<T, false, false>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -920,6 +920,28 @@ bool euler_stage_match_prim(const Ctx &c, const std::vector<LoopRec> &chain, int
     return true;
 }
 
+bool euler_stage_match_copy(const Ctx &c, const std::vector<LoopRec> &chain, int i, bool prim, EulerStage &E) {
+    if (i + 5 + (prim ? 11 : 10) > (int)chain.size()) return false;
+    if (!(prim ? euler_stage_match_prim(c, chain, i + 5, E) : euler_stage_match(c, chain, i + 5, E))) return false;
+    bool seen[5] = {false, false, false, false, false};
+    for (int k = 0; k < 5; ++k) {
+        const LoopRec &cp = chain[i + k];
+        if (cp.op != TC_OP_COPY || cp.ndim != 3 || cp.args.size() != 2) return false;
+        for (int d = 0; d < 3; ++d)
+            if (cp.lo[d] != E.lo[d] || cp.hi[d] != E.hi[d]) return false;
+        const ArgRec &dst = cp.args[0], &src = cp.args[1];
+        if (dst.kind != TC_ARG_DAT || src.kind != TC_ARG_DAT) return false;
+        if (c.dats[dst.handle].dtype != c.dats[src.handle].dtype) return false;
+        int comp = -1;
+        for (int cc = 0; cc < 5; ++cc)
+            if (E.q[cc] == src.handle && E.q0[cc] == dst.handle) comp = cc;
+        if (comp < 0 || seen[comp]) return false;
+        seen[comp] = true;
+    }
+    E.copy0 = true;
+    return true;
+}
+
 bool fused_op_supported(const LoopRec &lp) { return lp.op == TC_OP_WSUM && lp.ndim == 2; }
 
 std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3],
@@ -957,12 +979,14 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                 piece[j] = nullptr;
             }
             // a 3D Runge-Kutta stage ending here (with its primitive-variable
-            // loop when their values die in the chain): one z-marching kernel
-            for (int len : {11, 10}) {
+            // loop when their values die in the chain, and the step's copies
+            // Q0 = Q before it): one z-marching kernel
+            for (int len : {16, 15, 11, 10}) {
                 if (j < len) continue;
                 EulerStage E;
-                const bool ok = len == 11 ? euler_stage_match_prim(c, chain, j - 11, E)
-                                          : euler_stage_match(c, chain, j - 10, E);
+                const bool ok = len >= 15 ? euler_stage_match_copy(c, chain, j - len, len == 16, E)
+                                : len == 11 ? euler_stage_match_prim(c, chain, j - 11, E)
+                                            : euler_stage_match(c, chain, j - 10, E);
                 if (!ok) continue;
                 const LoopRec &f = chain[j - 10];
                 int nlive = 0;
@@ -1215,10 +1239,20 @@ tc_status euler_stage_run(Ctx &c, const std::vector<LoopRec> &chain, const Fused
             a.rsz[k] = dr.sz();
         }
     }
-    const int off = E.prim ? 1 : 0;
+    const int c0 = E.copy0 ? 5 : 0, off = c0 + (E.prim ? 1 : 0);
     const LoopRec &rhs = chain[G.g0 + off], &rk = chain[G.g0 + off + 5];
     a.prim = E.prim ? 1 : 0;
-    a.gm1 = E.prim ? chain[G.g0].params[0] : 0.0;
+    a.gm1 = E.prim ? chain[G.g0 + c0].params[0] : 0.0;
+    a.copy0 = E.copy0 ? 1 : 0;
+    if (E.copy0)
+        for (int k = 0; k < 5; ++k) {
+            // Q0 is read by no loop of the group but the updates at the same
+            // point, which take its value from Q: written in place
+            const Dataset &d0 = c.dats[E.q0[k]];
+            a.q0out[k] = d0.origin(d0.cur);
+            a.q0sy[k] = d0.sy();
+            a.q0sz[k] = d0.sz();
+        }
     a.s = rhs.params[1];
     a.a = rk.params[0];
     a.b = rk.params[1];

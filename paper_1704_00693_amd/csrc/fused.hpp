@@ -127,7 +127,8 @@ struct FusedGroup {
 struct EulerStage {
     int q[5], q0[5], r[5], u[3], p;  // datasets
     bool r_live[5];                  // R_c read by a later loop before it is overwritten
-    bool prim = false;               // the stage's EULER_PRIM loop is the group's first loop
+    bool prim = false;               // the stage's EULER_PRIM loop is in the group
+    bool copy0 = false;              // the group starts with the five copies Q0_c = Q_c
     int lo[3], hi[3];
 };
 
@@ -139,6 +140,9 @@ bool euler_stage_match(const Ctx &c, const std::vector<LoopRec> &chain, int i, E
 // the right-hand sides' reads) and the stage, with every primitive variable
 // overwritten by a later loop before any read (so none reaches memory).
 bool euler_stage_match_prim(const Ctx &c, const std::vector<LoopRec> &chain, int i, EulerStage &E);
+// Loops [i, i + 5 + n) with n = 11 (prim) or 10: five copies Q0_c = Q_c (one
+// per component, any order, each over the stage's range) and then the stage.
+bool euler_stage_match_copy(const Ctx &c, const std::vector<LoopRec> &chain, int i, bool prim, EulerStage &E);
 
 // Split a chain into fusion groups (loops outside any group run one kernel
 // each) and generate their kernels; returns the groups in chain order.

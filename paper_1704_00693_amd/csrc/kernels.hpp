@@ -31,7 +31,9 @@ hipError_t launch_euler_rhs3(const LoopDesc &d, const Box &b, int dtype, hipStre
 
 // One 3D Runge-Kutta stage: EULER_RHS for the five components and RK_STAGE
 // for the five components, fused (euler.hip), optionally with the stage's
-// EULER_PRIM loop before them (its results then never reach memory).
+// EULER_PRIM loop before them (its results then never reach memory) and the
+// step's five copies Q0_c = Q_c over the stage's range before that (Q0 is
+// then taken from Q in registers and written out).
 // Arrays (logical origins and strides): kQ + c the stage's Q_c (read at
 // +-2 along every axis), kQ0 + c the step's Q0_c, kU + d the velocities, kP
 // the pressure; out[c] receives the new Q_c, rout[c] (may be NULL) R_c.
@@ -46,6 +48,9 @@ struct EulerStageArgs {
     double s, a, b, dt;
     double gm1;            // prim: gamma - 1
     int prim;              // 1: the primitives are computed from Q (their loop is fused in)
+    int copy0;             // 1: Q0_c = Q_c is fused in; q0out[c] receives it (kQ0 + c is not read)
+    void *q0out[5];
+    int64_t q0sy[5], q0sz[5];
     int lo[3], hi[3];
     int nbx, nby, nb, tz;  // set by the launcher
 };

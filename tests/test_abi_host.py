@@ -287,3 +287,31 @@ def test_par_loops_records_like_par_loop():
         good.params[good.first_param[p2]:good.first_param[p2] + 2] = (0.25, -0.5)
         good.record()
         assert c.tc_pending() == 3 + len(loops)
+
+
+def test_euler_step_plan_fuses_stages_with_copies_and_primitives():
+    """The fused mode's plan of one RK3 step of the 3D Euler workload (host
+    only): each stage is one Runge-Kutta stage group; the first also takes
+    the step's five copies Q0 = Q and its primitive-variable loop, the second
+    its primitive-variable loop, and the third none (its primitives are
+    datasets the chain leaves behind).  A copy over another range stays a
+    loop of its own."""
+    import math
+    from paper_1704_00693_amd.apps import EulerRunner
+    n = 24
+    q = [np.zeros((n + 4,) * 3) for _ in range(5)]
+    with tc.Context(host_only=True) as c:
+        r = EulerRunner(c, q, n, 2 * math.pi / n)
+        r.record_step(1e-3)
+        assert c.tc_fused_groups() == [(0, 16), (16, 27), (28, 38)]
+    with tc.Context(host_only=True) as c:
+        r = EulerRunner(c, q, n, 2 * math.pi / n)
+        # the same step with the last copy over the padded range
+        record = c.tc_par_loop
+
+        def widened(op, blk, rng, args, params=(), name=""):
+            return record(op, blk, r.padded if name == "q0_4" else rng, args, params, name=name)
+
+        c.tc_par_loop = widened
+        r.record_step(1e-3)
+        assert c.tc_fused_groups() == [(5, 16), (16, 27), (28, 38)]
