@@ -206,10 +206,7 @@ hipError_t rhs3_t(const LoopDesc &d, const Box &b, hipStream_t s) {
 // at stencil offsets by neighbouring workgroups, so the new Q goes to the
 // datasets' second buffers; R is written only if a later loop reads it.
 // ---------------------------------------------------------------------------
-constexpr int kStageThreads = 256;  // four wavefronts, one per y row
 constexpr int kStageOut = 60;
-constexpr int kStageRows = 4;
-constexpr int kStageTz = 32;
 
 // Primitive variables of one point, as TC_OP_EULER_PRIM computes them.
 template <typename T>
@@ -229,14 +226,18 @@ __device__ __forceinline__ void prims3(const T q[5], T gm1, T &u, T &v, T &w, T 
 // primitive-variable loop is fused in) instead of being loaded.  COPY0: the
 // step's copies Q0 = Q are fused in: the update takes Q0 from the stage's Q
 // (the copy's value) and Q0 is stored at the owned points.
-template <typename T, bool PRIM, bool COPY0>
-__global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageArgs a) {
-    __shared__ T fy_lds[2][kStageRows + 4][5][64];
+// A workgroup is NW wavefronts, one per y row; wavefronts 0-3 also carry the
+// four rows just outside it (y0-2, y0-1, y0+NW, y0+NW+1).
+template <typename T, bool PRIM, bool COPY0, int NW>
+__global__ void __launch_bounds__(64 * NW) euler_stage3_kernel(EulerStageArgs a) {
+    __shared__ T fy_lds[2][NW + 4][5][64];
     const int lin = xcd_block(blockIdx.x, a.nb);
     const int bx = lin % a.nbx, rest = lin / a.nbx, by = rest % a.nby, bz = rest / a.nby;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: branches on it stay scalar
+    const bool outer = wave < 4;
     const int x = a.lo[0] + bx * kStageOut - 2 + lane;
-    const int y0 = a.lo[1] + by * kStageRows;
+    const int y0 = a.lo[1] + by * NW;
     const int y = y0 + wave;
     const bool active = lane >= 2 && lane < 2 + kStageOut && x < a.hi[0] && y < a.hi[1];
     const int z0 = a.lo[2] + bz * a.tz;
@@ -245,7 +246,7 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
     // allocation); lanes and rows beyond that are clamped and feed no output
     const int xc = min(max(x, a.lo[0] - 2), a.hi[0] + 1);
     const int yr = min(y, a.hi[1] + 1);
-    const int hslot = wave < 2 ? wave : wave + kStageRows;
+    const int hslot = wave < 2 ? wave : wave + NW;  // LDS row of this wavefront's outside row (wavefronts 0-3)
     const int yh = min(y0 - 2 + hslot, a.hi[1] + 1);
     // row bases: own row (yr) and outside row (yh), column xc
     auto at = [&](int k, int row) { return (const T *)a.ptr[k] + xc + (int64_t)row * a.sy[k]; };
@@ -288,7 +289,7 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
         cq[c] = ld(q[c], kQ + c, z0);
         nq[c] = ld(q[c], kQ + c, z0 + 1);
         lq[c] = ld(q[c], kQ + c, z0 + 2);
-        oq[c] = ld(hq[c], kQ + c, z0);
+        oq[c] = outer ? ld(hq[c], kQ + c, z0) : (T)1;  // (T)1: no division by zero in prims3
         cq0[c] = COPY0 ? cq[c] : ld(q0[c], kQ0 + c, z0);
     }
     T cu, cv, cp, nu, nv, np_, lu, lv, lw, lp, ov, op;
@@ -302,7 +303,8 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
         cu = ld(u, kU, z0), cv = ld(v, kU + 1, z0), cp = ld(p, kP, z0);
         nu = ld(u, kU, z0 + 1), nv = ld(v, kU + 1, z0 + 1), np_ = ld(p, kP, z0 + 1);
         lu = ld(u, kU, z0 + 2), lv = ld(v, kU + 1, z0 + 2), lw = ld(w, kU + 2, z0 + 2), lp = ld(p, kP, z0 + 2);
-        ov = ld(hv, kU + 1, z0), op = ld(hp, kP, z0);
+        ov = outer ? ld(hv, kU + 1, z0) : (T)0;
+        op = outer ? ld(hp, kP, z0) : (T)0;
     }
 
     T *qn[5], *rr[5], *q0o[5];
@@ -317,7 +319,7 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             fy_lds[buf][wave + 2][c][lane] = flux_c<T, 1>(c, cq[c], cv, cp);
-            fy_lds[buf][hslot][c][lane] = flux_c<T, 1>(c, oq[c], ov, op);
+            if (outer) fy_lds[buf][hslot][c][lane] = flux_c<T, 1>(c, oq[c], ov, op);
         }
         // the leading plane completes the z windows
 #pragma unroll
@@ -341,7 +343,7 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 iq[c] = ld(q[c], kQ + c, z + 3);
-                ioq[c] = ld(hq[c], kQ + c, z + 1);
+                ioq[c] = outer ? ld(hq[c], kQ + c, z + 1) : (T)1;
                 if constexpr (!COPY0) iq0[c] = ld(q0[c], kQ0 + c, z + 1);
             }
             if constexpr (PRIM) {
@@ -353,8 +355,10 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
                 iv = ld(v, kU + 1, z + 3);
                 iw = ld(w, kU + 2, z + 3);
                 ip = ld(p, kP, z + 3);
-                iov = ld(hv, kU + 1, z + 1);
-                iop = ld(hp, kP, z + 1);
+                if (outer) {
+                    iov = ld(hv, kU + 1, z + 1);
+                    iop = ld(hp, kP, z + 1);
+                }
             }
         }
         __syncthreads();
@@ -397,24 +401,43 @@ __global__ void __launch_bounds__(kStageThreads) euler_stage3_kernel(EulerStageA
     }
 }
 
-template <typename T>
-hipError_t go_stage3(const EulerStageArgs &in, hipStream_t s) {
+template <typename T, int NW>
+hipError_t go_stage3_nw(const EulerStageArgs &in, hipStream_t s) {
     EulerStageArgs a = in;
     a.nbx = (a.hi[0] - a.lo[0] + kStageOut - 1) / kStageOut;
-    a.nby = (a.hi[1] - a.lo[1] + kStageRows - 1) / kStageRows;
-    const int nbz = (a.hi[2] - a.lo[2] + kStageTz - 1) / kStageTz;
-    a.tz = kStageTz;
-    a.nb = a.nbx * a.nby * nbz;
-    if (a.nb <= 0) return hipSuccess;
+    a.nby = (a.hi[1] - a.lo[1] + NW - 1) / NW;
+    const int nz = a.hi[2] - a.lo[2];
+    if (a.tz <= 0) {
+        // longest march (fewest z-halo planes re-read) that still makes
+        // about 1000 workgroups
+        a.tz = 128;
+        while (a.tz > 32 && (int64_t)a.nbx * a.nby * ((nz + a.tz - 1) / a.tz) < 1000) a.tz /= 2;
+    }
+    a.nb = a.nbx * a.nby * ((nz + a.tz - 1) / a.tz);
+    if (a.nb <= 0 || a.nbx <= 0 || a.nby <= 0 || nz <= 0) return hipSuccess;
+    const dim3 g(a.nb), b(64 * NW);
     if (a.prim && a.copy0)
-        hipLaunchKernelGGL((euler_stage3_kernel<T, true, true>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
+        hipLaunchKernelGGL((euler_stage3_kernel<T, true, true, NW>), g, b, 0, s, a);
     else if (a.prim)
-        hipLaunchKernelGGL((euler_stage3_kernel<T, true, false>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
+        hipLaunchKernelGGL((euler_stage3_kernel<T, true, false, NW>), g, b, 0, s, a);
     else if (a.copy0)
-        hipLaunchKernelGGL((euler_stage3_kernel<T, false, true>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
+        hipLaunchKernelGGL((euler_stage3_kernel<T, false, true, NW>), g, b, 0, s, a);
     else
-        hipLaunchKernelGGL((euler_stage3_kernel<T, false, false>), dim3(a.nb), dim3(kStageThreads), 0, s, a);
+        hipLaunchKernelGGL((euler_stage3_kernel<T, false, false, NW>), g, b, 0, s, a);
     return hipGetLastError();
+}
+
+// rows: the given 4 or 8, or (0) 8 unless that leaves fewer than about 1000
+// workgroups of 32 planes
+template <typename T>
+hipError_t go_stage3(const EulerStageArgs &a, hipStream_t s) {
+    int rows = a.rows;
+    if (rows != 4 && rows != 8) {
+        const int64_t nb8 = (int64_t)((a.hi[0] - a.lo[0] + kStageOut - 1) / kStageOut) * ((a.hi[1] - a.lo[1] + 7) / 8) *
+                            ((a.hi[2] - a.lo[2] + 31) / 32);
+        rows = nb8 >= 1000 ? 8 : 4;
+    }
+    return rows == 4 ? go_stage3_nw<T, 4>(a, s) : go_stage3_nw<T, 8>(a, s);
 }
 
 }  // namespace

@@ -1261,6 +1261,8 @@ tc_status euler_stage_run(Ctx &c, const std::vector<LoopRec> &chain, const Fused
         a.lo[d] = E.lo[d];
         a.hi[d] = E.hi[d];
     }
+    a.rows = c.march.rows3;
+    a.tz = c.march.tz3;
     const hipError_t e = launch_euler_stage3(a, c.dats[E.q[0]].dtype, c.stream);
     if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "Runge-Kutta stage launch failed: %s", hipGetErrorString(e));
     for (int k = 0; k < 5; ++k) c.dats[E.q[k]].cur ^= 1;

@@ -52,7 +52,8 @@ struct EulerStageArgs {
     void *q0out[5];
     int64_t q0sy[5], q0sz[5];
     int lo[3], hi[3];
-    int nbx, nby, nb, tz;  // set by the launcher
+    int rows, tz;          // workgroup rows (4 or 8) and planes; 0: chosen by the launcher
+    int nbx, nby, nb;      // set by the launcher
 };
 hipError_t launch_euler_stage3(const EulerStageArgs &a, int dtype, hipStream_t s);
 

@@ -7,6 +7,7 @@ sequences make it bit-exact in practice) and the 256^3 Taylor-Green workload
 on two z-slabs against the window oracle, with the energy sum checked against
 the exactly rounded sum of the read-back field."""
 import math
+import os
 import sys
 
 import numpy as np
@@ -58,15 +59,28 @@ def test_rk3_step_small(tc, ndim, n):
     ref = EulerOracle(q, n, h)
     ref.step(1e-3)
     outs = {}
-    for mode, tile in [(tc.TC_TILING_NONE, (0, 0, 0)), (tc.TC_TILING_SKEWED, (0, 0, 5) if ndim == 3 else (0, 7, 0)),
-                       (tc.TC_TILING_FUSED, (0, 0, 0))]:
-        say(f"euler ndim={ndim} n={n} mode={mode}")
-        with tc.Context() as c:
-            c.tc_set_tiling(mode, tile)
-            r = EulerRunner(c, q, n, h)
-            esum = r.step(1e-3)
-            got = [c.tc_dat_read(d) for d in r.Q + r.R + r.vel + [r.p]]
-            groups = c.tc_get_stats()["last_groups"]
+    runs = [(0, tc.TC_TILING_NONE, (0, 0, 0), {}),
+            (1, tc.TC_TILING_SKEWED, (0, 0, 5) if ndim == 3 else (0, 7, 0), {}),
+            (2, tc.TC_TILING_FUSED, (0, 0, 0), {})]
+    if ndim == 3:
+        # the fused stage kernel's other workgroup shapes (rows of
+        # wavefronts, planes per workgroup; ragged in y and z here)
+        runs += [(3, tc.TC_TILING_FUSED, (0, 0, 0), {"TC_MARCH3_ROWS": "8"}),
+                 (4, tc.TC_TILING_FUSED, (0, 0, 0), {"TC_MARCH3_ROWS": "8", "TC_MARCH3_TZ": "12"}),
+                 (5, tc.TC_TILING_FUSED, (0, 0, 0), {"TC_MARCH3_ROWS": "4", "TC_MARCH3_TZ": "8"})]
+    for key, mode, tile, env in runs:
+        say(f"euler ndim={ndim} n={n} mode={mode} {env}")
+        os.environ.update(env)
+        try:
+            with tc.Context() as c:
+                c.tc_set_tiling(mode, tile)
+                r = EulerRunner(c, q, n, h)
+                esum = r.step(1e-3)
+                got = [c.tc_dat_read(d) for d in r.Q + r.R + r.vel + [r.p]]
+                groups = c.tc_get_stats()["last_groups"]
+        finally:
+            for k in env:
+                del os.environ[k]
         want = ref.q + ref.r + ref.vel + [ref.p]
         hh = 2
         for g, w in zip(got, want):
@@ -74,11 +88,11 @@ def test_rk3_step_small(tc, ndim, n):
             assert rel(g[sl], w[sl]) <= TOL
         e = ref.interior(ref.q[ndim + 1])
         assert abs(esum - math.fsum(e.ravel().tolist())) <= 1e-15 * float(np.abs(e).sum())
-        outs[mode] = got
+        outs[key] = got
         if mode == tc.TC_TILING_FUSED and ndim == 3:
             # the three stages ran as fused Runge-Kutta stage kernels
             assert groups == 3
-    for m in (1, 2):
+    for m in outs:
         for a, b in zip(outs[0], outs[m]):
             assert np.array_equal(a, b)
 
