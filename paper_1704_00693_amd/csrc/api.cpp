@@ -231,7 +231,10 @@ tc_status ensure_partials(Ctx &c, int64_t pairs, int nslots) {
         int64_t cap = std::max<int64_t>(nslots * 2, 64);
         c.red_out = (double *)dev_alloc(c, cap * sizeof(double));
         if (!c.red_out) return fail(c, TC_ERR_NOMEM, "cannot allocate reduction outputs");
-        HIPCHK(c, hipHostMalloc((void **)&c.red_host, cap * sizeof(double), hipHostMallocDefault));
+        // coherent: the combining kernel's stores reach host memory, not
+        // the GPU's caches, and are visible once the stream is synchronised
+        HIPCHK(c, hipHostMalloc((void **)&c.red_host, cap * sizeof(double), hipHostMallocCoherent));
+        HIPCHK(c, hipHostGetDevicePointer((void **)&c.red_host_dev, c.red_host, 0));
         c.red_out_cap = cap;
     }
     return TC_OK;
@@ -743,13 +746,22 @@ tc_status flush(Ctx &c) {
     if (!red_handles.empty()) {
         st = ensure_partials(c, 0, (int)red_handles.size());
         if (st != TC_OK) return st;
-        for (size_t s = 0; s < red_handles.size(); ++s)
-            HIPCHK(c, launch_finalize(c.partials + 2 * red_base[s], red_count[s], c.reds[red_handles[s]].op,
-                                      c.red_out + 2 * s, c.stream));
         std::vector<double> host_out(c.noalloc ? 2 * red_handles.size() : 0);
         double *dst = c.noalloc ? host_out.data() : c.red_host;
-        HIPCHK(c, hipMemcpyAsync(dst, c.red_out, red_handles.size() * 2 * sizeof(double), hipMemcpyDeviceToHost,
-                                 c.stream));
+        std::vector<int> ops(red_handles.size());
+        for (size_t s = 0; s < red_handles.size(); ++s) ops[s] = c.reds[red_handles[s]].op;
+        if (c.noalloc) {
+            // the results go to the scratch array and are copied from there
+            HIPCHK(c, launch_finalize_many(c.partials, red_base.data(), red_count.data(), ops.data(),
+                                           (int)red_handles.size(), c.red_out, c.stream));
+            HIPCHK(c, hipMemcpyAsync(dst, c.red_out, red_handles.size() * 2 * sizeof(double),
+                                     hipMemcpyDeviceToHost, c.stream));
+        } else {
+            // one launch combines every reduction's partials straight into
+            // the pinned host results: no copy
+            HIPCHK(c, launch_finalize_many(c.partials, red_base.data(), red_count.data(), ops.data(),
+                                           (int)red_handles.size(), c.red_host_dev, c.stream));
+        }
         HIPCHK(c, hipStreamSynchronize(c.stream));
         for (size_t s = 0; s < red_handles.size(); ++s) {
             Reduction &r = c.reds[red_handles[s]];

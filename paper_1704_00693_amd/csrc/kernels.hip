@@ -54,11 +54,21 @@ __global__ void __launch_bounds__(kBlockThreads) loop_kernel(LoopDesc d, Box b) 
     }
 }
 
-// One workgroup combines `count` partials in a fixed order.
-__global__ void __launch_bounds__(kBlockThreads) finalize_kernel(const double *part, int64_t count, int op,
-                                                                 double *out) {
+constexpr int kFinMax = 16;  // reductions per launch of finalize_many_kernel
+struct FinalizeMany {
+    const double *part;
+    double *out;
+    int64_t base[kFinMax], count[kFinMax];
+    int op[kFinMax];
+};
+
+// Workgroup r combines reduction r's partials in a fixed order.
+__global__ void __launch_bounds__(kBlockThreads) finalize_many_kernel(FinalizeMany f) {
+    const int r = blockIdx.x;
+    const int op = f.op[r];
+    const double *part = f.part + 2 * f.base[r];
     DD a = red_identity(op);
-    for (int64_t i = threadIdx.x; i < count; i += kBlockThreads) {
+    for (int64_t i = threadIdx.x; i < f.count[r]; i += kBlockThreads) {
         DD b;
         b.hi = part[2 * i];
         b.lo = part[2 * i + 1];
@@ -66,8 +76,8 @@ __global__ void __launch_bounds__(kBlockThreads) finalize_kernel(const double *p
     }
     a = block_reduce(op, a);
     if (threadIdx.x == 0) {
-        out[0] = a.hi;
-        out[1] = a.lo;
+        f.out[2 * r] = a.hi;
+        f.out[2 * r + 1] = a.lo;
     }
 }
 
@@ -145,9 +155,23 @@ hipError_t launch_loop(const LoopDesc &d, const Box &b, int dtype0, int dtype1, 
     return dtype0 == TC_F64 ? dispatch_t<double>(d, b, s) : dispatch_t<float>(d, b, s);
 }
 
-hipError_t launch_finalize(const double *part, int64_t count, int op, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlockThreads), 0, s, part, count, op, out);
-    return hipGetLastError();
+hipError_t launch_finalize_many(const double *part, const int64_t *base, const int64_t *count, const int *op, int n,
+                                double *out, hipStream_t s) {
+    for (int r0 = 0; r0 < n; r0 += kFinMax) {
+        FinalizeMany f;
+        const int m = std::min(kFinMax, n - r0);
+        f.part = part;
+        f.out = out + 2 * r0;
+        for (int k = 0; k < kFinMax; ++k) {
+            f.base[k] = k < m ? base[r0 + k] : 0;
+            f.count[k] = k < m ? count[r0 + k] : 0;
+            f.op[k] = k < m ? op[r0 + k] : 0;
+        }
+        hipLaunchKernelGGL(finalize_many_kernel, dim3(m), dim3(kBlockThreads), 0, s, f);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace tc

@@ -57,7 +57,10 @@ struct EulerStageArgs {
 };
 hipError_t launch_euler_stage3(const EulerStageArgs &a, int dtype, hipStream_t s);
 
-// Combine `count` (hi, lo) partials into out[0..1] with one workgroup.
-hipError_t launch_finalize(const double *part, int64_t count, int op, double *out, hipStream_t s);
+// Combine the (hi, lo) partials of n reductions, one workgroup each, in a
+// fixed order: reduction r's count[r] pairs start at part + 2 * base[r] and
+// its result goes to out[2r], out[2r+1].  base, count, op: host arrays.
+hipError_t launch_finalize_many(const double *part, const int64_t *base, const int64_t *count, const int *op, int n,
+                                double *out, hipStream_t s);
 
 }  // namespace tc

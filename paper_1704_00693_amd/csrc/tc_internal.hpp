@@ -235,7 +235,8 @@ struct Ctx {
     int64_t partials_cap = 0;  // in doubles
     double *red_out = nullptr;  // device: 2 doubles per reduction
     int64_t red_out_cap = 0;
-    double *red_host = nullptr;  // pinned host mirror
+    double *red_host = nullptr;      // pinned, coherent host memory: the flush's reduction results
+    double *red_host_dev = nullptr;  // its device address (the combining kernel writes it directly)
 
     tc_stats stats{};
 
