@@ -869,6 +869,10 @@ static tc_status impl_tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (const char *e = getenv("TC_JIT_FENCE")) c.jit_sched_fence = atoi(e) != 0;
     if (const char *e = getenv("TC_JIT_ALIGN")) c.jit_align_store = atoi(e) != 0;
     if (const char *e = getenv("TC_STAGED")) c.staged_mode = std::min(2, std::max(0, atoi(e)));
+    if (const char *e = getenv("TC_STAGED_THREADS")) {
+        const int v = atoi(e);
+        if (v == 256 || v == 1024) c.staged_threads = v;
+    }
     if (const char *e = getenv("TC_STAGED_TILE")) {
         int v[3] = {0, 0, 0};
         if (std::sscanf(e, "%d,%d,%d", &v[0], &v[1], &v[2]) >= 1)

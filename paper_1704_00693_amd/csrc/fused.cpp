@@ -1078,8 +1078,10 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
             }
             if (g->staged) {
                 const StagedGroup &S = *g->staged;
-                std::fprintf(stderr, "staged group [%d,%d): tile %dx%dx%d, %d tiles, %d slots, LDS %lld B, cost %.1f us\n",
-                             g->g0, g->g1, S.tile[0], S.tile[1], S.tile[2], S.ntot, (int)S.slots.size(),
+                std::fprintf(stderr,
+                             "staged group [%d,%d): tile %dx%dx%d, %d tiles of %d threads, %d slots, LDS %lld B, cost "
+                             "%.1f us\n",
+                             g->g0, g->g1, S.tile[0], S.tile[1], S.tile[2], S.ntot, S.threads, (int)S.slots.size(),
                              (long long)(S.desc_off + (int64_t)sizeof(LoopDesc)), S.cost * 1e6);
                 continue;
             }

@@ -298,6 +298,11 @@ bool layout(const Ctx &c, const Ana &A, StagedGroup &G, const std::vector<std::a
     const double t_lat = 3.0 * per_cu * per_tile / ((1.0 + 0.5 * (overlap - 1.0)) * 2.4e9);
     const double t_bw = (double)G.ntot * (bytes_sum / (double)tiles.size()) / 4.0e12;
     G.cost = std::max(t_lat, t_bw) + 5e-6;
+    // workgroup size: 256 threads unless asked otherwise.  On the PPCG chain
+    // 256 ran faster than 1024 at both measured sizes (256^2, boxes up to
+    // 52 x 36: 9.8 against 10.2 ms per solve; 700^2, boxes up to 84 x 52:
+    // 14.7 against 15.2 ms); the cost above was calibrated at 1024.
+    G.threads = c.staged_threads > 0 ? c.staged_threads : 256;
     return true;
 }
 
@@ -617,7 +622,7 @@ tc_status staged_run(Ctx &c, const std::vector<LoopRec> &chain, StagedGroup &G) 
         const std::vector<double> &p = chain[l].params;
         for (size_t i = 0; i < p.size() && S.prm_skip + (int)i < S.nprm; ++i) a.prm[S.prm_off + S.prm_skip + i] = p[i];
     }
-    const hipError_t e = launch_staged(a, G.dtype, (size_t)G.desc_off + sizeof(LoopDesc), c.stream);
+    const hipError_t e = launch_staged(a, G.dtype, (size_t)G.desc_off + sizeof(LoopDesc), G.threads, c.stream);
     if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "staged group launch failed: %s", hipGetErrorString(e));
     for (size_t s = 0; s < G.slots.size(); ++s)
         if (G.slots[s].twin) {

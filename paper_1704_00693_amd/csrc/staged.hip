@@ -1,4 +1,4 @@
-// Staged tiles on gfx950: one workgroup (1024 threads) per tile.  The datasets
+// Staged tiles on gfx950: one workgroup (256 or 1024 threads) per tile.  The datasets
 // the group writes are staged in LDS over the tile's boxes; the loops run in
 // order over their computed boxes with the per-loop kernels' functors,
 // re-pointed at the LDS copies (the descriptor itself is copied to LDS and
@@ -14,7 +14,7 @@
 namespace tc {
 
 static_assert(sizeof(LoopDesc) % 8 == 0, "descriptors are copied to LDS in 8-byte words");
-static_assert(sizeof(LoopDesc) <= 2 * 8 * kSThreads, "a descriptor is at most two words per thread");
+static_assert(sizeof(LoopDesc) <= 2 * 8 * 256, "a descriptor is at most two words per thread");
 static_assert(sizeof(SArgs) <= 4096, "staged kernel arguments stay within 4 KiB");
 
 namespace {
@@ -32,12 +32,13 @@ struct Pt {
     int x, y, z;
 };
 
-// Workgroup-wide combine of one DD value per thread (kSThreads threads):
-// within each wavefront by butterfly shuffles, then the wavefronts' values
-// in wavefront order by thread 0.
+// Workgroup-wide combine of one DD value per thread: within each wavefront
+// by butterfly shuffles, then the wavefronts' values in wavefront order by
+// thread 0.
 __device__ DD tile_reduce(int op, DD v) {
-    constexpr int kWaves = kSThreads / 64;
-    __shared__ double sh_hi[kWaves], sh_lo[kWaves];
+    constexpr int kMaxWaves = kSThreads / 64;
+    const int nwaves = (int)blockDim.x / 64;
+    __shared__ double sh_hi[kMaxWaves], sh_lo[kMaxWaves];
     for (int o = 32; o > 0; o >>= 1) {
         DD w;
         w.hi = __shfl_xor(v.hi, o);
@@ -54,7 +55,7 @@ __device__ DD tile_reduce(int op, DD v) {
         DD a;
         a.hi = sh_hi[0];
         a.lo = sh_lo[0];
-        for (int i = 1; i < kWaves; ++i) {
+        for (int i = 1; i < nwaves; ++i) {
             DD b;
             b.hi = sh_hi[i];
             b.lo = sh_lo[i];
@@ -103,13 +104,13 @@ __device__ void run_loop_box(const D &d, const int *C, const int *O, int nred, d
     red[0] = red_identity(d.red_op[0]);
     red[1] = red_identity(d.red_op[1]);
     if (nred == 0) {
-        for (int i = threadIdx.x; i < n; i += kSThreads) {
+        for (int i = threadIdx.x; i < n; i += (int)blockDim.x) {
             const Pt p = box_point(i);
             Op::run(d, p.x, p.y, p.z, red);
         }
         return;
     }
-    for (int i = threadIdx.x; i < n; i += kSThreads) {
+    for (int i = threadIdx.x; i < n; i += (int)blockDim.x) {
         const Pt p = box_point(i);
         const bool own = p.x >= O[0] && p.x < O[3] && p.y >= O[1] && p.y < O[4] && p.z >= O[2] && p.z < O[5];
         if (own) {
@@ -163,6 +164,7 @@ __device__ void dispatch(const D &d, const int *C, const int *O, int tile) {
 template <typename T>
 __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    const int nt = (int)blockDim.x;  // 256 or 1024
     T *lds = (T *)smem;
     LoopDesc &d = *(LoopDesc *)(smem + a.desc_off);
     const int tile = tile_order(blockIdx.x, gridDim.x);
@@ -187,12 +189,12 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
         const int n = wx * wy * wz;
         const BoxWalk box_point(L, wx, wy);
         // kBatch loads in flight per lane before their stores
-        for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * kSThreads) {
+        for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * nt) {
             T v[kBatch];
             int o[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
-                const int i = i0 + k * kSThreads;
+                const int i = i0 + k * nt;
                 o[k] = -1;
                 if (i < n) {
                     const Pt p = box_point(i);
@@ -257,7 +259,7 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
     int l = next_loop(-1);
     if (l < a.nloops) {
         const uint64_t *from = (const uint64_t *)(a.loops + l);
-        for (int i = threadIdx.x; i < kWords; i += kSThreads) dw[i] = word(l, i, from[i]);
+        for (int i = threadIdx.x; i < kWords; i += nt) dw[i] = word(l, i, from[i]);
     }
     __syncthreads();
     while (l < a.nloops) {
@@ -266,7 +268,7 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
         if (ln < a.nloops) {  // in flight while this loop computes
             const uint64_t *from = (const uint64_t *)(a.loops + ln);
             if (threadIdx.x < (unsigned)kWords) w0 = from[threadIdx.x];
-            if (threadIdx.x + kSThreads < (unsigned)kWords) w1 = from[threadIdx.x + kSThreads];
+            if (threadIdx.x + nt < (unsigned)kWords) w1 = from[threadIdx.x + nt];
         }
         if (a.sl[l].all_lds)  // every dataset in LDS: LDS-addressed loads and stores
             dispatch<T>(static_cast<const LdsDesc &>(d), r + 6 + 9 * ns + 6 * l, O, tile);
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
         __syncthreads();
         if (ln < a.nloops) {
             if (threadIdx.x < (unsigned)kWords) dw[threadIdx.x] = word(ln, threadIdx.x, w0);
-            if (threadIdx.x + kSThreads < (unsigned)kWords) dw[threadIdx.x + kSThreads] = word(ln, threadIdx.x + kSThreads, w1);
+            if (threadIdx.x + nt < (unsigned)kWords) dw[threadIdx.x + nt] = word(ln, threadIdx.x + nt, w1);
         }
         __syncthreads();
         l = ln;
@@ -298,12 +300,12 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
         const T *box = lds + S.lds_off;
         const int n = wx * wy * wz;
         const BoxWalk box_point(lo, wx, wy);
-        for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * kSThreads) {
+        for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * nt) {
             T v[kBatch];
             int64_t o[kBatch];
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
-                const int i = i0 + k * kSThreads;
+                const int i = i0 + k * nt;
                 o[k] = 0;
                 if (i < n) {  // logical offsets may be negative (halo points)
                     const Pt p = box_point(i);
@@ -313,13 +315,13 @@ __global__ void __launch_bounds__(kSThreads) staged_kernel(SArgs a) {
             }
 #pragma unroll
             for (int k = 0; k < kBatch; ++k)
-                if (i0 + k * kSThreads < n) dst[o[k]] = v[k];
+                if (i0 + k * nt < n) dst[o[k]] = v[k];
         }
     }
 }
 
 template <typename T>
-hipError_t go(const SArgs &a, size_t lds, hipStream_t s) {
+hipError_t go(const SArgs &a, size_t lds, int threads, hipStream_t s) {
     static bool attr = false;
     if (!attr) {
         const hipError_t e = hipFuncSetAttribute((const void *)staged_kernel<T>,
@@ -327,15 +329,15 @@ hipError_t go(const SArgs &a, size_t lds, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(staged_kernel<T>, dim3(a.ntot), dim3(kSThreads), lds, s, a);
+    hipLaunchKernelGGL(staged_kernel<T>, dim3(a.ntot), dim3(threads == 256 ? 256 : kSThreads), lds, s, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_staged(const SArgs &a, int dtype, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_staged(const SArgs &a, int dtype, size_t lds_bytes, int threads, hipStream_t s) {
     if (a.ntot <= 0) return hipSuccess;
-    return dtype == TC_F64 ? go<double>(a, lds_bytes, s) : go<float>(a, lds_bytes, s);
+    return dtype == TC_F64 ? go<double>(a, lds_bytes, threads, s) : go<float>(a, lds_bytes, threads, s);
 }
 
 }  // namespace tc

@@ -35,8 +35,7 @@ namespace tc {
 constexpr int kSMaxDat = 24;        // datasets one staged group names
 constexpr int kSMaxLoops = 128;     // loops of one staged group
 constexpr int kSMaxPrm = 256;       // scalar parameters of one group (kernel arguments)
-constexpr int kSThreads = 1024;     // threads per tile workgroup (16 wavefronts: a tile's LDS
-                                    // allows few workgroups per CU, so each brings many waves)
+constexpr int kSThreads = 1024;     // most threads per tile workgroup (the default is 256)
 constexpr int64_t kSLdsBudget = 150 * 1024;  // bytes of LDS for the staged datasets and one descriptor
 
 // Per dataset slot of a group (device copy in the group's table).
@@ -68,6 +67,7 @@ struct StagedGroup {
     int ulo[3] = {0, 0, 0}, uhi[3] = {1, 1, 1};  // union of the loop ranges
     int nt[3] = {1, 1, 1};
     int ntot = 0;                  // tiles
+    int threads = kSThreads;       // workgroup size: 256 or 1024
     std::vector<int> dats;         // dataset of every slot
     std::vector<SSlot> slots;
     std::vector<SLoop> loops;
@@ -124,6 +124,7 @@ struct SArgs {
     int64_t gsy[kSMaxDat], gsz[kSMaxDat];  // device strides of every slot
     double prm[kSMaxPrm];
 };
-hipError_t launch_staged(const SArgs &a, int dtype, size_t lds_bytes, hipStream_t s);
+// threads: 256 or 1024 (one workgroup per tile)
+hipError_t launch_staged(const SArgs &a, int dtype, size_t lds_bytes, int threads, hipStream_t s);
 
 }  // namespace tc

@@ -79,10 +79,13 @@ def run(tc, ch, data, mode):
     return out, vals, st
 
 
+@pytest.mark.parametrize("threads", ["256", "1024"])
 @pytest.mark.parametrize("ndim", [1, 2, 3])
-def test_staged_random_chains(tc, ndim, monkeypatch):
-    # every group the analysis accepts is taken, whatever its modelled cost
+def test_staged_random_chains(tc, ndim, threads, monkeypatch):
+    # every group the analysis accepts is taken, whatever its modelled cost,
+    # with workgroups of either size
     monkeypatch.setenv("TC_STAGED", "2")
+    monkeypatch.setenv("TC_STAGED_THREADS", threads)
     rng = random.Random(7300 + ndim)
     staged_runs = 0
     for it in range(14 if ndim < 3 else 10):
@@ -90,7 +93,7 @@ def test_staged_random_chains(tc, ndim, monkeypatch):
         data = op_chain_data(ch, seed=100 + it)
         plain = dict(ch, loops=[lp for lp in ch["loops"] if lp["op"] != "DOT"])
         ref = run_op_chain_oracle(plain, data)
-        say(f"staged random chain ndim={ndim} it={it} n={ch['n']} loops={len(ch['loops'])}")
+        say(f"staged random chain ndim={ndim} threads={threads} it={it} n={ch['n']} loops={len(ch['loops'])}")
         base, vb, _ = run(tc, ch, data, tc.TC_TILING_NONE)
         got, vg, st = run(tc, ch, data, tc.TC_TILING_FUSED)
         staged_runs += st["last_groups"] > 0
