@@ -1054,6 +1054,7 @@ static tc_status impl_tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_bl
     lp.block = blk;
     lp.ndim = ndim;
     lp.name = name ? name : "";
+    lp.args.reserve((size_t)nargs);
     for (int d = 0; d < 3; ++d) {
         lp.lo[d] = d < ndim ? range[2 * d] : 0;
         lp.hi[d] = d < ndim ? range[2 * d + 1] : 1;
@@ -1146,6 +1147,7 @@ static tc_status impl_tc_par_loop(tc_ctx *ctx, const char *name, tc_op op, tc_bl
         }
     }
     lp.params.assign(params, params + nparams);
+    if (c.chain.capacity() == c.chain.size()) c.chain.reserve(std::max<size_t>(128, 2 * c.chain.size()));
     c.chain.push_back(std::move(lp));
     c.stats.loops_recorded++;
     return TC_OK;

@@ -184,6 +184,43 @@ def test_chain_sum_reduction(tc):
         assert abs(got - want) <= 4e-16 * abs(want) + 1e-300
 
 
+def test_many_reductions_in_one_flush(tc):
+    """21 reductions recorded in one chain (more than one combining launch
+    holds): sums over random sub-ranges and one maximum, all fetched after
+    a single flush, each equal to the exactly rounded sum (double-double
+    partials) or the exact maximum of its range."""
+    import math
+    rng = np.random.default_rng(11)
+    a = rng.uniform(-1.0, 1.0, size=(44, 53))
+    with tc.Context() as c:
+        b = c.tc_decl_block(2)
+        d = c.tc_decl_dat(b, [51, 42], [1, 1], [1, 1], a)
+        cen = c.tc_decl_stencil([(0, 0)])
+        reds, want = [], []
+        for k in range(20):
+            x0, y0 = int(rng.integers(0, 30)), int(rng.integers(0, 25))
+            x1, y1 = x0 + int(rng.integers(1, 21)), y0 + int(rng.integers(1, 17))
+            r = c.tc_decl_reduction(tc.TC_RED_SUM, f"s{k}")
+            c.tc_par_loop("SUM", b, [x0, x1, y0, y1], [(d, cen, "R"), ("red", r)])
+            reds.append(r)
+            want.append(math.fsum(a[1 + y0:1 + y1, 1 + x0:1 + x1].ravel().tolist()))
+        mx = c.tc_decl_reduction(tc.TC_RED_MAX, "m")
+        sx = c.tc_decl_stencil([(0, 0), (1, 0)])
+        sy = c.tc_decl_stencil([(0, 0), (0, 1)])
+        c.tc_par_loop("TEA_GERSH", b, [0, 50, 0, 41], [(d, sx, "R"), (d, sy, "R"), ("red", mx)])
+        flushes = c.tc_get_stats()["flushes"]
+        got = [c.tc_reduction_result(r) for r in reds]
+        assert c.tc_get_stats()["flushes"] == flushes + 1  # one flush served every fetch
+        gmax = c.tc_reduction_result(mx)
+    for g, w in zip(got, want):
+        assert abs(g - w) <= 4e-16 * max(abs(w), 1e-300) + 1e-300, (g, w)
+    # the Gershgorin bound's per-point value, in the op's order: 2 s + 1 with
+    # s = ((kx(x+1) + kx(x)) + ky(y+1)) + ky(y), one rounding for 2 s + 1
+    kx0, kx1 = a[1:42, 1:51], a[1:42, 2:52]
+    ky0, ky1 = a[1:42, 1:51], a[2:43, 1:51]
+    assert gmax == float(np.max(2.0 * (((kx1 + kx0) + ky1) + ky0) + 1.0))
+
+
 def test_reduction_accumulates_until_fetched(tc):
     with tc.Context() as c:
         b = c.tc_decl_block(2)
