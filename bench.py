@@ -276,7 +276,7 @@ def _tune(ctx, fn, limit=80):
 
 
 def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(), jacobi_two_columns=True,
-                    tealeaf_sizes=(256,)):
+                    tealeaf_sizes=(256,), jacobi_select=None, jacobi_variants=("non_copy", "copy")):
     """The other configurations, each in the execution modes that apply:
     heat-conduction PPCG 256^2 (50 iterations of 10 Chebyshev steps), the
     256^3 Taylor-Green RK3 step, the 8192^2 Jacobi iteration (250 iterations,
@@ -330,6 +330,8 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
             u0 = jacobi_field(n, seed=5)
             res = {}
             for variant, copy in (("non_copy", False), ("copy", True)):
+                if variant not in jacobi_variants:
+                    continue
                 per = {}
                 extra = [(f"skewed_rows{t}", tc.TC_TILING_SKEWED, (0, t, 0)) for t in jacobi_skew_rows]
                 if jacobi_two_columns:
@@ -339,6 +341,8 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
                     extra.append(("fused_2col_regs240", tc.TC_TILING_FUSED, (0, 240, 0)))
                     extra.append(("auto", tc.TC_TILING_AUTO, (0, 0, 0)))
                 for name, m, tile in modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))] + extra:
+                    if jacobi_select and name not in jacobi_select:
+                        continue
                     saved = os.environ.get("TC_JIT_CPL")
                     if name == "fused_2col_regs240":
                         os.environ["TC_JIT_CPL"] = "2"
@@ -364,10 +368,11 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
                         per[name].update({"tuned": settled, "chosen_mode": st["last_mode"],
                                           "chosen_tile": st["last_tile"], "chosen_columns_per_lane": st["last_cpl"]})
                 fused_names = [k for k in per if k.startswith("fused")]
-                best_fused = min(fused_names, key=lambda k: per[k]["seconds_per_run"])
-                per["fused_best_layout"] = best_fused
-                per["fused_speedup_vs_untiled"] = (per["none"]["seconds_per_run"] /
-                                                   per[best_fused]["seconds_per_run"])
+                if fused_names and "none" in per:
+                    best_fused = min(fused_names, key=lambda k: per[k]["seconds_per_run"])
+                    per["fused_best_layout"] = best_fused
+                    per["fused_speedup_vs_untiled"] = (per["none"]["seconds_per_run"] /
+                                                       per[best_fused]["seconds_per_run"])
                 res[variant] = per
                 log(f"jacobi {n}^2 {variant}: {per}")
             out[f"jacobi_{n}"] = {
@@ -540,6 +545,10 @@ def main():
                     help="extra skewed Jacobi runs with these tile heights in rows, comma list (a tile-height study)")
     ap.add_argument("--jacobi-one-layout", action="store_true",
                     help="time the fused Jacobi in its default layout only (no two-column layout, no autotuner)")
+    ap.add_argument("--jacobi-select", default="",
+                    help="Jacobi modes to time, comma list of none, skewed, fused, fused_2col_regs240, auto "
+                         "(default: all)")
+    ap.add_argument("--jacobi-variants", default="non_copy,copy", help="Jacobi variants to time: non_copy, copy")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -615,7 +624,9 @@ def main():
                 "kernel": kname, "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": alg}
     others = (other_workloads(tc, args.other.split(","), 10, [int(v) for v in args.jacobi_n.split(",")],
                               [int(v) for v in args.jacobi_skew_rows.split(",") if v], not args.jacobi_one_layout,
-                              [int(v) for v in args.tealeaf_n.split(",")])
+                              [int(v) for v in args.tealeaf_n.split(",")],
+                              [v for v in args.jacobi_select.split(",") if v] or None,
+                              tuple(v for v in args.jacobi_variants.split(",") if v))
               if args.other else None)
     batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
     served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None
