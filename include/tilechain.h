@@ -58,10 +58,16 @@ typedef int32_t tc_dat;
 typedef int32_t tc_stencil;
 typedef int32_t tc_red;
 
-typedef enum { TC_F64 = 0, TC_F32 = 1 } tc_dtype;
-typedef enum { TC_READ = 0, TC_WRITE = 1, TC_RW = 2, TC_INC = 3 } tc_access;
-typedef enum { TC_ARG_DAT = 0, TC_ARG_RED = 1 } tc_argkind;
-typedef enum { TC_RED_SUM = 0, TC_RED_MIN = 1, TC_RED_MAX = 2 } tc_redop;
+/* Every enum below also holds TC_ENUM_MIN_ and TC_ENUM_MAX_, which name no
+ * value: they give the type the whole int32 range, so a caller may pass any
+ * int32 (calls reject values outside the listed ones with TC_ERR_ARG). */
+#define TC_ENUM_MIN_ (-0x7fffffff - 1)
+#define TC_ENUM_MAX_ 0x7fffffff
+
+typedef enum { TC_F64 = 0, TC_F32 = 1, TC_DTYPE_MIN_ = TC_ENUM_MIN_, TC_DTYPE_MAX_ = TC_ENUM_MAX_ } tc_dtype;
+typedef enum { TC_READ = 0, TC_WRITE = 1, TC_RW = 2, TC_INC = 3, TC_ACCESS_MIN_ = TC_ENUM_MIN_, TC_ACCESS_MAX_ = TC_ENUM_MAX_ } tc_access;
+typedef enum { TC_ARG_DAT = 0, TC_ARG_RED = 1, TC_ARGKIND_MIN_ = TC_ENUM_MIN_, TC_ARGKIND_MAX_ = TC_ENUM_MAX_ } tc_argkind;
+typedef enum { TC_RED_SUM = 0, TC_RED_MIN = 1, TC_RED_MAX = 2, TC_REDOP_MIN_ = TC_ENUM_MIN_, TC_REDOP_MAX_ = TC_ENUM_MAX_ } tc_redop;
 
 /* Tiling of a flushed chain.
  *   NONE       : every loop runs over its whole range, one kernel per loop.
@@ -72,7 +78,14 @@ typedef enum { TC_RED_SUM = 0, TC_RED_MIN = 1, TC_RED_MAX = 2 } tc_redop;
  *                working set in LDS; one kernel per fusion group.
  *   AUTO       : the autotuner measures the candidates once per chain
  *                structure and keeps the fastest. */
-typedef enum { TC_TILING_NONE = 0, TC_TILING_SKEWED = 1, TC_TILING_FUSED = 2, TC_TILING_AUTO = 3 } tc_tiling;
+typedef enum {
+    TC_TILING_NONE = 0,
+    TC_TILING_SKEWED = 1,
+    TC_TILING_FUSED = 2,
+    TC_TILING_AUTO = 3,
+    TC_TILING_MIN_ = TC_ENUM_MIN_,
+    TC_TILING_MAX_ = TC_ENUM_MAX_
+} tc_tiling;
 
 /* Point operations (closed vocabulary).  Argument lists are positional; the
  * accesses and stencils given at tc_par_loop must match the signature.
@@ -134,7 +147,9 @@ typedef enum {
     TC_OP_TEA_GERSH = 19,
     TC_OP_EULER_PRIM = 20,
     TC_OP_EULER_RHS = 21,
-    TC_OP_RK_STAGE = 22
+    TC_OP_RK_STAGE = 22,
+    TC_OP_MIN_ = TC_ENUM_MIN_,
+    TC_OP_MAX_ = TC_ENUM_MAX_
 } tc_op;
 
 /* One loop argument: a dataset through a stencil with an access mode, or a

@@ -66,8 +66,8 @@ struct Dataset {
     }
     int64_t sy() const { return pitch; }
     int64_t sz() const { return pitch * ny_alloc; }
-    void *origin(int which) const {
-        return (char *)buf[which] + origin_offset() * (int64_t)esize();
+    void *origin(int which) const {  // NULL while the buffer does not exist (host-only contexts)
+        return buf[which] ? (char *)buf[which] + origin_offset() * (int64_t)esize() : nullptr;
     }
 };
 
