@@ -869,6 +869,7 @@ static tc_status impl_tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (const char *e = getenv("TC_JIT_FENCE")) c.jit_sched_fence = atoi(e) != 0;
     if (const char *e = getenv("TC_JIT_ALIGN")) c.jit_align_store = atoi(e) != 0;
     if (const char *e = getenv("TC_STAGED")) c.staged_mode = std::min(2, std::max(0, atoi(e)));
+    if (const char *e = getenv("TC_CHEB")) c.cheb_enabled = atoi(e) != 0;
     if (const char *e = getenv("TC_STAGED_THREADS")) {
         const int v = atoi(e);
         if (v == 256 || v == 1024) c.staged_threads = v;
@@ -1323,8 +1324,8 @@ static tc_status impl_tc_chain_plan(tc_ctx *ctx, tc_tiling mode, const int32_t *
             for (int k = 1; k < 7; ++k) per[7 * l + k] = 0;
         }
         for (const auto &g : groups) {
-            if (g->estage) {
-                for (int l = g->g0; l < g->g1; ++l) per[7 * l] = 3;
+            if (g->estage || g->cheb) {
+                for (int l = g->g0; l < g->g1; ++l) per[7 * l] = g->estage ? 3 : 4;
                 continue;
             }
             if (g->staged) {

@@ -942,6 +942,84 @@ bool euler_stage_match_copy(const Ctx &c, const std::vector<LoopRec> &chain, int
     return true;
 }
 
+namespace {
+
+// One reflective ghost fill of dataset d along axis `axis`, side `side`,
+// depth h, as the 2D heat-conduction chains record them.
+bool is_fill(const Ctx &c, const LoopRec &lp, int d, int axis, int side, int h, const int n[2]) {
+    if (lp.op != TC_OP_HALO_REFLECT || lp.ndim != 2 || lp.args.size() != 1 || lp.params.size() != 3) return false;
+    if (lp.args[0].kind != TC_ARG_DAT || lp.args[0].handle != d) return false;
+    if ((int)lp.params[0] != axis || (int)lp.params[1] != side || (int)lp.params[2] != n[axis] ||
+        lp.params[0] != (double)axis || lp.params[1] != (double)side || lp.params[2] != (double)n[axis])
+        return false;
+    const int a = axis, o = 1 - axis;
+    const int lo_a = side == 0 ? -h : n[a], hi_a = side == 0 ? 0 : n[a] + h;
+    // x fills cover the interior rows, y fills every column (the ghosts too)
+    const int lo_o = axis == 0 ? 0 : -h, hi_o = axis == 0 ? n[o] : n[o] + h;
+    return lp.lo[a] == lo_a && lp.hi[a] == hi_a && lp.lo[o] == lo_o && lp.hi[o] == hi_o;
+}
+
+bool interior_2d(const LoopRec &lp, const int n[2]) {
+    return lp.ndim == 2 && lp.lo[0] == 0 && lp.hi[0] == n[0] && lp.lo[1] == 0 && lp.hi[1] == n[1];
+}
+
+}  // namespace
+
+int cheb_match(const Ctx &c, const std::vector<LoopRec> &chain, int i, ChebGroup &C) {
+    const int L = (int)chain.size();
+    C = ChebGroup();
+    // the first step's TEA_P1 names the datasets
+    if (i + 5 > L) return 0;
+    const LoopRec &p1 = chain[i + 4];
+    if (p1.op != TC_OP_TEA_P1 || p1.ndim != 2 || p1.args.size() != 5 || !p1.params.empty()) return 0;
+    for (const auto &a : p1.args)
+        if (a.kind != TC_ARG_DAT) return 0;
+    C.kx = p1.args[0].handle;
+    C.ky = p1.args[1].handle;
+    C.sd = p1.args[2].handle;
+    C.rt = p1.args[3].handle;
+    C.z = p1.args[4].handle;
+    const int ds[5] = {C.kx, C.ky, C.sd, C.rt, C.z};
+    for (int a = 0; a < 5; ++a)
+        for (int b = a + 1; b < 5; ++b)
+            if (ds[a] == ds[b]) return 0;
+    const Dataset &S = c.dats[C.sd];
+    for (int a = 0; a < 5; ++a)
+        if (c.dats[ds[a]].dtype != S.dtype || c.dats[ds[a]].block != S.block) return 0;
+    C.n[0] = S.size[0];
+    C.n[1] = S.size[1];
+    if (!interior_2d(p1, C.n)) return 0;
+    const LoopRec &f0 = chain[i];
+    if (f0.op != TC_OP_HALO_REFLECT || f0.ndim != 2) return 0;
+    C.h = -f0.lo[0];
+    if (C.h < 1 || C.h > kChebMaxSteps || C.h > S.hneg[0] || C.h > S.hneg[1] || C.h > S.hpos[0] ||
+        C.h > S.hpos[1] || C.n[0] < 2 * C.h || C.n[1] < 2 * C.h)
+        return 0;
+    int l = i;
+    while (C.steps < kChebMaxSteps && l + 5 <= L) {
+        bool ok = is_fill(c, chain[l], C.sd, 0, 0, C.h, C.n) && is_fill(c, chain[l + 1], C.sd, 0, 1, C.h, C.n) &&
+                  is_fill(c, chain[l + 2], C.sd, 1, 0, C.h, C.n) && is_fill(c, chain[l + 3], C.sd, 1, 1, C.h, C.n);
+        const LoopRec &q = chain[l + 4];
+        ok = ok && q.op == TC_OP_TEA_P1 && q.args.size() == 5 && interior_2d(q, C.n);
+        for (int a = 0; ok && a < 5; ++a) ok = q.args[a].kind == TC_ARG_DAT && q.args[a].handle == ds[a];
+        if (!ok) break;
+        l += 5;
+        ++C.steps;
+        const bool p2 = l < L && chain[l].op == TC_OP_TEA_P2 && chain[l].args.size() == 2 &&
+                        interior_2d(chain[l], C.n) && chain[l].args[0].kind == TC_ARG_DAT &&
+                        chain[l].args[0].handle == C.sd && chain[l].args[1].kind == TC_ARG_DAT &&
+                        chain[l].args[1].handle == C.rt && chain[l].params.size() == 2;
+        if (!p2) {
+            C.last_p2 = false;
+            C.p2_loop.push_back(-1);
+            break;
+        }
+        C.p2_loop.push_back(l);
+        ++l;
+    }
+    return C.steps > 0 ? l - i : 0;
+}
+
 bool fused_op_supported(const LoopRec &lp) { return lp.op == TC_OP_WSUM && lp.ndim == 2; }
 
 std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<LoopRec> &chain, const int tile[3],
@@ -971,6 +1049,34 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
         std::vector<int> from(L + 1, -1);
         std::vector<std::shared_ptr<FusedGroup>> piece(L + 1);
         best[0] = 0.0;
+        // runs of 2D Chebyshev steps: every whole-step prefix of the longest
+        // run from each loop, by the group's end
+        std::vector<std::vector<std::shared_ptr<FusedGroup>>> cheb_end(L + 1);
+        for (int i = 0; i < L; ++i) {
+            ChebGroup C;
+            if (!c.cheb_enabled || chain[i].op != TC_OP_HALO_REFLECT || cheb_match(c, chain, i, C) == 0) continue;
+            for (int m = 1; m <= C.steps; ++m) {
+                auto P = std::make_shared<ChebGroup>(C);
+                P->steps = m;
+                P->last_p2 = C.p2_loop[m - 1] >= 0;
+                P->p2_loop.resize(m);
+                const int len = 5 * m + (P->last_p2 ? m : m - 1);
+                // bytes: face coefficients, rt and sd over the region of a
+                // tile (H = 3 or 5 cells around 64 x 16), z over the owned
+                // cells; rt, z and sd written once
+                const int H = m <= 3 ? 3 : 5;
+                const double f = (double)(kChebTX + 2 * H) * (kChebTY + 2 * H) / ((double)kChebTX * kChebTY);
+                const double cells = (double)C.n[0] * C.n[1];
+                const double bytes = cells * c.dats[C.sd].esize() * (4.0 * f + 1.0 + 3.0);
+                auto G = std::make_shared<FusedGroup>();
+                G->g0 = i;
+                G->g1 = i + len;
+                G->cost = bytes / 4.5e12 + 6e-6;
+                G->alg_bytes = (int64_t)(cells * c.dats[C.sd].esize() * 8.0);
+                G->cheb = P;
+                cheb_end[i + len].push_back(G);
+            }
+        }
         for (int j = 1; j <= L; ++j) {
             const double s = best[j - 1] + single_loop_cost(c, chain[j - 1]);
             if (s < best[j]) {
@@ -978,6 +1084,12 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                 from[j] = j - 1;
                 piece[j] = nullptr;
             }
+            for (const auto &G : cheb_end[j])
+                if (best[G->g0] + G->cost < best[j]) {
+                    best[j] = best[G->g0] + G->cost;
+                    from[j] = G->g0;
+                    piece[j] = G;
+                }
             // a 3D Runge-Kutta stage ending here (with its primitive-variable
             // loop when their values die in the chain, and the step's copies
             // Q0 = Q before it): one z-marching kernel
@@ -1076,6 +1188,11 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                 std::fprintf(stderr, "Runge-Kutta stage group [%d,%d): cost %.1f us\n", g->g0, g->g1, g->cost * 1e6);
                 continue;
             }
+            if (g->cheb) {
+                std::fprintf(stderr, "Chebyshev group [%d,%d): %d steps%s, cost %.1f us\n", g->g0, g->g1,
+                             g->cheb->steps, g->cheb->last_p2 ? "" : " (last without P2)", g->cost * 1e6);
+                continue;
+            }
             if (g->staged) {
                 const StagedGroup &S = *g->staged;
                 std::fprintf(stderr,
@@ -1101,7 +1218,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
 tc_status fused_compile(Ctx &c, const std::vector<LoopRec> &chain, std::vector<std::shared_ptr<FusedGroup>> &all) {
     std::vector<std::shared_ptr<FusedGroup>> groups;
     for (auto &g : all) {
-        if (g->estage) continue;  // a precompiled kernel
+        if (g->estage || g->cheb) continue;  // a precompiled kernel
         if (!g->staged) {
             groups.push_back(g);
             continue;
@@ -1271,9 +1388,53 @@ tc_status euler_stage_run(Ctx &c, const std::vector<LoopRec> &chain, const Fused
     return TC_OK;
 }
 
+tc_status cheb_run(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &G) {
+    const ChebGroup &C = *G.cheb;
+    if (C.steps > kChebMaxSteps) return fail(c, TC_ERR_STATE, "Chebyshev group of %d steps", C.steps);
+    ChebArgs a;
+    std::memset(&a, 0, sizeof a);
+    const Dataset &kx = c.dats[C.kx], &ky = c.dats[C.ky];
+    a.kx = kx.origin(kx.cur);
+    a.skx = kx.sy();
+    a.ky = ky.origin(ky.cur);
+    a.sky = ky.sy();
+    Dataset &sd = c.dats[C.sd], &rt = c.dats[C.rt], &z = c.dats[C.z];
+    a.sd_in = sd.origin(sd.cur);
+    a.ssd_in = sd.sy();
+    a.rt_in = rt.origin(rt.cur);
+    a.srt_in = rt.sy();
+    a.z = z.origin(z.cur);
+    a.sz = z.sy();
+    // sd is written over the interior and its ghosts, rt over the interior
+    const int slo[3] = {-C.h, -C.h, 0}, shi[3] = {C.n[0] + C.h, C.n[1] + C.h, 1};
+    const int rlo[3] = {0, 0, 0}, rhi[3] = {C.n[0], C.n[1], 1};
+    tc_status st = second_buffer(c, sd, slo, shi, &a.sd_out);
+    if (st != TC_OK) return st;
+    st = second_buffer(c, rt, rlo, rhi, &a.rt_out);
+    if (st != TC_OK) return st;
+    a.ssd_out = sd.sy();
+    a.srt_out = rt.sy();
+    for (int j = 0; j < C.steps; ++j)
+        if (C.p2_loop[j] >= 0) {
+            a.al[j] = chain[C.p2_loop[j]].params[0];
+            a.be[j] = chain[C.p2_loop[j]].params[1];
+        }
+    a.n0 = C.n[0];
+    a.n1 = C.n[1];
+    a.h = C.h;
+    a.steps = C.steps;
+    a.last_p2 = C.last_p2 ? 1 : 0;
+    const hipError_t e = launch_cheb2(a, sd.dtype, c.stream);
+    if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "Chebyshev group launch failed: %s", hipGetErrorString(e));
+    sd.cur ^= 1;
+    rt.cur ^= 1;
+    return TC_OK;
+}
+
 tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
     if (G.staged) return staged_run(c, chain, *G.staged);
     if (G.estage) return euler_stage_run(c, chain, G);
+    if (G.cheb) return cheb_run(c, chain, G);
     if (G.baked) {
         // kernels with the weights compiled in serve only the weights they
         // were generated for; on a change the group falls back for good to
@@ -1362,6 +1523,16 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
 
 tc_status fused_check_noalloc(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &G) {
     if (G.staged) return staged_check_noalloc(c, *G.staged);
+    if (G.cheb) {
+        for (int d : {G.cheb->sd, G.cheb->rt}) {
+            const Dataset &ds = c.dats[d];
+            if (!ds.raw[0] || !ds.raw[1])
+                return fail(c, TC_ERR_STATE,
+                            "the second buffer of %s does not exist yet and a call that allocates nothing cannot "
+                            "create it; flush this chain once with tc_flush first", ds.name.c_str());
+        }
+        return TC_OK;
+    }
     if (G.estage) {
         for (int k = 0; k < 5; ++k) {
             const Dataset &ds = c.dats[G.estage->q[k]];

@@ -122,6 +122,9 @@ struct FusedGroup {
     // set for a 3D Runge-Kutta stage (EULER_RHS for the five components,
     // then RK_STAGE for the five): one z-marching kernel (euler.hip)
     std::shared_ptr<struct EulerStage> estage;
+    // set for a run of 2D Chebyshev steps of the heat-conduction
+    // preconditioner: one launch of cheb.hip
+    std::shared_ptr<struct ChebGroup> cheb;
 };
 
 struct EulerStage {
@@ -131,6 +134,22 @@ struct EulerStage {
     bool copy0 = false;              // the group starts with the five copies Q0_c = Q_c
     int lo[3], hi[3];
 };
+
+// A run of Chebyshev steps on a 2D grid: per step the four reflective ghost
+// fills of sd (x sides over the interior rows, then y sides over all
+// columns, depth h), TEA_P1 (kx, ky, sd, rt, z) over the interior [0, n) and
+// TEA_P2 (sd, rt) over it; the last step may end after TEA_P1.
+struct ChebGroup {
+    int kx, ky, sd, rt, z;  // datasets
+    int steps = 0;
+    bool last_p2 = true;
+    int n[2] = {0, 0}, h = 0;
+    std::vector<int> p2_loop;  // chain index of each step's TEA_P2 (-1: none)
+};
+// The longest run of such steps starting at loop i (at most kChebMaxSteps
+// steps): fills C and returns the number of loops, else 0.  Every prefix of
+// whole steps is a run too.
+int cheb_match(const Ctx &c, const std::vector<LoopRec> &chain, int i, ChebGroup &C);
 
 // Loops [i, i + 10) as a 3D Runge-Kutta stage (the five right-hand sides,
 // then the five updates over one range, sharing Q, the velocities and the

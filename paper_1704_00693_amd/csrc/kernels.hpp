@@ -57,6 +57,28 @@ struct EulerStageArgs {
 };
 hipError_t launch_euler_stage3(const EulerStageArgs &a, int dtype, hipStream_t s);
 
+// Chebyshev steps of the heat-conduction preconditioner on a 2D grid, fused
+// (cheb.hip): `steps` repetitions of [reflective ghost fill of sd to depth h,
+// TEA_P1, TEA_P2], the last TEA_P2 left out when last_p2 is 0.  A workgroup
+// owns kChebTX x kChebTY cells and recomputes `steps` cells around them.
+// Arrays by logical origin and row stride: kx, ky read; sd and rt read from
+// *_in and written to *_out (other workgroups still read the old values);
+// z read and written in place (only ever read at its own cell).  The ghost
+// cells of sd are written as the last step's fill leaves them.
+constexpr int kChebMaxSteps = 5;
+constexpr int kChebTX = 64, kChebTY = 16;
+struct ChebArgs {
+    const void *kx, *ky, *sd_in, *rt_in;
+    void *sd_out, *rt_out, *z;
+    int64_t skx, sky, ssd_in, srt_in, ssd_out, srt_out, sz;  // row strides (elements)
+    double al[kChebMaxSteps], be[kChebMaxSteps];
+    int n0, n1;            // interior extent along x and y
+    int h;                 // ghost depth of the fills
+    int steps, last_p2;
+    int ntx, nty;          // set by the launcher
+};
+hipError_t launch_cheb2(const ChebArgs &a, int dtype, hipStream_t s);
+
 // Combine the (hi, lo) partials of n reductions, one workgroup each, in a
 // fixed order: reduction r's count[r] pairs start at part + 2 * base[r] and
 // its result goes to out[2r], out[2r+1].  base, count, op: host arrays.

@@ -267,6 +267,7 @@ struct Ctx {
     // accepts whatever the cost model says, TC_STAGED_TILE=x,y,z fixes the
     // owned box
     int staged_mode = 1;
+    bool cheb_enabled = true;  // TC_CHEB=0: no fused Chebyshev-step groups
     int staged_threads = 0;  // TC_STAGED_THREADS=256|1024: workgroup size of staged tiles (0: by box size)
     int staged_tile[3] = {0, 0, 0};
     std::vector<void *> staged_allocs;  // device tables of staged groups (freed at finalize)

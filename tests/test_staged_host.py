@@ -108,7 +108,9 @@ def test_staged_tiles_pass_stamps(ndim, monkeypatch):
     assert groups_checked >= 10
 
 
-def test_ppcg_chain_is_one_staged_group():
+def test_ppcg_chain_is_one_staged_group(monkeypatch):
+    # without the dedicated Chebyshev-step groups
+    monkeypatch.setenv("TC_CHEB", "0")
     from paper_1704_00693_amd.apps import HeatSolver, chebyshev_coefs
     n = 256
     with tc.Context(host_only=True) as c:
@@ -132,3 +134,56 @@ def test_ppcg_chain_is_one_staged_group():
     # the last preconditioner step and the dot products: the owned box only
     assert per[-1][1:5] == (0, 0, 0, 0) and per[-3][1:5] == (0, 0, 0, 0)
     assert tiles and (g0, g1) == groups[0]
+
+
+@pytest.mark.parametrize("inner", [1, 3, 4, 10, 12])
+def test_ppcg_chebyshev_steps_become_chebyshev_groups(inner):
+    """The preconditioner's Chebyshev steps (four ghost fills of sd, TEA_P1,
+    TEA_P2) form runs of at most five steps, each one Chebyshev group (plan
+    code 4); the last step, without TEA_P2, ends the last group; the set-up,
+    the update and the dot products around them run on their own.  A fill
+    of another depth breaks the run."""
+    from paper_1704_00693_amd.apps import HeatSolver, chebyshev_coefs
+    n = 256
+    with tc.Context(host_only=True) as c:
+        hs = HeatSolver(c, np.full((n, n), 0.5), np.full((n, n), 1.5))
+        theta, delta, al, be = chebyshev_coefs(1.0, 100.0, inner)
+        hs.loop("TEA_CG_UPDATE", [hs.F("u", "RW"), hs.F("r", "RW"), hs.F("p", "R"), hs.F("w", "R")], [0.3])
+        hs.precondition(theta, al, be, inner)
+        hs.dot("r", "z", hs.r_sum[1])
+        hs.dot("r", "r", hs.r_sum[2])
+        L = c.tc_pending()
+        groups, per = c.tc_fused_plan()
+    # the steps occupy loops [2, L - 2): 6 loops each, the last one 5
+    assert 2 + 6 * inner - 1 == L - 2
+    assert len(groups) == (inner + 4) // 5
+    assert groups[0][0] == 2 and groups[-1][1] == L - 2
+    for (a0, a1), (b0, b1) in zip(groups, groups[1:]):
+        assert a1 == b0
+    for g0, g1 in groups[:-1]:
+        assert (g1 - g0) % 6 == 0 and (g1 - g0) // 6 <= 5
+    assert (groups[-1][1] - groups[-1][0] + 1) % 6 == 0 and (groups[-1][1] - groups[-1][0] + 1) // 6 <= 5
+    for g0, g1 in groups:
+        assert all(per[i][0] == 4 for i in range(g0, g1))
+    assert [p[0] for p in per[:2]] == [-1, -1] and [p[0] for p in per[-2:]] == [-1, -1]
+
+
+def test_chebyshev_run_needs_the_recorded_fill_pattern():
+    from paper_1704_00693_amd.apps import HeatSolver, chebyshev_coefs
+    n = 64
+    with tc.Context(host_only=True) as c:
+        hs = HeatSolver(c, np.full((n, n), 0.5), np.full((n, n), 1.5))
+        theta, delta, al, be = chebyshev_coefs(1.0, 100.0, 3)
+        hs.loop("TEA_PRECON_INIT", [hs.F("r", "R"), hs.F("rt", "W"), hs.F("sd", "W"), hs.F("z", "W")], [theta])
+        hs.halo_fill("sd")
+        hs.loop("TEA_P1", hs.K() + [hs.F("sd", "R", hs.S_star), hs.F("rt", "RW"), hs.F("z", "RW")])
+        hs.loop("TEA_P2", [hs.F("sd", "RW"), hs.F("rt", "R")], [al[0], be[0]])
+        # the second step fills only three sides: no run through it
+        for axis, side in ((0, 0), (0, 1), (1, 0)):
+            rng = [-2, 0, 0, n] if (axis, side) == (0, 0) else [n, n + 2, 0, n] if axis == 0 else [-2, n + 2, -2, 0]
+            c.tc_par_loop("HALO_REFLECT", hs.blk, rng, [(hs.f["sd"], hs.S_reflect[(axis, side)], "RW")],
+                          [axis, side, n])
+        hs.loop("TEA_P1", hs.K() + [hs.F("sd", "R", hs.S_star), hs.F("rt", "RW"), hs.F("z", "RW")])
+        groups, per = c.tc_fused_plan()
+    assert (1, 7) in groups
+    assert all(per[i][0] != 4 for i in range(7, len(per)))
