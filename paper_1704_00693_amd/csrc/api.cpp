@@ -870,6 +870,7 @@ static tc_status impl_tc_init(const tc_init_opts *opts, tc_ctx **out) {
     if (const char *e = getenv("TC_JIT_ALIGN")) c.jit_align_store = atoi(e) != 0;
     if (const char *e = getenv("TC_STAGED")) c.staged_mode = std::min(2, std::max(0, atoi(e)));
     if (const char *e = getenv("TC_CHEB")) c.cheb_enabled = atoi(e) != 0;
+    if (const char *e = getenv("TC_CHEB_STEPS")) c.cheb_steps = std::min(kChebMaxSteps, std::max(1, atoi(e)));
     if (const char *e = getenv("TC_STAGED_THREADS")) {
         const int v = atoi(e);
         if (v == 256 || v == 1024) c.staged_threads = v;

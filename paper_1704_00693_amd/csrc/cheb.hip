@@ -36,6 +36,10 @@ __device__ __forceinline__ float fmaC<float>(float a, float b, float c) {
     return __builtin_fmaf(a, b, c);
 }
 
+// Per-cell flags: inside the domain, owned, and which of the east, west,
+// north and south neighbours are other region cells (else the cell itself).
+enum : unsigned { kAct = 1, kOwn = 2, kE = 4, kW = 8, kN = 16, kS = 32 };
+
 template <typename T, int H>
 __global__ void __launch_bounds__(256) cheb2_kernel(ChebArgs a) {
     constexpr int RW = kChebTX + 2 * H, RH = kChebTY + 2 * H, RC = RW * RH;
@@ -49,29 +53,30 @@ __global__ void __launch_bounds__(256) cheb2_kernel(ChebArgs a) {
     T *zp = (T *)a.z;
     const int n0 = a.n0, n1 = a.n1;
     T ke[PER], kw[PER], kn[PER], ks[PER], rt[PER], z[PER];
-    int oe[PER], ow[PER], on[PER], os[PER], cx[PER], cy[PER];
-    bool act[PER], own[PER];
+    unsigned fl[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int i = (int)threadIdx.x + 256 * k;
         const int lx = i % RW, ly = i / RW;
         const int x = rx0 + lx, y = ry0 + ly;
-        cx[k] = x;
-        cy[k] = y;
-        act[k] = i < RC && x >= 0 && x < n0 && y >= 0 && y < n1;
-        own[k] = act[k] && lx >= H && lx < H + kChebTX && ly >= H && ly < H + kChebTY;
-        oe[k] = (x + 1 < n0 && lx + 1 < RW) ? 1 : 0;
-        ow[k] = (x > 0 && lx > 0) ? -1 : 0;
-        on[k] = (y + 1 < n1 && ly + 1 < RH) ? RW : 0;
-        os[k] = (y > 0 && ly > 0) ? -RW : 0;
+        unsigned f = 0;
+        if (i < RC && x >= 0 && x < n0 && y >= 0 && y < n1) {
+            f |= kAct;
+            if (lx >= H && lx < H + kChebTX && ly >= H && ly < H + kChebTY) f |= kOwn;
+            if (x + 1 < n0 && lx + 1 < RW) f |= kE;
+            if (x > 0 && lx > 0) f |= kW;
+            if (y + 1 < n1 && ly + 1 < RH) f |= kN;
+            if (y > 0 && ly > 0) f |= kS;
+        }
+        fl[k] = f;
         z[k] = (T)0;
-        if (act[k]) {
+        if (f & kAct) {
             ke[k] = kx[(x + 1) + (int64_t)y * a.skx];
             kw[k] = kx[x + (int64_t)y * a.skx];
             kn[k] = ky[x + (int64_t)(y + 1) * a.sky];
             ks[k] = ky[x + (int64_t)y * a.sky];
             rt[k] = rti[x + (int64_t)y * a.srt_in];
-            if (own[k]) z[k] = zp[x + (int64_t)y * a.sz];
+            if (f & kOwn) z[k] = zp[x + (int64_t)y * a.sz];
             v[0][i] = sd[x + (int64_t)y * a.ssd_in];
         }
     }
@@ -89,13 +94,14 @@ __global__ void __launch_bounds__(256) cheb2_kernel(ChebArgs a) {
             // mirror cell (x: -1 - g or 2 n - 1 - g, y alike)
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
-                if (!own[k]) continue;
-                const int x = cx[k], y = cy[k];
+                if (!(fl[k] & kOwn)) continue;
+                const int i = (int)threadIdx.x + 256 * k;
+                const int x = rx0 + i % RW, y = ry0 + i / RW;
                 const bool xl = x < h, xr = x >= n0 - h, yl = y < h, yr = y >= n1 - h;
                 if (!(xl || xr || yl || yr)) continue;
-                const T val = vv[(int)threadIdx.x + 256 * k];
-                const int gx[3] = {x, xl ? -1 - x : 2 * n0 - 1 - x, 0};
-                const int gy[3] = {y, yl ? -1 - y : 2 * n1 - 1 - y, 0};
+                const T val = vv[i];
+                const int gx[2] = {x, xl ? -1 - x : 2 * n0 - 1 - x};
+                const int gy[2] = {y, yl ? -1 - y : 2 * n1 - 1 - y};
                 const int nx = (xl || xr) ? 2 : 1, ny = (yl || yr) ? 2 : 1;
                 for (int b = 0; b < ny; ++b)
                     for (int c = 0; c < nx; ++c)
@@ -104,7 +110,8 @@ __global__ void __launch_bounds__(256) cheb2_kernel(ChebArgs a) {
         }
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            if (!act[k]) continue;
+            const unsigned f = fl[k];
+            if (!(f & kAct)) continue;
             const int i = (int)threadIdx.x + 256 * k;
             T diag = (T)1 + ke[k];
             diag = diag + kw[k];
@@ -112,13 +119,13 @@ __global__ void __launch_bounds__(256) cheb2_kernel(ChebArgs a) {
             diag = diag + ks[k];
             const T vc = vv[i];
             T av = diag * vc;
-            av = fmaC<T>(-ke[k], vv[i + oe[k]], av);
-            av = fmaC<T>(-kw[k], vv[i + ow[k]], av);
-            av = fmaC<T>(-kn[k], vv[i + on[k]], av);
-            av = fmaC<T>(-ks[k], vv[i + os[k]], av);
+            av = fmaC<T>(-ke[k], vv[(f & kE) ? i + 1 : i], av);
+            av = fmaC<T>(-kw[k], vv[(f & kW) ? i - 1 : i], av);
+            av = fmaC<T>(-kn[k], vv[(f & kN) ? i + RW : i], av);
+            av = fmaC<T>(-ks[k], vv[(f & kS) ? i - RW : i], av);
             const T rtv = rt[k] - av;
             rt[k] = rtv;
-            if (own[k]) z[k] = z[k] + vc;
+            if (f & kOwn) z[k] = z[k] + vc;
             if (p2) vn[i] = fmaC<T>(al, vc, be * rtv);
         }
         __syncthreads();
@@ -127,11 +134,12 @@ __global__ void __launch_bounds__(256) cheb2_kernel(ChebArgs a) {
     T *rto = (T *)a.rt_out;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        if (!own[k]) continue;
-        const int64_t x = cx[k], y = cy[k];
+        if (!(fl[k] & kOwn)) continue;
+        const int i = (int)threadIdx.x + 256 * k;
+        const int64_t x = rx0 + i % RW, y = ry0 + i / RW;
         rto[x + y * a.srt_out] = rt[k];
         zp[x + y * a.sz] = z[k];
-        sdo[x + y * a.ssd_out] = v[buf][(int)threadIdx.x + 256 * k];
+        sdo[x + y * a.ssd_out] = v[buf][i];
     }
 }
 
@@ -146,13 +154,21 @@ hipError_t go_cheb2(const ChebArgs &in, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t cheb2_t(const ChebArgs &a, hipStream_t s) {
+    switch (cheb_halo(a.steps)) {
+    case 3: return go_cheb2<T, 3>(a, s);
+    case 5: return go_cheb2<T, 5>(a, s);
+    case 7: return go_cheb2<T, 7>(a, s);
+    default: return go_cheb2<T, 9>(a, s);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_cheb2(const ChebArgs &a, int dtype, hipStream_t s) {
     if (a.steps < 1 || a.steps > kChebMaxSteps || a.h < 1 || a.h > kChebMaxSteps) return hipErrorInvalidValue;
-    if (a.steps <= 3)
-        return dtype == TC_F64 ? go_cheb2<double, 3>(a, s) : go_cheb2<float, 3>(a, s);
-    return dtype == TC_F64 ? go_cheb2<double, 5>(a, s) : go_cheb2<float, 5>(a, s);
+    return dtype == TC_F64 ? cheb2_t<double>(a, s) : cheb2_t<float>(a, s);
 }
 
 }  // namespace tc

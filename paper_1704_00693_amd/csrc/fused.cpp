@@ -1055,7 +1055,12 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
         for (int i = 0; i < L; ++i) {
             ChebGroup C;
             if (!c.cheb_enabled || chain[i].op != TC_OP_HALO_REFLECT || cheb_match(c, chain, i, C) == 0) continue;
+            // at most five steps unless asked: measured on the PPCG solve at
+            // 2000^2 (ms per solve) 3 steps 29.3, 4 28.4, 5 24.3, 7 34.1,
+            // 9 39.4 (the wider recomputed borders and their registers cost
+            // more than the traffic they save)
             for (int m = 1; m <= C.steps; ++m) {
+                if (c.cheb_steps > 0 ? m != std::min(C.steps, c.cheb_steps) : m > 5) continue;
                 auto P = std::make_shared<ChebGroup>(C);
                 P->steps = m;
                 P->last_p2 = C.p2_loop[m - 1] >= 0;
@@ -1064,7 +1069,7 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                 // bytes: face coefficients, rt and sd over the region of a
                 // tile (H = 3 or 5 cells around 64 x 16), z over the owned
                 // cells; rt, z and sd written once
-                const int H = m <= 3 ? 3 : 5;
+                const int H = cheb_halo(m);
                 const double f = (double)(kChebTX + 2 * H) * (kChebTY + 2 * H) / ((double)kChebTX * kChebTY);
                 const double cells = (double)C.n[0] * C.n[1];
                 const double bytes = cells * c.dats[C.sd].esize() * (4.0 * f + 1.0 + 3.0);

@@ -65,7 +65,7 @@ hipError_t launch_euler_stage3(const EulerStageArgs &a, int dtype, hipStream_t s
 // *_in and written to *_out (other workgroups still read the old values);
 // z read and written in place (only ever read at its own cell).  The ghost
 // cells of sd are written as the last step's fill leaves them.
-constexpr int kChebMaxSteps = 5;
+constexpr int kChebMaxSteps = 9;
 constexpr int kChebTX = 64, kChebTY = 16;
 struct ChebArgs {
     const void *kx, *ky, *sd_in, *rt_in;
@@ -78,6 +78,8 @@ struct ChebArgs {
     int ntx, nty;          // set by the launcher
 };
 hipError_t launch_cheb2(const ChebArgs &a, int dtype, hipStream_t s);
+// Cells recomputed around a tile for a group of `steps` steps (3, 5, 7 or 9).
+inline int cheb_halo(int steps) { return steps <= 3 ? 3 : steps <= 5 ? 5 : steps <= 7 ? 7 : 9; }
 
 // Combine the (hi, lo) partials of n reductions, one workgroup each, in a
 // fixed order: reduction r's count[r] pairs start at part + 2 * base[r] and

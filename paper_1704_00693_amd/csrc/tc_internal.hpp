@@ -268,6 +268,7 @@ struct Ctx {
     // owned box
     int staged_mode = 1;
     bool cheb_enabled = true;  // TC_CHEB=0: no fused Chebyshev-step groups
+    int cheb_steps = 0;        // TC_CHEB_STEPS=k: Chebyshev groups of exactly k steps (or a run's shorter rest)
     int staged_threads = 0;  // TC_STAGED_THREADS=256|1024: workgroup size of staged tiles (0: by box size)
     int staged_tile[3] = {0, 0, 0};
     std::vector<void *> staged_allocs;  // device tables of staged groups (freed at finalize)

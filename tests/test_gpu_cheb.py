@@ -3,8 +3,8 @@ preconditioner's steps, one launch each) against the untiled execution and
 the oracle.
 
 * PPCG solves of ragged sizes (37^2, 130^2: partial 64 x 16 tiles on the
-  top and right) with 1, 2, 3, 4 and 7 inner steps, which give groups of one
-  to five steps, with and without the last TEA_P2: every dataset (halos
+  top and right) with 1, 2, 3, 4, 7, 9 and 12 inner steps, which give groups
+  of one to nine steps, with and without the last TEA_P2: every dataset (halos
   included, so the ghost cells of sd the groups store) and every scalar of
   the solve equal the untiled run's bits, and the solution matches the
   oracle's FP64 solve.
@@ -45,14 +45,19 @@ def solve(tc, hp, mode, outer, inner, dtype):
     return info, fields
 
 
+@pytest.mark.parametrize("steps", ["", "7", "9"])
 @pytest.mark.parametrize("n", [37, 130])
-@pytest.mark.parametrize("inner", [1, 2, 3, 4, 7])
-def test_chebyshev_groups_match_untiled(tc, n, inner):
+@pytest.mark.parametrize("inner", [1, 2, 3, 4, 7, 9, 12])
+def test_chebyshev_groups_match_untiled(tc, n, inner, steps, monkeypatch):
+    # groups as the split search picks them (at most five steps), or of
+    # seven or nine steps (the kernel's wider borders)
+    if steps:
+        monkeypatch.setenv("TC_CHEB_STEPS", steps)
     from oracle.tealeaf import ppcg_solve
     from synthgen import heat_problem
     hp = heat_problem(n, seed=11)
     outer = 3
-    say(f"chebyshev groups n={n} inner={inner}")
+    say(f"chebyshev groups n={n} inner={inner} steps={steps or 'searched'}")
     base, fb = solve(tc, hp, tc.TC_TILING_NONE, outer, inner, tc.TC_F64)
     got, fg = solve(tc, hp, tc.TC_TILING_FUSED, outer, inner, tc.TC_F64)
     for k in FIELDS:
