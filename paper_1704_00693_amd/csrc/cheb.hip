@@ -75,9 +75,16 @@ __global__ void __launch_bounds__(256) cheb2_kernel(ChebArgs a) {
             kw[k] = kx[x + (int64_t)y * a.skx];
             kn[k] = ky[x + (int64_t)(y + 1) * a.sky];
             ks[k] = ky[x + (int64_t)y * a.sky];
-            rt[k] = rti[x + (int64_t)y * a.srt_in];
-            if (f & kOwn) z[k] = zp[x + (int64_t)y * a.sz];
-            v[0][i] = sd[x + (int64_t)y * a.ssd_in];
+            if (a.start) {
+                // TEA_PRECON_INIT: rt = r, sd = r / theta, z = 0
+                const T rv = ((const T *)a.r)[x + (int64_t)y * a.sr];
+                rt[k] = rv;
+                v[0][i] = rv / (T)a.theta;
+            } else {
+                rt[k] = rti[x + (int64_t)y * a.srt_in];
+                if (f & kOwn) z[k] = zp[x + (int64_t)y * a.sz];
+                v[0][i] = sd[x + (int64_t)y * a.ssd_in];
+            }
         }
     }
     __syncthreads();

@@ -1054,7 +1054,27 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
         std::vector<std::vector<std::shared_ptr<FusedGroup>>> cheb_end(L + 1);
         for (int i = 0; i < L; ++i) {
             ChebGroup C;
-            if (!c.cheb_enabled || chain[i].op != TC_OP_HALO_REFLECT || cheb_match(c, chain, i, C) == 0) continue;
+            // a run may start with the preconditioner's set-up (TEA_PRECON_INIT:
+            // r read, rt, sd and z written over the interior, theta)
+            const bool init = chain[i].op == TC_OP_TEA_PRECON_INIT;
+            const int f0 = init ? i + 1 : i;
+            if (!c.cheb_enabled || f0 >= L || chain[f0].op != TC_OP_HALO_REFLECT || cheb_match(c, chain, f0, C) == 0)
+                continue;
+            if (init) {
+                const LoopRec &q = chain[i];
+                bool ok = q.ndim == 2 && q.args.size() == 4 && q.params.size() == 1 && q.lo[0] == 0 &&
+                          q.hi[0] == C.n[0] && q.lo[1] == 0 && q.hi[1] == C.n[1];
+                for (int a = 0; ok && a < 4; ++a) ok = q.args[a].kind == TC_ARG_DAT;
+                ok = ok && q.args[1].handle == C.rt && q.args[2].handle == C.sd && q.args[3].handle == C.z;
+                if (ok) {
+                    const int r = q.args[0].handle;
+                    ok = r != C.kx && r != C.ky && r != C.sd && r != C.rt && r != C.z &&
+                         c.dats[r].dtype == c.dats[C.sd].dtype && c.dats[r].block == c.dats[C.sd].block;
+                    C.r = r;
+                    C.init_loop = i;
+                }
+                if (!ok) continue;
+            }
             // at most five steps unless asked: measured on the PPCG solve at
             // 2000^2 (ms per solve) 3 steps 29.3, 4 28.4, 5 24.3, 7 34.1,
             // 9 39.4 (the wider recomputed borders and their registers cost
@@ -1065,14 +1085,16 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                 P->steps = m;
                 P->last_p2 = C.p2_loop[m - 1] >= 0;
                 P->p2_loop.resize(m);
-                const int len = 5 * m + (P->last_p2 ? m : m - 1);
+                const int len = 5 * m + (P->last_p2 ? m : m - 1) + (init ? 1 : 0);
                 // bytes: face coefficients, rt and sd over the region of a
                 // tile (H = 3 or 5 cells around 64 x 16), z over the owned
                 // cells; rt, z and sd written once
                 const int H = cheb_halo(m);
                 const double f = (double)(kChebTX + 2 * H) * (kChebTY + 2 * H) / ((double)kChebTX * kChebTY);
                 const double cells = (double)C.n[0] * C.n[1];
-                const double bytes = cells * c.dats[C.sd].esize() * (4.0 * f + 1.0 + 3.0);
+                // (with the set-up first: r over the region instead of rt,
+                // sd and z)
+                const double bytes = cells * c.dats[C.sd].esize() * (init ? 3.0 * f + 3.0 : 4.0 * f + 1.0 + 3.0);
                 auto G = std::make_shared<FusedGroup>();
                 G->g0 = i;
                 G->g1 = i + len;
@@ -1424,6 +1446,13 @@ tc_status cheb_run(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &
             a.al[j] = chain[C.p2_loop[j]].params[0];
             a.be[j] = chain[C.p2_loop[j]].params[1];
         }
+    if (C.init_loop >= 0) {
+        const Dataset &r = c.dats[C.r];
+        a.start = 1;
+        a.r = r.origin(r.cur);
+        a.sr = r.sy();
+        a.theta = chain[C.init_loop].params[0];
+    }
     a.n0 = C.n[0];
     a.n1 = C.n[1];
     a.h = C.h;

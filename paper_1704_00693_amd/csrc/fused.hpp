@@ -141,6 +141,7 @@ struct EulerStage {
 // TEA_P2 (sd, rt) over it; the last step may end after TEA_P1.
 struct ChebGroup {
     int kx, ky, sd, rt, z;  // datasets
+    int r = -1, init_loop = -1;  // with the preconditioner's TEA_PRECON_INIT first: r and that loop
     int steps = 0;
     bool last_p2 = true;
     int n[2] = {0, 0}, h = 0;

@@ -64,13 +64,20 @@ hipError_t launch_euler_stage3(const EulerStageArgs &a, int dtype, hipStream_t s
 // Arrays by logical origin and row stride: kx, ky read; sd and rt read from
 // *_in and written to *_out (other workgroups still read the old values);
 // z read and written in place (only ever read at its own cell).  The ghost
-// cells of sd are written as the last step's fill leaves them.
+// cells of sd are written as the last step's fill leaves them.  Optionally
+// the preconditioner's set-up (TEA_PRECON_INIT) comes first.
 constexpr int kChebMaxSteps = 9;
 constexpr int kChebTX = 64, kChebTY = 16;
 struct ChebArgs {
     const void *kx, *ky, *sd_in, *rt_in;
     void *sd_out, *rt_out, *z;
     int64_t skx, sky, ssd_in, srt_in, ssd_out, srt_out, sz;  // row strides (elements)
+    // start != 0: TEA_PRECON_INIT first (rt = r, sd = r / theta, z = 0);
+    // sd_in, rt_in and z are then not read
+    const void *r;
+    int64_t sr;
+    double theta;
+    int start;
     double al[kChebMaxSteps], be[kChebMaxSteps];
     int n0, n1;            // interior extent along x and y
     int h;                 // ghost depth of the fills
