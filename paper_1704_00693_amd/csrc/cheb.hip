@@ -77,7 +77,18 @@ __global__ void __launch_bounds__(256) cheb2_kernel(ChebArgs a) {
             ks[k] = ky[x + (int64_t)y * a.sky];
             if (a.start) {
                 // TEA_PRECON_INIT: rt = r, sd = r / theta, z = 0
-                const T rv = ((const T *)a.r)[x + (int64_t)y * a.sr];
+                T rv = ((const T *)a.r)[x + (int64_t)y * a.sr];
+                if (a.update) {
+                    // TEA_CG_UPDATE before it: r -= alpha w (every region
+                    // cell), x += alpha p (owned cells)
+                    const T al = (T)a.alpha;
+                    rv = fmaC<T>(-al, ((const T *)a.w)[x + (int64_t)y * a.sw], rv);
+                    if (f & kOwn) {
+                        T *xp = (T *)a.x + x + (int64_t)y * a.sx;
+                        *xp = fmaC<T>(al, ((const T *)a.p)[x + (int64_t)y * a.sp], *xp);
+                        ((T *)a.r_out)[x + (int64_t)y * a.sro] = rv;
+                    }
+                }
                 rt[k] = rv;
                 v[0][i] = rv / (T)a.theta;
             } else {

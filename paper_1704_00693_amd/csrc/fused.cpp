@@ -404,7 +404,8 @@ bool analyse(const Ctx &c, const std::vector<LoopRec> &chain, int g0, int g1, co
 // 256 MB cache (consecutive loops then mostly hit it), and at least a
 // launch.  Measured per-loop PPCG kernels: 3-4 us at 256^2 and 700^2, a
 // matrix-vector step over 2000^2 (224 MB moved, 160 MB of datasets) 32 us.
-double single_loop_cost(const Ctx &c, const LoopRec &lp) {
+// The streaming part alone: its bytes at that rate.
+double loop_stream_time(const Ctx &c, const LoopRec &lp) {
     double b = 0.0, footprint = 0.0;
     for (const auto &a : lp.args)
         if (a.kind == TC_ARG_DAT) {
@@ -412,8 +413,10 @@ double single_loop_cost(const Ctx &c, const LoopRec &lp) {
             footprint += (double)c.dats[a.handle].bytes;
         }
     const double bw = footprint < 192e6 ? 7.0e12 : 4.2e12;
-    return std::max(3e-6, (double)lp.points() * b / bw) + 1e-6;
+    return (double)lp.points() * b / bw;
 }
+
+double single_loop_cost(const Ctx &c, const LoopRec &lp) { return std::max(3e-6, loop_stream_time(c, lp)) + 1e-6; }
 
 // ---------------------------------------------------------------------------
 // code generation
@@ -1056,12 +1059,16 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
             ChebGroup C;
             // a run may start with the preconditioner's set-up (TEA_PRECON_INIT:
             // r read, rt, sd and z written over the interior, theta)
-            const bool init = chain[i].op == TC_OP_TEA_PRECON_INIT;
-            const int f0 = init ? i + 1 : i;
+            // and the CG update of x and r before that (TEA_CG_UPDATE)
+            const bool upd = chain[i].op == TC_OP_TEA_CG_UPDATE && i + 1 < L &&
+                             chain[i + 1].op == TC_OP_TEA_PRECON_INIT;
+            const int i0 = upd ? i + 1 : i;
+            const bool init = chain[i0].op == TC_OP_TEA_PRECON_INIT;
+            const int f0 = init ? i0 + 1 : i0;
             if (!c.cheb_enabled || f0 >= L || chain[f0].op != TC_OP_HALO_REFLECT || cheb_match(c, chain, f0, C) == 0)
                 continue;
             if (init) {
-                const LoopRec &q = chain[i];
+                const LoopRec &q = chain[i0];
                 bool ok = q.ndim == 2 && q.args.size() == 4 && q.params.size() == 1 && q.lo[0] == 0 &&
                           q.hi[0] == C.n[0] && q.lo[1] == 0 && q.hi[1] == C.n[1];
                 for (int a = 0; ok && a < 4; ++a) ok = q.args[a].kind == TC_ARG_DAT;
@@ -1071,7 +1078,26 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                     ok = r != C.kx && r != C.ky && r != C.sd && r != C.rt && r != C.z &&
                          c.dats[r].dtype == c.dats[C.sd].dtype && c.dats[r].block == c.dats[C.sd].block;
                     C.r = r;
-                    C.init_loop = i;
+                    C.init_loop = i0;
+                }
+                if (!ok) continue;
+            }
+            if (upd) {
+                const LoopRec &q = chain[i];
+                bool ok = q.ndim == 2 && q.args.size() == 4 && q.params.size() == 1 && q.lo[0] == 0 &&
+                          q.hi[0] == C.n[0] && q.lo[1] == 0 && q.hi[1] == C.n[1];
+                for (int a = 0; ok && a < 4; ++a) ok = q.args[a].kind == TC_ARG_DAT;
+                ok = ok && q.args[1].handle == C.r;
+                if (ok) {
+                    C.x = q.args[0].handle;
+                    C.p = q.args[2].handle;
+                    C.w = q.args[3].handle;
+                    const int all[9] = {C.kx, C.ky, C.sd, C.rt, C.z, C.r, C.x, C.p, C.w};
+                    for (int a = 0; ok && a < 9; ++a)
+                        for (int b = a + 1; ok && b < 9; ++b) ok = all[a] != all[b];
+                    for (int d : {C.x, C.p, C.w})
+                        ok = ok && c.dats[d].dtype == c.dats[C.sd].dtype && c.dats[d].block == c.dats[C.sd].block;
+                    C.update_loop = i;
                 }
                 if (!ok) continue;
             }
@@ -1085,20 +1111,29 @@ std::vector<std::shared_ptr<FusedGroup>> fused_split(Ctx &c, const std::vector<L
                 P->steps = m;
                 P->last_p2 = C.p2_loop[m - 1] >= 0;
                 P->p2_loop.resize(m);
-                const int len = 5 * m + (P->last_p2 ? m : m - 1) + (init ? 1 : 0);
+                const int len = 5 * m + (P->last_p2 ? m : m - 1) + (init ? 1 : 0) + (upd ? 1 : 0);
                 // bytes: face coefficients, rt and sd over the region of a
-                // tile (H = 3 or 5 cells around 64 x 16), z over the owned
-                // cells; rt, z and sd written once
-                const int H = cheb_halo(m);
-                const double f = (double)(kChebTX + 2 * H) * (kChebTY + 2 * H) / ((double)kChebTX * kChebTY);
+                // tile, z over the owned cells; rt, z and sd written once.
+                // A region's border is mostly read from L2 (the neighbouring
+                // tiles load it too): HBM sees about 1.15 times the owned
+                // cells of each region-loaded array
+                const double f = 1.15;
                 const double cells = (double)C.n[0] * C.n[1];
                 // (with the set-up first: r over the region instead of rt,
                 // sd and z)
-                const double bytes = cells * c.dats[C.sd].esize() * (init ? 3.0 * f + 3.0 : 4.0 * f + 1.0 + 3.0);
+                const double arrays = init ? 3.0 * f + 3.0 : 4.0 * f + 1.0 + 3.0;
+                const double bytes = cells * c.dats[C.sd].esize() * arrays;
                 auto G = std::make_shared<FusedGroup>();
                 G->g0 = i;
                 G->g1 = i + len;
                 G->cost = bytes / 4.5e12 + 6e-6;
+                // the update folded in saves its launch but reads w and r
+                // over every region and x and p with them: measured, the
+                // fold gains on small grids (256^2 5.42 -> 5.20 ms per solve,
+                // 700^2 7.10 -> 6.81) and loses on large ones (2000^2 23.31
+                // -> 24.62, 4000^2 85.74 -> 88.58), so it is modelled at 1.2
+                // times the update's own streaming time
+                if (upd) G->cost += 1.2 * loop_stream_time(c, chain[i]);
                 G->alg_bytes = (int64_t)(cells * c.dats[C.sd].esize() * 8.0);
                 G->cheb = P;
                 cheb_end[i + len].push_back(G);
@@ -1447,11 +1482,29 @@ tc_status cheb_run(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &
             a.be[j] = chain[C.p2_loop[j]].params[1];
         }
     if (C.init_loop >= 0) {
-        const Dataset &r = c.dats[C.r];
+        Dataset &r = c.dats[C.r];
         a.start = 1;
         a.r = r.origin(r.cur);
         a.sr = r.sy();
         a.theta = chain[C.init_loop].params[0];
+        if (C.update_loop >= 0) {
+            // r is read over every workgroup's region: its new values go to
+            // the second buffer; x is read and written at its own cells only
+            const Dataset &p = c.dats[C.p], &w = c.dats[C.w];
+            Dataset &x = c.dats[C.x];
+            a.update = 1;
+            a.alpha = chain[C.update_loop].params[0];
+            a.p = p.origin(p.cur);
+            a.sp = p.sy();
+            a.w = w.origin(w.cur);
+            a.sw = w.sy();
+            a.x = x.origin(x.cur);
+            a.sx = x.sy();
+            const int ilo[3] = {0, 0, 0}, ihi[3] = {C.n[0], C.n[1], 1};
+            st = second_buffer(c, r, ilo, ihi, &a.r_out);
+            if (st != TC_OK) return st;
+            a.sro = r.sy();
+        }
     }
     a.n0 = C.n[0];
     a.n1 = C.n[1];
@@ -1462,6 +1515,7 @@ tc_status cheb_run(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &
     if (e != hipSuccess) return fail(c, TC_ERR_DEVICE, "Chebyshev group launch failed: %s", hipGetErrorString(e));
     sd.cur ^= 1;
     rt.cur ^= 1;
+    if (C.update_loop >= 0) c.dats[C.r].cur ^= 1;
     return TC_OK;
 }
 
@@ -1558,7 +1612,7 @@ tc_status fused_run(Ctx &c, const std::vector<LoopRec> &chain, FusedGroup &G) {
 tc_status fused_check_noalloc(Ctx &c, const std::vector<LoopRec> &chain, const FusedGroup &G) {
     if (G.staged) return staged_check_noalloc(c, *G.staged);
     if (G.cheb) {
-        for (int d : {G.cheb->sd, G.cheb->rt}) {
+        for (int d : {G.cheb->sd, G.cheb->rt, G.cheb->update_loop >= 0 ? G.cheb->r : G.cheb->sd}) {
             const Dataset &ds = c.dats[d];
             if (!ds.raw[0] || !ds.raw[1])
                 return fail(c, TC_ERR_STATE,

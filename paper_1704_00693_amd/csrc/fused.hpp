@@ -142,6 +142,8 @@ struct EulerStage {
 struct ChebGroup {
     int kx, ky, sd, rt, z;  // datasets
     int r = -1, init_loop = -1;  // with the preconditioner's TEA_PRECON_INIT first: r and that loop
+    // with TEA_CG_UPDATE (x, r, p, w; alpha) before the set-up: its datasets and loop
+    int x = -1, p = -1, w = -1, update_loop = -1;
     int steps = 0;
     bool last_p2 = true;
     int n[2] = {0, 0}, h = 0;

@@ -65,7 +65,8 @@ hipError_t launch_euler_stage3(const EulerStageArgs &a, int dtype, hipStream_t s
 // *_in and written to *_out (other workgroups still read the old values);
 // z read and written in place (only ever read at its own cell).  The ghost
 // cells of sd are written as the last step's fill leaves them.  Optionally
-// the preconditioner's set-up (TEA_PRECON_INIT) comes first.
+// the preconditioner's set-up (TEA_PRECON_INIT) comes first, and the CG
+// update of x and r (TEA_CG_UPDATE) before it.
 constexpr int kChebMaxSteps = 9;
 constexpr int kChebTX = 64, kChebTY = 16;
 struct ChebArgs {
@@ -78,6 +79,13 @@ struct ChebArgs {
     int64_t sr;
     double theta;
     int start;
+    // update != 0 (with start): TEA_CG_UPDATE first, x = fma(alpha, p, x)
+    // and r = fma(-alpha, w, r) (x in place, the new r to r_out)
+    const void *p, *w;
+    void *x, *r_out;
+    int64_t sp, sw, sx, sro;
+    double alpha;
+    int update;
     double al[kChebMaxSteps], be[kChebMaxSteps];
     int n0, n1;            // interior extent along x and y
     int h;                 // ghost depth of the fills

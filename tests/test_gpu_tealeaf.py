@@ -96,15 +96,18 @@ def true_residual(hp, x):
     return float(np.linalg.norm(b - o.apply_A("u")) / np.linalg.norm(b)), lmax
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("n,ndim,tol", [(40, 2, 1e-8), (96, 2, 1e-10), (16, 3, 1e-8)])
-def test_mixed_precision_refinement(tc, n, ndim, tol):
+def test_mixed_precision_refinement(tc, n, ndim, tol, fused):
     """FP32 sweeps + FP64 reductions + FP64 refinement reach the FP64 residual
     tolerance; the error against the FP64 solution is bounded by the condition
     number (lmax / lmin, lmin = 1) times the two residuals."""
     from paper_1704_00693_amd.apps import MixedHeatSolver
     hp = heat_problem(n, seed=3, ndim=ndim)
-    say(f"mixed n={n} ndim={ndim} tol={tol}")
+    say(f"mixed n={n} ndim={ndim} tol={tol} fused={fused}")
     with tc.Context() as c:
+        if fused:  # FP32 corrections through the fused groups (2D: Chebyshev groups)
+            c.tc_set_tiling(tc.TC_TILING_FUSED, (0, 0, 0))
         s = MixedHeatSolver(c, hp.density, hp.energy)
         info = s.solve(tol=tol)
         x = s.field("u")
