@@ -276,7 +276,8 @@ def _tune(ctx, fn, limit=80):
 
 
 def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(), jacobi_two_columns=True,
-                    tealeaf_sizes=(256,), jacobi_select=None, jacobi_variants=("non_copy", "copy")):
+                    tealeaf_sizes=(256,), jacobi_select=None, jacobi_variants=("non_copy", "copy"),
+                    chain3d_staged=False):
     """The other configurations, each in the execution modes that apply:
     heat-conduction PPCG 256^2 (50 iterations of 10 Chebyshev steps), the
     256^3 Taylor-Green RK3 step, the 8192^2 Jacobi iteration (250 iterations,
@@ -391,15 +392,33 @@ def other_workloads(tc, which, steps, jacobi_sizes=(8192,), jacobi_skew_rows=(),
         ch = chain_3d()
         data = chain_data(ch)
         res = {}
-        with tc.Context(0) as c:
-            r = ChainRunner(c, ch, data)
-            del data
-            for name, m, tile in modes:
-                c.tc_set_tiling(m, tile)
-                dt = _timed(lambda: r.run(), steps)
-                st = c.tc_get_stats()
-                res[name] = {"ms_per_step": dt * 1e3, "cell_updates_per_s": st["cell_updates"] / dt,
-                             "effective_GBps": st["modelled_bytes"] / dt / 1e9, "launches": st["last_launches"]}
+        # fused: the split search keeps a loop on its own kernel unless a
+        # group is modelled faster; fused_staged_all: every run the staged
+        # analysis accepts becomes a staged group (TC_STAGED=2), to time them
+        runs = [(None, modes + [("fused", tc.TC_TILING_FUSED, (0, 0, 0))])]
+        if chain3d_staged:
+            runs.append(("2", [("fused_staged_all", tc.TC_TILING_FUSED, (0, 0, 0))]))
+        for env, ms in runs:
+            old = os.environ.get("TC_STAGED")
+            if env is not None:
+                os.environ["TC_STAGED"] = env
+            try:
+                with tc.Context(0) as c:
+                    r = ChainRunner(c, ch, data)
+                    for name, m, tile in ms:
+                        c.tc_set_tiling(m, tile)
+                        dt = _timed(lambda: r.run(), steps)
+                        st = c.tc_get_stats()
+                        res[name] = {"ms_per_step": dt * 1e3, "cell_updates_per_s": st["cell_updates"] / dt,
+                                     "effective_GBps": st["modelled_bytes"] / dt / 1e9,
+                                     "launches": st["last_launches"], "groups": st["last_groups"]}
+            finally:
+                if env is not None:
+                    if old is None:
+                        del os.environ["TC_STAGED"]
+                    else:
+                        os.environ["TC_STAGED"] = old
+        del data
         out["chain_384_3d"] = {"workload": "3D synthetic chain 384^3 FP64, 25 datasets, 60 loops of 7/13-point "
                                            "stars + final sum, seed 2", "modes": res}
         log(f"chain 384^3: {res}")
@@ -548,6 +567,8 @@ def main():
     ap.add_argument("--jacobi-select", default="",
                     help="Jacobi modes to time, comma list of none, skewed, fused, fused_2col_regs240, auto "
                          "(default: all)")
+    ap.add_argument("--chain3d-staged", action="store_true",
+                    help="also time the 3D chain with every run the staged analysis accepts as a staged group")
     ap.add_argument("--jacobi-variants", default="non_copy,copy", help="Jacobi variants to time: non_copy, copy")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
@@ -626,7 +647,7 @@ def main():
                               [int(v) for v in args.jacobi_skew_rows.split(",") if v], not args.jacobi_one_layout,
                               [int(v) for v in args.tealeaf_n.split(",")],
                               [v for v in args.jacobi_select.split(",") if v] or None,
-                              tuple(v for v in args.jacobi_variants.split(",") if v))
+                              tuple(v for v in args.jacobi_variants.split(",") if v), args.chain3d_staged)
               if args.other else None)
     batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
     served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None

@@ -138,22 +138,33 @@ def test_synthetic_chain_small(tc, ndim, n, ndat, nloops, tiles):
     # the generic weighted-sum kernel instead of the register-window one, and
     # in 3D the register-window kernel's other workgroup shapes (rows of
     # wavefronts, planes per workgroup; ragged in y and z here)
+    # In 3D the fused mode keeps every loop on its own kernel (no group is
+    # modelled faster); with TC_STAGED=2 every run the staged analysis
+    # accepts becomes a staged group
     import os
     variants = [("generic", {"TC_WSUM_MARCH": "0"})]
     if ndim == 3:
         variants += [("rows 4", {"TC_MARCH3_ROWS": "4"}), ("rows 8", {"TC_MARCH3_ROWS": "8"}),
                      ("rows 8, 8 planes", {"TC_MARCH3_ROWS": "8", "TC_MARCH3_TZ": "8"}),
-                     ("rows 4, 12 planes", {"TC_MARCH3_ROWS": "4", "TC_MARCH3_TZ": "12"})]
+                     ("rows 4, 12 planes", {"TC_MARCH3_ROWS": "4", "TC_MARCH3_TZ": "12"}),
+                     ("staged groups", {"TC_STAGED": "2"})]
     for name, env in variants:
         say(f"synthetic chain ndim={ndim} n={n} {name}")
         os.environ.update(env)
         try:
             with tc.Context() as c:
+                staged = "TC_STAGED" in env
+                if staged:
+                    c.tc_set_tiling(tc.TC_TILING_FUSED, (0, 0, 0))
                 r = ChainRunner(c, ch, data)
                 r.run()
                 r.run()
                 r.run()
                 results[name] = [r.read(d) for d in range(ndat)]
+                if staged:
+                    st = c.tc_get_stats()
+                    say(f"  staged groups={st['last_groups']} launches={st['last_launches']}")
+                    assert st["last_groups"] >= 1
         finally:
             for k in env:
                 del os.environ[k]
