@@ -380,12 +380,13 @@ tc_status tc_pending(tc_ctx *ctx, int32_t *nloops);
  * operator, reflective boundaries, Gershgorin bound and Chebyshev
  * preconditioner of the library's TEA_* loops) advanced together on one
  * GPU.  Every solver phase is one kernel launch over all resident instances
- * (for 2D instances the Chebyshev steps run several per launch, on tiles
- * with a recomputed border, with the same per-cell arithmetic); the phases
- * of one iteration are captured once in a HIP graph and replayed.  The HBM
- * footprint of a solve is 9 + ndim field arrays of (n + 2)^ndim values
- * (FP64; mixed: 3 + ndim FP64 and 8 + ndim FP32 arrays), one more sweep
- * array for 2D solves, each rounded up to 256 bytes.
+ * (the Chebyshev steps run several per launch, with the same per-cell
+ * arithmetic: for 2D instances on tiles with a recomputed border, for 3D
+ * instances in a march up z-segments of their planes); the phases of one
+ * iteration are captured once in a HIP graph and replayed.  The HBM
+ * footprint of a solve is 10 + ndim field arrays of (n + 2)^ndim values
+ * (FP64; mixed: 3 + ndim FP64 and 9 + ndim FP32 arrays), each rounded up to
+ * 256 bytes.
  * Each instance keeps its state machine, scalars and convergence test on the
  * device; the host admits new solves into free slots by HBM footprint
  * (continuous batching), retires finished ones and rebuilds the tile list

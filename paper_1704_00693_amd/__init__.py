@@ -122,6 +122,11 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1704_00693_amd.build`")
+    # torch's wheel carries its own HIP runtime under the same soname: loaded
+    # first, it is the one the library binds to, so the streams and memory a
+    # context borrows from torch belong to the library's runtime too (loaded
+    # after the library, a second HIP and HSA runtime would come up beside it)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, i64 = ctypes.c_int32, ctypes.c_int64

@@ -17,7 +17,7 @@
 namespace tc {
 hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
                                    const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed, int fh,
-                                   int fty, bool with3d, bool setup, hipStream_t s);
+                                   int fty, int f3, bool with3d, bool setup, hipStream_t s);
 }
 
 using namespace tc;
@@ -26,10 +26,12 @@ struct tc_batch {
     tc_ctx *ctx = nullptr;
     tc_batch_opts o{};
     BInst *d_inst = nullptr, *h_inst = nullptr;
-    // every resident solve's tiles (kBTX x kBTY), the 3D solves' tiles, and
-    // the 2D solves' fused Chebyshev tiles (kFTX x kFTY)
+    // every resident solve's tiles (kBTX x kBTY), the 3D solves' tiles (their
+    // kBTX x kBTY tiles, or kF3X x kF3Y x kF3Z segments when their Chebyshev
+    // steps are fused), and the 2D solves' fused Chebyshev tiles (kFTX x kFTY)
     BTileList all, three, fused;
     int fh = kFH, fty = kFTY;  // fused Chebyshev steps per launch (0: one launch per step) and tile height
+    int f3 = 3;                // 3D: fused Chebyshev steps per launch (0: one launch per step)
     double *d_part = nullptr;
     int64_t tile_cap = 0;
     int grid = 0;
@@ -84,15 +86,14 @@ int64_t tiles_of(const tc_solve_desc &d) {
 int64_t round256(int64_t v) { return (v + 255) / 256 * 256; }
 
 // Bytes of one solve's fields (each field padded by one ghost layer and
-// aligned to 256 bytes): FP64 mode 9 + ndim double fields; mixed mode
-// 3 + ndim double fields and 8 + ndim float fields; 2D solves one more
-// sweep field (the second rt buffer).
+// aligned to 256 bytes): FP64 mode 10 + ndim double fields; mixed mode
+// 3 + ndim double fields and 9 + ndim float fields (the sweep fields include
+// the second rt buffer of the fused Chebyshev steps).
 int64_t footprint(const tc_solve_desc &d, bool mixed) {
     const int64_t cells = padded_cells(d);
     const int64_t f8 = round256(cells * 8), f4 = round256(cells * 4);
-    const int extra = d.ndim == 2 ? 1 : 0;
-    if (!mixed) return (9 + d.ndim + extra) * f8;
-    return (3 + d.ndim) * f8 + (8 + d.ndim + extra) * f4;
+    if (!mixed) return (10 + d.ndim) * f8;
+    return (3 + d.ndim) * f8 + (9 + d.ndim) * f4;
 }
 
 tc_status admit(tc_batch *b, int slot, const tc_batch::Req &q) {
@@ -153,7 +154,7 @@ tc_status admit(tc_batch *b, int slot, const tc_batch::Req &q) {
         I.rt = take(f8);
         I.sd0 = take(f8);
         I.sd1 = take(f8);
-        I.rt2 = d.ndim == 2 ? take(f8) : nullptr;
+        I.rt2 = take(f8);
     } else {
         I.xi = take(f4);
         I.ri = take(f4);
@@ -166,7 +167,7 @@ tc_status admit(tc_batch *b, int slot, const tc_batch::Req &q) {
         I.rt = take(f4);
         I.sd0 = take(f4);
         I.sd1 = take(f4);
-        I.rt2 = d.ndim == 2 ? take(f4) : nullptr;
+        I.rt2 = take(f4);
     }
     b->resident_bytes += bytes;
     b->resident_tiles += S.tiles;
@@ -229,12 +230,19 @@ tc_status rebuild_tiles(tc_batch *b) {
         }
         const int tx = (I.n + kBTX - 1) / kBTX, ty = (I.n + kBTY - 1) / kBTY, tz = I.ndim == 3 ? I.n : 1;
         I.tile0 = nt;
+        const bool march3 = I.ndim == 3 && b->fh > 0 && b->f3 > 0;
         for (int z = 0; z < tz; ++z)
             for (int y = 0; y < ty; ++y)
                 for (int x = 0; x < tx; ++x) {
                     b->all.h[nt++] = BTile{(int32_t)s, x, y, z};
-                    if (I.ndim == 3) b->three.h[n3++] = BTile{(int32_t)s, x, y, z};
+                    if (I.ndim == 3 && !march3) b->three.h[n3++] = BTile{(int32_t)s, x, y, z};
                 }
+        if (march3) {
+            const int mx = (I.n + kF3X - 1) / kF3X, my = (I.n + kF3Y - 1) / kF3Y, mz = (I.n + kF3Z - 1) / kF3Z;
+            for (int z = 0; z < mz; ++z)
+                for (int y = 0; y < my; ++y)
+                    for (int x = 0; x < mx; ++x) b->three.h[n3++] = BTile{(int32_t)s, x, y, z};
+        }
         I.ntile = nt - I.tile0;
         if (I.ndim == 2) {
             const int fx = (I.n + kFTX - 1) / kFTX, fy = (I.n + b->fty - 1) / b->fty;
@@ -269,7 +277,7 @@ tc_status capture(tc_batch *b) {
                 return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed to start");
             const hipError_t e = batch_enqueue_iteration(b->d_inst, (int)b->slots.size(), b->all, b->three, b->fused,
                                                          b->d_part, b->grid, b->o.cheb_steps, b->o.mixed != 0, b->fh,
-                                                         b->fty, with3d != 0, setup != 0, c.cap_stream);
+                                                         b->fty, b->f3, with3d != 0, setup != 0, c.cap_stream);
             const hipError_t e2 = hipStreamEndCapture(c.cap_stream, &g);
             if (e != hipSuccess || e2 != hipSuccess || !g)
                 return fail(c, TC_ERR_DEVICE, "tc_batch: graph capture failed");
@@ -332,6 +340,8 @@ static tc_status impl_tc_batch_create(tc_ctx *ctx, const tc_batch_opts *opts, tc
         b->fh = fh <= 0 ? 0 : (shape ? fh : kFH);
         b->fty = shape ? fty : kFTY;
     }
+    // TC_BATCH_FUSED3=0: the 3D solves' Chebyshev steps one launch each
+    if (const char *e = getenv("TC_BATCH_FUSED3")) b->f3 = atoi(e) > 0 ? 3 : 0;
     if (rebuild_tiles(b) != TC_OK || capture(b) != TC_OK) {
         tc_batch_destroy(b);
         return TC_ERR_DEVICE;

@@ -450,6 +450,181 @@ __global__ void __launch_bounds__(256) bk_cheb_fused(BInst *insts, const BTile *
     }
 }
 
+// Chebyshev steps j0 .. j0+S-1 (S = 1 or 3) of 3D instances; the last step,
+// with its reductions, stays with bk_cheb.  A workgroup takes a tile of
+// kF3X x kF3Y owned cells of one z-segment [za, zb) of kF3Z planes and
+// marches up the planes: at march m, step s works on plane m - s, so the
+// direction a step writes for plane p is there when the next step, one march
+// later, needs it as the upper z neighbour of plane p - 1.  Each step level's
+// direction lives in LDS, a ring of three planes of the region (the owned
+// cells and S cells around them in x and y); rt and z live in registers, a
+// ring of S planes (plane p in slot (p - m0) mod S, so the march is unrolled
+// by S and every slot index is a constant).  Step s computes the cells within
+// S-1-s of the owned ones (in x and y, and in planes around the segment), so
+// every neighbour it reads was loaded or written by the step before it.  The
+// face coefficients are read from memory at every step (the plane's lines
+// are cached by then).  Neighbouring tiles and segments read this tile's
+// cells as their border, so rt alternates between two buffers (rt_alt: read
+// rt2, write rt) and an odd S puts the direction in the other sd buffer.  At
+// the domain boundary the mirrored neighbour is the cell itself, as in
+// bk_cheb, and every cell's operations are bk_cheb's, in the same order.
+template <typename T, int S>
+__global__ void __launch_bounds__(256) bk_cheb3_fused(BInst *insts, const BTile *tiles, const int64_t *ntiles, int j0,
+                                                      int rt_alt) {
+    constexpr int RW = kF3X + 2 * S, RH = kF3Y + 2 * S, RC = RW * RH;
+    constexpr int PER = (RC + 255) / 256;
+    // per-slot flags: inside the domain, owned, which in-plane neighbours
+    // are other region cells (else the cell itself); bits 8..: distance to
+    // the owned cells
+    enum : unsigned { fAct = 1, fOwn = 2, fE = 4, fW = 8, fN = 16, fS = 32 };
+    __shared__ T ring[S][3][RC];
+    const int64_t nt = *ntiles;
+    const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
+    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const BTile tl = tiles[t];
+        const BInst &I = insts[tl.inst];
+        if (!serves(I, mask) || I.ndim != 3 || j0 + S > I.cheb_steps) continue;  // the same for the whole workgroup
+        const int n = I.n;
+        const int64_t sy = I.sy, sz = I.sz;
+        const T *rt_in = (const T *)(rt_alt ? I.rt2 : I.rt);
+        T *rt_out = (T *)(rt_alt ? I.rt : I.rt2);
+        const T *sdi = (const T *)((j0 & 1) ? I.sd0 : I.sd1);
+        T *sdo = (T *)((j0 & 1) ? I.sd1 : I.sd0);
+        const T *kx = (const T *)I.kxi, *ky = (const T *)I.kyi, *kz = (const T *)I.kzi;
+        T *zp = (T *)I.z;
+        const int za = tl.tz * kF3Z, zb = min(n, za + kF3Z);
+        int lo[S], hi[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            lo[s] = max(0, za - (S - 1 - s));
+            hi[s] = min(n, zb + (S - 1 - s));
+        }
+        const int ld_lo = max(0, za - S), ld_hi = min(n, zb + S);  // planes of the loaded direction
+        const int m0 = lo[0];
+        int m_end = m0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) m_end = max(m_end, hi[s] + s);
+        const int rx0 = tl.tx * kF3X - S, ry0 = tl.ty * kF3Y - S;  // region origin
+        unsigned fl[PER];
+        int64_t cxy[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            const int lx = i % RW, ly = i / RW;
+            const int x = rx0 + lx, y = ry0 + ly;
+            unsigned f = 0;
+            if (i < RC && x >= 0 && x < n && y >= 0 && y < n) {
+                const int dx = lx < S ? S - lx : (lx >= S + kF3X ? lx - (S + kF3X - 1) : 0);
+                const int dy = ly < S ? S - ly : (ly >= S + kF3Y ? ly - (S + kF3Y - 1) : 0);
+                const int d = max(dx, dy);
+                f = fAct | ((unsigned)d << 8);
+                if (d == 0) f |= fOwn;
+                if (x + 1 < n && lx + 1 < RW) f |= fE;
+                if (x > 0 && lx > 0) f |= fW;
+                if (y + 1 < n && ly + 1 < RH) f |= fN;
+                if (y > 0 && ly > 0) f |= fS;
+            }
+            fl[k] = f;
+            cxy[k] = I.org + x + (int64_t)y * sy;
+        }
+        // planes m0 - 1 and m0 of the direction to LDS; plane m0 + 1, rt and
+        // z of plane m0 to the prefetch registers
+        T sd_nx[PER], rt_nx[PER], z_nx[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            sd_nx[k] = rt_nx[k] = z_nx[k] = (T)0;
+            if (!(fl[k] & fAct)) continue;
+            const int i = (int)threadIdx.x + 256 * k;
+            for (int q = m0 - 1; q <= m0; ++q)
+                if (q >= ld_lo && q < ld_hi) ring[0][q % 3][i] = sdi[cxy[k] + q * sz];
+            if (m0 + 1 < ld_hi) sd_nx[k] = sdi[cxy[k] + (m0 + 1) * sz];
+            if (m0 < hi[0]) rt_nx[k] = rt_in[cxy[k] + m0 * sz];
+            if ((fl[k] & fOwn) && m0 >= za && m0 < zb) z_nx[k] = zp[cxy[k] + m0 * sz];
+        }
+        T rt[S][PER], z[S][PER];
+        for (int mb = m0; mb < m_end; mb += S) {
+#pragma unroll
+            for (int u = 0; u < S; ++u) {
+                const int m = mb + u;
+                if (m >= m_end) break;
+                // plane m + 1 of the direction to LDS, rt and z of plane m to
+                // their ring slot; then the loads of the next march
+                const bool sd_ok = m + 1 < ld_hi;
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    if (!(fl[k] & fAct)) continue;
+                    const int i = (int)threadIdx.x + 256 * k;
+                    if (sd_ok) ring[0][(m + 1) % 3][i] = sd_nx[k];
+                    rt[u][k] = rt_nx[k];
+                    z[u][k] = z_nx[k];
+                    if (m + 2 < ld_hi) sd_nx[k] = sdi[cxy[k] + (m + 2) * sz];
+                    if (m + 1 < hi[0]) rt_nx[k] = rt_in[cxy[k] + (m + 1) * sz];
+                    if ((fl[k] & fOwn) && m + 1 >= za && m + 1 < zb) z_nx[k] = zp[cxy[k] + (m + 1) * sz];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const int p = m - s;
+                    if (p < lo[s] || p >= hi[s]) continue;  // the same for the whole workgroup
+                    const int r = (u - s + S) % S;  // ring slot of plane p
+                    const T al = (T)I.al[j0 + s - 1], be = (T)I.be[j0 + s - 1];
+                    const T *vc_p = ring[s][p % 3];
+                    const T *vt_p = ring[s][(p + 1 < n ? p + 1 : p) % 3];
+                    const T *vb_p = ring[s][(p > 0 ? p - 1 : p) % 3];
+                    const bool own_plane = p >= za && p < zb;
+#pragma unroll
+                    for (int k = 0; k < PER; ++k) {
+                        const unsigned f = fl[k];
+                        if (!(f & fAct) || (int)(f >> 8) > S - 1 - s) continue;
+                        const int i = (int)threadIdx.x + 256 * k;
+                        const int64_t c = cxy[k] + p * sz;
+                        const T ke = kx[c + 1], kw = kx[c];
+                        const T kn = ky[c + sy], ks = ky[c];
+                        T diag = (T)1 + ke;
+                        diag = diag + kw;
+                        diag = diag + kn;
+                        diag = diag + ks;
+                        const T kt = kz[c + sz], kb = kz[c];
+                        diag = diag + kt;
+                        diag = diag + kb;
+                        const T vc = vc_p[i];
+                        T av = diag * vc;
+                        av = fmaB<T>(-ke, vc_p[(f & fE) ? i + 1 : i], av);
+                        av = fmaB<T>(-kw, vc_p[(f & fW) ? i - 1 : i], av);
+                        av = fmaB<T>(-kn, vc_p[(f & fN) ? i + RW : i], av);
+                        av = fmaB<T>(-ks, vc_p[(f & fS) ? i - RW : i], av);
+                        av = fmaB<T>(-kt, vt_p[i], av);
+                        av = fmaB<T>(-kb, vb_p[i], av);
+                        const T rtv = rt[r][k] - av;
+                        rt[r][k] = rtv;
+                        if ((f & fOwn) && own_plane) z[r][k] = z[r][k] + vc;
+                        const T vn = fmaB<T>(al, vc, be * rtv);
+                        if (s + 1 < S)
+                            ring[s + 1 < S ? s + 1 : 0][p % 3][i] = vn;
+                        else if ((f & fOwn) && own_plane)
+                            sdo[c] = vn;
+                    }
+                    // the next step reads what this one wrote; with S == 1 the
+                    // next march overwrites a plane this step read
+                    if (s + 1 < S || S == 1) __syncthreads();
+                }
+                // rt and z of plane m - S + 1 are final
+                const int pf = m - (S - 1);
+                if (pf >= za && pf < zb) {
+                    const int r = (u + 1) % S;
+#pragma unroll
+                    for (int k = 0; k < PER; ++k) {
+                        if (!(fl[k] & fOwn)) continue;
+                        rt_out[cxy[k] + pf * sz] = rt[r][k];
+                        zp[cxy[k] + pf * sz] = z[r][k];
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the next tile reuses the LDS rings
+    }
+}
+
 // ---- per-instance finalize ------------------------------------------------
 // Combine slot `slot` of the instance's tile partials in tile order (the
 // same order and grouping as the library's finalize kernel); value = hi + lo
@@ -556,7 +731,7 @@ template <typename T>
 hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, const int64_t *ntiles,
                                const BTile *tiles3, const int64_t *ntiles3, const BTile *ftiles,
                                const int64_t *nftiles, double *part, int grid, int cheb_steps, bool mixed,
-                               int fh, int fty, bool with3d, bool setup, hipStream_t s) {
+                               int fh, int fty, int f3, bool with3d, bool setup, hipStream_t s) {
     const bool fused = fh > 0;
     const dim3 g(grid), b(256), f(ninst);
     // set-up of newly admitted instances (only the first iteration after an
@@ -580,7 +755,8 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
     hipLaunchKernelGGL(bk_update_init<T>, g, b, 0, s, insts, tiles, ntiles, skip2d);
     if (fused) {
         // 2D instances: steps 1 .. cheb_steps-1 in launches of at most fh
-        // steps (an odd number each), on the fused tiles; 3D instances:
+        // steps (an odd number each), on the fused tiles; 3D instances: in
+        // launches of three steps (or one) marching their z-segments (f3), or
         // one launch per step on their own tiles; then everybody's last step
         // (with the r.z and r.r partials)
         int launches = 0;
@@ -602,9 +778,21 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
             ++launches;
             j0 = j1;
         }
-        if (with3d)
+        if (with3d && f3 > 0) {
+            int l3 = 0;
+            for (int j0 = 1; j0 < cheb_steps; ++l3) {
+                int len = cheb_steps - j0 < 3 ? cheb_steps - j0 : 3;
+                len -= (len & 1) ^ 1;
+                if (len == 3)
+                    hipLaunchKernelGGL((bk_cheb3_fused<T, 3>), g, b, 0, s, insts, tiles3, ntiles3, j0, l3 & 1);
+                else
+                    hipLaunchKernelGGL((bk_cheb3_fused<T, 1>), g, b, 0, s, insts, tiles3, ntiles3, j0, l3 & 1);
+                j0 += len;
+            }
+        } else if (with3d) {
             for (int j = 1; j < cheb_steps; ++j)
                 hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles3, ntiles3, part, j);
+        }
         hipLaunchKernelGGL(bk_cheb<T>, g, b, 0, s, insts, tiles, ntiles, part, cheb_steps);
     } else {
         for (int j = 1; j <= cheb_steps; ++j)
@@ -621,11 +809,11 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
 // to its own state.
 hipError_t batch_enqueue_iteration(BInst *insts, int ninst, const BTileList &all, const BTileList &three,
                                    const BTileList &fused, double *part, int grid, int cheb_steps, bool mixed, int fh,
-                                   int fty, bool with3d, bool setup, hipStream_t s) {
+                                   int fty, int f3, bool with3d, bool setup, hipStream_t s) {
     return mixed ? enqueue_iteration_t<float>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
-                                              grid, cheb_steps, true, fh, fty, with3d, setup, s)
+                                              grid, cheb_steps, true, fh, fty, f3, with3d, setup, s)
                  : enqueue_iteration_t<double>(insts, ninst, all.d, all.dn, three.d, three.dn, fused.d, fused.dn, part,
-                                               grid, cheb_steps, false, fh, fty, with3d, setup, s);
+                                               grid, cheb_steps, false, fh, fty, f3, with3d, setup, s);
 }
 
 }  // namespace tc

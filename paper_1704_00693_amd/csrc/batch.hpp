@@ -37,6 +37,10 @@ constexpr int kBTX = 64, kBTY = 4;  // cells of one tile: one workgroup of 256 t
 // cells (plus FH cells around them, recomputed), with the direction in LDS;
 // (FH, FTY) is one of the compiled shapes below (default kFH, kFTY)
 constexpr int kFTX = 64, kFTY = 16, kFH = 3;
+// 3D Chebyshev steps run up to three at a time in a march up the planes of
+// z-segments of kF3Z planes, on tiles of kF3X x kF3Y owned cells (plus a
+// border of one cell per step, recomputed)
+constexpr int kF3X = 64, kF3Y = 8, kF3Z = 32;
 constexpr int kBMaxCheb = 32;
 
 struct BInst {
@@ -53,7 +57,7 @@ struct BInst {
     // fields of the PPCG sweeps (FP64 mode: double, aliasing u, r, kx..;
     // mixed mode: float)
     void *xi, *ri, *p, *w, *z, *rt, *sd0, *sd1, *kxi, *kyi, *kzi;
-    void *rt2;  // 2D: the second rt buffer of the fused Chebyshev steps (neighbouring tiles read rt around theirs)
+    void *rt2;  // the second rt buffer of the fused Chebyshev steps (neighbouring tiles read rt around theirs)
 };
 
 struct BTile {

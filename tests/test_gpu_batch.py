@@ -210,6 +210,39 @@ def test_fused_chebyshev_shapes_bit_identical(tc, monkeypatch, mixed):
 
 
 @pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("cheb_steps", [10, 5, 2])
+def test_fused_chebyshev_3d_bit_identical(tc, monkeypatch, mixed, cheb_steps):
+    """The 3D Chebyshev steps run three (or one) at a time, marching up
+    z-segments of 32 planes on 64 x 8 tiles with a recomputed border: 12^3
+    (one tile, one segment), 40^3 (two segments, the second partial) and
+    70^3 (two x tiles and three segments, all partial), next to a 2D solve.
+    Every solve takes the iterations and gives the bits of the per-step
+    kernels (TC_BATCH_FUSED=0), also with only the 2D steps fused
+    (TC_BATCH_FUSED3=0).  10 steps per preconditioner give launches of
+    3 + 3 + 3 steps, 5 give 3 + 1 and 2 give 1."""
+    cases = [(3, 12, 71), (3, 40, 72), (2, 50, 73), (3, 70, 74)]
+    results = {}
+    for name, env in (("per step", {"TC_BATCH_FUSED": "0"}), ("2D fused", {"TC_BATCH_FUSED3": "0"}),
+                      ("2D and 3D fused", {})):
+        for k in ("TC_BATCH_FUSED", "TC_BATCH_FUSED3"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        say(f"batch 3D mixed={mixed} cheb_steps={cheb_steps} {name}")
+        with tc.Context() as c, tc.Batch(c, mixed=mixed, max_instances=4, cheb_steps=cheb_steps) as b:
+            ts = [b.tc_batch_submit(nd, n, seed, tol=1e-9, keep_x=True) for nd, n, seed in cases]
+            b.tc_batch_wait()
+            results[name] = [(b.tc_batch_poll(t)["iterations"], b.tc_batch_poll(t)["converged"],
+                              b.tc_batch_read_x(t)) for t in ts]
+    base = results["per step"]
+    for name, res in results.items():
+        for (nd, n, _), (it0, cv0, x0), (it, cv, x) in zip(cases, base, res):
+            assert cv == cv0 and (mixed or cv0 == 1), (name, nd, n)
+            assert it == it0, (name, nd, n)
+            assert np.array_equal(x, x0), (name, nd, n)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
 def test_batch_full_size_instances(tc, mixed):
     """Instances at the top of the batched workload's size range (1023^2,
     the largest 2D size drawn) next to smaller 2D and 3D ones: every solve
