@@ -32,6 +32,9 @@ struct tc_batch {
     BTileList all, three, fused;
     int fh = kFH, fty = kFTY;  // fused Chebyshev steps per launch (0: one launch per step) and tile height
     int f3 = 3;                // 3D: fused Chebyshev steps per launch (0: one launch per step)
+    bool graphs = true;        // replay the captured iteration (else enqueue its launches directly)
+    double *stage = nullptr;   // pinned staging memory of kept solutions
+    int64_t stage_cap = 0;     // its size in doubles
     double *d_part = nullptr;
     int64_t tile_cap = 0;
     int grid = 0;
@@ -175,19 +178,30 @@ tc_status admit(tc_batch *b, int slot, const tc_batch::Req &q) {
     return TC_OK;
 }
 
-// Copy the interior of x (n^ndim values) of a resident solve to host memory.
+// Copy the interior of x (n^ndim values) of a resident solve to host memory:
+// the padded field in one copy into pinned staging memory, then its rows.
 tc_status copy_x(tc_batch *b, int slot, std::vector<double> &out) {
     Ctx &c = C(b);
     const BInst &I = b->h_inst[slot];
     const int64_t n = I.n, nz = I.ndim == 3 ? n : 1;
-    out.assign((size_t)(n * n * nz), 0.0);
-    for (int64_t z = 0; z < nz; ++z) {
-        const double *src = I.u + I.org + z * I.sz;
-        if (hipMemcpy2DAsync(out.data() + z * n * n, (size_t)n * 8, src, (size_t)I.sy * 8, (size_t)n * 8, (size_t)n,
-                             hipMemcpyDeviceToHost, c.stream) != hipSuccess)
-            return fail(c, TC_ERR_DEVICE, "tc_batch: copy of a solution failed");
+    const int64_t cells = padded_cells(b->slots[slot].d);
+    if (b->stage_cap < cells) {
+        if (b->stage) (void)hipHostFree(b->stage);
+        b->stage = nullptr;
+        b->stage_cap = 0;
+        if (hipHostMalloc((void **)&b->stage, (size_t)cells * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return fail(c, TC_ERR_NOMEM, "tc_batch: cannot allocate %lld bytes of pinned staging memory",
+                        (long long)(cells * 8));
+        b->stage_cap = cells;
     }
-    if (hipStreamSynchronize(c.stream) != hipSuccess) return fail(c, TC_ERR_DEVICE, "tc_batch: sync failed");
+    if (hipMemcpyAsync(b->stage, I.u, (size_t)cells * sizeof(double), hipMemcpyDeviceToHost, c.stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c.stream) != hipSuccess)
+        return fail(c, TC_ERR_DEVICE, "tc_batch: copy of a solution failed");
+    out.assign((size_t)(n * n * nz), 0.0);
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < n; ++y)
+            std::memcpy(out.data() + (z * n + y) * n, b->stage + I.org + y * I.sy + z * I.sz, (size_t)n * sizeof(double));
     return TC_OK;
 }
 
@@ -342,6 +356,8 @@ static tc_status impl_tc_batch_create(tc_ctx *ctx, const tc_batch_opts *opts, tc
     }
     // TC_BATCH_FUSED3=0: the 3D solves' Chebyshev steps one launch each
     if (const char *e = getenv("TC_BATCH_FUSED3")) b->f3 = atoi(e) > 0 ? 3 : 0;
+    // TC_BATCH_GRAPHS=0: enqueue each iteration's launches instead of replaying the graph
+    if (const char *e = getenv("TC_BATCH_GRAPHS")) b->graphs = atoi(e) != 0;
     if (rebuild_tiles(b) != TC_OK || capture(b) != TC_OK) {
         tc_batch_destroy(b);
         return TC_ERR_DEVICE;
@@ -413,9 +429,18 @@ static tc_status impl_tc_batch_step(tc_batch *b, int32_t *unfinished) {
         // instances are in the set-up state only from their admission to the
         // end of the next iteration
         const int with3d = b->has3d || b->fh == 0 ? 1 : 0;
-        for (int k = 0; k < b->o.replays_per_step; ++k)
-            if (hipGraphLaunch(b->gx[admitted && k == 0 ? 1 : 0][with3d], c.stream) != hipSuccess)
+        for (int k = 0; k < b->o.replays_per_step; ++k) {
+            const bool setup = admitted && k == 0;
+            if (!b->graphs) {
+                // the same launches as the captured iteration, enqueued directly
+                if (batch_enqueue_iteration(b->d_inst, (int)b->slots.size(), b->all, b->three, b->fused, b->d_part,
+                                            b->grid, b->o.cheb_steps, b->o.mixed != 0, b->fh, b->fty, b->f3,
+                                            with3d != 0, setup, c.stream) != hipSuccess)
+                    return fail(c, TC_ERR_DEVICE, "tc_batch_step: launch failed");
+            } else if (hipGraphLaunch(b->gx[setup ? 1 : 0][with3d], c.stream) != hipSuccess) {
                 return fail(c, TC_ERR_DEVICE, "tc_batch_step: graph launch failed");
+            }
+        }
         b->replayed = true;
     }
     if (unfinished) *unfinished = (int32_t)(b->running.size() + b->pending.size());
@@ -474,6 +499,7 @@ static tc_status impl_tc_batch_destroy(tc_batch *b) {
     }
     if (b->d_part) dev_free(c, b->d_part);
     if (b->h_inst) (void)hipHostFree(b->h_inst);
+    if (b->stage) (void)hipHostFree(b->stage);
     delete b;
     return TC_OK;
 }

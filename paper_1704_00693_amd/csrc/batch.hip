@@ -97,6 +97,15 @@ __device__ __forceinline__ T apply_A(const BInst &I, const T *kx, const T *ky, c
 
 __device__ __forceinline__ bool serves(const BInst &I, unsigned mask) { return (mask >> I.state) & 1u; }
 
+// First tile of a workgroup's grid-stride walk over the tile list.  Hardware
+// block b runs on XCD b % 8; when the grid is a multiple of 8, XCD k takes
+// the logical blocks [k G/8, (k+1) G/8), so consecutive tiles (neighbours,
+// whose borders overlap) are walked by one XCD and share its L2.
+__device__ __forceinline__ int64_t first_tile() {
+    const unsigned g = gridDim.x, b = blockIdx.x;
+    return (g & 7u) ? b : (b & 7u) * (g >> 3) + (b >> 3);
+}
+
 __device__ __forceinline__ void write_partial(double *part, int64_t t, int slot, DD v) {
     if (threadIdx.x == 0) {
         part[4 * t + 2 * slot] = v.hi;
@@ -109,7 +118,7 @@ __device__ __forceinline__ void write_partial(double *part, int64_t t, int slot,
 // u0 = u = e * rho; partial u0 . u0 (slot 0).
 __global__ void __launch_bounds__(256) bk_init(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part) {
     const int64_t nt = *ntiles;
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, 1u << B_INIT)) continue;
@@ -141,7 +150,7 @@ __global__ void __launch_bounds__(256) bk_init(BInst *insts, const BTile *tiles,
 template <typename T>
 __global__ void __launch_bounds__(256) bk_faces(BInst *insts, const BTile *tiles, const int64_t *ntiles) {
     const int64_t nt = *ntiles;
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, 1u << B_INIT)) continue;
@@ -170,7 +179,7 @@ __global__ void __launch_bounds__(256) bk_faces(BInst *insts, const BTile *tiles
 // partial maximum (slot 1).
 __global__ void __launch_bounds__(256) bk_gersh(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part) {
     const int64_t nt = *ntiles;
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, 1u << B_INIT)) continue;
@@ -196,7 +205,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) bk_resid(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part) {
     const int64_t nt = *ntiles;
     const unsigned mask = (1u << B_RESID) | (1u << B_OUTER) | (1u << B_VERIFY);
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, mask)) continue;
@@ -220,7 +229,7 @@ __global__ void __launch_bounds__(256) bk_resid(BInst *insts, const BTile *tiles
 template <typename T>
 __global__ void __launch_bounds__(256) bk_apply_correction(BInst *insts, const BTile *tiles, const int64_t *ntiles) {
     const int64_t nt = *ntiles;
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, 1u << B_OUTER)) continue;
@@ -236,7 +245,7 @@ __global__ void __launch_bounds__(256) bk_apply_correction(BInst *insts, const B
 template <typename T>
 __global__ void __launch_bounds__(256) bk_cg_p(BInst *insts, const BTile *tiles, const int64_t *ntiles) {
     const int64_t nt = *ntiles;
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, 1u << B_INNER)) continue;
@@ -251,7 +260,7 @@ __global__ void __launch_bounds__(256) bk_cg_p(BInst *insts, const BTile *tiles,
 template <typename T>
 __global__ void __launch_bounds__(256) bk_matvec(BInst *insts, const BTile *tiles, const int64_t *ntiles, double *part) {
     const int64_t nt = *ntiles;
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, 1u << B_INNER)) continue;
@@ -276,7 +285,7 @@ __global__ void __launch_bounds__(256) bk_update_init(BInst *insts, const BTile 
                                                       int skip2d) {
     const int64_t nt = *ntiles;
     const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, mask)) continue;
@@ -305,7 +314,7 @@ __global__ void __launch_bounds__(256) bk_cheb(BInst *insts, const BTile *tiles,
                                                int j) {
     const int64_t nt = *ntiles;
     const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, mask) || j > I.cheb_steps) continue;
@@ -363,7 +372,7 @@ __global__ void __launch_bounds__(256) bk_cheb_fused(BInst *insts, const BTile *
     __shared__ T sdl[2][RC];
     const int64_t nt = *ntiles;
     const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         const int K = I.cheb_steps;
@@ -480,7 +489,7 @@ __global__ void __launch_bounds__(256) bk_cheb3_fused(BInst *insts, const BTile 
     __shared__ T ring[S][3][RC];
     const int64_t nt = *ntiles;
     const unsigned mask = (1u << B_INNER) | (1u << B_INNER_START);
-    for (int64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int64_t t = first_tile(); t < nt; t += gridDim.x) {
         const BTile tl = tiles[t];
         const BInst &I = insts[tl.inst];
         if (!serves(I, mask) || I.ndim != 3 || j0 + S > I.cheb_steps) continue;  // the same for the whole workgroup
