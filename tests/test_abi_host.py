@@ -29,6 +29,26 @@ def test_exports_every_declared_symbol():
     assert sorted(tc.EXPORTS) == names
 
 
+def test_library_binds_to_one_hip_runtime():
+    """torch's wheel carries its own HIP runtime under the soname the library
+    links: loading the library must leave exactly one HIP runtime in the
+    process (the one torch uses), or the streams and memory a context borrows
+    from torch would belong to another runtime.  Checked in a fresh process
+    that loads the library before it imports torch itself."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1704_00693_amd as tc\n"
+            "tc.lib()\n"
+            "import torch\n"
+            "paths = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(paths), *sorted(paths))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    fields = out.stdout.split()
+    assert fields[0] == "1", out.stdout
+
+
 def host_ctx():
     return tc.Context(host_only=True)
 
