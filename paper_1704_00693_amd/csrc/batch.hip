@@ -460,28 +460,39 @@ __global__ void __launch_bounds__(256) bk_cheb_fused(BInst *insts, const BTile *
 }
 
 // Chebyshev steps j0 .. j0+S-1 (S = 1 or 3) of 3D instances; the last step,
-// with its reductions, stays with bk_cheb.  A workgroup takes a tile of
-// kF3X x kF3Y owned cells of one z-segment [za, zb) of kF3Z planes and
-// marches up the planes: at march m, step s works on plane m - s, so the
+// with its reductions, stays with bk_cheb.  A workgroup (f3_threads<T>) takes
+// a tile of kF3X x kF3Y owned cells of one z-segment [za, zb) of kF3Z planes
+// and marches up the planes: at march m, step s works on plane m - s, so the
 // direction a step writes for plane p is there when the next step, one march
 // later, needs it as the upper z neighbour of plane p - 1.  Each step level's
 // direction lives in LDS, a ring of three planes of the region (the owned
-// cells and S cells around them in x and y); rt and z live in registers, a
-// ring of S planes (plane p in slot (p - m0) mod S, so the march is unrolled
-// by S and every slot index is a constant).  Step s computes the cells within
+// cells and S cells around them in x and y); rt and z of a cell live in
+// registers, a ring of S planes (plane p in slot (p - m0) mod S, so the march
+// is unrolled by S and every slot index is a constant), loaded one plane
+// ahead.  In FP64 the six face coefficients of a cell join that ring, loaded
+// when their plane enters it, with 512-thread workgroups so that two slots
+// per thread leave room for them; in FP32 (where the smaller registers keep
+// four 256-thread workgroups per CU) every step reads them from memory
+// (cached lines by then).  Step s computes the cells within
 // S-1-s of the owned ones (in x and y, and in planes around the segment), so
-// every neighbour it reads was loaded or written by the step before it.  The
-// face coefficients are read from memory at every step (the plane's lines
-// are cached by then).  Neighbouring tiles and segments read this tile's
-// cells as their border, so rt alternates between two buffers (rt_alt: read
-// rt2, write rt) and an odd S puts the direction in the other sd buffer.  At
-// the domain boundary the mirrored neighbour is the cell itself, as in
-// bk_cheb, and every cell's operations are bk_cheb's, in the same order.
+// every neighbour it reads was loaded or written by the step before it.
+// Neighbouring tiles and segments read this tile's cells as their border, so
+// rt alternates between two buffers (rt_alt: read rt2, write rt) and an odd S
+// puts the direction in the other sd buffer.  At the domain boundary the
+// mirrored neighbour is the cell itself, as in bk_cheb, and every cell's
+// operations are bk_cheb's, in the same order.
+template <typename T>
+constexpr int f3_threads() {
+    return sizeof(T) == 8 ? 512 : 256;
+}
+
 template <typename T, int S>
-__global__ void __launch_bounds__(256) bk_cheb3_fused(BInst *insts, const BTile *tiles, const int64_t *ntiles, int j0,
-                                                      int rt_alt) {
+__global__ void __launch_bounds__(f3_threads<T>())
+    bk_cheb3_fused(BInst *insts, const BTile *tiles, const int64_t *ntiles, int j0, int rt_alt) {
+    constexpr int NT = f3_threads<T>();
+    constexpr bool RING = sizeof(T) == 8;  // face coefficients in the register ring
     constexpr int RW = kF3X + 2 * S, RH = kF3Y + 2 * S, RC = RW * RH;
-    constexpr int PER = (RC + 255) / 256;
+    constexpr int PER = (RC + NT - 1) / NT;
     // per-slot flags: inside the domain, owned, which in-plane neighbours
     // are other region cells (else the cell itself); bits 8..: distance to
     // the owned cells
@@ -518,7 +529,7 @@ __global__ void __launch_bounds__(256) bk_cheb3_fused(BInst *insts, const BTile 
         int64_t cxy[PER];
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int i = (int)threadIdx.x + 256 * k;
+            const int i = (int)threadIdx.x + NT * k;
             const int lx = i % RW, ly = i / RW;
             const int x = rx0 + lx, y = ry0 + ly;
             unsigned f = 0;
@@ -536,36 +547,48 @@ __global__ void __launch_bounds__(256) bk_cheb3_fused(BInst *insts, const BTile 
             fl[k] = f;
             cxy[k] = I.org + x + (int64_t)y * sy;
         }
-        // planes m0 - 1 and m0 of the direction to LDS; plane m0 + 1, rt and
-        // z of plane m0 to the prefetch registers
+        // the cells step 0 computes (every later step computes a subset)
+        auto stepped = [&](int k) { return (fl[k] & fAct) && (int)(fl[k] >> 8) <= S - 1; };
+        // planes m0 - 1 and m0 of the direction to LDS; plane m0 + 1 of the
+        // direction, and rt and z of plane m0, to the prefetch registers
         T sd_nx[PER], rt_nx[PER], z_nx[PER];
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             sd_nx[k] = rt_nx[k] = z_nx[k] = (T)0;
             if (!(fl[k] & fAct)) continue;
-            const int i = (int)threadIdx.x + 256 * k;
+            const int i = (int)threadIdx.x + NT * k;
             for (int q = m0 - 1; q <= m0; ++q)
                 if (q >= ld_lo && q < ld_hi) ring[0][q % 3][i] = sdi[cxy[k] + q * sz];
             if (m0 + 1 < ld_hi) sd_nx[k] = sdi[cxy[k] + (m0 + 1) * sz];
             if (m0 < hi[0]) rt_nx[k] = rt_in[cxy[k] + m0 * sz];
             if ((fl[k] & fOwn) && m0 >= za && m0 < zb) z_nx[k] = zp[cxy[k] + m0 * sz];
         }
-        T rt[S][PER], z[S][PER];
+        T rt[S][PER], z[S][PER], cf[RING ? S : 1][6][RING ? PER : 1];
         for (int mb = m0; mb < m_end; mb += S) {
 #pragma unroll
             for (int u = 0; u < S; ++u) {
                 const int m = mb + u;
                 if (m >= m_end) break;
                 // plane m + 1 of the direction to LDS, rt and z of plane m to
-                // their ring slot; then the loads of the next march
-                const bool sd_ok = m + 1 < ld_hi;
+                // their ring slot, the face coefficients of plane m loaded
+                // into theirs; then the loads of the next march
+                const bool sd_ok = m + 1 < ld_hi, cf_ok = m < hi[0];
 #pragma unroll
                 for (int k = 0; k < PER; ++k) {
                     if (!(fl[k] & fAct)) continue;
-                    const int i = (int)threadIdx.x + 256 * k;
+                    const int i = (int)threadIdx.x + NT * k;
                     if (sd_ok) ring[0][(m + 1) % 3][i] = sd_nx[k];
                     rt[u][k] = rt_nx[k];
                     z[u][k] = z_nx[k];
+                    if (RING && cf_ok && stepped(k)) {
+                        const int64_t c = cxy[k] + m * sz;
+                        cf[u][0][k] = kx[c + 1];
+                        cf[u][1][k] = kx[c];
+                        cf[u][2][k] = ky[c + sy];
+                        cf[u][3][k] = ky[c];
+                        cf[u][4][k] = kz[c + sz];
+                        cf[u][5][k] = kz[c];
+                    }
                     if (m + 2 < ld_hi) sd_nx[k] = sdi[cxy[k] + (m + 2) * sz];
                     if (m + 1 < hi[0]) rt_nx[k] = rt_in[cxy[k] + (m + 1) * sz];
                     if ((fl[k] & fOwn) && m + 1 >= za && m + 1 < zb) z_nx[k] = zp[cxy[k] + (m + 1) * sz];
@@ -585,15 +608,15 @@ __global__ void __launch_bounds__(256) bk_cheb3_fused(BInst *insts, const BTile 
                     for (int k = 0; k < PER; ++k) {
                         const unsigned f = fl[k];
                         if (!(f & fAct) || (int)(f >> 8) > S - 1 - s) continue;
-                        const int i = (int)threadIdx.x + 256 * k;
+                        const int i = (int)threadIdx.x + NT * k;
                         const int64_t c = cxy[k] + p * sz;
-                        const T ke = kx[c + 1], kw = kx[c];
-                        const T kn = ky[c + sy], ks = ky[c];
+                        const T ke = RING ? cf[r][0][k] : kx[c + 1], kw = RING ? cf[r][1][k] : kx[c];
+                        const T kn = RING ? cf[r][2][k] : ky[c + sy], ks = RING ? cf[r][3][k] : ky[c];
                         T diag = (T)1 + ke;
                         diag = diag + kw;
                         diag = diag + kn;
                         diag = diag + ks;
-                        const T kt = kz[c + sz], kb = kz[c];
+                        const T kt = RING ? cf[r][4][k] : kz[c + sz], kb = RING ? cf[r][5][k] : kz[c];
                         diag = diag + kt;
                         diag = diag + kb;
                         const T vc = vc_p[i];
@@ -793,9 +816,11 @@ hipError_t enqueue_iteration_t(BInst *insts, int ninst, const BTile *tiles, cons
                 int len = cheb_steps - j0 < 3 ? cheb_steps - j0 : 3;
                 len -= (len & 1) ^ 1;
                 if (len == 3)
-                    hipLaunchKernelGGL((bk_cheb3_fused<T, 3>), g, b, 0, s, insts, tiles3, ntiles3, j0, l3 & 1);
+                    hipLaunchKernelGGL((bk_cheb3_fused<T, 3>), g, dim3(f3_threads<T>()), 0, s, insts, tiles3, ntiles3,
+                                       j0, l3 & 1);
                 else
-                    hipLaunchKernelGGL((bk_cheb3_fused<T, 1>), g, b, 0, s, insts, tiles3, ntiles3, j0, l3 & 1);
+                    hipLaunchKernelGGL((bk_cheb3_fused<T, 1>), g, dim3(f3_threads<T>()), 0, s, insts, tiles3, ntiles3,
+                                       j0, l3 & 1);
                 j0 += len;
             }
         } else if (with3d) {
