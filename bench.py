@@ -179,7 +179,8 @@ def reference_copy_GBps(nbytes: int = 1 << 31, reps: int = 20) -> float:
 BATCH_BYTES_PER_CELL_ITERATION = 32 + 48 + 32 + 10 * 56 + 9 * 24 + 24 + 24
 
 
-def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8):
+def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8,
+                modes=("fp64", "mixed", "fp64_sequential")):
     """Batched heat-conduction solves: `count` instances of log-uniform size
     64^2..1024^2 (synthgen.batch_sizes), all submitted at once, to `tol`
     relative residual; FP64 sweeps, FP32 sweeps with FP64 reductions and
@@ -189,7 +190,7 @@ def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8):
     sizes = batch_sizes(count, seed)
     cells = sum((n + 2) ** 2 for n, _ in sizes)
     out = {"instances": count, "sizes": "n log-uniform in [64, 1024), 2D", "tol": tol}
-    for mode in ("fp64", "mixed", "fp64_sequential"):
+    for mode in modes:
         seq = mode == "fp64_sequential"
         with tc.Context(0) as c, tc.Batch(c, mixed=(mode == "mixed"), max_instances=1 if seq else count,
                                          max_cells=max(n * n for n, _ in sizes) if seq else cells,
@@ -219,8 +220,10 @@ def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8):
                                                 "model": "per-loop bytes of one PPCG iteration, makespan time"}
         log(f"batch {mode}: {out[mode]['solves_per_s']:.1f} solves/s, makespan {dt:.2f} s, "
             f"converged {out[mode]['converged']}/{count}")
-    out["mixed_over_sequential_fp64"] = out["mixed"]["solves_per_s"] / out["fp64_sequential"]["solves_per_s"]
-    out["fp64_batched_over_sequential"] = out["fp64"]["solves_per_s"] / out["fp64_sequential"]["solves_per_s"]
+    if "fp64_sequential" in out:
+        for mode, key in (("mixed", "mixed_over_sequential_fp64"), ("fp64", "fp64_batched_over_sequential")):
+            if mode in out:
+                out[key] = out[mode]["solves_per_s"] / out["fp64_sequential"]["solves_per_s"]
     return out
 
 
@@ -570,6 +573,8 @@ def main():
     ap.add_argument("--chain3d-staged", action="store_true",
                     help="also time the 3D chain with every run the staged analysis accepts as a staged group")
     ap.add_argument("--jacobi-variants", default="non_copy,copy", help="Jacobi variants to time: non_copy, copy")
+    ap.add_argument("--batch-modes", default="fp64,mixed,fp64_sequential",
+                    help="batched-solve modes to time: fp64, mixed, fp64_sequential")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="serving trace window in seconds (0: skip); arrivals at --serve-rate")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -649,7 +654,8 @@ def main():
                               [v for v in args.jacobi_select.split(",") if v] or None,
                               tuple(v for v in args.jacobi_variants.split(",") if v), args.chain3d_staged)
               if args.other else None)
-    batched = batch_bench(tc, args.batch_count) if args.batch_count > 0 else None
+    batched = (batch_bench(tc, args.batch_count, modes=[m for m in args.batch_modes.split(",") if m])
+               if args.batch_count > 0 else None)
     served = serve_bench(tc, args.serve_rate, args.serve_seconds, args.serve_drain) if args.serve_seconds > 0 else None
     cpu = cpu_baseline(ch, args.cpu_sample, args.cpu_procs) if args.cpu_sample > 0 else None
     untiled = results.get("none")
