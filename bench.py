@@ -187,6 +187,9 @@ def batch_bench(tc, count: int, seed: int = 3, tol: float = 1e-8,
     refinement, and FP64 solves one at a time (the sequential baseline)."""
     import numpy as np
     from synthgen import batch_sizes
+    unknown = set(modes) - {"fp64", "mixed", "fp64_sequential"}
+    if unknown:
+        raise SystemExit(f"unknown batched-solve modes {sorted(unknown)}: use fp64, mixed, fp64_sequential")
     sizes = batch_sizes(count, seed)
     cells = sum((n + 2) ** 2 for n, _ in sizes)
     out = {"instances": count, "sizes": "n log-uniform in [64, 1024), 2D", "tol": tol}
