@@ -10,6 +10,7 @@ the oracle.
   oracle's FP64 solve.
 * FP32 datasets (the precision the mixed solver's corrections use), and
   1000^2 for two iterations (many tiles), fused against untiled.
+* Grids of 4^2, 5^2 and 9^2, smaller than one tile and its border.
 """
 import sys
 
@@ -66,6 +67,27 @@ def test_chebyshev_groups_match_untiled(tc, n, inner, steps, monkeypatch):
     ref = ppcg_solve(hp.density, hp.energy, outer=outer, inner=inner)
     h = 2
     x = fg["u"][h:h + n, h:h + n]
+    assert float(np.abs(x - ref.x).max() / np.abs(ref.x).max()) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [4, 5, 9])
+@pytest.mark.parametrize("inner", [3, 10])
+def test_chebyshev_groups_on_tiny_grids(tc, n, inner):
+    """Grids as small as the groups take (n = 4 = twice the ghost depth: a
+    cell mirrors ghosts on one side only), far smaller than a tile and its
+    border: the same bits as untiled, and the oracle's solution."""
+    from oracle.tealeaf import ppcg_solve
+    from synthgen import heat_problem
+    hp = heat_problem(n, seed=13)
+    outer = 3
+    say(f"chebyshev groups tiny n={n} inner={inner}")
+    base, fb = solve(tc, hp, tc.TC_TILING_NONE, outer, inner, tc.TC_F64)
+    got, fg = solve(tc, hp, tc.TC_TILING_FUSED, outer, inner, tc.TC_F64)
+    for k in FIELDS:
+        assert np.array_equal(fg[k], fb[k]), k
+    assert got["rr"] == base["rr"] and got["rz"] == base["rz"]
+    ref = ppcg_solve(hp.density, hp.energy, outer=outer, inner=inner)
+    x = fg["u"][2:2 + n, 2:2 + n]
     assert float(np.abs(x - ref.x).max() / np.abs(ref.x).max()) <= 1e-12
 
 

@@ -191,3 +191,17 @@ def test_chebyshev_run_needs_the_recorded_fill_pattern():
         groups, per = c.tc_fused_plan()
     assert (0, 7) in groups  # with the set-up
     assert all(per[i][0] != 4 for i in range(7, len(per)))
+
+
+def test_chebyshev_runs_need_twice_the_ghost_depth():
+    """A grid narrower than twice the ghost depth has cells that mirror ghosts
+    on both sides: no Chebyshev group takes it (n = 3, depth 2); n = 4 does."""
+    from paper_1704_00693_amd.apps import HeatSolver, chebyshev_coefs
+    for n, want in ((3, False), (4, True)):
+        with tc.Context(host_only=True) as c:
+            hs = HeatSolver(c, np.full((n, n), 0.5), np.full((n, n), 1.5))
+            theta, delta, al, be = chebyshev_coefs(1.0, 100.0, 4)
+            hs.loop("TEA_PRECON_INIT", [hs.F("r", "R"), hs.F("rt", "W"), hs.F("sd", "W"), hs.F("z", "W")], [theta])
+            hs.precondition(theta, al, be, 4)
+            groups, per = c.tc_fused_plan()
+        assert any(p[0] == 4 for p in per) == want, n
