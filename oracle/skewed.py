@@ -171,6 +171,36 @@ def execute_tiled(plan: Plan, n_loops: int, run_loop) -> None:
                 run_loop(l, lo, hi)
 
 
+def wavefronts(plan: Plan):
+    """Skewed tiles grouped for wavefront-parallel execution, the alternative
+    to in-order tile execution that the end of Section 4.2 names as future
+    work: wavefront w holds the tiles whose indices sum to w, in the order of
+    Plan.tiles().  Wavefronts run in increasing order; the tiles of one
+    wavefront are meant to run at the same time."""
+    waves = {}
+    for t in plan.tiles():
+        waves.setdefault(sum(t), []).append(t)
+    return [waves[w] for w in sorted(waves)]
+
+
+def wavefront_schedule(plan: Plan, n_loops: int, interleave: bool = True, reverse: bool = False):
+    """(loop, lo, hi) steps of the wavefront-parallel schedule.  Within a
+    wavefront the tiles either advance together, loop by loop (interleave:
+    every tile runs loop l before any runs loop l + 1, as one launch per
+    loop and wavefront would), or one after another; reverse flips the
+    order of the tiles of each wavefront."""
+    out = []
+    for wave in wavefronts(plan):
+        ts = wave[::-1] if reverse else wave
+        order = ([(l, t) for l in range(n_loops) for t in ts] if interleave
+                 else [(l, t) for t in ts for l in range(n_loops)])
+        for l, t in order:
+            lo, hi = plan.box(t, l)
+            if all(h > o for o, h in zip(lo, hi)):
+                out.append((l, lo, hi))
+    return out
+
+
 def max_skew(plan: Plan, d: int) -> int:
     """Largest difference over interior tile boundaries between the loops'
     ends, i.e. the skew between the bottom and top of a tile along d."""

@@ -4,7 +4,12 @@
 * brute-force version stamps on random tiny chains (every read sees the same
   writer as in program order; every point of every loop runs exactly once);
 * a planted mistake in a plan is caught by the stamp check;
-* the CPU tiled schedule of a weighted-sum chain is bit-exact to program order.
+* the CPU tiled schedule of a weighted-sum chain is bit-exact to program order;
+* wavefront-parallel skewed tiles: the tiles of one wavefront (equal tile
+  index sums) touch disjoint data wherever one of them writes, over the whole
+  chain, so any interleaving of them is program order; the stamp check agrees
+  for interleaved and reversed orders, and rejects a grouping that puts
+  dependent tiles in one wavefront.
 """
 import json
 import os
@@ -14,7 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.skewed import READ, WRITE, Arg, Loop, skewed_plan, execute_tiled, max_skew
+from oracle.skewed import READ, WRITE, Arg, Loop, skewed_plan, execute_tiled, max_skew, wavefront_schedule, wavefronts
 from oracle.stamps import check_schedule, tiled_schedule
 from randchains import random_chain, to_oracle
 
@@ -113,3 +118,65 @@ def test_cpu_tiled_chain_bit_exact(ndim, n, tile):
     execute_tiled(plan, len(loops), run_loop)
     for a, b in zip(arrs, ref):
         assert np.array_equal(a, b)
+
+
+def _footprint(plan, loops, t):
+    """Points a tile reads and writes over the whole chain, as (dataset, point)."""
+    import itertools
+    reads, writes = set(), set()
+    for l, lp in enumerate(loops):
+        lo, hi = plan.box(t, l)
+        for x in itertools.product(*[range(a, b) for a, b in zip(lo, hi)]):
+            for a in lp.args:
+                if a.reads():
+                    for q in a.stencil:
+                        reads.add((a.dat, tuple(xi + qi for xi, qi in zip(x, q))))
+                if a.writes():
+                    writes.add((a.dat, x))
+    return reads, writes
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_wavefront_parallel_tiles(ndim):
+    import itertools
+    rng = random.Random(7000 + ndim)
+    pairs = 0
+    col_conflicts = [0]
+    for _ in range(60 if ndim == 2 else 30):
+        ch = random_chain(rng, ndim)
+        loops = to_oracle(ch)
+        plan = skewed_plan(loops, ndim, [rng.randint(1, 5) for _ in range(ndim)])
+        for wave in wavefronts(plan):
+            fp = [_footprint(plan, loops, t) for t in wave]
+            for (ra, wa), (rb, wb) in itertools.combinations(fp, 2):
+                assert not (wa & (rb | wb)) and not (wb & ra)
+                pairs += 1
+        for interleave, reverse in ((True, False), (True, True), (False, True)):
+            check_schedule(loops, wavefront_schedule(plan, len(loops), interleave, reverse))
+        # the same check finds conflicts when a column of tiles (one x index,
+        # consecutive y indices, which depend on each other) is grouped instead
+        cols = {}
+        for t in plan.tiles():
+            cols.setdefault(t[0], []).append(t)
+        for col in cols.values():
+            fp = [_footprint(plan, loops, t) for t in col]
+            for (ra, wa), (rb, wb) in itertools.combinations(fp, 2):
+                col_conflicts[0] += bool((wa & (rb | wb)) or (wb & ra))
+    assert pairs > 100 and col_conflicts[0] > 0
+
+
+def test_wavefront_check_rejects_dependent_tiles():
+    n = 12
+    # a 1D chain whose tiles depend on each other in sequence: its tiles form
+    # one wavefront each; put all of them in one wavefront, run one after the
+    # other in reverse order, and program order breaks
+    loops = [Loop([0], [n], [Arg(0, [(-1,), (0,), (1,)], READ), Arg(1, [(0,)], WRITE)]),
+             Loop([0], [n], [Arg(1, [(-1,), (0,), (1,)], READ), Arg(2, [(0,)], WRITE)]),
+             Loop([0], [n], [Arg(2, [(-1,), (0,), (1,)], READ), Arg(0, [(0,)], WRITE)])]
+    plan = skewed_plan(loops, 1, [3])
+    check_schedule(loops, wavefront_schedule(plan, len(loops)))
+    assert len(wavefronts(plan)) == plan.num_tiles[0] > 1
+    together = [(l, *plan.box((t,), l)) for t in reversed(range(plan.num_tiles[0])) for l in range(len(loops))
+                if plan.box((t,), l)[1][0] > plan.box((t,), l)[0][0]]
+    with pytest.raises(AssertionError):
+        check_schedule(loops, together)
