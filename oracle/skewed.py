@@ -1,4 +1,6 @@
-"""Skewed tiling plan (Algorithm 1) and tiled execution order (Algorithm 2).
+"""Skewed tiling plan (Algorithm 1), tiled execution order (Algorithm 2) and
+the wavefront-parallel order of the same tiles (future work, end of Section
+4.2).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
